@@ -1,0 +1,138 @@
+"""Pins of the multigrid and adjoint oracles (no GPU).
+
+Multigrid: the transfer operators of Sec. 4 (full weighting, bilinear interpolation) against
+their textbook identities, and the V-cycle against the textbook contraction of red-black
+Gauss-Seidel on the Poisson problem. Adjoint: central finite differences and dense-LU
+solves (library routines), plus the identity g^T x = lambda^T b.
+"""
+import numpy as np
+import pytest
+
+from oracle import adjoint as AD
+from oracle import gabp as G
+from oracle import mg as MG
+from paper_1904_04093_amd import workloads as W
+
+
+def _unit_images(fn, n_in, n_out):
+    M = np.zeros((n_out, n_in))
+    for k in range(n_in):
+        e = np.zeros(n_in)
+        e[k] = 1.0
+        M[:, k] = fn(e)
+    return M
+
+
+def test_full_weighting_is_quarter_transpose_of_bilinear():
+    n_c = 7
+    n_f = 2 * n_c + 1
+    P = _unit_images(lambda e: MG.prolong_bilinear(e, n_c), n_c * n_c, n_f * n_f)
+    R = _unit_images(lambda e: MG.restrict_fw(e, n_f), n_f * n_f, n_c * n_c)
+    assert np.array_equal(R, P.T / 4.0)
+    assert np.allclose(R.sum(1)[(n_c + 1) // 2], 1.0)     # weights sum to one inside
+
+
+def test_bilinear_reproduces_bilinear_functions():
+    n_c = 7
+    n_f = 2 * n_c + 1
+    f = lambda x, y: (0.3 + 1.7 * x) * (-0.2 + 0.9 * y)
+    hc, hf = 1.0 / (n_c + 1), 1.0 / (n_f + 1)
+    t = (np.arange(n_c) + 1) * hc
+    yc, xc = np.meshgrid(t, t, indexing="ij")
+    e = MG.prolong_bilinear(f(xc, yc).reshape(-1), n_c).reshape(n_f, n_f)
+    t = (np.arange(n_f) + 1) * hf
+    yf, xf = np.meshgrid(t, t, indexing="ij")
+    inner = (slice(1, n_f - 1), slice(1, n_f - 1))    # stencils that avoid the boundary
+    assert np.abs(e[inner] - f(xf, yf)[inner]).max() < 1e-15
+
+
+def test_full_weighting_of_linear_function():
+    n_f = 15
+    hf = 1.0 / (n_f + 1)
+    t = (np.arange(n_f) + 1) * hf
+    yf, xf = np.meshgrid(t, t, indexing="ij")
+    r = (2.0 + 3.0 * xf - 1.0 * yf).reshape(-1)
+    rc = MG.restrict_fw(r, n_f).reshape(7, 7)
+    tc = (np.arange(7) + 1) * (2 * hf)
+    yc, xc = np.meshgrid(tc, tc, indexing="ij")
+    assert np.abs(rc - (2.0 + 3.0 * xc - 1.0 * yc)).max() < 1e-14
+
+
+def test_vcycle_rbgs_poisson_textbook_contraction():
+    levels = W.mg_hierarchy(6, coarsest=3, kx=1.0, ky=1.0, peclet=0.0)
+    h = MG.Hierarchy(levels, smoother="rbgs", nu1=2, nu2=2)
+    b = W.rng(120, 0).uniform(-1, 1, levels[0].n)
+    x, hist = h.solve(b, 1e-10, 20)
+    rates = np.array(hist[1:]) / np.array(hist[:-1])
+    assert rates[2:].max() < 0.15
+    assert hist[-1] <= 1e-10
+
+
+def test_vcycle_exact_coarse_solve_two_levels():
+    """Two levels with no smoothing: x = P A_c^{-1} R b exactly (dense check)."""
+    levels = W.mg_hierarchy(3, coarsest=3, kx=1.0, ky=1.0, peclet=1.0)
+    assert [a.n for a in levels] == [49, 9]
+    h = MG.Hierarchy(levels, smoother="rbgs", nu1=0, nu2=0)
+    b = W.rng(121, 0).uniform(-1, 1, 49)
+    x = h.vcycle(b, np.zeros(49))
+    Ac = W.csr_to_dense(levels[1])
+    P = _unit_images(lambda e: MG.prolong_bilinear(e, 3), 9, 49)
+    assert np.allclose(x, P @ np.linalg.solve(Ac, P.T @ b / 4.0), rtol=1e-13, atol=1e-15)
+
+
+def _theta_setup(n=16, t=0):
+    theta = W.theta_problem(n, t)
+    b = W.rng(5, 101).uniform(-1, 1, n * n)
+    xt = W.rng(5, 100).uniform(-1, 1, n * n)
+    return theta, b, xt
+
+
+def _loss(n, theta, b, xt):
+    A = W.csr_to_dense(W.theta_operator(n, theta))
+    x = np.linalg.solve(A, b)
+    return 0.5 * float((x - xt) @ (x - xt))
+
+
+def test_adjoint_gradient_matches_central_differences():
+    n = 16
+    theta, b, xt = _theta_setup(n)
+    a, jptr, jnnz, jw = W.theta_jacobian(n, theta)
+    ref = AD.dense_reference(W.csr_to_dense(a), b, xt, a.row_of_nnz(), a.col,
+                             jac=(jptr, jnnz, jw))
+    eps = 1e-6
+    ps = W.rng(122, 0).choice(n * n, 16, replace=False)
+    fd = []
+    for p in ps:
+        tp, tm = theta.copy(), theta.copy()
+        tp[p] += eps
+        tm[p] -= eps
+        fd.append((_loss(n, tp, b, xt) - _loss(n, tm, b, xt)) / (2 * eps))
+    fd = np.array(fd)
+    # norm-wise over the sampled parameters: the FD round-off floor (~eps_mach L / eps)
+    # dominates tiny individual components
+    assert np.linalg.norm(fd - ref["dtheta"][ps]) <= 1e-6 * np.linalg.norm(fd)
+
+
+def test_adjoint_dot_product_identity_and_gabp_adjoint():
+    n = 16
+    theta, b, xt = _theta_setup(n, 1)
+    a, jptr, jnnz, jw = W.theta_jacobian(n, theta)
+    ref = AD.dense_reference(W.csr_to_dense(a), b, xt, a.row_of_nnz(), a.col,
+                             jac=(jptr, jnnz, jw))
+    gx = ref["x"] - xt
+    assert float(gx @ ref["x"]) == pytest.approx(float(ref["lam"] @ b), rel=1e-12)
+    out = AD.gabp_adjoint(G.Graph.from_csr(a), b, xt, 1e-14, 20000, jac=(jptr, jnnz, jw),
+                          check_every=10)
+    assert np.linalg.norm(out["lam"] - ref["lam"]) <= 1e-9 * np.linalg.norm(ref["lam"])
+    assert np.linalg.norm(out["dtheta"] - ref["dtheta"]) <= 1e-8 * np.linalg.norm(ref["dtheta"])
+
+
+def test_transposed_graph_swaps_coefficients():
+    r = W.rng(123, 0)
+    a = W.random_walk_summable(20, 0.2, r)
+    g = G.Graph.from_csr(a)
+    gt = g.transposed()
+    assert np.array_equal(gt.dense(), g.dense().T)
+    b = r.uniform(-1, 1, 20)
+    x, info, _, _ = G.solve(gt, b, 1e-14, 5000)
+    assert np.allclose(x, np.linalg.solve(g.dense().T, b), rtol=1e-11)
