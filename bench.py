@@ -1,0 +1,257 @@
+"""Benchmark of the flood GaBP hot path on one MI355X.
+
+Workload: the variable-coefficient upwind convection-diffusion operator on a 2048 x 2048
+interior grid (4,194,304 unknowns, 20,963,328 nonzeros, 16,769,024 directed message edges),
+k = exp(g) with g a 16-mode random field, rotating velocity 20(-(y-1/2), x-1/2),
+b ~ U(-1,1), seeded synthetic data.
+
+One *step* = one block of the solver's main loop: ``check_every`` (16) flood sweeps of
+Algorithm 1 in FP64 (joint Lt and m update, read-off on the last one) followed by the
+residual check r = b - A x with its norms. ``value`` = directed edge-message updates per
+second over the timed steps (inputs resident in HBM).
+
+Also reported on the same JSON line:
+  * roofline of the dominant kernel (the joint sweep): algorithmic bytes per launch over its
+    average launch time from HIP events on the launch stream;
+  * FP32 mean-only sweep rate (the inner kernel of FP32-message iterative refinement) and
+    FP64 mean-only sweep rate with precomputed Lt;
+  * time to relative residual 1e-8, plain FP64 GaBP vs FP32 messages + FP64 refinement, on a
+    smaller grid of the same family (the 2048 grid needs ~6M sweeps per solve);
+  * the CPU oracle timed on a bounded sample of sweeps on this host (a baseline only).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--ttr-grid 512]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
+
+
+def sweep_bytes_joint64(slots, n):
+    # per slot: Lt_in, m_in, coefficient (8 B each), reverse index (4 B), Lt_out, m_out (8 B each)
+    # per row: diagonal and b (8 B each)
+    return 44 * slots + 16 * n
+
+
+def sweep_bytes_mean32(slots, n):
+    # per slot: m_in, Lt* (FP32), reverse index, m_out (4 B each); per row: FP32 rhs
+    return 16 * slots + 4 * n
+
+
+def sweep_bytes_mean64(slots, n):
+    # per slot: m_in, Lt* (8 B), reverse index (4 B), m_out (8 B); per row: b (8 B)
+    return 28 * slots + 8 * n
+
+
+def _events_time(fn, reps):
+    import torch
+    st = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(st)
+    fn(reps)
+    e1.record(st)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / 1e3
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--grid", type=int, default=2048)
+    ap.add_argument("--ttr-grid", type=int, default=512)
+    ap.add_argument("--no-ttr", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-sweeps", type=int, default=12)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "layout is a design note, not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1904_04093_amd import gabp
+    from paper_1904_04093_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)
+    n = args.grid
+    t0 = time.time()
+    a, b = W.precision_at_scale(n)
+    log(f"[bench] generated {n}x{n} operator: N={a.n} nnz={a.nnz} ({time.time()-t0:.1f}s)")
+    edges = a.nnz - a.n
+    CE = 16
+    t0 = time.time()
+    sj = gabp.Solver.from_csr(a, mode="joint", check_every=CE)
+    lay = sj.layout_info()
+    log(f"[bench] setup {time.time()-t0:.1f}s layout {lay}")
+    bt = torch.as_tensor(b).cuda()
+    x = torch.zeros(a.n, dtype=torch.float64, device="cuda")
+
+    def step(k):
+        for _ in range(k):
+            sj.sweeps(bt, CE, reset=False, x=x)
+            sj.residual(bt, x, want_r=False)
+
+    sj.sweeps(bt, 1, reset=True, x=x)
+    step(args.warmup)
+    torch.cuda.synchronize()
+    tw = time.perf_counter()
+    t_gpu = _events_time(step, args.steps)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - tw
+    ms_step = 1e3 * t_gpu / args.steps
+    value = edges * CE * args.steps / t_gpu
+    log(f"[bench] timed {args.steps} steps: {ms_step:.3f} ms/step, {value/1e9:.2f} G edge-upd/s")
+
+    # dominant kernel: the joint FP64 sweep, back-to-back launches on the launch stream
+    NS = 200
+    sweeps_only = lambda k: sj.sweeps(bt, k, reset=False, x=x)
+    sweeps_only(20)
+    t_sw = _events_time(sweeps_only, NS) / NS
+    ab = sweep_bytes_joint64(lay["slots"], a.n)
+    achieved = ab / t_sw / 1e9
+    log(f"[bench] joint sweep {t_sw*1e6:.1f} us, {achieved:.0f} GB/s algorithmic")
+
+    # residual kernel (for the record)
+    res_only = lambda k: [sj.residual(bt, x, want_r=False) for _ in range(k)]
+    t_res = _events_time(res_only, 20) / 20
+
+    # FP32 mean-only sweep and FP64 mean-only sweep with precomputed Lt
+    s32 = gabp.Solver.from_csr(a, mode="precomp", precision="f32_ir", check_every=CE,
+                               tol_lambda=1e-7)
+    lsw = s32.precompute_lambda()
+    sp = gabp.Solver.from_csr(a, mode="precomp", check_every=CE, tol_lambda=1e-12)
+    lsw64 = sp.precompute_lambda()
+    sp.sweeps(bt, 1, reset=True, x=x)
+    t_m64 = _events_time(lambda k: sp.sweeps(bt, k, reset=False, x=x), NS) / NS
+    # FP32 mean-only sweeps (the inner kernel of iterative refinement): the call also casts
+    # b and widens x once, removed by differencing two sweep counts
+    x32 = torch.zeros_like(x)
+    s32.sweeps(bt, 2, reset=True, x=x32)
+    t_a = _events_time(lambda k: s32.sweeps(bt, NS + 1, reset=False, x=x32), 1)
+    t_b = _events_time(lambda k: s32.sweeps(bt, 1, reset=False, x=x32), 1)
+    t_m32 = (t_a - t_b) / NS
+    log(f"[bench] mean sweeps: FP64 {t_m64*1e6:.1f} us, FP32 {t_m32*1e6:.1f} us "
+        f"(Lt phase {lsw} / {lsw64} sweeps)")
+
+    out = {
+        "metric": "edge-msg updates/s, HBM GB/s; time to rel.res 1e-8: FP32+refine vs FP64",
+        "value": value,
+        "unit": "edge-msg updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"upwind convection-diffusion {n}x{n}, variable k=exp(g), "
+                               "rotating v, FP64 joint flood GaBP, 16 sweeps + residual check per step",
+                   "unknowns": a.n, "nnz": a.nnz, "directed_edges": edges,
+                   "sweeps_per_step": CE},
+        "roofline": {"bound": "hbm", "kernel": "k_joint (FP64 joint flood sweep)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes_per_launch": ab, "launch_us": t_sw * 1e6},
+        "wall_s_timed": t_wall,
+        "kernels": {
+            "joint_f64_sweep_us": t_sw * 1e6,
+            "joint_f64_edge_updates_per_s": edges / t_sw,
+            "mean_f64_sweep_us": t_m64 * 1e6,
+            "mean_f64_edge_updates_per_s": edges / t_m64,
+            "mean_f64_GBs": sweep_bytes_mean64(lay["slots"], a.n) / t_m64 / 1e9,
+            "mean_f32_sweep_us": t_m32 * 1e6,
+            "mean_f32_edge_updates_per_s": edges / t_m32,
+            "mean_f32_GBs": sweep_bytes_mean32(lay["slots"], a.n) / t_m32 / 1e9,
+            "residual_us": t_res * 1e6,
+            "lambda_phase_sweeps_f32": lsw, "lambda_phase_sweeps_f64": lsw64,
+        },
+    }
+    del s32, sp
+
+    if not args.no_ttr:
+        out["time_to_rel_res"] = time_to_residual(args.ttr_grid, log)
+
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(a, b, args.cpu_sweeps, log)
+    print(json.dumps(out), flush=True)
+
+
+def time_to_residual(n, log):
+    """Plain FP64 joint GaBP vs FP32 messages + FP64 refinement to rel.res 1e-8."""
+    import torch
+    from paper_1904_04093_amd import gabp
+    from paper_1904_04093_amd import workloads as W
+    a, b = W.precision_at_scale(n)
+    bt = torch.as_tensor(b).cuda()
+    res = {"grid": n, "unknowns": a.n, "tol": 1e-8}
+    try:
+        import scipy.sparse as sp
+        import scipy.sparse.linalg as spl
+        A = sp.csr_matrix((a.val, a.col, a.rowptr), shape=(a.n, a.n))
+        xs = spl.spsolve(A.tocsc(), b)
+        ref = "scipy sparse LU (FP64)"
+    except Exception:  # pragma: no cover
+        xs, ref = None, None
+    for name, kw in (("fp64_joint", dict(mode="joint")),
+                     ("fp64_precomp", dict(mode="precomp", tol_lambda=1e-12)),
+                     ("fp32_ir", dict(mode="precomp", precision="f32_ir", tol_lambda=1e-7))):
+        s = gabp.Solver.from_csr(a, check_every=64, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, info = s.solve(bt, 1e-8, 5_000_000)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        entry = {"seconds": dt, "sweeps": info.sweeps, "lambda_sweeps": info.lambda_sweeps,
+                 "outer_iters": info.outer_iters, "rel_res2": info.rel_res2,
+                 "status": info.status}
+        if xs is not None:
+            xe = x.cpu().numpy()
+            entry["x_rel_err_vs_" + "sparse_lu"] = float(np.linalg.norm(xe - xs) / np.linalg.norm(xs))
+        res[name] = entry
+        log(f"[bench] ttr {name}: {dt:.2f}s {info}")
+        del s
+    res["reference"] = ref
+    if res["fp64_joint"]["seconds"] > 0:
+        res["speedup_fp32_ir_vs_fp64_joint"] = res["fp64_joint"]["seconds"] / res["fp32_ir"]["seconds"]
+    return res
+
+
+def cpu_baseline(a, b, sweeps, log):
+    """The FP64 oracle, as it stands, on this host: ``sweeps`` flood sweeps of the full grid."""
+    from oracle import gabp as G
+    t0 = time.perf_counter()
+    g = G.Graph.from_csr(a)
+    t_build = time.perf_counter() - t0
+    Lt = np.zeros(g.E)
+    m = np.zeros(g.E)
+    t0 = time.perf_counter()
+    for _ in range(sweeps):
+        _, Lt, m, _, _ = G.sweep(g, b, Lt, m)
+    t = time.perf_counter() - t0
+    rate = g.E * sweeps / t
+    log(f"[bench] cpu oracle: {t/sweeps:.3f} s/sweep, {rate/1e6:.1f} M edge-upd/s")
+    return {"value": rate, "unit": "edge-msg updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{sweeps} FP64 joint flood sweeps of the full {int(np.sqrt(a.n))}^2 grid "
+                      f"(numpy, single-threaded; graph build {t_build:.1f}s excluded)",
+            "host_cpus": os.cpu_count()}
+
+
+if __name__ == "__main__":
+    main()

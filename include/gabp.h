@@ -1,0 +1,187 @@
+/*
+ * gabp.h -- C ABI of the MI355X (gfx950) flood Gaussian-belief-propagation solver.
+ *
+ * Solves A x = b for a square, invertible, possibly nonsymmetric sparse A with a nonzero
+ * diagonal (arXiv 1904.04093, Sec. 1, eq. linear_problem; the convergence theorem of
+ * Sec. 2.3 assumes A_ii != 0) by the reparametrised GaBP of Sec. 2.3
+ * (eq. nonsymmetric_GaBP_rules, Algorithm 1) run in the flood ("parallel") schedule of
+ * Sec. 2.2: every message of sweep n+1 is computed from the messages of sweep n.
+ *
+ * Graph and messages. The directed edge j -> i exists iff A_ij != 0 (Sec. 2.3). Every edge
+ * carries (Lt_ji, m_ji) with Lt = Lambda / A_ji, m = mu * Lambda
+ * (eq. nonsymmetric_GaBP_messages). One sweep, for every node j:
+ *     Sigma_j = A_jj + sum_k Lt_kj A_kj,   M_j = b_j + sum_k m_kj,   x_j = M_j / Sigma_j,
+ * and for every edge j -> i:
+ *     Lt_ji = -A_ij / (Sigma_j - Lt_ij A_ij),   m_ji = Lt_ji (M_j - m_ij).
+ * A sweep reads off x from the messages it receives and then updates them, so the s-th
+ * read-off uses s-1 updates (one sweep applies h^2/4 to the 5-point Laplacian, two apply
+ * h^2/12 [1; 1 4 1; 1], Sec. 4.1). Messages start at zero.
+ *
+ * Conventions for every entry point:
+ *  - Return value: a GABP_* status below. Nothing aborts the process; after a non-zero
+ *    return gabp_last_error() describes the failure (thread-local string).
+ *  - "device" pointers are HIP device allocations (e.g. torch tensors on cuda:0) on the
+ *    device the context was created on; "host" pointers are ordinary CPU memory.
+ *  - Every device-side operation is enqueued on the caller's `stream` (0 = null stream).
+ *    Calls that report convergence block the host on small (<= 64-byte) readbacks.
+ *  - Contexts are not thread-safe: calls on one context must not overlap.
+ *  - int32 row/column indices; the internal slot count (twice the number of off-diagonal
+ *    pairs of the symmetrised pattern, padded) must stay below 2^31 - 1.
+ */
+#ifndef GABP_H
+#define GABP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes -------------------------------------------------------------------- */
+#define GABP_OK 0          /* converged (or the requested fixed work was done)            */
+#define GABP_MAXSWEEPS 1   /* tolerance not reached; outputs hold the last iterate         */
+#define GABP_EINVAL -1     /* bad argument: CSR structure, rev index, sizes, NULL pointer  */
+#define GABP_ENOMEM -2     /* device or host allocation failed                              */
+#define GABP_EZERODIAG -3  /* a diagonal entry A_ii is missing or zero                      */
+#define GABP_ENUMERIC -4   /* non-finite read-off or residual (zero cavity precision, ...) */
+#define GABP_EDEVICE -5    /* a HIP runtime call failed                                     */
+#define GABP_ENOTSUPP -6   /* valid request this build does not support                     */
+
+/* ---- options ------------------------------------------------------------------------- */
+#define GABP_MODE_JOINT 0    /* Algorithm 1 literally: Lt and m updated every sweep        */
+#define GABP_MODE_PRECOMP 1  /* Lt iterated alone to convergence first, then frozen and
+                                shared by every right-hand side and smoother call
+                                (Sec. 2.3 remark on decoupling; Sec. 4.2)                    */
+#define GABP_F64 0           /* all message arithmetic in FP64                              */
+#define GABP_F32_IR 1        /* FP32 mean messages (precomputed Lt rounded to FP32) inside
+                                FP64 iterative refinement: r = b - A x and x += d are the
+                                only FP64 steps                                             */
+#define GABP_SCHED_FLOOD 0   /* all nodes send every sweep (Sec. 2.2)                       */
+#define GABP_SCHED_REDBLACK 1/* red nodes send, then black nodes, using the newest messages
+                                (the paper's red-black GaBP, Sec. 5); needs node colours    */
+#define GABP_WARM_RESET_M 0  /* smoother: mean messages restart from zero every call        */
+#define GABP_WARM_ALL 1      /* smoother: mean messages carry over between calls            */
+
+typedef struct {
+  int32_t mode;              /* GABP_MODE_*                      default GABP_MODE_JOINT   */
+  int32_t precision;         /* GABP_F64 | GABP_F32_IR           default GABP_F64          */
+  int32_t check_every;       /* sweeps between residual checks   default 16               */
+  double tol_lambda;         /* Lt converged when max|dLt| <= tol_lambda * max|Lt|
+                                (0: run exactly max_lambda_sweeps)  default 1e-14          */
+  int32_t max_lambda_sweeps; /* cap on the Lt phase               default 100000           */
+  int32_t warm;              /* GABP_WARM_*                       default RESET_M          */
+  double ir_inner_tol;       /* IR: inner solve ends when ||r_new|| <= ir_inner_tol*||r||
+                                                                  default 1e-4             */
+  int32_t ir_max_inner;      /* IR: cap on inner sweeps per outer step  default 1000000   */
+  int32_t schedule;          /* GABP_SCHED_*                      default FLOOD            */
+} gabp_options;
+
+typedef struct {
+  int32_t status;        /* GABP_OK or GABP_MAXSWEEPS (or a negative error)                */
+  int32_t sweeps;        /* mean/joint sweeps done (all IR inner sweeps summed)            */
+  int32_t lambda_sweeps; /* sweeps of the Lt phase (PRECOMP), 0 when reused or JOINT       */
+  int32_t outer_iters;   /* IR outer steps (0 for plain solves)                            */
+  double rel_res2;       /* ||b - A x||_2 / ||b||_2 of the returned x                      */
+  double res_inf;        /* ||b - A x||_inf of the returned x                              */
+} gabp_info;
+
+typedef struct gabp_ctx gabp_ctx;
+typedef struct mg_ctx mg_ctx;
+
+void gabp_default_options(gabp_options* opt);
+const char* gabp_strerror(int status);
+const char* gabp_last_error(void);
+
+/* Check a CSR matrix on the host. rowptr[n+1], col[nnz], val[nnz]: host pointers; columns
+ * strictly increasing within each row, every diagonal present, finite and nonzero.
+ * rev[nnz] (host, may be NULL): rev[e] is the index of the transposed entry (j,i) of entry
+ * e = (i,j), or -1 when A has no stored (j,i); a diagonal entry may give itself or -1.
+ * Returns GABP_OK, GABP_EINVAL or GABP_EZERODIAG. Needs no GPU. */
+int gabp_validate_csr(int32_t n, int64_t nnz, const int32_t* rowptr, const int32_t* col,
+                      const double* val, const int32_t* rev);
+
+/* Build a solver context for A (Sec. 2.3: graph of A plus reverse-edge pairing). rowptr,
+ * col, val, rev: HOST pointers as in gabp_validate_csr (rev NULL: built here). The matrix
+ * is copied into context-owned device memory in slice-of-64-rows, column-major order over
+ * the symmetrised pattern; the caller may free its arrays on return. opt NULL = defaults.
+ * `colour` (host, may be NULL): one byte per row, 0 = red, 1 = black; required by
+ * GABP_SCHED_REDBLACK, and no edge may join two nodes of one colour.
+ * The context belongs to the current HIP device. */
+int gabp_setup(gabp_ctx** out, int32_t n, int64_t nnz, const int32_t* rowptr,
+               const int32_t* col, const double* val, const int32_t* rev,
+               const uint8_t* colour, const gabp_options* opt, hipStream_t stream);
+
+/* Replace the values of A, same pattern as at setup. val: DEVICE pointer, nnz doubles in
+ * the setup CSR order. Precomputed Lt (if any) is invalidated and rebuilt on next use. */
+int gabp_update_values(gabp_ctx* ctx, const double* val, hipStream_t stream);
+
+void gabp_destroy(gabp_ctx* ctx);
+
+/* Algorithm 1: solve A x = b (b, x: DEVICE, n doubles) from zero messages until
+ * ||b - A x||_2 / ||b||_2 <= tol, checked every opt.check_every sweeps (so the sweep count
+ * is a multiple of it, or max_sweeps), or max_sweeps. Mode and precision from the options:
+ * JOINT/F64 runs the joint sweep; PRECOMP/F64 computes (or reuses) Lt then runs mean-only
+ * sweeps; F32_IR runs FP32 mean-only sweeps inside FP64 iterative refinement (max_sweeps
+ * then caps the total inner sweeps). info may be NULL. */
+int gabp_solve(gabp_ctx* ctx, const double* b, double* x, double tol, int32_t max_sweeps,
+               gabp_info* info, hipStream_t stream);
+
+/* Same as gabp_solve for A^T lambda = g (adjoint solves): GaBP on the transposed graph,
+ * i.e. with A_ij and A_ji exchanged in every rule. g, lambda: DEVICE, n doubles. */
+int gabp_solve_transposed(gabp_ctx* ctx, const double* g, double* lambda, double tol,
+                          int32_t max_sweeps, gabp_info* info, hipStream_t stream);
+
+/* Exactly `sweeps` sweeps of the configured mode/schedule with no residual check.
+ * reset != 0 starts from zero messages (PRECOMP: with the precomputed Lt, computed first if
+ * needed); reset == 0 continues from the context's current messages. x (DEVICE) receives
+ * the read-off of the last sweep. Precision GABP_F32_IR runs FP32 mean-only sweeps on
+ * fp32(b) and widens the FP32 read-off into x. For parity checks, checkpoints and timing. */
+int gabp_sweeps(gabp_ctx* ctx, const double* b, double* x, int32_t sweeps, int32_t reset,
+                int32_t transposed, hipStream_t stream);
+
+/* Lt phase only (Sec. 2.3: Lt does not depend on b): iterate Lt from zero until
+ * opt.tol_lambda / opt.max_lambda_sweeps, keep Lt*, 1/Sigma* (FP64 and FP32 copies).
+ * sweeps_out (host, may be NULL) receives the number of Lt updates. */
+int gabp_precompute_lambda(gabp_ctx* ctx, int32_t transposed, int32_t* sweeps_out,
+                           hipStream_t stream);
+
+/* Algorithm 3 (error-correction smoother): r = b - A x; mu sweeps on A e = r with the
+ * context's mode/schedule/precision and warm policy; x += e^mu (the mu-th read-off).
+ * b: DEVICE const, x: DEVICE in/out, n doubles. */
+int gabp_smooth(gabp_ctx* ctx, const double* b, double* x, int32_t mu, hipStream_t stream);
+
+/* r = b - A x (transposed != 0: b - A^T x) and its norms. b, x, r: DEVICE (r may be NULL).
+ * norms (host, may be NULL): [||r||_2, ||r||_inf, ||b||_2]. Deterministic reduction order. */
+int gabp_residual(gabp_ctx* ctx, const double* b, const double* x, double* r,
+                  int32_t transposed, double* norms, hipStream_t stream);
+
+/* Adjoint scatter for L(x(A)) with A x = b: G_e = dL/dA_e = -lambda_row(e) x_col(e) for
+ * every stored entry e in setup CSR order (lambda solves A^T lambda = dL/dx). lambda, x:
+ * DEVICE n doubles; G: DEVICE nnz doubles (may be NULL). If jptr != NULL the entry
+ * gradient is also reduced onto nparam parameters through a parameter-major sparse
+ * Jacobian: dtheta_p = sum_{k in jptr[p]..jptr[p+1]} jw[k] * G[jnnz[k]] (jptr, jnnz, jw,
+ * dtheta: DEVICE). Each parameter is reduced by one thread in index order (deterministic). */
+int gabp_adjoint_scatter(gabp_ctx* ctx, const double* lambda, const double* x, double* G,
+                         int32_t nparam, const int32_t* jptr, const int32_t* jnnz,
+                         const double* jw, double* dtheta, hipStream_t stream);
+
+/* Checkpoint: the complete iteration state (messages, precomputed Lt, sweep parity).
+ * gabp_get_state with dst == NULL stores the needed size in *bytes; otherwise dst (host)
+ * must hold *bytes. gabp_set_state restores a state taken from a context with the same
+ * matrix pattern and options. */
+int gabp_get_state(gabp_ctx* ctx, void* dst, size_t* bytes, hipStream_t stream);
+int gabp_set_state(gabp_ctx* ctx, const void* src, size_t bytes, hipStream_t stream);
+
+/* Sizes of the internal layout (host outputs, any may be NULL): number of rows, stored
+ * nonzeros, directed message slots (2 x off-diagonal pairs), padded slot count. */
+int gabp_layout_info(const gabp_ctx* ctx, int32_t* n, int64_t* nnz, int64_t* slots,
+                     int64_t* padded_slots);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GABP_H */

@@ -296,3 +296,48 @@ def ir_solve(g: Graph, b, tol, lam32, inner_sweeps, max_outer=50):
             info.sweeps += 1
         x = x + s * d.astype(np.float64)
     return x, info
+
+
+# ----------------------------------------------------------------------------------------
+# Red-black schedule (the paper's "red-black GaBP", Sec. 5): Algorithm 1 visiting all red
+# nodes, then all black nodes; a visit reads off x_j and sends j's messages, and a node
+# of the second colour already receives the messages sent in the first half.
+# ----------------------------------------------------------------------------------------
+
+def sweep_coloured(g: Graph, b, Lt, m, colour, lambda_fixed=None):
+    """One red-black sweep. colour: 0 (red) / 1 (black) per node, a proper 2-colouring.
+
+    ``lambda_fixed = (Lt*, S*)``: mean-only with frozen Lambda~ (x = M / S*).
+    Returns (x, Lt, m) with x the read-off of each node at its visit.
+    """
+    colour = np.asarray(colour)
+    x = np.zeros(g.n)
+    Lt = Lt.copy()
+    m = m.copy()
+    for c in (0, 1):
+        if lambda_fixed is None:
+            S, M = node_totals(g, b, Lt, m)
+        else:
+            S = lambda_fixed[1]
+            M = b + np.bincount(g.dst, weights=m, minlength=g.n)
+        sel = colour == c
+        x[sel] = M[sel] / S[sel]
+        upd = colour[g.src] == c
+        back_m = _gather(m, g.rev)
+        if lambda_fixed is None:
+            back_L = _gather(Lt, g.rev)
+            with np.errstate(divide="ignore", invalid="ignore"):
+                L_new = -g.a_ij / (S[g.src] - back_L * g.a_ij)
+            m_new = L_new * (M[g.src] - back_m)
+            Lt = np.where(upd, L_new, Lt)
+        else:
+            m_new = lambda_fixed[0] * (M[g.src] - back_m)
+        m = np.where(upd, m_new, m)
+    return x, Lt, m
+
+
+def grid_colour(nx, ny=None):
+    """Red-black colouring of an nx x ny grid, x fastest: colour = (ix + iy) mod 2."""
+    ny = nx if ny is None else ny
+    iy, ix = np.divmod(np.arange(nx * ny), nx)
+    return ((ix + iy) % 2).astype(np.uint8)

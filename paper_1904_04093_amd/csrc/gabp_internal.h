@@ -1,0 +1,172 @@
+// Internal declarations shared by the host drivers and the HIP kernels of libgabp.
+//
+// Layout ("SELL-64 over the symmetrised pattern"):
+//  * Every row j owns one slot per neighbour i of the symmetrised off-diagonal pattern
+//    {i != j : A_ji != 0 or A_ij != 0}, columns ascending. Slot (j,i) holds the message
+//    i -> j that row j *receives* (Lt_ij, m_ij), plus val = A_ji (row j's own coefficient,
+//    used by r = b - A x) and aT = A_ij (the coefficient of the message j -> i that row j
+//    *sends*, and of Lt_ij in Sigma_j). A missing entry is stored as 0, which makes the
+//    corresponding message exactly zero (Sec. 2.3: if A_jk = 0, x_k is not eliminated).
+//  * Rows are grouped into slices of 64 (one wavefront); slice s occupies
+//    [sptr[s], sptr[s+1]) and stores slot k of row 64 s + lane at sptr[s] + 64 k + lane,
+//    so the 64 lanes of a wavefront touch 64 consecutive elements for every k.
+//  * rev[p] is the position of the reverse slot (i,j); padding slots point at a trash
+//    position `epad` that nobody reads.
+//  * The sweep is written "push" style, as Algorithm 1 is: the thread of row j reads its
+//    own incoming messages (contiguous), forms Sigma_j and M_j, reads off x_j and writes
+//    every outgoing message j -> i straight into the receiver's slot rev[p].
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/gabp.h"
+
+namespace gabp {
+
+constexpr int kSlice = 64;      // rows per slice = wavefront size on CDNA
+constexpr int kBlock = 256;     // threads per block for row kernels (4 slices)
+constexpr int kRedBlock = 256;  // threads per block for reductions
+
+struct Precomp {
+  bool valid = false;
+  int sweeps = 0;
+  double* lamout = nullptr;    // [epad] Lt*_ji of the message j -> i, stored at slot (j,i)
+  double* S = nullptr;         // [n] Sigma*_j
+  float* lamout32 = nullptr;   // [epad] FP32 copy of lamout
+  float* invS32 = nullptr;     // [n] FP32 of 1/Sigma* (computed in FP64, rounded once)
+};
+
+struct Layout {
+  int32_t n = 0;
+  int64_t nnz = 0;
+  int64_t slots = 0;      // directed message slots (symmetrised pattern)
+  int64_t epad = 0;       // padded slot count; position epad is the trash slot
+  int32_t nslices = 0;
+  int32_t max_width = 0;  // max slots per row
+  // device
+  int32_t* sptr = nullptr;   // [nslices+1]
+  int32_t* rev = nullptr;    // [epad]
+  int32_t* col = nullptr;    // [epad]
+  double* val = nullptr;     // [epad] A_ji at slot (j,i)
+  double* aT = nullptr;      // [epad] A_ij at slot (j,i)
+  double* diag = nullptr;    // [n]
+  int32_t* val_src = nullptr;   // [epad] CSR index feeding val (-1: zero)
+  int32_t* aT_src = nullptr;    // [epad] CSR index feeding aT (-1: zero)
+  int32_t* diag_src = nullptr;  // [n]
+  int32_t* csr_row = nullptr;   // [nnz] row of each stored entry (adjoint scatter)
+  int32_t* csr_col = nullptr;   // [nnz]
+  uint8_t* colour = nullptr;    // [n] or null
+};
+
+}  // namespace gabp
+
+struct gabp_ctx {
+  int device = 0;
+  gabp_options opt{};
+  gabp::Layout L;
+  // message state: lam[parity], msg[parity] hold the current incoming messages
+  double* lam[2] = {nullptr, nullptr};
+  double* msg[2] = {nullptr, nullptr};
+  float* msg32[2] = {nullptr, nullptr};
+  int parity = 0;
+  int parity32 = 0;
+  gabp::Precomp pre[2];       // [0] A, [1] A^T
+  // work vectors
+  double* r = nullptr;        // [n]
+  double* r2 = nullptr;       // [n]
+  double* e = nullptr;        // [n]
+  float* r32 = nullptr;       // [n]
+  float* d32 = nullptr;       // [n]
+  // reductions
+  int32_t nred = 0;           // blocks of the residual kernel
+  double* partials = nullptr; // [3 * nred]
+  double* red = nullptr;      // [8] device scalars: 0 ||r||2^2, 1 max|r|, 2 ||b||2^2, 3 scale
+  unsigned long long* lmax = nullptr;  // [2] max|dLt|, max|Lt| as ordered bit patterns
+  double* host_red = nullptr;          // pinned [8]
+};
+
+namespace gabp {
+
+// ---- error reporting ----
+int fail(int code, const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+#define GABP_HIP(call)                                           \
+  do {                                                           \
+    hipError_t _e = (call);                                      \
+    if (_e != hipSuccess) return ::gabp::hip_fail(_e, #call);    \
+  } while (0)
+
+// ---- kernel launchers (kernels.hip) ----
+struct SweepArgs {
+  const Layout* L;
+  const double* coef;       // aT (forward) or val (transposed)
+  const double* b;
+  const double* lam_in;
+  const double* msg_in;
+  double* lam_out;
+  double* msg_out;
+  double* x;                // null: no read-off written
+  int colour;               // -1 flood, 0/1 only rows of that colour (in place)
+};
+hipError_t launch_joint_sweep(const SweepArgs& a, hipStream_t s);
+
+struct MeanArgs64 {
+  const Layout* L;
+  const double* lamout;
+  const double* S;
+  const double* b;
+  const double* msg_in;
+  double* msg_out;
+  double* x;
+  int colour;
+};
+hipError_t launch_mean_sweep64(const MeanArgs64& a, hipStream_t s);
+
+struct MeanArgs32 {
+  const Layout* L;
+  const float* lamout;
+  const float* invS;
+  const float* b;
+  const float* msg_in;
+  float* msg_out;
+  float* x;
+  int colour;
+};
+hipError_t launch_mean_sweep32(const MeanArgs32& a, hipStream_t s);
+
+hipError_t launch_lambda_sweep(const Layout* L, const double* coef, const double* lam_in,
+                               double* lam_out, double* lamout, unsigned long long* lmax,
+                               hipStream_t s);
+hipError_t launch_lambda_finalize(const Layout* L, const double* coef, const double* lam_in,
+                                  Precomp* P, hipStream_t s);
+
+// r = b - A_eff x_eff, x_eff = x (+ scale[0] * dx if dx); writes r (if r) and block
+// partials; then reduces them into red[0..2].
+hipError_t launch_residual(const Layout* L, const double* coef_row, const double* b,
+                           const double* x, const float* dx, const double* scale, double* r,
+                           double* partials, int32_t nred, double* red, hipStream_t s);
+
+hipError_t launch_fill64(double* p, int64_t n, double v, hipStream_t s);
+hipError_t launch_fill32(float* p, int64_t n, float v, hipStream_t s);
+hipError_t launch_copy64(double* dst, const double* src, int64_t n, hipStream_t s);
+// dst = (float)(src / scale[0])
+hipError_t launch_cast_scaled(float* dst, const double* src, const double* scale, int64_t n,
+                              hipStream_t s);
+// x += scale[0] * (double)d    (scale may be null: 1)
+hipError_t launch_axpy32(double* x, const float* d, const double* scale, int64_t n,
+                         hipStream_t s);
+hipError_t launch_axpy64(double* x, const double* d, int64_t n, hipStream_t s);
+hipError_t launch_update_values(const Layout* L, const double* csr_val, int* flag,
+                                hipStream_t s);
+hipError_t launch_entry_grad(const Layout* L, const double* lam, const double* x, double* G,
+                             hipStream_t s);
+hipError_t launch_param_reduce(int32_t nparam, const int32_t* jptr, const int32_t* jnnz,
+                               const double* jw, const double* lam, const double* x,
+                               const int32_t* row, const int32_t* col, double* dtheta,
+                               hipStream_t s);
+
+}  // namespace gabp

@@ -1,0 +1,609 @@
+// HIP kernels of libgabp for gfx950 (CDNA4).
+//
+// Everything here is bandwidth-bound sparse work (about 0.2-0.4 flop per byte against an
+// FP64 ridge near 10 flop/byte), so there is no MFMA: the design goal is that every
+// wavefront touches whole, contiguous 64-element runs of each per-slot array.
+//
+// Row kernels: one thread per row, 64 consecutive rows per wavefront (= one slice of the
+// layout), 256 threads per block. A thread keeps its row's incoming messages in registers
+// (widths up to 16 slots; a two-pass variant re-reads wider rows from cache), so the
+// per-row sums of Algorithm 1 are plain in-register accumulations and no cross-lane
+// traffic is needed. Reductions (residual norms, Lt convergence) go through wavefront
+// shuffles and LDS in a fixed order, so repeated runs give identical bits.
+#include <cmath>
+
+#include "gabp_internal.h"
+
+namespace gabp {
+namespace {
+
+inline int nblocks(int64_t n, int b = kBlock) { return static_cast<int>((n + b - 1) / b); }
+
+__device__ __forceinline__ int row_base(const int32_t* __restrict__ sptr, int j, int* w) {
+  const int s = j >> 6;
+  const int a = sptr[s];
+  *w = (sptr[s + 1] - a) >> 6;
+  return a + (j & 63);
+}
+
+// ---- wavefront / block reductions (deterministic) -------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// ---------------------------------------------------------------------------------------
+// Joint flood sweep (Algorithm 1, FP64): read off x_j, then send Lt_ji and m_ji.
+// KMAX > 0: row held in registers; KMAX == 0: two passes over memory for wide rows.
+// colour >= 0: only rows of that colour work, in place (red-black schedule).
+// ---------------------------------------------------------------------------------------
+template <int KMAX, bool WX>
+__global__ __launch_bounds__(kBlock) void k_joint(
+    int n, const int32_t* __restrict__ sptr, const int32_t* __restrict__ rev,
+    const double* __restrict__ coef, const double* __restrict__ diag,
+    const double* __restrict__ b, const double* lam_in, const double* msg_in,
+    double* lam_out, double* msg_out, double* __restrict__ x,
+    const uint8_t* __restrict__ colour, int c) {
+  const int j = blockIdx.x * kBlock + threadIdx.x;
+  if (j >= n) return;
+  if (c >= 0 && colour[j] != c) return;
+  int w;
+  const int p0 = row_base(sptr, j, &w);
+  double S = diag[j];
+  double M = b[j];
+  if constexpr (KMAX > 0) {
+    double l[KMAX], m[KMAX], a[KMAX];
+    int r[KMAX];
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+      if (k < w) {
+        const int p = p0 + 64 * k;
+        l[k] = lam_in[p];
+        m[k] = msg_in[p];
+        a[k] = coef[p];
+        r[k] = rev[p];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+      if (k < w) {
+        S = fma(l[k], a[k], S);
+        M += m[k];
+      }
+    }
+    if (WX) x[j] = M / S;
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+      if (k < w) {
+        const double L = -a[k] / (S - l[k] * a[k]);
+        lam_out[r[k]] = L;
+        msg_out[r[k]] = L * (M - m[k]);
+      }
+    }
+  } else {
+    for (int k = 0; k < w; ++k) {
+      const int p = p0 + 64 * k;
+      S = fma(lam_in[p], coef[p], S);
+      M += msg_in[p];
+    }
+    if (WX) x[j] = M / S;
+    for (int k = 0; k < w; ++k) {
+      const int p = p0 + 64 * k;
+      const double l = lam_in[p], a = coef[p], m = msg_in[p];
+      const int r = rev[p];
+      const double L = -a / (S - l * a);
+      lam_out[r] = L;
+      msg_out[r] = L * (M - m);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Mean-only sweep with frozen Lt* (Sec. 2.3 decoupling, Sec. 4.2), FP64 and FP32.
+// lamout[p] = Lt*_ji of the message row j sends through slot p = (j,i).
+// ---------------------------------------------------------------------------------------
+template <typename T>
+struct ReadOff;
+template <>
+struct ReadOff<double> {
+  static __device__ __forceinline__ double f(double M, const double* S, int j) { return M / S[j]; }
+};
+template <>
+struct ReadOff<float> {
+  static __device__ __forceinline__ float f(float M, const float* invS, int j) {
+    return M * invS[j];
+  }
+};
+
+template <typename T, int KMAX, bool WX>
+__global__ __launch_bounds__(kBlock) void k_mean(
+    int n, const int32_t* __restrict__ sptr, const int32_t* __restrict__ rev,
+    const T* __restrict__ lamout, const T* __restrict__ Sx, const T* __restrict__ b,
+    const T* msg_in, T* msg_out, T* __restrict__ x, const uint8_t* __restrict__ colour,
+    int c) {
+  const int j = blockIdx.x * kBlock + threadIdx.x;
+  if (j >= n) return;
+  if (c >= 0 && colour[j] != c) return;
+  int w;
+  const int p0 = row_base(sptr, j, &w);
+  T M = b[j];
+  if constexpr (KMAX > 0) {
+    T m[KMAX], lo[KMAX];
+    int r[KMAX];
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+      if (k < w) {
+        const int p = p0 + 64 * k;
+        m[k] = msg_in[p];
+        lo[k] = lamout[p];
+        r[k] = rev[p];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k)
+      if (k < w) M += m[k];
+    if (WX) x[j] = ReadOff<T>::f(M, Sx, j);
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k)
+      if (k < w) msg_out[r[k]] = lo[k] * (M - m[k]);
+  } else {
+    for (int k = 0; k < w; ++k) M += msg_in[p0 + 64 * k];
+    if (WX) x[j] = ReadOff<T>::f(M, Sx, j);
+    for (int k = 0; k < w; ++k) {
+      const int p = p0 + 64 * k;
+      msg_out[rev[p]] = lamout[p] * (M - msg_in[p]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Lt-only flood sweep for the precompute phase. Also records the outgoing value at the
+// sender's own slot (lamout) and the largest change / magnitude of this sweep.
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ unsigned long long dbits(double v) {
+  return static_cast<unsigned long long>(__double_as_longlong(v));
+}
+
+template <int KMAX>
+__global__ __launch_bounds__(kBlock) void k_lambda(
+    int n, const int32_t* __restrict__ sptr, const int32_t* __restrict__ rev,
+    const double* __restrict__ coef, const double* __restrict__ diag, const double* lam_in,
+    double* lam_out, double* __restrict__ lamout, unsigned long long* __restrict__ lmax) {
+  __shared__ double sh[2][kBlock / 64];
+  const int j = blockIdx.x * kBlock + threadIdx.x;
+  double dm = 0.0, lm = 0.0;
+  if (j < n) {
+    int w;
+    const int p0 = row_base(sptr, j, &w);
+    double S = diag[j];
+    if constexpr (KMAX > 0) {
+      double l[KMAX], a[KMAX];
+      int r[KMAX];
+#pragma unroll
+      for (int k = 0; k < KMAX; ++k) {
+        if (k < w) {
+          const int p = p0 + 64 * k;
+          l[k] = lam_in[p];
+          a[k] = coef[p];
+          r[k] = rev[p];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < KMAX; ++k)
+        if (k < w) S = fma(l[k], a[k], S);
+#pragma unroll
+      for (int k = 0; k < KMAX; ++k) {
+        if (k < w) {
+          const int p = p0 + 64 * k;
+          const double L = -a[k] / (S - l[k] * a[k]);
+          dm = fmax(dm, fabs(L - lamout[p]));
+          lm = fmax(lm, fabs(L));
+          lamout[p] = L;
+          lam_out[r[k]] = L;
+        }
+      }
+    } else {
+      for (int k = 0; k < w; ++k) {
+        const int p = p0 + 64 * k;
+        S = fma(lam_in[p], coef[p], S);
+      }
+      for (int k = 0; k < w; ++k) {
+        const int p = p0 + 64 * k;
+        const double l = lam_in[p], a = coef[p];
+        const double L = -a / (S - l * a);
+        dm = fmax(dm, fabs(L - lamout[p]));
+        lm = fmax(lm, fabs(L));
+        lamout[p] = L;
+        lam_out[rev[p]] = L;
+      }
+    }
+  }
+  // NaN anywhere must stop the phase: map it to +inf for the ordered-bits maximum
+  if (dm != dm) dm = INFINITY;
+  if (lm != lm) lm = INFINITY;
+  dm = wave_max(dm);
+  lm = wave_max(lm);
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sh[0][wv] = dm;
+    sh[1][wv] = lm;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double d2 = sh[0][0], l2 = sh[1][0];
+    for (int q = 1; q < kBlock / 64; ++q) {
+      d2 = fmax(d2, sh[0][q]);
+      l2 = fmax(l2, sh[1][q]);
+    }
+    atomicMax(&lmax[0], dbits(d2));
+    atomicMax(&lmax[1], dbits(l2));
+  }
+}
+
+template <int KMAX>
+__global__ __launch_bounds__(kBlock) void k_lambda_fin(
+    int n, const int32_t* __restrict__ sptr, const double* __restrict__ coef,
+    const double* __restrict__ diag, const double* __restrict__ lam_in,
+    const double* __restrict__ lamout, double* __restrict__ Sout, float* __restrict__ lamout32,
+    float* __restrict__ invS32) {
+  const int j = blockIdx.x * kBlock + threadIdx.x;
+  if (j >= n) return;
+  int w;
+  const int p0 = row_base(sptr, j, &w);
+  double S = diag[j];
+  for (int k = 0; k < w; ++k) {
+    const int p = p0 + 64 * k;
+    S = fma(lam_in[p], coef[p], S);
+    lamout32[p] = static_cast<float>(lamout[p]);
+  }
+  Sout[j] = S;
+  invS32[j] = static_cast<float>(1.0 / S);
+}
+
+// ---------------------------------------------------------------------------------------
+// Residual r = b - A x (coef_row = val) or b - A^T x (coef_row = aT), optionally at
+// x + scale * dx, with per-block partial norms.
+// ---------------------------------------------------------------------------------------
+template <bool XADD>
+__global__ __launch_bounds__(kRedBlock) void k_residual(
+    int n, const int32_t* __restrict__ sptr, const int32_t* __restrict__ col,
+    const double* __restrict__ coef_row, const double* __restrict__ diag,
+    const double* __restrict__ b, const double* __restrict__ x, const float* __restrict__ dx,
+    const double* __restrict__ scale, double* __restrict__ r, double* __restrict__ partials) {
+  __shared__ double sh[3][kRedBlock / 64];
+  const int j = blockIdx.x * kRedBlock + threadIdx.x;
+  double rr = 0.0, ra = 0.0, bb = 0.0;
+  if (j < n) {
+    int w;
+    const int p0 = row_base(sptr, j, &w);
+    const double sc = XADD ? scale[0] : 0.0;
+    double xj = x[j];
+    if (XADD) xj = fma(sc, static_cast<double>(dx[j]), xj);
+    const double bj = b[j];
+    double acc = fma(-diag[j], xj, bj);
+    for (int k = 0; k < w; ++k) {
+      const int p = p0 + 64 * k;
+      const int cc = col[p];
+      double xc = x[cc];
+      if (XADD) xc = fma(sc, static_cast<double>(dx[cc]), xc);
+      acc = fma(-coef_row[p], xc, acc);
+    }
+    if (r) r[j] = acc;
+    rr = acc * acc;
+    ra = fabs(acc);
+    if (ra != ra) ra = INFINITY;
+    bb = bj * bj;
+  }
+  rr = wave_sum(rr);
+  ra = wave_max(ra);
+  bb = wave_sum(bb);
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sh[0][wv] = rr;
+    sh[1][wv] = ra;
+    sh[2][wv] = bb;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s0 = sh[0][0], s1 = sh[1][0], s2 = sh[2][0];
+    for (int q = 1; q < kRedBlock / 64; ++q) {
+      s0 += sh[0][q];
+      s1 = fmax(s1, sh[1][q]);
+      s2 += sh[2][q];
+    }
+    partials[3 * blockIdx.x + 0] = s0;
+    partials[3 * blockIdx.x + 1] = s1;
+    partials[3 * blockIdx.x + 2] = s2;
+  }
+}
+
+__global__ __launch_bounds__(kRedBlock) void k_finalize_norms(
+    int nred, const double* __restrict__ partials, double* __restrict__ red) {
+  __shared__ double sh[3][kRedBlock / 64];
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  for (int q = threadIdx.x; q < nred; q += kRedBlock) {
+    s0 += partials[3 * q + 0];
+    s1 = fmax(s1, partials[3 * q + 1]);
+    s2 += partials[3 * q + 2];
+  }
+  s0 = wave_sum(s0);
+  s1 = wave_max(s1);
+  s2 = wave_sum(s2);
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sh[0][wv] = s0;
+    sh[1][wv] = s1;
+    sh[2][wv] = s2;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t0 = sh[0][0], t1 = sh[1][0], t2 = sh[2][0];
+    for (int q = 1; q < kRedBlock / 64; ++q) {
+      t0 += sh[0][q];
+      t1 = fmax(t1, sh[1][q]);
+      t2 += sh[2][q];
+    }
+    red[0] = t0;
+    red[1] = t1;
+    red[2] = t2;
+    red[3] = t1;  // max|r|: the scale used by iterative refinement
+  }
+}
+
+// ---- elementwise helpers --------------------------------------------------------------
+template <typename T>
+__global__ void k_fill(T* __restrict__ p, int64_t n, T v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+__global__ void k_copy64(double* __restrict__ d, const double* __restrict__ s, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    d[i] = s[i];
+}
+__global__ void k_cast_scaled(float* __restrict__ d, const double* __restrict__ s,
+                              const double* __restrict__ scale, int64_t n) {
+  const double inv = scale ? 1.0 / scale[0] : 1.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    d[i] = static_cast<float>(s[i] * inv);
+}
+__global__ void k_axpy32(double* __restrict__ x, const float* __restrict__ d,
+                         const double* __restrict__ scale, int64_t n) {
+  const double sc = scale ? scale[0] : 1.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = fma(sc, static_cast<double>(d[i]), x[i]);
+}
+__global__ void k_axpy64(double* __restrict__ x, const double* __restrict__ d, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    x[i] += d[i];
+}
+
+__global__ void k_update_slots(int64_t epad, const int32_t* __restrict__ vsrc,
+                               const int32_t* __restrict__ asrc, const double* __restrict__ csr,
+                               double* __restrict__ val, double* __restrict__ aT) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < epad;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t v = vsrc[p], a = asrc[p];
+    val[p] = v >= 0 ? csr[v] : 0.0;
+    aT[p] = a >= 0 ? csr[a] : 0.0;
+  }
+}
+__global__ void k_update_diag(int n, const int32_t* __restrict__ dsrc,
+                              const double* __restrict__ csr, double* __restrict__ diag,
+                              int* __restrict__ bad) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const double d = csr[dsrc[j]];
+  diag[j] = d;
+  if (!(d != 0.0) || !isfinite(d)) atomicOr(bad, 1);
+}
+
+__global__ void k_entry_grad(int64_t nnz, const int32_t* __restrict__ row,
+                             const int32_t* __restrict__ col, const double* __restrict__ lam,
+                             const double* __restrict__ x, double* __restrict__ G) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz;
+       e += (int64_t)gridDim.x * blockDim.x)
+    G[e] = -lam[row[e]] * x[col[e]];
+}
+__global__ void k_param_reduce(int np, const int32_t* __restrict__ jptr,
+                               const int32_t* __restrict__ jnnz, const double* __restrict__ jw,
+                               const double* __restrict__ lam, const double* __restrict__ x,
+                               const int32_t* __restrict__ row, const int32_t* __restrict__ col,
+                               double* __restrict__ out) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  double acc = 0.0;
+  for (int k = jptr[p]; k < jptr[p + 1]; ++k) {
+    const int e = jnnz[k];
+    acc = fma(jw[k], -lam[row[e]] * x[col[e]], acc);
+  }
+  out[p] = acc;
+}
+
+int grid_for(int64_t n) {
+  const int64_t b = (n + 255) / 256;
+  return static_cast<int>(b < 65536 ? (b < 1 ? 1 : b) : 65536);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------------------
+#define GABP_DISPATCH_WIDTH(W, CALL4, CALL8, CALL16, CALL0) \
+  do {                                                      \
+    if ((W) <= 4) { CALL4; }                                \
+    else if ((W) <= 8) { CALL8; }                           \
+    else if ((W) <= 16) { CALL16; }                         \
+    else { CALL0; }                                         \
+  } while (0)
+
+hipError_t launch_joint_sweep(const SweepArgs& a, hipStream_t s) {
+  const Layout& L = *a.L;
+  const int g = nblocks(L.n);
+#define JOINT_ARGS                                                                      \
+  L.n, L.sptr, L.rev, a.coef, L.diag, a.b, a.lam_in, a.msg_in, a.lam_out, a.msg_out, a.x, \
+      L.colour, a.colour
+  if (a.x) {
+    GABP_DISPATCH_WIDTH(L.max_width,
+                        (k_joint<4, true><<<g, kBlock, 0, s>>>(JOINT_ARGS)),
+                        (k_joint<8, true><<<g, kBlock, 0, s>>>(JOINT_ARGS)),
+                        (k_joint<16, true><<<g, kBlock, 0, s>>>(JOINT_ARGS)),
+                        (k_joint<0, true><<<g, kBlock, 0, s>>>(JOINT_ARGS)));
+  } else {
+    GABP_DISPATCH_WIDTH(L.max_width,
+                        (k_joint<4, false><<<g, kBlock, 0, s>>>(JOINT_ARGS)),
+                        (k_joint<8, false><<<g, kBlock, 0, s>>>(JOINT_ARGS)),
+                        (k_joint<16, false><<<g, kBlock, 0, s>>>(JOINT_ARGS)),
+                        (k_joint<0, false><<<g, kBlock, 0, s>>>(JOINT_ARGS)));
+  }
+#undef JOINT_ARGS
+  return hipGetLastError();
+}
+
+hipError_t launch_mean_sweep64(const MeanArgs64& a, hipStream_t s) {
+  const Layout& L = *a.L;
+  const int g = nblocks(L.n);
+#define MEAN_ARGS \
+  L.n, L.sptr, L.rev, a.lamout, a.S, a.b, a.msg_in, a.msg_out, a.x, L.colour, a.colour
+  if (a.x) {
+    GABP_DISPATCH_WIDTH(L.max_width,
+                        (k_mean<double, 4, true><<<g, kBlock, 0, s>>>(MEAN_ARGS)),
+                        (k_mean<double, 8, true><<<g, kBlock, 0, s>>>(MEAN_ARGS)),
+                        (k_mean<double, 16, true><<<g, kBlock, 0, s>>>(MEAN_ARGS)),
+                        (k_mean<double, 0, true><<<g, kBlock, 0, s>>>(MEAN_ARGS)));
+  } else {
+    GABP_DISPATCH_WIDTH(L.max_width,
+                        (k_mean<double, 4, false><<<g, kBlock, 0, s>>>(MEAN_ARGS)),
+                        (k_mean<double, 8, false><<<g, kBlock, 0, s>>>(MEAN_ARGS)),
+                        (k_mean<double, 16, false><<<g, kBlock, 0, s>>>(MEAN_ARGS)),
+                        (k_mean<double, 0, false><<<g, kBlock, 0, s>>>(MEAN_ARGS)));
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_mean_sweep32(const MeanArgs32& a, hipStream_t s) {
+  const Layout& L = *a.L;
+  const int g = nblocks(L.n);
+  const float* S = a.invS;
+  (void)S;
+  if (a.x) {
+    GABP_DISPATCH_WIDTH(L.max_width,
+                        (k_mean<float, 4, true><<<g, kBlock, 0, s>>>(L.n, L.sptr, L.rev, a.lamout, a.invS, a.b, a.msg_in, a.msg_out, a.x, L.colour, a.colour)),
+                        (k_mean<float, 8, true><<<g, kBlock, 0, s>>>(L.n, L.sptr, L.rev, a.lamout, a.invS, a.b, a.msg_in, a.msg_out, a.x, L.colour, a.colour)),
+                        (k_mean<float, 16, true><<<g, kBlock, 0, s>>>(L.n, L.sptr, L.rev, a.lamout, a.invS, a.b, a.msg_in, a.msg_out, a.x, L.colour, a.colour)),
+                        (k_mean<float, 0, true><<<g, kBlock, 0, s>>>(L.n, L.sptr, L.rev, a.lamout, a.invS, a.b, a.msg_in, a.msg_out, a.x, L.colour, a.colour)));
+  } else {
+    GABP_DISPATCH_WIDTH(L.max_width,
+                        (k_mean<float, 4, false><<<g, kBlock, 0, s>>>(L.n, L.sptr, L.rev, a.lamout, a.invS, a.b, a.msg_in, a.msg_out, a.x, L.colour, a.colour)),
+                        (k_mean<float, 8, false><<<g, kBlock, 0, s>>>(L.n, L.sptr, L.rev, a.lamout, a.invS, a.b, a.msg_in, a.msg_out, a.x, L.colour, a.colour)),
+                        (k_mean<float, 16, false><<<g, kBlock, 0, s>>>(L.n, L.sptr, L.rev, a.lamout, a.invS, a.b, a.msg_in, a.msg_out, a.x, L.colour, a.colour)),
+                        (k_mean<float, 0, false><<<g, kBlock, 0, s>>>(L.n, L.sptr, L.rev, a.lamout, a.invS, a.b, a.msg_in, a.msg_out, a.x, L.colour, a.colour)));
+  }
+#undef MEAN_ARGS
+  return hipGetLastError();
+}
+
+hipError_t launch_lambda_sweep(const Layout* Lp, const double* coef, const double* lam_in,
+                               double* lam_out, double* lamout, unsigned long long* lmax,
+                               hipStream_t s) {
+  const Layout& L = *Lp;
+  const int g = nblocks(L.n);
+  k_fill<unsigned long long><<<1, 64, 0, s>>>(lmax, 2, 0ull);
+  GABP_DISPATCH_WIDTH(
+      L.max_width,
+      (k_lambda<4><<<g, kBlock, 0, s>>>(L.n, L.sptr, L.rev, coef, L.diag, lam_in, lam_out, lamout, lmax)),
+      (k_lambda<8><<<g, kBlock, 0, s>>>(L.n, L.sptr, L.rev, coef, L.diag, lam_in, lam_out, lamout, lmax)),
+      (k_lambda<16><<<g, kBlock, 0, s>>>(L.n, L.sptr, L.rev, coef, L.diag, lam_in, lam_out, lamout, lmax)),
+      (k_lambda<0><<<g, kBlock, 0, s>>>(L.n, L.sptr, L.rev, coef, L.diag, lam_in, lam_out, lamout, lmax)));
+  return hipGetLastError();
+}
+
+hipError_t launch_lambda_finalize(const Layout* Lp, const double* coef, const double* lam_in,
+                                  Precomp* P, hipStream_t s) {
+  const Layout& L = *Lp;
+  k_lambda_fin<0><<<nblocks(L.n), kBlock, 0, s>>>(L.n, L.sptr, coef, L.diag, lam_in,
+                                                  P->lamout, P->S, P->lamout32, P->invS32);
+  return hipGetLastError();
+}
+
+hipError_t launch_residual(const Layout* Lp, const double* coef_row, const double* b,
+                           const double* x, const float* dx, const double* scale, double* r,
+                           double* partials, int32_t nred, double* red, hipStream_t s) {
+  const Layout& L = *Lp;
+  if (dx)
+    k_residual<true><<<nred, kRedBlock, 0, s>>>(L.n, L.sptr, L.col, coef_row, L.diag, b, x,
+                                                dx, scale, r, partials);
+  else
+    k_residual<false><<<nred, kRedBlock, 0, s>>>(L.n, L.sptr, L.col, coef_row, L.diag, b, x,
+                                                 nullptr, nullptr, r, partials);
+  k_finalize_norms<<<1, kRedBlock, 0, s>>>(nred, partials, red);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill64(double* p, int64_t n, double v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_fill<double><<<grid_for(n), 256, 0, s>>>(p, n, v);
+  return hipGetLastError();
+}
+hipError_t launch_fill32(float* p, int64_t n, float v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_fill<float><<<grid_for(n), 256, 0, s>>>(p, n, v);
+  return hipGetLastError();
+}
+hipError_t launch_copy64(double* d, const double* src, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_copy64<<<grid_for(n), 256, 0, s>>>(d, src, n);
+  return hipGetLastError();
+}
+hipError_t launch_cast_scaled(float* d, const double* src, const double* scale, int64_t n,
+                              hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_cast_scaled<<<grid_for(n), 256, 0, s>>>(d, src, scale, n);
+  return hipGetLastError();
+}
+hipError_t launch_axpy32(double* x, const float* d, const double* scale, int64_t n,
+                         hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_axpy32<<<grid_for(n), 256, 0, s>>>(x, d, scale, n);
+  return hipGetLastError();
+}
+hipError_t launch_axpy64(double* x, const double* d, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_axpy64<<<grid_for(n), 256, 0, s>>>(x, d, n);
+  return hipGetLastError();
+}
+hipError_t launch_update_values(const Layout* Lp, const double* csr, int* bad, hipStream_t s) {
+  const Layout& L = *Lp;
+  k_update_slots<<<grid_for(L.epad), 256, 0, s>>>(L.epad, L.val_src, L.aT_src, csr, L.val,
+                                                  L.aT);
+  k_update_diag<<<nblocks(L.n), 256, 0, s>>>(L.n, L.diag_src, csr, L.diag, bad);
+  return hipGetLastError();
+}
+hipError_t launch_entry_grad(const Layout* Lp, const double* lam, const double* x, double* G,
+                             hipStream_t s) {
+  const Layout& L = *Lp;
+  if (L.nnz <= 0) return hipSuccess;
+  k_entry_grad<<<grid_for(L.nnz), 256, 0, s>>>(L.nnz, L.csr_row, L.csr_col, lam, x, G);
+  return hipGetLastError();
+}
+hipError_t launch_param_reduce(int32_t np, const int32_t* jptr, const int32_t* jnnz,
+                               const double* jw, const double* lam, const double* x,
+                               const int32_t* row, const int32_t* col, double* out,
+                               hipStream_t s) {
+  if (np <= 0) return hipSuccess;
+  k_param_reduce<<<nblocks(np), 256, 0, s>>>(np, jptr, jnnz, jw, lam, x, row, col, out);
+  return hipGetLastError();
+}
+
+}  // namespace gabp

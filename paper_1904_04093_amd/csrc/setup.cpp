@@ -1,0 +1,366 @@
+// Host side of the context: CSR validation, the symmetrised slice layout with its
+// reverse-slot index, device allocation and value updates.
+//
+// Graph construction follows Sec. 2.3: edge j -> i iff A_ij != 0. The layout stores, for
+// every row j and every neighbour i of the symmetrised pattern, the message i -> j that j
+// receives together with A_ji and A_ij; where only one of the two entries is stored the
+// other coefficient is zero, so the message through it is identically zero (Sec. 2.3,
+// remark after Algorithm 1), which is how structurally nonsymmetric A is handled.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "gabp_internal.h"
+
+namespace gabp {
+
+static thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+  return e == hipErrorOutOfMemory ? GABP_ENOMEM : GABP_EDEVICE;
+}
+
+namespace {
+
+int validate(int32_t n, int64_t nnz, const int32_t* rowptr, const int32_t* col,
+             const double* val, const int32_t* rev) {
+  if (n <= 0) return fail(GABP_EINVAL, "n must be positive");
+  if (!rowptr || !col || !val) return fail(GABP_EINVAL, "NULL CSR array");
+  if (nnz < n) return fail(GABP_EINVAL, "nnz < n: the diagonal must be stored");
+  if (rowptr[0] != 0 || rowptr[n] != nnz) return fail(GABP_EINVAL, "rowptr[0] != 0 or rowptr[n] != nnz");
+  for (int32_t i = 0; i < n; ++i) {
+    if (rowptr[i + 1] < rowptr[i]) return fail(GABP_EINVAL, "rowptr not monotone at row " + std::to_string(i));
+    bool has_diag = false;
+    for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+      const int32_t c = col[e];
+      if (c < 0 || c >= n) return fail(GABP_EINVAL, "column out of range in row " + std::to_string(i));
+      if (e > rowptr[i] && col[e - 1] >= c)
+        return fail(GABP_EINVAL, "columns not strictly increasing in row " + std::to_string(i));
+      if (!std::isfinite(val[e])) return fail(GABP_EINVAL, "non-finite value in row " + std::to_string(i));
+      if (c == i) {
+        has_diag = true;
+        if (val[e] == 0.0) return fail(GABP_EZERODIAG, "zero diagonal at row " + std::to_string(i));
+      }
+    }
+    if (!has_diag) return fail(GABP_EZERODIAG, "missing diagonal at row " + std::to_string(i));
+  }
+  if (rev) {
+    std::vector<int32_t> row_of(static_cast<size_t>(nnz));
+    for (int32_t i = 0; i < n; ++i)
+      for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) row_of[e] = i;
+    for (int32_t i = 0; i < n; ++i) {
+      for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+        const int32_t j = col[e];
+        const int64_t r = rev[e];
+        // locate (j, i) by binary search
+        const int32_t* b = col + rowptr[j];
+        const int32_t* en = col + rowptr[j + 1];
+        const int32_t* f = std::lower_bound(b, en, i);
+        const int64_t expect = (f != en && *f == i) ? (f - col) : -1;
+        if (j == i) {
+          if (r != e && r != -1) return fail(GABP_EINVAL, "rev of a diagonal entry must be itself or -1");
+          continue;
+        }
+        if (r != expect)
+          return fail(GABP_EINVAL, "rev inconsistent at entry " + std::to_string(e));
+        if (r >= 0 && (row_of[r] != j || col[r] != i))
+          return fail(GABP_EINVAL, "rev does not point at the transposed entry");
+      }
+    }
+  }
+  return GABP_OK;
+}
+
+template <typename T>
+int upload(T** dst, const std::vector<T>& src, hipStream_t s) {
+  const size_t bytes = std::max<size_t>(src.size(), 1) * sizeof(T);
+  GABP_HIP(hipMalloc(reinterpret_cast<void**>(dst), bytes));
+  if (!src.empty())
+    GABP_HIP(hipMemcpyAsync(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  return GABP_OK;
+}
+
+template <typename T>
+int alloc(T** dst, int64_t count) {
+  const size_t bytes = static_cast<size_t>(std::max<int64_t>(count, 1)) * sizeof(T);
+  GABP_HIP(hipMalloc(reinterpret_cast<void**>(dst), bytes));
+  return GABP_OK;
+}
+
+}  // namespace
+}  // namespace gabp
+
+using namespace gabp;
+
+extern "C" {
+
+void gabp_default_options(gabp_options* o) {
+  if (!o) return;
+  o->mode = GABP_MODE_JOINT;
+  o->precision = GABP_F64;
+  o->check_every = 16;
+  o->tol_lambda = 1e-14;
+  o->max_lambda_sweeps = 100000;
+  o->warm = GABP_WARM_RESET_M;
+  o->ir_inner_tol = 1e-4;
+  o->ir_max_inner = 1000000;
+  o->schedule = GABP_SCHED_FLOOD;
+}
+
+const char* gabp_strerror(int s) {
+  switch (s) {
+    case GABP_OK: return "ok";
+    case GABP_MAXSWEEPS: return "tolerance not reached within max_sweeps";
+    case GABP_EINVAL: return "invalid argument";
+    case GABP_ENOMEM: return "out of memory";
+    case GABP_EZERODIAG: return "missing or zero diagonal entry";
+    case GABP_ENUMERIC: return "non-finite value (zero cavity precision or divergence)";
+    case GABP_EDEVICE: return "HIP runtime error";
+    case GABP_ENOTSUPP: return "not supported";
+    default: return "unknown status";
+  }
+}
+
+const char* gabp_last_error(void) { return g_last_error.c_str(); }
+
+int gabp_validate_csr(int32_t n, int64_t nnz, const int32_t* rowptr, const int32_t* col,
+                      const double* val, const int32_t* rev) {
+  return validate(n, nnz, rowptr, col, val, rev);
+}
+
+int gabp_setup(gabp_ctx** out, int32_t n, int64_t nnz, const int32_t* rowptr,
+               const int32_t* col, const double* val, const int32_t* rev,
+               const uint8_t* colour, const gabp_options* opt, hipStream_t stream) {
+  if (!out) return fail(GABP_EINVAL, "out is NULL");
+  *out = nullptr;
+  int st = validate(n, nnz, rowptr, col, val, rev);
+  if (st != GABP_OK) return st;
+  gabp_options o;
+  gabp_default_options(&o);
+  if (opt) o = *opt;
+  if (o.check_every < 1 || o.max_lambda_sweeps < 0 || o.tol_lambda < 0 ||
+      (o.mode != GABP_MODE_JOINT && o.mode != GABP_MODE_PRECOMP) ||
+      (o.precision != GABP_F64 && o.precision != GABP_F32_IR) ||
+      (o.schedule != GABP_SCHED_FLOOD && o.schedule != GABP_SCHED_REDBLACK) ||
+      (o.warm != GABP_WARM_RESET_M && o.warm != GABP_WARM_ALL) || o.ir_max_inner < 1 ||
+      !(o.ir_inner_tol > 0.0))
+    return fail(GABP_EINVAL, "invalid options");
+  if (o.schedule == GABP_SCHED_REDBLACK && !colour)
+    return fail(GABP_EINVAL, "red-black schedule needs node colours");
+
+  // --- transposed pattern (counting sort): tptr/trow/tidx list entries (i, j) by column j
+  std::vector<int64_t> tptr(n + 1, 0);
+  for (int64_t e = 0; e < nnz; ++e) tptr[col[e] + 1]++;
+  for (int32_t j = 0; j < n; ++j) tptr[j + 1] += tptr[j];
+  std::vector<int32_t> trow(nnz), tidx(nnz);
+  {
+    std::vector<int64_t> cur(tptr.begin(), tptr.end() - 1);
+    for (int32_t i = 0; i < n; ++i)
+      for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+        const int64_t q = cur[col[e]]++;
+        trow[q] = i;
+        tidx[q] = static_cast<int32_t>(e);
+      }
+  }
+  // --- symmetrised off-diagonal pattern of every row (merge of row j and column j)
+  std::vector<int64_t> uptr(n + 1, 0);
+  std::vector<int32_t> unbr, uval, uaT;   // neighbour, CSR index of A_ji, CSR index of A_ij
+  unbr.reserve(static_cast<size_t>(nnz) * 2);
+  uval.reserve(static_cast<size_t>(nnz) * 2);
+  uaT.reserve(static_cast<size_t>(nnz) * 2);
+  std::vector<int32_t> diag_src(n, -1);
+  int32_t max_w = 0;
+  for (int32_t j = 0; j < n; ++j) {
+    int64_t a = rowptr[j], ae = rowptr[j + 1];
+    int64_t t = tptr[j], te = tptr[j + 1];
+    int32_t w = 0;
+    while (a < ae || t < te) {
+      const int32_t ca = a < ae ? col[a] : std::numeric_limits<int32_t>::max();
+      const int32_t ct = t < te ? trow[t] : std::numeric_limits<int32_t>::max();
+      const int32_t c = std::min(ca, ct);
+      int32_t iv = -1, ia = -1;
+      if (ca == c) iv = static_cast<int32_t>(a++);
+      if (ct == c) ia = tidx[t++];
+      if (c == j) {
+        diag_src[j] = iv;
+        continue;
+      }
+      unbr.push_back(c);
+      uval.push_back(iv);
+      uaT.push_back(ia);
+      ++w;
+    }
+    uptr[j + 1] = uptr[j] + w;
+    max_w = std::max(max_w, w);
+  }
+  const int64_t slots = uptr[n];
+  // --- slices of 64 rows, column-major inside a slice
+  const int32_t nslices = (n + kSlice - 1) / kSlice;
+  std::vector<int64_t> sptr64(nslices + 1, 0);
+  for (int32_t s = 0; s < nslices; ++s) {
+    int64_t w = 0;
+    for (int32_t j = s * kSlice; j < std::min(n, (s + 1) * kSlice); ++j)
+      w = std::max<int64_t>(w, uptr[j + 1] - uptr[j]);
+    sptr64[s + 1] = sptr64[s] + w * kSlice;
+  }
+  const int64_t epad = sptr64[nslices];
+  if (epad + 1 >= std::numeric_limits<int32_t>::max())
+    return fail(GABP_ENOTSUPP, "more than 2^31-1 padded message slots");
+  auto pos = [&](int32_t j, int64_t k) -> int64_t {
+    return sptr64[j / kSlice] + k * kSlice + (j % kSlice);
+  };
+  std::vector<int32_t> h_rev(epad, static_cast<int32_t>(epad)), h_col(epad, 0);
+  std::vector<int32_t> h_vsrc(epad, -1), h_asrc(epad, -1);
+  std::vector<double> h_val(epad, 0.0), h_aT(epad, 0.0), h_diag(n);
+  for (int32_t s = 0; s < nslices; ++s) {   // padding slots: own row as column (coef 0)
+    const int64_t w = (sptr64[s + 1] - sptr64[s]) / kSlice;
+    for (int32_t lane = 0; lane < kSlice; ++lane)
+      for (int64_t k = 0; k < w; ++k)
+        h_col[sptr64[s] + k * kSlice + lane] = std::min(n - 1, s * kSlice + lane);
+  }
+  std::vector<int64_t> cursor(uptr.begin(), uptr.end() - 1);
+  for (int32_t j = 0; j < n; ++j) {
+    h_diag[j] = val[diag_src[j]];
+    for (int64_t k = 0; k < uptr[j + 1] - uptr[j]; ++k) {
+      const int64_t u = uptr[j] + k;
+      const int32_t i = unbr[u];
+      const int64_t p = pos(j, k);
+      // rows are visited in ascending j and every row lists its neighbours ascending, so
+      // the next unvisited slot of row i is (i, j)
+      const int64_t ui = cursor[i]++;
+      if (unbr[ui] != j) return fail(GABP_EINVAL, "internal: asymmetric union pattern");
+      h_rev[p] = static_cast<int32_t>(pos(i, ui - uptr[i]));
+      h_col[p] = i;
+      h_vsrc[p] = uval[u];
+      h_asrc[p] = uaT[u];
+      h_val[p] = uval[u] >= 0 ? val[uval[u]] : 0.0;
+      h_aT[p] = uaT[u] >= 0 ? val[uaT[u]] : 0.0;
+    }
+  }
+  if (colour) {
+    for (int32_t j = 0; j < n; ++j) {
+      if (colour[j] > 1) return fail(GABP_EINVAL, "colour must be 0 or 1");
+      for (int64_t u = uptr[j]; u < uptr[j + 1]; ++u)
+        if (colour[unbr[u]] == colour[j])
+          return fail(GABP_EINVAL, "colouring is not proper: edge inside one colour at row " +
+                                       std::to_string(j));
+    }
+  }
+  std::vector<int32_t> h_sptr(nslices + 1);
+  for (int32_t s = 0; s <= nslices; ++s) h_sptr[s] = static_cast<int32_t>(sptr64[s]);
+  std::vector<int32_t> h_row(nnz), h_ccol(col, col + nnz);
+  for (int32_t i = 0; i < n; ++i)
+    for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) h_row[e] = i;
+
+  gabp_ctx* c = new gabp_ctx();
+  c->opt = o;
+  GABP_HIP(hipGetDevice(&c->device));
+  Layout& L = c->L;
+  L.n = n;
+  L.nnz = nnz;
+  L.slots = slots;
+  L.epad = epad;
+  L.nslices = nslices;
+  L.max_width = max_w;
+  auto cleanup_fail = [&](int code) {
+    gabp_destroy(c);
+    return code;
+  };
+#define UP(dst, src) \
+  if ((st = upload(&(dst), src, stream)) != GABP_OK) return cleanup_fail(st)
+#define AL(dst, cnt) \
+  if ((st = alloc(&(dst), cnt)) != GABP_OK) return cleanup_fail(st)
+  UP(L.sptr, h_sptr);
+  UP(L.rev, h_rev);
+  UP(L.col, h_col);
+  UP(L.val, h_val);
+  UP(L.aT, h_aT);
+  UP(L.diag, h_diag);
+  UP(L.val_src, h_vsrc);
+  UP(L.aT_src, h_asrc);
+  UP(L.diag_src, diag_src);
+  UP(L.csr_row, h_row);
+  UP(L.csr_col, h_ccol);
+  if (colour) {
+    std::vector<uint8_t> hc(colour, colour + n);
+    UP(L.colour, hc);
+  }
+  for (int q = 0; q < 2; ++q) {
+    AL(c->lam[q], epad + 1);
+    AL(c->msg[q], epad + 1);
+  }
+  AL(c->r, n);
+  AL(c->r2, n);
+  AL(c->e, n);
+  AL(c->r32, n);
+  AL(c->d32, n);
+  c->nred = (n + kRedBlock - 1) / kRedBlock;
+  AL(c->partials, 3 * (int64_t)c->nred);
+  AL(c->red, 8);
+  AL(c->lmax, 2);
+#undef UP
+#undef AL
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->host_red), 8 * sizeof(double),
+                    hipHostMallocDefault) != hipSuccess)
+    return cleanup_fail(fail(GABP_ENOMEM, "pinned host buffer"));
+  for (int q = 0; q < 2; ++q) {
+    hipError_t e1 = launch_fill64(c->lam[q], epad + 1, 0.0, stream);
+    hipError_t e2 = launch_fill64(c->msg[q], epad + 1, 0.0, stream);
+    if (e1 != hipSuccess || e2 != hipSuccess) return cleanup_fail(hip_fail(e1 != hipSuccess ? e1 : e2, "fill"));
+  }
+  hipError_t e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return cleanup_fail(hip_fail(e, "hipStreamSynchronize(setup)"));
+  *out = c;
+  return GABP_OK;
+}
+
+int gabp_update_values(gabp_ctx* c, const double* val, hipStream_t stream) {
+  if (!c || !val) return fail(GABP_EINVAL, "NULL argument");
+  int* bad = reinterpret_cast<int*>(c->lmax);   // reuse 16 bytes of scratch as a flag
+  GABP_HIP(hipMemsetAsync(bad, 0, sizeof(int), stream));
+  GABP_HIP(launch_update_values(&c->L, val, bad, stream));
+  int hbad = 0;
+  GABP_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, stream));
+  GABP_HIP(hipStreamSynchronize(stream));
+  c->pre[0].valid = c->pre[1].valid = false;
+  if (hbad) return fail(GABP_EZERODIAG, "zero or non-finite diagonal in updated values");
+  return GABP_OK;
+}
+
+void gabp_destroy(gabp_ctx* c) {
+  if (!c) return;
+  auto F = [](void* p) {
+    if (p) (void)hipFree(p);
+  };
+  Layout& L = c->L;
+  F(L.sptr); F(L.rev); F(L.col); F(L.val); F(L.aT); F(L.diag); F(L.val_src); F(L.aT_src);
+  F(L.diag_src); F(L.csr_row); F(L.csr_col); F(L.colour);
+  for (int q = 0; q < 2; ++q) {
+    F(c->lam[q]); F(c->msg[q]); F(c->msg32[q]);
+    F(c->pre[q].lamout); F(c->pre[q].S); F(c->pre[q].lamout32); F(c->pre[q].invS32);
+  }
+  F(c->r); F(c->r2); F(c->e); F(c->r32); F(c->d32); F(c->partials); F(c->red); F(c->lmax);
+  if (c->host_red) (void)hipHostFree(c->host_red);
+  delete c;
+}
+
+int gabp_layout_info(const gabp_ctx* c, int32_t* n, int64_t* nnz, int64_t* slots,
+                     int64_t* padded) {
+  if (!c) return fail(GABP_EINVAL, "NULL context");
+  if (n) *n = c->L.n;
+  if (nnz) *nnz = c->L.nnz;
+  if (slots) *slots = c->L.slots;
+  if (padded) *padded = c->L.epad;
+  return GABP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,498 @@
+// Solve drivers of libgabp: Algorithm 1 in the flood (or red-black) schedule, the
+// precomputed-Lt variant, FP32-message iterative refinement, the error-correction smoother
+// (Algorithm 3), residuals, the adjoint scatter and checkpoints.
+//
+// All device work is enqueued on the caller's stream. Convergence is read back every
+// `check_every` sweeps through one small pinned buffer; nothing else synchronises.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "gabp_internal.h"
+
+using namespace gabp;
+
+namespace {
+
+struct Norms {
+  double r2, rinf, b2;
+};
+
+int read_norms(gabp_ctx* c, hipStream_t s, Norms* nm) {
+  GABP_HIP(hipMemcpyAsync(c->host_red, c->red, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+  GABP_HIP(hipStreamSynchronize(s));
+  nm->r2 = std::sqrt(c->host_red[0]);
+  nm->rinf = c->host_red[1];
+  nm->b2 = std::sqrt(c->host_red[2]);
+  return GABP_OK;
+}
+
+inline const double* sweep_coef(const gabp_ctx* c, int T) { return T ? c->L.val : c->L.aT; }
+inline const double* row_coef(const gabp_ctx* c, int T) { return T ? c->L.aT : c->L.val; }
+
+int residual(gabp_ctx* c, int T, const double* b, const double* x, const float* dx,
+             const double* scale, double* r, hipStream_t s) {
+  GABP_HIP(launch_residual(&c->L, row_coef(c, T), b, x, dx, scale, r, c->partials, c->nred,
+                           c->red, s));
+  return GABP_OK;
+}
+
+int ensure_pre(gabp_ctx* c, int T, hipStream_t s) {
+  Precomp& P = c->pre[T];
+  if (P.valid) return GABP_OK;
+  const Layout& L = c->L;
+  if (!P.lamout) {
+    GABP_HIP(hipMalloc(reinterpret_cast<void**>(&P.lamout), (L.epad + 1) * sizeof(double)));
+    GABP_HIP(hipMalloc(reinterpret_cast<void**>(&P.S), L.n * sizeof(double)));
+    GABP_HIP(hipMalloc(reinterpret_cast<void**>(&P.lamout32), (L.epad + 1) * sizeof(float)));
+    GABP_HIP(hipMalloc(reinterpret_cast<void**>(&P.invS32), L.n * sizeof(float)));
+  }
+  GABP_HIP(launch_fill64(P.lamout, L.epad + 1, 0.0, s));
+  GABP_HIP(launch_fill64(c->lam[0], L.epad + 1, 0.0, s));
+  GABP_HIP(launch_fill64(c->lam[1], L.epad + 1, 0.0, s));
+  const double* coef = sweep_coef(c, T);
+  int par = 0, done = 0;
+  const double tol = c->opt.tol_lambda;
+  for (int it = 1; it <= c->opt.max_lambda_sweeps; ++it) {
+    GABP_HIP(launch_lambda_sweep(&L, coef, c->lam[par], c->lam[par ^ 1], P.lamout, c->lmax, s));
+    par ^= 1;
+    done = it;
+    if (tol > 0.0) {
+      unsigned long long h[2];
+      GABP_HIP(hipMemcpyAsync(h, c->lmax, sizeof(h), hipMemcpyDeviceToHost, s));
+      GABP_HIP(hipStreamSynchronize(s));
+      double dm, lm;
+      std::memcpy(&dm, &h[0], sizeof(double));
+      std::memcpy(&lm, &h[1], sizeof(double));
+      if (!std::isfinite(dm) || !std::isfinite(lm))
+        return fail(GABP_ENUMERIC, "non-finite precision message in the Lt phase");
+      if (dm <= tol * lm) break;
+    }
+  }
+  GABP_HIP(launch_lambda_finalize(&L, coef, c->lam[par], &P, s));
+  P.sweeps = done;
+  P.valid = true;
+  c->parity = 0;   // the joint-mode message buffers were used as scratch
+  GABP_HIP(launch_fill64(c->lam[0], L.epad + 1, 0.0, s));
+  GABP_HIP(launch_fill64(c->msg[0], L.epad + 1, 0.0, s));
+  return GABP_OK;
+}
+
+int ensure_msg32(gabp_ctx* c) {
+  if (c->msg32[0]) return GABP_OK;
+  for (int q = 0; q < 2; ++q)
+    GABP_HIP(hipMalloc(reinterpret_cast<void**>(&c->msg32[q]), (c->L.epad + 1) * sizeof(float)));
+  return GABP_OK;
+}
+
+// One FP64 sweep of the configured mode and schedule on right-hand side b.
+// x != null: the read-off of this sweep is written there.
+int sweep64(gabp_ctx* c, int T, const double* b, double* x, hipStream_t s) {
+  const bool rb = c->opt.schedule == GABP_SCHED_REDBLACK;
+  if (c->opt.mode == GABP_MODE_JOINT) {
+    SweepArgs a{&c->L, sweep_coef(c, T), b, nullptr, nullptr, nullptr, nullptr, x, -1};
+    if (!rb) {
+      a.lam_in = c->lam[c->parity];
+      a.msg_in = c->msg[c->parity];
+      a.lam_out = c->lam[c->parity ^ 1];
+      a.msg_out = c->msg[c->parity ^ 1];
+      GABP_HIP(launch_joint_sweep(a, s));
+      c->parity ^= 1;
+    } else {
+      a.lam_in = a.lam_out = c->lam[c->parity];
+      a.msg_in = a.msg_out = c->msg[c->parity];
+      for (int col = 0; col < 2; ++col) {
+        a.colour = col;
+        GABP_HIP(launch_joint_sweep(a, s));
+      }
+    }
+  } else {
+    const Precomp& P = c->pre[T];
+    MeanArgs64 a{&c->L, P.lamout, P.S, b, nullptr, nullptr, x, -1};
+    if (!rb) {
+      a.msg_in = c->msg[c->parity];
+      a.msg_out = c->msg[c->parity ^ 1];
+      GABP_HIP(launch_mean_sweep64(a, s));
+      c->parity ^= 1;
+    } else {
+      a.msg_in = a.msg_out = c->msg[c->parity];
+      for (int col = 0; col < 2; ++col) {
+        a.colour = col;
+        GABP_HIP(launch_mean_sweep64(a, s));
+      }
+    }
+  }
+  return GABP_OK;
+}
+
+int sweep32(gabp_ctx* c, int T, const float* b, float* x, hipStream_t s) {
+  const Precomp& P = c->pre[T];
+  MeanArgs32 a{&c->L, P.lamout32, P.invS32, b, nullptr, nullptr, x, -1};
+  if (c->opt.schedule != GABP_SCHED_REDBLACK) {
+    a.msg_in = c->msg32[c->parity32];
+    a.msg_out = c->msg32[c->parity32 ^ 1];
+    GABP_HIP(launch_mean_sweep32(a, s));
+    c->parity32 ^= 1;
+  } else {
+    a.msg_in = a.msg_out = c->msg32[c->parity32];
+    for (int col = 0; col < 2; ++col) {
+      a.colour = col;
+      GABP_HIP(launch_mean_sweep32(a, s));
+    }
+  }
+  return GABP_OK;
+}
+
+int reset_messages64(gabp_ctx* c, hipStream_t s) {
+  c->parity = 0;
+  GABP_HIP(launch_fill64(c->msg[0], c->L.epad + 1, 0.0, s));
+  if (c->opt.mode == GABP_MODE_JOINT) GABP_HIP(launch_fill64(c->lam[0], c->L.epad + 1, 0.0, s));
+  return GABP_OK;
+}
+
+int reset_messages32(gabp_ctx* c, hipStream_t s) {
+  c->parity32 = 0;
+  GABP_HIP(launch_fill32(c->msg32[0], c->L.epad + 1, 0.0f, s));
+  return GABP_OK;
+}
+
+void fill_info(gabp_info* info, int status, int sweeps, int lsweeps, int outer,
+               const Norms& nm) {
+  if (!info) return;
+  info->status = status;
+  info->sweeps = sweeps;
+  info->lambda_sweeps = lsweeps;
+  info->outer_iters = outer;
+  info->rel_res2 = nm.b2 > 0 ? nm.r2 / nm.b2 : nm.r2;
+  info->res_inf = nm.rinf;
+}
+
+// Plain FP64 solve (JOINT or PRECOMP, flood or red-black).
+int solve64(gabp_ctx* c, int T, const double* b, double* x, double tol, int max_sweeps,
+            gabp_info* info, hipStream_t s) {
+  int st, lsw = 0;
+  if (c->opt.mode == GABP_MODE_PRECOMP) {
+    const bool had = c->pre[T].valid;
+    if ((st = ensure_pre(c, T, s)) != GABP_OK) return st;
+    lsw = had ? 0 : c->pre[T].sweeps;
+  }
+  if ((st = reset_messages64(c, s)) != GABP_OK) return st;
+  Norms nm{0, 0, 0};
+  int done = 0;
+  while (done < max_sweeps) {
+    const int k = std::min(c->opt.check_every, max_sweeps - done);
+    for (int i = 0; i < k; ++i)
+      if ((st = sweep64(c, T, b, i == k - 1 ? x : nullptr, s)) != GABP_OK) return st;
+    done += k;
+    if ((st = residual(c, T, b, x, nullptr, nullptr, nullptr, s)) != GABP_OK) return st;
+    if ((st = read_norms(c, s, &nm)) != GABP_OK) return st;
+    if (!std::isfinite(nm.r2) || !std::isfinite(nm.rinf)) {
+      fill_info(info, GABP_ENUMERIC, done, lsw, 0, nm);
+      return fail(GABP_ENUMERIC, "non-finite residual after sweep " + std::to_string(done));
+    }
+    const double rel = nm.b2 > 0 ? nm.r2 / nm.b2 : nm.r2;
+    if (rel <= tol) {
+      fill_info(info, GABP_OK, done, lsw, 0, nm);
+      return GABP_OK;
+    }
+  }
+  fill_info(info, GABP_MAXSWEEPS, done, lsw, 0, nm);
+  return GABP_MAXSWEEPS;
+}
+
+// FP32 mean messages inside FP64 iterative refinement.
+//   x = 0, r = b; loop: stop at ||r||_2/||b||_2 <= tol; s = ||r||_inf; inner GaBP on
+//   A d = r / s in FP32 from zero messages, checked every check_every sweeps through the
+//   FP64 residual of x + s d; the inner solve ends when that residual fell by
+//   ir_inner_tol, met tol, stopped improving, or hit the caps; then x += s d, r = that
+//   residual.
+int solve_ir(gabp_ctx* c, int T, const double* b, double* x, double tol, int max_sweeps,
+             gabp_info* info, hipStream_t s) {
+  int st;
+  const bool had = c->pre[T].valid;
+  if ((st = ensure_pre(c, T, s)) != GABP_OK) return st;
+  const int lsw = had ? 0 : c->pre[T].sweeps;
+  if ((st = ensure_msg32(c)) != GABP_OK) return st;
+  const int64_t n = c->L.n;
+  GABP_HIP(launch_fill64(x, n, 0.0, s));
+  double* r = c->r;
+  double* rtry = c->r2;
+  // r = b - A 0 = b, with its norms
+  if ((st = residual(c, T, b, x, nullptr, nullptr, r, s)) != GABP_OK) return st;
+  Norms nm;
+  if ((st = read_norms(c, s, &nm)) != GABP_OK) return st;
+  if (!std::isfinite(nm.r2)) return fail(GABP_EINVAL, "non-finite right-hand side");
+  const double bn = nm.b2;
+  int total = 0, outer = 0;
+  double* scale = c->red + 4;   // device copy of s for this outer step
+  while (true) {
+    const double rel = bn > 0 ? nm.r2 / bn : nm.r2;
+    if (rel <= tol || nm.r2 == 0.0) {
+      fill_info(info, GABP_OK, total, lsw, outer, nm);
+      return GABP_OK;
+    }
+    if (total >= max_sweeps) break;
+    GABP_HIP(launch_copy64(scale, c->red + 3, 1, s));   // s = ||r||_inf
+    GABP_HIP(launch_cast_scaled(c->r32, r, scale, n, s));
+    if ((st = reset_messages32(c, s)) != GABP_OK) return st;
+    const double rn = nm.r2;
+    double best = rn;
+    Norms nt = nm;
+    int inner = 0;
+    bool improved = false;
+    while (true) {
+      const int k = std::min({c->opt.check_every, max_sweeps - total, c->opt.ir_max_inner - inner});
+      for (int i = 0; i < k; ++i)
+        if ((st = sweep32(c, T, c->r32, i == k - 1 ? c->d32 : nullptr, s)) != GABP_OK) return st;
+      inner += k;
+      total += k;
+      if ((st = residual(c, T, b, x, c->d32, scale, rtry, s)) != GABP_OK) return st;
+      if ((st = read_norms(c, s, &nt)) != GABP_OK) return st;
+      if (!std::isfinite(nt.r2)) {
+        fill_info(info, GABP_ENUMERIC, total, lsw, outer, nt);
+        return fail(GABP_ENUMERIC, "non-finite residual in iterative refinement");
+      }
+      const bool better = nt.r2 < best;
+      if (better) {
+        best = nt.r2;
+        improved = true;
+      }
+      if (nt.r2 <= c->opt.ir_inner_tol * rn || (bn > 0 ? nt.r2 / bn : nt.r2) <= tol ||
+          !better || inner >= c->opt.ir_max_inner || total >= max_sweeps)
+        break;
+    }
+    if (!improved) {   // the FP32 inner solve cannot reduce this residual any further
+      fill_info(info, GABP_MAXSWEEPS, total, lsw, outer, nm);
+      return fail(GABP_MAXSWEEPS, "iterative refinement stagnated");
+    }
+    // accept x += s d; its residual is the last one computed only if that check improved,
+    // otherwise recompute it for the accepted iterate
+    GABP_HIP(launch_axpy32(x, c->d32, scale, n, s));
+    if (nt.r2 == best) {
+      std::swap(r, rtry);
+      nm = nt;
+    } else {
+      if ((st = residual(c, T, b, x, nullptr, nullptr, r, s)) != GABP_OK) return st;
+      if ((st = read_norms(c, s, &nm)) != GABP_OK) return st;
+    }
+    ++outer;
+  }
+  fill_info(info, GABP_MAXSWEEPS, total, lsw, outer, nm);
+  return GABP_MAXSWEEPS;
+}
+
+int solve_any(gabp_ctx* c, int T, const double* b, double* x, double tol, int32_t max_sweeps,
+              gabp_info* info, hipStream_t s) {
+  if (!c || !b || !x) return fail(GABP_EINVAL, "NULL argument");
+  if (max_sweeps < 1 || !(tol >= 0.0)) return fail(GABP_EINVAL, "max_sweeps < 1 or tol < 0");
+  GABP_HIP(hipSetDevice(c->device));
+  if (c->opt.precision == GABP_F32_IR) return solve_ir(c, T, b, x, tol, max_sweeps, info, s);
+  return solve64(c, T, b, x, tol, max_sweeps, info, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+int gabp_solve(gabp_ctx* c, const double* b, double* x, double tol, int32_t max_sweeps,
+               gabp_info* info, hipStream_t s) {
+  return solve_any(c, 0, b, x, tol, max_sweeps, info, s);
+}
+
+int gabp_solve_transposed(gabp_ctx* c, const double* g, double* lam, double tol,
+                          int32_t max_sweeps, gabp_info* info, hipStream_t s) {
+  return solve_any(c, 1, g, lam, tol, max_sweeps, info, s);
+}
+
+int gabp_precompute_lambda(gabp_ctx* c, int32_t transposed, int32_t* sweeps_out,
+                           hipStream_t s) {
+  if (!c) return fail(GABP_EINVAL, "NULL context");
+  const int T = transposed ? 1 : 0;
+  c->pre[T].valid = false;
+  int st = ensure_pre(c, T, s);
+  if (st != GABP_OK) return st;
+  GABP_HIP(hipStreamSynchronize(s));
+  if (sweeps_out) *sweeps_out = c->pre[T].sweeps;
+  return GABP_OK;
+}
+
+int gabp_sweeps(gabp_ctx* c, const double* b, double* x, int32_t sweeps, int32_t reset,
+                int32_t transposed, hipStream_t s) {
+  if (!c || !b || !x) return fail(GABP_EINVAL, "NULL argument");
+  if (sweeps < 1) return fail(GABP_EINVAL, "sweeps must be >= 1");
+  const int T = transposed ? 1 : 0;
+  int st;
+  if (c->opt.precision == GABP_F32_IR) {
+    // FP32 mean-only sweeps on fp32(b) with the FP32 copy of the precomputed Lt
+    if ((st = ensure_pre(c, T, s)) != GABP_OK) return st;
+    const bool fresh = !c->msg32[0];
+    if ((st = ensure_msg32(c)) != GABP_OK) return st;
+    GABP_HIP(launch_cast_scaled(c->r32, b, nullptr, c->L.n, s));
+    if ((reset || fresh) && (st = reset_messages32(c, s)) != GABP_OK) return st;
+    for (int i = 0; i < sweeps; ++i)
+      if ((st = sweep32(c, T, c->r32, i == sweeps - 1 ? c->d32 : nullptr, s)) != GABP_OK) return st;
+    GABP_HIP(launch_fill64(x, c->L.n, 0.0, s));
+    GABP_HIP(launch_axpy32(x, c->d32, nullptr, c->L.n, s));
+    return GABP_OK;
+  }
+  if (c->opt.mode == GABP_MODE_PRECOMP && (st = ensure_pre(c, T, s)) != GABP_OK) return st;
+  if (reset && (st = reset_messages64(c, s)) != GABP_OK) return st;
+  for (int i = 0; i < sweeps; ++i)
+    if ((st = sweep64(c, T, b, i == sweeps - 1 ? x : nullptr, s)) != GABP_OK) return st;
+  return GABP_OK;
+}
+
+int gabp_smooth(gabp_ctx* c, const double* b, double* x, int32_t mu, hipStream_t s) {
+  if (!c || !b || !x) return fail(GABP_EINVAL, "NULL argument");
+  if (mu < 1) return fail(GABP_EINVAL, "mu must be >= 1");
+  int st;
+  const int64_t n = c->L.n;
+  const bool warm = c->opt.warm == GABP_WARM_ALL;
+  if ((st = residual(c, 0, b, x, nullptr, nullptr, c->r, s)) != GABP_OK) return st;
+  if (c->opt.precision == GABP_F32_IR) {
+    if ((st = ensure_pre(c, 0, s)) != GABP_OK) return st;
+    const bool fresh = !c->msg32[0];
+    if ((st = ensure_msg32(c)) != GABP_OK) return st;
+    GABP_HIP(launch_cast_scaled(c->r32, c->r, nullptr, n, s));
+    if ((!warm || fresh) && (st = reset_messages32(c, s)) != GABP_OK) return st;
+    for (int i = 0; i < mu; ++i)
+      if ((st = sweep32(c, 0, c->r32, i == mu - 1 ? c->d32 : nullptr, s)) != GABP_OK) return st;
+    GABP_HIP(launch_axpy32(x, c->d32, nullptr, n, s));
+    return GABP_OK;
+  }
+  if (c->opt.mode == GABP_MODE_PRECOMP && (st = ensure_pre(c, 0, s)) != GABP_OK) return st;
+  if (!warm && (st = reset_messages64(c, s)) != GABP_OK) return st;
+  for (int i = 0; i < mu; ++i)
+    if ((st = sweep64(c, 0, c->r, i == mu - 1 ? c->e : nullptr, s)) != GABP_OK) return st;
+  GABP_HIP(launch_axpy64(x, c->e, n, s));
+  return GABP_OK;
+}
+
+int gabp_residual(gabp_ctx* c, const double* b, const double* x, double* r,
+                  int32_t transposed, double* norms, hipStream_t s) {
+  if (!c || !b || !x) return fail(GABP_EINVAL, "NULL argument");
+  int st = residual(c, transposed ? 1 : 0, b, x, nullptr, nullptr, r, s);
+  if (st != GABP_OK) return st;
+  if (norms) {
+    Norms nm;
+    if ((st = read_norms(c, s, &nm)) != GABP_OK) return st;
+    norms[0] = nm.r2;
+    norms[1] = nm.rinf;
+    norms[2] = nm.b2;
+  }
+  return GABP_OK;
+}
+
+int gabp_adjoint_scatter(gabp_ctx* c, const double* lam, const double* x, double* G,
+                         int32_t nparam, const int32_t* jptr, const int32_t* jnnz,
+                         const double* jw, double* dtheta, hipStream_t s) {
+  if (!c || !lam || !x) return fail(GABP_EINVAL, "NULL argument");
+  if (jptr && (!jnnz || !jw || !dtheta || nparam < 0))
+    return fail(GABP_EINVAL, "incomplete parameter Jacobian");
+  if (G) GABP_HIP(launch_entry_grad(&c->L, lam, x, G, s));
+  if (jptr)
+    GABP_HIP(launch_param_reduce(nparam, jptr, jnnz, jw, lam, x, c->L.csr_row, c->L.csr_col,
+                                 dtheta, s));
+  return GABP_OK;
+}
+
+// ---- checkpoints ----------------------------------------------------------------------
+namespace {
+struct StateHeader {
+  uint64_t magic;
+  int64_t n, epad;
+  int32_t pre_valid[2], pre_sweeps[2];
+  int32_t has32, pad;
+};
+constexpr uint64_t kMagic = 0x6761627073743031ull;  // "gabpst01"
+}  // namespace
+
+int gabp_get_state(gabp_ctx* c, void* dst, size_t* bytes, hipStream_t s) {
+  if (!c || !bytes) return fail(GABP_EINVAL, "NULL argument");
+  const Layout& L = c->L;
+  const size_t E = static_cast<size_t>(L.epad + 1), N = static_cast<size_t>(L.n);
+  size_t need = sizeof(StateHeader) + 2 * E * sizeof(double);
+  for (int T = 0; T < 2; ++T)
+    if (c->pre[T].valid) need += E * (sizeof(double) + sizeof(float)) + N * (sizeof(double) + sizeof(float));
+  if (c->msg32[0]) need += E * sizeof(float);
+  if (!dst) {
+    *bytes = need;
+    return GABP_OK;
+  }
+  if (*bytes < need) return fail(GABP_EINVAL, "state buffer too small");
+  StateHeader h{kMagic, L.n, L.epad, {c->pre[0].valid, c->pre[1].valid},
+                {c->pre[0].sweeps, c->pre[1].sweeps}, c->msg32[0] != nullptr, 0};
+  char* p = static_cast<char*>(dst);
+  std::memcpy(p, &h, sizeof(h));
+  p += sizeof(h);
+  auto get = [&](const void* src, size_t nb) -> int {
+    GABP_HIP(hipMemcpyAsync(p, src, nb, hipMemcpyDeviceToHost, s));
+    p += nb;
+    return GABP_OK;
+  };
+  int st;
+  if ((st = get(c->lam[c->parity], E * sizeof(double))) || (st = get(c->msg[c->parity], E * sizeof(double))))
+    return st;
+  for (int T = 0; T < 2; ++T)
+    if (c->pre[T].valid) {
+      if ((st = get(c->pre[T].lamout, E * sizeof(double))) || (st = get(c->pre[T].S, N * sizeof(double))) ||
+          (st = get(c->pre[T].lamout32, E * sizeof(float))) || (st = get(c->pre[T].invS32, N * sizeof(float))))
+        return st;
+    }
+  if (c->msg32[0] && (st = get(c->msg32[c->parity32], E * sizeof(float)))) return st;
+  GABP_HIP(hipStreamSynchronize(s));
+  *bytes = need;
+  return GABP_OK;
+}
+
+int gabp_set_state(gabp_ctx* c, const void* src, size_t bytes, hipStream_t s) {
+  if (!c || !src || bytes < sizeof(StateHeader)) return fail(GABP_EINVAL, "bad state");
+  StateHeader h;
+  std::memcpy(&h, src, sizeof(h));
+  const Layout& L = c->L;
+  if (h.magic != kMagic || h.n != L.n || h.epad != L.epad)
+    return fail(GABP_EINVAL, "state was taken from a different layout");
+  const size_t E = static_cast<size_t>(L.epad + 1), N = static_cast<size_t>(L.n);
+  size_t need = sizeof(StateHeader) + 2 * E * sizeof(double);
+  for (int T = 0; T < 2; ++T)
+    if (h.pre_valid[T]) need += E * (sizeof(double) + sizeof(float)) + N * (sizeof(double) + sizeof(float));
+  if (h.has32) need += E * sizeof(float);
+  if (bytes < need) return fail(GABP_EINVAL, "state blob truncated");
+  const char* p = static_cast<const char*>(src) + sizeof(h);
+  auto put = [&](void* d, size_t nb) -> int {
+    GABP_HIP(hipMemcpyAsync(d, p, nb, hipMemcpyHostToDevice, s));
+    p += nb;
+    return GABP_OK;
+  };
+  int st;
+  c->parity = 0;
+  if ((st = put(c->lam[0], E * sizeof(double))) || (st = put(c->msg[0], E * sizeof(double)))) return st;
+  for (int T = 0; T < 2; ++T) {
+    if (!h.pre_valid[T]) {
+      c->pre[T].valid = false;
+      continue;
+    }
+    Precomp& P = c->pre[T];
+    if (!P.lamout) {
+      GABP_HIP(hipMalloc(reinterpret_cast<void**>(&P.lamout), E * sizeof(double)));
+      GABP_HIP(hipMalloc(reinterpret_cast<void**>(&P.S), N * sizeof(double)));
+      GABP_HIP(hipMalloc(reinterpret_cast<void**>(&P.lamout32), E * sizeof(float)));
+      GABP_HIP(hipMalloc(reinterpret_cast<void**>(&P.invS32), N * sizeof(float)));
+    }
+    if ((st = put(P.lamout, E * sizeof(double))) || (st = put(P.S, N * sizeof(double))) ||
+        (st = put(P.lamout32, E * sizeof(float))) || (st = put(P.invS32, N * sizeof(float))))
+      return st;
+    P.valid = true;
+    P.sweeps = h.pre_sweeps[T];
+  }
+  if (h.has32) {
+    if ((st = ensure_msg32(c)) != GABP_OK) return st;
+    c->parity32 = 0;
+    if ((st = put(c->msg32[0], E * sizeof(float)))) return st;
+  }
+  GABP_HIP(hipStreamSynchronize(s));
+  return GABP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,284 @@
+"""Python binding of libgabp (ctypes). Argument marshalling only.
+
+Every step of the solver runs in the HIP library; PyTorch supplies device memory (CUDA
+tensors on ROCm) and the current stream. If the library is missing the import of this
+module succeeds but every call raises: there is no CPU fallback.
+
+Entry points mirror ``include/gabp.h``; see that header for the meaning of each argument.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgabp.so")
+
+OK, MAXSWEEPS = 0, 1
+EINVAL, ENOMEM, EZERODIAG, ENUMERIC, EDEVICE, ENOTSUPP = -1, -2, -3, -4, -5, -6
+MODES = {"joint": 0, "precomp": 1}
+PRECISIONS = {"f64": 0, "f32_ir": 1}
+SCHEDULES = {"flood": 0, "redblack": 1}
+WARM = {"reset": 0, "all": 1}
+
+
+class GaBPError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"gabp status {status}: {msg}")
+        self.status = status
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("check_every", ctypes.c_int32), ("tol_lambda", ctypes.c_double),
+                ("max_lambda_sweeps", ctypes.c_int32), ("warm", ctypes.c_int32),
+                ("ir_inner_tol", ctypes.c_double), ("ir_max_inner", ctypes.c_int32),
+                ("schedule", ctypes.c_int32)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("sweeps", ctypes.c_int32),
+                ("lambda_sweeps", ctypes.c_int32), ("outer_iters", ctypes.c_int32),
+                ("rel_res2", ctypes.c_double), ("res_inf", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+_D = ctypes.c_double
+_PI32 = ctypes.POINTER(ctypes.c_int32)
+_PI64 = ctypes.POINTER(ctypes.c_int64)
+
+_SIGS = {
+    "gabp_default_options": (None, [ctypes.POINTER(Options)]),
+    "gabp_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "gabp_last_error": (ctypes.c_char_p, []),
+    "gabp_validate_csr": (ctypes.c_int, [_I32, _I64, _P, _P, _P, _P]),
+    "gabp_setup": (ctypes.c_int, [ctypes.POINTER(_P), _I32, _I64, _P, _P, _P, _P, _P,
+                                  ctypes.POINTER(Options), _P]),
+    "gabp_update_values": (ctypes.c_int, [_P, _P, _P]),
+    "gabp_destroy": (None, [_P]),
+    "gabp_solve": (ctypes.c_int, [_P, _P, _P, _D, _I32, ctypes.POINTER(Info), _P]),
+    "gabp_solve_transposed": (ctypes.c_int, [_P, _P, _P, _D, _I32, ctypes.POINTER(Info), _P]),
+    "gabp_sweeps": (ctypes.c_int, [_P, _P, _P, _I32, _I32, _I32, _P]),
+    "gabp_precompute_lambda": (ctypes.c_int, [_P, _I32, _PI32, _P]),
+    "gabp_smooth": (ctypes.c_int, [_P, _P, _P, _I32, _P]),
+    "gabp_residual": (ctypes.c_int, [_P, _P, _P, _P, _I32, _P, _P]),
+    "gabp_adjoint_scatter": (ctypes.c_int, [_P, _P, _P, _P, _I32, _P, _P, _P, _P, _P]),
+    "gabp_get_state": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_size_t), _P]),
+    "gabp_set_state": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P]),
+    "gabp_layout_info": (ctypes.c_int, [_P, _PI32, _PI64, _PI64, _PI64]),
+}
+
+_lib = None
+
+
+def load():
+    """Load libgabp.so (torch first, so that both share one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libgabp.so is not built ({LIB_PATH}); run "
+                           "`python -m paper_1904_04093_amd.build`")
+    try:
+        import torch  # noqa: F401  (loads the HIP runtime torch was built with)
+    except ImportError:
+        pass
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def declared_symbols():
+    return list(_SIGS)
+
+
+def _check(status, allow=(OK,)):
+    if status in allow:
+        return status
+    msg = load().gabp_last_error().decode() or load().gabp_strerror(status).decode()
+    raise GaBPError(status, msg)
+
+
+def _host(a, dtype):
+    arr = np.ascontiguousarray(np.asarray(a), dtype=dtype)
+    return arr, arr.ctypes.data_as(_P)
+
+
+def validate_csr(n, rowptr, col, val, rev=None) -> int:
+    """Host-side CSR check (no GPU). Returns the status code."""
+    rp, prp = _host(rowptr, np.int32)
+    c, pc = _host(col, np.int32)
+    v, pv = _host(val, np.float64)
+    if rev is not None:
+        r, pr = _host(rev, np.int32)
+    else:
+        r, pr = None, None
+    return load().gabp_validate_csr(int(n), int(rp[-1]), prp, pc, pv, pr)
+
+
+def _stream():
+    import torch
+    return _P(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t, n, dtype_name="float64"):
+    import torch
+    dt = getattr(torch, dtype_name)
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a CUDA (HIP) tensor")
+    if t.dtype != dt or not t.is_contiguous() or t.numel() != n:
+        raise ValueError(f"expected a contiguous {dtype_name} tensor with {n} elements")
+    return _P(t.data_ptr())
+
+
+@dataclass
+class SolveInfo:
+    status: int
+    sweeps: int
+    lambda_sweeps: int
+    outer_iters: int
+    rel_res2: float
+    res_inf: float
+
+
+class Solver:
+    """One GaBP context on the current device for a CSR matrix (host arrays)."""
+
+    def __init__(self, n, rowptr, col, val, rev=None, colour=None, *, mode="joint",
+                 precision="f64", check_every=16, tol_lambda=1e-14,
+                 max_lambda_sweeps=100000, warm="reset", ir_inner_tol=1e-4,
+                 ir_max_inner=1000000, schedule="flood"):
+        lib = load()
+        self._lib = lib
+        o = Options()
+        lib.gabp_default_options(ctypes.byref(o))
+        o.mode, o.precision = MODES[mode], PRECISIONS[precision]
+        o.check_every, o.tol_lambda = int(check_every), float(tol_lambda)
+        o.max_lambda_sweeps, o.warm = int(max_lambda_sweeps), WARM[warm]
+        o.ir_inner_tol, o.ir_max_inner = float(ir_inner_tol), int(ir_max_inner)
+        o.schedule = SCHEDULES[schedule]
+        self.options = o
+        rp, prp = _host(rowptr, np.int32)
+        c, pc = _host(col, np.int32)
+        v, pv = _host(val, np.float64)
+        self.n, self.nnz = int(n), int(rp[-1])
+        pr = _host(rev, np.int32) if rev is not None else (None, None)
+        pk = _host(colour, np.uint8) if colour is not None else (None, None)
+        h = _P()
+        _check(lib.gabp_setup(ctypes.byref(h), self.n, self.nnz, prp, pc, pv, pr[1], pk[1],
+                              ctypes.byref(o), _stream()))
+        self._h = h
+
+    @classmethod
+    def from_csr(cls, a, **kw):
+        return cls(a.n, a.rowptr, a.col, a.val, **kw)
+
+    # ---- lifecycle
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.gabp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _new(self, dtype="float64"):
+        import torch
+        return torch.empty(self.n, dtype=getattr(torch, dtype), device="cuda")
+
+    # ---- solves
+    def solve(self, b, tol, max_sweeps, x=None, transposed=False):
+        x = self._new() if x is None else x
+        info = Info()
+        fn = self._lib.gabp_solve_transposed if transposed else self._lib.gabp_solve
+        st = fn(self._h, _dev(b, self.n), _dev(x, self.n), float(tol), int(max_sweeps),
+                ctypes.byref(info), _stream())
+        _check(st, allow=(OK, MAXSWEEPS))
+        return x, SolveInfo(**info.as_dict())
+
+    def solve_transposed(self, g, tol, max_sweeps, lam=None):
+        return self.solve(g, tol, max_sweeps, x=lam, transposed=True)
+
+    def sweeps(self, b, sweeps, reset=True, transposed=False, x=None):
+        x = self._new() if x is None else x
+        _check(self._lib.gabp_sweeps(self._h, _dev(b, self.n), _dev(x, self.n), int(sweeps),
+                                     int(bool(reset)), int(bool(transposed)), _stream()))
+        return x
+
+    def precompute_lambda(self, transposed=False):
+        k = ctypes.c_int32(0)
+        _check(self._lib.gabp_precompute_lambda(self._h, int(bool(transposed)),
+                                                ctypes.byref(k), _stream()))
+        return k.value
+
+    def smooth(self, b, x, mu):
+        _check(self._lib.gabp_smooth(self._h, _dev(b, self.n), _dev(x, self.n), int(mu),
+                                     _stream()))
+        return x
+
+    def residual(self, b, x, transposed=False, want_r=True):
+        r = self._new() if want_r else None
+        norms = (ctypes.c_double * 3)()
+        _check(self._lib.gabp_residual(self._h, _dev(b, self.n), _dev(x, self.n),
+                                       _dev(r, self.n) if want_r else None,
+                                       int(bool(transposed)), norms, _stream()))
+        return r, tuple(norms)
+
+    def adjoint_scatter(self, lam, x, jac=None, want_G=True):
+        import torch
+        G = torch.empty(self.nnz, dtype=torch.float64, device="cuda") if want_G else None
+        dtheta = None
+        args = [None, 0, None, None, None, None]
+        if jac is not None:
+            jptr, jnnz, jw = jac
+            npar = int(jptr.numel()) - 1
+            dtheta = torch.empty(npar, dtype=torch.float64, device="cuda")
+            args = [_dev(jptr, npar + 1, "int32"), _dev(jnnz, jnnz.numel(), "int32"),
+                    _dev(jw, jw.numel()), _dev(dtheta, npar)]
+            _check(self._lib.gabp_adjoint_scatter(
+                self._h, _dev(lam, self.n), _dev(x, self.n),
+                _dev(G, self.nnz) if want_G else None, npar, *args, _stream()))
+        else:
+            _check(self._lib.gabp_adjoint_scatter(
+                self._h, _dev(lam, self.n), _dev(x, self.n), _dev(G, self.nnz), 0,
+                None, None, None, None, _stream()))
+        return G, dtheta
+
+    def update_values(self, val):
+        _check(self._lib.gabp_update_values(self._h, _dev(val, self.nnz), _stream()))
+
+    def get_state(self) -> bytes:
+        nb = ctypes.c_size_t(0)
+        _check(self._lib.gabp_get_state(self._h, None, ctypes.byref(nb), _stream()))
+        buf = ctypes.create_string_buffer(nb.value)
+        _check(self._lib.gabp_get_state(self._h, buf, ctypes.byref(nb), _stream()))
+        return buf.raw[: nb.value]
+
+    def set_state(self, blob: bytes):
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        _check(self._lib.gabp_set_state(self._h, buf, len(blob), _stream()))
+
+    def layout_info(self):
+        n, nnz, slots, pad = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(self._lib.gabp_layout_info(self._h, ctypes.byref(n), ctypes.byref(nnz),
+                                          ctypes.byref(slots), ctypes.byref(pad)))
+        return {"n": n.value, "nnz": nnz.value, "slots": slots.value, "padded_slots": pad.value}
+
+    @property
+    def handle(self):
+        return self._h

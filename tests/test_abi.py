@@ -1,0 +1,99 @@
+"""The C-ABI library loads, exports every symbol include/gabp.h declares, and its host-only
+entry points behave (no GPU needed: nothing here launches a kernel)."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from conftest import ROOT
+from paper_1904_04093_amd import gabp as B
+from paper_1904_04093_amd import workloads as W
+
+HEADERS = [os.path.join(ROOT, "include", f) for f in sorted(os.listdir(os.path.join(ROOT, "include")))
+           if f.endswith(".h")]
+
+
+def _declared():
+    names = []
+    for h in HEADERS:
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names += re.findall(r"^\s*(?:[A-Za-z_][\w\s\*]*?)\b((?:gabp|mg)_\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = B.load()
+    declared = _declared()
+    assert len(declared) >= 15
+    for name in declared:
+        assert hasattr(lib, name), f"{name} declared but not exported"
+    assert set(declared) == set(B.declared_symbols()), "binding and header disagree"
+
+
+def test_strerror_and_defaults():
+    lib = B.load()
+    assert lib.gabp_strerror(0) == b"ok"
+    assert b"diagonal" in lib.gabp_strerror(-3)
+    o = B.Options()
+    lib.gabp_default_options(o)
+    assert o.check_every == 16 and o.mode == 0 and o.tol_lambda == 1e-14
+
+
+def _rev(a):
+    d = {}
+    rows = a.row_of_nnz()
+    for e, (i, j) in enumerate(zip(rows, a.col)):
+        d[(int(i), int(j))] = e
+    return np.array([d.get((int(j), int(i)), -1) for i, j in zip(rows, a.col)], dtype=np.int32)
+
+
+def test_validate_csr_accepts_good_input():
+    a, _ = W.small_upwind(8)
+    assert B.validate_csr(a.n, a.rowptr, a.col, a.val) == B.OK
+    assert B.validate_csr(a.n, a.rowptr, a.col, a.val, _rev(a)) == B.OK
+    # structurally nonsymmetric matrix with its rev index (-1 where A_ji is absent)
+    r = W.rng(200, 0)
+    b = W.random_walk_summable(50, 0.1, r)
+    assert B.validate_csr(b.n, b.rowptr, b.col, b.val, _rev(b)) == B.OK
+
+
+def test_validate_csr_rejects_bad_input():
+    a, _ = W.small_upwind(6)
+    val = a.val.copy()
+    diag = np.nonzero(a.row_of_nnz() == a.col)[0]
+    val[diag[3]] = 0.0
+    assert B.validate_csr(a.n, a.rowptr, a.col, val) == B.EZERODIAG
+    # missing diagonal
+    A = W.csr_to_dense(a)
+    A[5, 5] = 0.0
+    m = W.csr_from_dense(A)
+    assert B.validate_csr(m.n, m.rowptr, m.col, m.val) == B.EZERODIAG
+    # unsorted columns
+    col = a.col.copy()
+    col[[0, 1]] = col[[1, 0]]
+    assert B.validate_csr(a.n, a.rowptr, col, a.val) == B.EINVAL
+    # out of range column
+    col = a.col.copy()
+    col[3] = a.n
+    assert B.validate_csr(a.n, a.rowptr, col, a.val) == B.EINVAL
+    # inconsistent reverse index
+    rv = _rev(a)
+    off = np.nonzero(rv >= 0)[0]
+    rv[off[5]] = rv[off[6]]
+    assert B.validate_csr(a.n, a.rowptr, a.col, a.val, rv) == B.EINVAL
+    # non-finite value
+    val = a.val.copy()
+    val[2] = np.nan
+    assert B.validate_csr(a.n, a.rowptr, a.col, val) == B.EINVAL
+    # bad rowptr
+    rp = a.rowptr.copy()
+    rp[-1] += 1
+    assert B.validate_csr(a.n, rp, np.append(a.col, 0), np.append(a.val, 1.0)) == B.EINVAL
+
+
+def test_binding_refuses_host_tensors():
+    torch = pytest.importorskip("torch")
+    with pytest.raises(TypeError):
+        B._dev(torch.zeros(4, dtype=torch.float64), 4)

@@ -1,0 +1,365 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+FP64 sweeps must match the oracle to 1e-12 relative (max-norm) after the same number of
+sweeps; converged solves must reach the dense solution. Inputs are seeded and synthetic
+(upwind convection-diffusion grids, random walk-summable and tree matrices), sized so the
+oracle finishes in seconds while spanning several 64-row slices and a ragged tail.
+"""
+import numpy as np
+import pytest
+
+from conftest import golden
+from oracle import adjoint as AD
+from oracle import gabp as G
+from paper_1904_04093_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1904_04093_amd import gabp
+    gabp.load()
+    return gabp
+
+
+def _cuda(a):
+    return torch.as_tensor(np.asarray(a, dtype=np.float64)).cuda()
+
+
+def _rel_inf(x, y):
+    x = np.asarray(x)
+    y = np.asarray(y)
+    return float(np.abs(x - y).max() / max(np.abs(y).max(), 1e-300))
+
+
+def _cases():
+    out = {}
+    a, b = W.small_upwind(32)
+    out["upwind32"] = (a, b, None)
+    r = W.rng(300, 0)
+    a = W.random_walk_summable(200, 0.03, r)               # structurally nonsymmetric, ragged
+    out["walk200"] = (a, r.uniform(-1, 1, a.n), None)
+    a = W.random_tridiagonal(130, W.rng(300, 1))
+    out["tridiag130"] = (a, W.rng(300, 2).uniform(-1, 1, a.n), None)
+    a, _ = W.random_tree(150, W.rng(300, 3), one_way=0.3)
+    out["tree150"] = (a, W.rng(300, 4).uniform(-1, 1, a.n), None)
+    a, b = W.precision_at_scale(45)
+    out["field45"] = (a, b, None)
+    a = W.csr_from_dense(np.array([[2.5]]))
+    out["n1"] = (a, np.array([0.7]), None)
+    a, b = W.small_upwind(9)                                # n = 81: one slice + tail
+    out["upwind9"] = (a, b, None)
+    return out
+
+
+CASES = _cases()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_joint_sweeps_match_oracle(B, name):
+    a, b, _ = CASES[name]
+    s = B.Solver.from_csr(a)
+    g = G.Graph.from_csr(a)
+    bt = _cuda(b)
+    for sweeps in (1, 2, 3, 10, 100):
+        x = s.sweeps(bt, sweeps).cpu().numpy()
+        xo, _, _ = G.run(g, b, sweeps)
+        assert _rel_inf(x, xo) <= TOL, (name, sweeps)
+
+
+@pytest.mark.parametrize("name", ["upwind32", "walk200", "field45", "tree150"])
+def test_precomp_sweeps_match_oracle(B, name):
+    a, b, _ = CASES[name]
+    L = 40
+    s = B.Solver.from_csr(a, mode="precomp", tol_lambda=0.0, max_lambda_sweeps=L)
+    assert s.precompute_lambda() == L
+    g = G.Graph.from_csr(a)
+    Lt, S, k = G.lambda_phase(g, 0.0, L)
+    bt = _cuda(b)
+    for sweeps in (1, 2, 5, 50):
+        x = s.sweeps(bt, sweeps).cpu().numpy()
+        m = np.zeros(g.E)
+        for _ in range(sweeps):
+            xo, m = G.msweep(g, b, Lt, S, m)
+        assert _rel_inf(x, xo) <= TOL, (name, sweeps)
+
+
+@pytest.mark.parametrize("mode", ["joint", "precomp"])
+def test_redblack_sweeps_match_oracle(B, mode):
+    n = 24
+    a, b = W.small_upwind(n)
+    colour = G.grid_colour(n)
+    kw = dict(mode=mode, schedule="redblack")
+    if mode == "precomp":
+        kw.update(tol_lambda=0.0, max_lambda_sweeps=30)
+    s = B.Solver.from_csr(a, colour=colour, **kw)
+    g = G.Graph.from_csr(a)
+    lam = None
+    if mode == "precomp":
+        Lt, S, _ = G.lambda_phase(g, 0.0, 30)
+        lam = (Lt, S)
+    bt = _cuda(b)
+    for sweeps in (1, 2, 7, 40):
+        x = s.sweeps(bt, sweeps).cpu().numpy()
+        Lt0 = np.zeros(g.E) if lam is None else lam[0]
+        m = np.zeros(g.E)
+        for _ in range(sweeps):
+            xo, Lt0, m = G.sweep_coloured(g, b, Lt0, m, colour, lambda_fixed=lam)
+        assert _rel_inf(x, xo) <= TOL, (mode, sweeps)
+
+
+def test_redblack_rejects_improper_colouring(B):
+    a, _ = W.small_upwind(8)
+    with pytest.raises(B.GaBPError) as e:
+        B.Solver.from_csr(a, colour=np.zeros(64, np.uint8), schedule="redblack")
+    assert e.value.status == B.EINVAL
+
+
+@pytest.mark.parametrize("mode", ["joint", "precomp"])
+def test_solve_reaches_dense_solution(B, mode):
+    a, b, _ = CASES["upwind32"]
+    s = B.Solver.from_csr(a, mode=mode, check_every=8)
+    x, info = s.solve(_cuda(b), 1e-13, 20000)
+    assert info.status == B.OK and info.rel_res2 <= 1e-13
+    xs = np.linalg.solve(W.csr_to_dense(a), b)
+    assert _rel_inf(x.cpu().numpy(), xs) <= 1e-10
+    # the oracle needs the same number of sweeps up to one check interval
+    if mode == "joint":
+        _, oinfo, _, _ = G.solve(G.Graph.from_csr(a), b, 1e-13, 20000, check_every=8)
+        assert abs(oinfo.sweeps - info.sweeps) <= 8
+
+
+def test_ir_fp32_messages_reach_fp64_accuracy(B):
+    for name in ("upwind32", "field45"):
+        a, b, _ = CASES[name]
+        s = B.Solver.from_csr(a, precision="f32_ir", check_every=16, tol_lambda=1e-12)
+        x, info = s.solve(_cuda(b), 1e-12, 200000)
+        assert info.status == B.OK, (name, info)
+        assert info.rel_res2 <= 1e-12 and info.outer_iters >= 2
+        xs = np.linalg.solve(W.csr_to_dense(a), b)
+        assert _rel_inf(x.cpu().numpy(), xs) <= 1e-8, name
+
+
+@pytest.mark.parametrize("name", ["upwind32", "walk200", "tree150"])
+def test_transposed_sweeps_match_oracle_on_AT(B, name):
+    a, b, _ = CASES[name]
+    s = B.Solver.from_csr(a)
+    gt = G.Graph.from_csr(a).transposed()
+    bt = _cuda(b)
+    for sweeps in (1, 3, 30):
+        x = s.sweeps(bt, sweeps, transposed=True).cpu().numpy()
+        xo, _, _ = G.run(gt, b, sweeps)
+        assert _rel_inf(x, xo) <= TOL
+
+
+def test_transposed_solve(B):
+    a, b, _ = CASES["field45"]
+    s = B.Solver.from_csr(a, mode="precomp")
+    lam, info = s.solve_transposed(_cuda(b), 1e-13, 50000)
+    assert info.status == B.OK
+    ls = np.linalg.solve(W.csr_to_dense(a).T, b)
+    assert _rel_inf(lam.cpu().numpy(), ls) <= 1e-10
+
+
+@pytest.mark.parametrize("mode,warm", [("joint", "reset"), ("precomp", "reset"),
+                                       ("joint", "all"), ("precomp", "all")])
+def test_smoother_matches_oracle(B, mode, warm):
+    a, b = W.small_upwind(20)
+    g = G.Graph.from_csr(a)
+    kw = dict(mode=mode, warm=warm)
+    lam = None
+    if mode == "precomp":
+        kw.update(tol_lambda=0.0, max_lambda_sweeps=25)
+        Lt, S, _ = G.lambda_phase(g, 0.0, 25)
+        lam = (Lt, S)
+    s = B.Solver.from_csr(a, **kw)
+    x0 = W.rng(301, 0).uniform(-1, 1, a.n)
+    xg = _cuda(x0)
+    bt = _cuda(b)
+    xo = x0.copy()
+    m_state = None
+    Lt_state = None
+    for mu in (1, 2, 3, 2):
+        s.smooth(bt, xg, mu)
+        if mode == "joint" and warm == "all":
+            # joint smoother carrying both message kinds between calls
+            r = g.residual(b, xo)
+            Lt_c = np.zeros(g.E) if Lt_state is None else Lt_state
+            m_c = np.zeros(g.E) if m_state is None else m_state
+            for _ in range(mu):
+                e, Lt_c, m_c, _, _ = G.sweep(g, r, Lt_c, m_c)
+            xo = xo + e
+            Lt_state, m_state = Lt_c, m_c
+        else:
+            xo, m_new = G.smooth(g, b, xo, mu, lam=lam,
+                                 m_state=m_state if warm == "all" else None)
+            if warm == "all":
+                m_state = m_new
+        assert _rel_inf(xg.cpu().numpy(), xo) <= TOL, (mode, warm, mu)
+
+
+def test_residual_and_norms(B):
+    a, b, _ = CASES["walk200"]
+    s = B.Solver.from_csr(a)
+    x = W.rng(302, 0).uniform(-1, 1, a.n)
+    r, (n2, ninf, bn) = s.residual(_cuda(b), _cuda(x))
+    ro = G.Graph.from_csr(a).residual(b, x)
+    assert _rel_inf(r.cpu().numpy(), ro) <= 1e-14
+    assert n2 == pytest.approx(np.linalg.norm(ro), rel=1e-13)
+    assert ninf == np.abs(ro).max()
+    assert bn == pytest.approx(np.linalg.norm(b), rel=1e-13)
+    rt, _ = s.residual(_cuda(b), _cuda(x), transposed=True)
+    assert _rel_inf(rt.cpu().numpy(), b - W.csr_to_dense(a).T @ x) <= 1e-14
+
+
+def test_adjoint_scatter_matches_oracle(B):
+    n = 16
+    theta = W.theta_problem(n, 0)
+    a, jptr, jnnz, jw = W.theta_jacobian(n, theta)
+    s = B.Solver.from_csr(a)
+    r = W.rng(303, 0)
+    lam = r.uniform(-1, 1, a.n)
+    x = r.uniform(-1, 1, a.n)
+    Gd, dth = s.adjoint_scatter(_cuda(lam), _cuda(x),
+                                jac=(torch.as_tensor(jptr).cuda(), torch.as_tensor(jnnz).cuda(),
+                                     _cuda(jw)))
+    Go = AD.nnz_gradient(a.row_of_nnz(), a.col, lam, x)
+    assert np.array_equal(Gd.cpu().numpy(), Go)
+    do = AD.reduce_to_params(Go, jptr, jnnz, jw)
+    assert _rel_inf(dth.cpu().numpy(), do) <= 1e-14
+
+
+def test_checkpoint_resume_is_bitwise(B):
+    a, b, _ = CASES["walk200"]
+    s = B.Solver.from_csr(a)
+    bt = _cuda(b)
+    s.sweeps(bt, 7)
+    blob = s.get_state()
+    x1 = s.sweeps(bt, 5, reset=False).cpu().numpy()
+    s.sweeps(bt, 3)                 # disturb the state
+    s.set_state(blob)
+    x2 = s.sweeps(bt, 5, reset=False).cpu().numpy()
+    assert np.array_equal(x1, x2)
+    x12 = s.sweeps(bt, 12).cpu().numpy()
+    assert np.array_equal(x12, x1)   # 7 + 5 sweeps from zero, same bits
+
+
+def test_repeat_runs_are_bitwise_identical(B):
+    a, b, _ = CASES["field45"]
+    s = B.Solver.from_csr(a, check_every=4)
+    bt = _cuda(b)
+    x1, i1 = s.solve(bt, 1e-8, 400)
+    x2, i2 = s.solve(bt, 1e-8, 400)
+    assert np.array_equal(x1.cpu().numpy(), x2.cpu().numpy())
+    assert i1.rel_res2 == i2.rel_res2
+
+
+def test_update_values_matches_fresh_setup(B):
+    n = 20
+    t0, t1 = W.theta_problem(n, 0), W.theta_problem(n, 1)
+    a0 = W.theta_operator(n, t0)
+    a1 = W.theta_operator(n, t1)
+    assert np.array_equal(a0.col, a1.col)
+    b = W.rng(304, 0).uniform(-1, 1, a0.n)
+    s = B.Solver.from_csr(a0)
+    s.update_values(_cuda(a1.val))
+    fresh = B.Solver.from_csr(a1)
+    bt = _cuda(b)
+    assert np.array_equal(s.sweeps(bt, 9).cpu().numpy(), fresh.sweeps(bt, 9).cpu().numpy())
+    bad = a1.val.copy()
+    bad[a1.row_of_nnz() == a1.col] = 0.0
+    with pytest.raises(B.GaBPError) as e:
+        s.update_values(_cuda(bad))
+    assert e.value.status == B.EZERODIAG
+
+
+def test_failure_modes(B):
+    # zero cavity precision: [[1, 1], [1, 1]] has Sigma_j - Lt_ij A_ij = 1 - 1 = 0 at sweep 2
+    a = W.csr_from_dense(np.array([[1.0, 1.0], [1.0, 1.0]]))
+    s = B.Solver.from_csr(a, check_every=1)
+    with pytest.raises(B.GaBPError) as e:
+        s.solve(_cuda([1.0, 2.0]), 1e-12, 10)
+    assert e.value.status == B.ENUMERIC
+    # the 7x7 example of Sec. 3.4 does not converge
+    A = np.loadtxt(golden("paper_7x7.txt"), comments="#")
+    s = B.Solver.from_csr(W.csr_from_dense(A), check_every=50)
+    try:
+        _, info = s.solve(_cuda(np.ones(7)), 1e-10, 2000)
+        assert info.status == B.MAXSWEEPS
+    except B.GaBPError as err:
+        assert err.status == B.ENUMERIC
+    # max_sweeps reached
+    a, b, _ = CASES["upwind32"]
+    s = B.Solver.from_csr(a, check_every=4)
+    _, info = s.solve(_cuda(b), 1e-14, 8)
+    assert info.status == B.MAXSWEEPS and info.sweeps == 8
+    with pytest.raises(B.GaBPError):
+        s.solve(_cuda(b), 1e-14, 0)
+
+
+def _ball(a, centre, radius):
+    seen = {int(centre)}
+    frontier = [int(centre)]
+    for _ in range(radius):
+        nxt = []
+        for u in frontier:
+            for c in a.col[a.rowptr[u]:a.rowptr[u + 1]]:
+                if int(c) not in seen:
+                    seen.add(int(c))
+                    nxt.append(int(c))
+        frontier = nxt
+    return np.array(sorted(seen))
+
+
+def test_full_size_sampled_parity(B):
+    """2048 x 2048 variable-coefficient operator (4.19M unknowns) in the launch
+    configuration the benchmark times: sampled read-offs after s sweeps equal the oracle run
+    on the radius-s ball around each sample (x_j after s sweeps depends on nothing else)."""
+    a, b = W.precision_at_scale(2048)
+    s = B.Solver.from_csr(a)
+    bt = _cuda(b)
+    samples = W.rng(305, 0).choice(a.n, 12, replace=False)
+    samples[0], samples[1] = 0, a.n - 1                   # corners
+    for sweeps in (1, 2, 5):
+        x = s.sweeps(bt, sweeps).cpu().numpy()
+        for j in samples:
+            nodes = _ball(a, j, sweeps)
+            sub = np.searchsorted(nodes, j)
+            rows = []
+            for u in nodes:
+                lo, hi = a.rowptr[u], a.rowptr[u + 1]
+                keep = np.isin(a.col[lo:hi], nodes)
+                rows.append((np.searchsorted(nodes, a.col[lo:hi][keep]), a.val[lo:hi][keep]))
+            rp = np.zeros(len(nodes) + 1, dtype=np.int32)
+            rp[1:] = np.cumsum([len(c) for c, _ in rows])
+            sub_a = W.CSR(len(nodes), rp, np.concatenate([c for c, _ in rows]).astype(np.int32),
+                          np.concatenate([v for _, v in rows]))
+            xo, _, _ = G.run(G.Graph.from_csr(sub_a), b[nodes], sweeps)
+            assert abs(x[j] - xo[sub]) <= TOL * max(abs(xo[sub]), 1e-300) + 1e-300, (j, sweeps)
+    # property at full size: the residual of the 5-sweep read-off is finite and below that of x = 0
+    r, (n2, _, bn) = s.residual(bt, torch.as_tensor(x).cuda())
+    assert np.isfinite(n2) and n2 < bn
+
+
+def test_f32_mean_sweeps_track_fp64_oracle(B):
+    """FP32 mean-only sweeps (the refinement inner kernel) against the FP64 oracle: equal up
+    to FP32 rounding, which grows at most linearly with the sweep count."""
+    for name in ("upwind32", "field45", "walk200"):
+        a, b, _ = CASES[name]
+        s = B.Solver.from_csr(a, mode="precomp", precision="f32_ir", tol_lambda=0.0,
+                              max_lambda_sweeps=40)
+        g = G.Graph.from_csr(a)
+        Lt, S, _ = G.lambda_phase(g, 0.0, 40)
+        bt = _cuda(b)
+        for sweeps in (1, 5, 50):
+            x = s.sweeps(bt, sweeps).cpu().numpy()
+            m = np.zeros(g.E)
+            for _ in range(sweeps):
+                xo, m = G.msweep(g, b, Lt, S, m)
+            assert _rel_inf(x, xo) <= 2e-6 * (1 + sweeps), (name, sweeps)

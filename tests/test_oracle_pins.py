@@ -326,3 +326,42 @@ def test_ir_fp32_messages_reaches_fp64_accuracy():
                          inner_sweeps=400)
     assert info.status == G.OK
     assert _relerr(x, np.linalg.solve(_dense(a), b)) < 1e-9
+
+
+# --------------------------------------------------------------------------------------
+# Red-black schedule (the paper's red-black GaBP)
+# --------------------------------------------------------------------------------------
+
+def test_redblack_first_sweep_closed_form():
+    """Sweep 1 from zero messages: red nodes read D^-1 b; black nodes see one elimination
+    of their red neighbours: x_j = (b_j - sum_k A_jk b_k / A_kk) / (A_jj - sum_k A_jk A_kj / A_kk).
+    """
+    a, b = W.small_upwind(8)
+    g = _graph(a)
+    colour = G.grid_colour(8)
+    x, _, _ = G.sweep_coloured(g, b, np.zeros(g.E), np.zeros(g.E), colour)
+    A = _dense(a)
+    for j in range(a.n):
+        if colour[j] == 0:
+            assert x[j] == pytest.approx(b[j] / A[j, j], rel=1e-15)
+        else:
+            ks = [k for k in range(a.n) if k != j and A[j, k] != 0]
+            num = b[j] - sum(A[j, k] * b[k] / A[k, k] for k in ks)
+            den = A[j, j] - sum(A[j, k] * A[k, j] / A[k, k] for k in ks)
+            assert x[j] == pytest.approx(num / den, rel=1e-13)
+
+
+@pytest.mark.parametrize("precomp", [False, True])
+def test_redblack_fixed_point_is_dense_solution(precomp):
+    a, b = W.small_upwind(16)
+    g = _graph(a)
+    colour = G.grid_colour(16)
+    lam = None
+    if precomp:
+        Lt, S, _ = G.lambda_phase(g, 1e-15, 500)
+        lam = (Lt, S)
+    Lt = np.zeros(g.E) if lam is None else lam[0]
+    m = np.zeros(g.E)
+    for _ in range(400):
+        x, Lt, m = G.sweep_coloured(g, b, Lt, m, colour, lambda_fixed=lam)
+    assert _relerr(x, np.linalg.solve(_dense(a), b)) < 1e-12
