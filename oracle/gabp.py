@@ -264,11 +264,15 @@ def smooth(g: Graph, b, x, mu, lam=None, m_state=None):
 # FP32 messages inside FP64 iterative refinement
 # ----------------------------------------------------------------------------------------
 
-def ir_solve(g: Graph, b, tol, lam32, inner_sweeps, max_outer=50):
+def ir_solve(g: Graph, b, tol, lam32, check_every=16, inner_tol=1e-4, max_sweeps=10**6,
+             patience=8):
     """Iterative refinement with FP32 mean-only GaBP as the inner solver.
 
-    Outer loop in FP64: r = b - A x, stop at ||r||_2/||b||_2 <= tol; inner: ``inner_sweeps``
-    mean-only sweeps on A d = r / ||r||_inf in FP32 with FP32 Lt*, 1/S*; x += ||r||_inf d.
+    Outer loop in FP64: r = b - A x; stop at ||r||_2/||b||_2 <= tol. Inner: mean-only sweeps
+    on A d = r / s (s = ||r||_inf) in FP32 with FP32 Lt*, 1/S*, from zero messages; every
+    ``check_every`` sweeps the FP64 residual of x + s d is formed and the best trial kept;
+    the inner solve ends when the best trial reached inner_tol * ||r|| or tol * ||b||, or
+    after ``patience`` checks without a new best once one was found. Then x += s d_best.
     ``lam32 = (Lt*, 1/S*)`` as float32 arrays. Parity unpinned as a bitwise reference (the
     FP32 rounding order is free); only its converged result is compared.
     """
@@ -277,25 +281,40 @@ def ir_solve(g: Graph, b, tol, lam32, inner_sweeps, max_outer=50):
     x = np.zeros(g.n)
     bnorm = float(np.linalg.norm(b)) or 1.0
     info = Info(status=MAXSWEEPS)
-    for k in range(max_outer):
-        r = g.residual(b, x)
-        rel = float(np.linalg.norm(r)) / bnorm
-        info.rel_res2, info.res_inf, info.outer_iters = rel, float(np.abs(r).max()), k
-        if rel <= tol:
+    r = g.residual(b, x)
+    while True:
+        rn = float(np.linalg.norm(r))
+        info.rel_res2, info.res_inf = rn / bnorm, float(np.abs(r).max())
+        if info.rel_res2 <= tol:
             info.status = OK
-            break
+            return x, info
+        if info.sweeps >= max_sweeps:
+            return x, info
         s = float(np.abs(r).max())
         r32 = (r / s).astype(f32)
         m = np.zeros(g.E, dtype=f32)
-        src, dst = g.src, g.dst
-        for _ in range(inner_sweeps):
-            M = r32 + np.bincount(dst, weights=m, minlength=g.n).astype(f32)
-            d = M * invS32
-            back = np.where(g.rev >= 0, m[np.maximum(g.rev, 0)], f32(0))
-            m = (Lt32 * (M[src] - back)).astype(f32)
-            info.sweeps += 1
-        x = x + s * d.astype(np.float64)
-    return x, info
+        best, d_best, r_best, since = rn, None, None, 0
+        while True:
+            for _ in range(check_every):
+                M = r32 + np.bincount(g.dst, weights=m, minlength=g.n).astype(f32)
+                d = M * invS32
+                back = np.where(g.rev >= 0, m[np.maximum(g.rev, 0)], f32(0))
+                m = (Lt32 * (M[g.src] - back)).astype(f32)
+                info.sweeps += 1
+            rt = b - g.matvec(x + s * d.astype(np.float64))
+            nt = float(np.linalg.norm(rt))
+            if nt < best:
+                best, d_best, r_best, since = nt, d.copy(), rt, 0
+            else:
+                since += 1
+            if (best <= inner_tol * rn or best / bnorm <= tol or
+                    (d_best is not None and since >= patience) or info.sweeps >= max_sweeps):
+                break
+        if d_best is None:
+            return x, info
+        x = x + s * d_best.astype(np.float64)
+        r = r_best
+        info.outer_iters += 1
 
 
 # ----------------------------------------------------------------------------------------

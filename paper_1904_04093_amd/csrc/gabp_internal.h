@@ -81,6 +81,7 @@ struct gabp_ctx {
   double* e = nullptr;        // [n]
   float* r32 = nullptr;       // [n]
   float* d32 = nullptr;       // [n]
+  float* dbest32 = nullptr;   // [n] best inner correction of the current refinement step
   // reductions
   int32_t nred = 0;           // blocks of the residual kernel
   double* partials = nullptr; // [3 * nred]

@@ -348,7 +348,7 @@ void gabp_destroy(gabp_ctx* c) {
     F(c->lam[q]); F(c->msg[q]); F(c->msg32[q]);
     F(c->pre[q].lamout); F(c->pre[q].S); F(c->pre[q].lamout32); F(c->pre[q].invS32);
   }
-  F(c->r); F(c->r2); F(c->e); F(c->r32); F(c->d32); F(c->partials); F(c->red); F(c->lmax);
+  F(c->r); F(c->r2); F(c->e); F(c->r32); F(c->d32); F(c->dbest32); F(c->partials); F(c->red); F(c->lmax);
   if (c->host_red) (void)hipHostFree(c->host_red);
   delete c;
 }

@@ -79,10 +79,15 @@ int ensure_pre(gabp_ctx* c, int T, hipStream_t s) {
   return GABP_OK;
 }
 
-int ensure_msg32(gabp_ctx* c) {
+// Both FP32 message buffers start at zero: padding slots (short rows inside a slice) are
+// read by every sweep but never written, so they must hold zeros in both buffers.
+int ensure_msg32(gabp_ctx* c, hipStream_t s) {
   if (c->msg32[0]) return GABP_OK;
-  for (int q = 0; q < 2; ++q)
+  for (int q = 0; q < 2; ++q) {
     GABP_HIP(hipMalloc(reinterpret_cast<void**>(&c->msg32[q]), (c->L.epad + 1) * sizeof(float)));
+    GABP_HIP(launch_fill32(c->msg32[q], c->L.epad + 1, 0.0f, s));
+  }
+  GABP_HIP(hipMalloc(reinterpret_cast<void**>(&c->dbest32), c->L.n * sizeof(float)));
   return GABP_OK;
 }
 
@@ -213,13 +218,14 @@ int solve_ir(gabp_ctx* c, int T, const double* b, double* x, double tol, int max
   const bool had = c->pre[T].valid;
   if ((st = ensure_pre(c, T, s)) != GABP_OK) return st;
   const int lsw = had ? 0 : c->pre[T].sweeps;
-  if ((st = ensure_msg32(c)) != GABP_OK) return st;
+  if ((st = ensure_msg32(c, s)) != GABP_OK) return st;
   const int64_t n = c->L.n;
   GABP_HIP(launch_fill64(x, n, 0.0, s));
-  double* r = c->r;
-  double* rtry = c->r2;
+  // three FP64 residual buffers: the accepted residual, the best trial, the next trial
+  double* buf[3] = {c->r, c->r2, c->e};
+  int ir = 0;
   // r = b - A 0 = b, with its norms
-  if ((st = residual(c, T, b, x, nullptr, nullptr, r, s)) != GABP_OK) return st;
+  if ((st = residual(c, T, b, x, nullptr, nullptr, buf[ir], s)) != GABP_OK) return st;
   Norms nm;
   if ((st = read_norms(c, s, &nm)) != GABP_OK) return st;
   if (!std::isfinite(nm.r2)) return fail(GABP_EINVAL, "non-finite right-hand side");
@@ -234,48 +240,53 @@ int solve_ir(gabp_ctx* c, int T, const double* b, double* x, double tol, int max
     }
     if (total >= max_sweeps) break;
     GABP_HIP(launch_copy64(scale, c->red + 3, 1, s));   // s = ||r||_inf
-    GABP_HIP(launch_cast_scaled(c->r32, r, scale, n, s));
+    GABP_HIP(launch_cast_scaled(c->r32, buf[ir], scale, n, s));
     if ((st = reset_messages32(c, s)) != GABP_OK) return st;
     const double rn = nm.r2;
     double best = rn;
-    Norms nt = nm;
-    int inner = 0;
-    bool improved = false;
+    Norms nbest = nm;
+    int ibest = -1, itry = (ir + 1) % 3;
+    int inner = 0, since_best = 0;
     while (true) {
       const int k = std::min({c->opt.check_every, max_sweeps - total, c->opt.ir_max_inner - inner});
       for (int i = 0; i < k; ++i)
         if ((st = sweep32(c, T, c->r32, i == k - 1 ? c->d32 : nullptr, s)) != GABP_OK) return st;
       inner += k;
       total += k;
-      if ((st = residual(c, T, b, x, c->d32, scale, rtry, s)) != GABP_OK) return st;
+      Norms nt;
+      if ((st = residual(c, T, b, x, c->d32, scale, buf[itry], s)) != GABP_OK) return st;
       if ((st = read_norms(c, s, &nt)) != GABP_OK) return st;
       if (!std::isfinite(nt.r2)) {
         fill_info(info, GABP_ENUMERIC, total, lsw, outer, nt);
         return fail(GABP_ENUMERIC, "non-finite residual in iterative refinement");
       }
-      const bool better = nt.r2 < best;
-      if (better) {
+      // GaBP residuals are not monotone (a restart from zero messages first amplifies
+      // rough residual components for a while): keep the best trial, and declare the FP32
+      // floor only once the residual has improved and then shown no new best for
+      // kPatience checks
+      constexpr int kPatience = 8;
+      if (nt.r2 < best) {
         best = nt.r2;
-        improved = true;
+        nbest = nt;
+        ibest = itry;
+        itry = 3 - ir - ibest;
+        GABP_HIP(hipMemcpyAsync(c->dbest32, c->d32, n * sizeof(float), hipMemcpyDeviceToDevice, s));
+        since_best = 0;
+      } else {
+        ++since_best;
       }
-      if (nt.r2 <= c->opt.ir_inner_tol * rn || (bn > 0 ? nt.r2 / bn : nt.r2) <= tol ||
-          !better || inner >= c->opt.ir_max_inner || total >= max_sweeps)
+      if (best <= c->opt.ir_inner_tol * rn || (bn > 0 ? best / bn : best) <= tol ||
+          (ibest >= 0 && since_best >= kPatience) || inner >= c->opt.ir_max_inner ||
+          total >= max_sweeps)
         break;
     }
-    if (!improved) {   // the FP32 inner solve cannot reduce this residual any further
+    if (ibest < 0) {   // the FP32 inner solve could not reduce this residual at all
       fill_info(info, GABP_MAXSWEEPS, total, lsw, outer, nm);
       return fail(GABP_MAXSWEEPS, "iterative refinement stagnated");
     }
-    // accept x += s d; its residual is the last one computed only if that check improved,
-    // otherwise recompute it for the accepted iterate
-    GABP_HIP(launch_axpy32(x, c->d32, scale, n, s));
-    if (nt.r2 == best) {
-      std::swap(r, rtry);
-      nm = nt;
-    } else {
-      if ((st = residual(c, T, b, x, nullptr, nullptr, r, s)) != GABP_OK) return st;
-      if ((st = read_norms(c, s, &nm)) != GABP_OK) return st;
-    }
+    GABP_HIP(launch_axpy32(x, c->dbest32, scale, n, s));   // x += s d_best
+    ir = ibest;
+    nm = nbest;
     ++outer;
   }
   fill_info(info, GABP_MAXSWEEPS, total, lsw, outer, nm);
@@ -327,7 +338,7 @@ int gabp_sweeps(gabp_ctx* c, const double* b, double* x, int32_t sweeps, int32_t
     // FP32 mean-only sweeps on fp32(b) with the FP32 copy of the precomputed Lt
     if ((st = ensure_pre(c, T, s)) != GABP_OK) return st;
     const bool fresh = !c->msg32[0];
-    if ((st = ensure_msg32(c)) != GABP_OK) return st;
+    if ((st = ensure_msg32(c, s)) != GABP_OK) return st;
     GABP_HIP(launch_cast_scaled(c->r32, b, nullptr, c->L.n, s));
     if ((reset || fresh) && (st = reset_messages32(c, s)) != GABP_OK) return st;
     for (int i = 0; i < sweeps; ++i)
@@ -353,7 +364,7 @@ int gabp_smooth(gabp_ctx* c, const double* b, double* x, int32_t mu, hipStream_t
   if (c->opt.precision == GABP_F32_IR) {
     if ((st = ensure_pre(c, 0, s)) != GABP_OK) return st;
     const bool fresh = !c->msg32[0];
-    if ((st = ensure_msg32(c)) != GABP_OK) return st;
+    if ((st = ensure_msg32(c, s)) != GABP_OK) return st;
     GABP_HIP(launch_cast_scaled(c->r32, c->r, nullptr, n, s));
     if ((!warm || fresh) && (st = reset_messages32(c, s)) != GABP_OK) return st;
     for (int i = 0; i < mu; ++i)
@@ -487,7 +498,7 @@ int gabp_set_state(gabp_ctx* c, const void* src, size_t bytes, hipStream_t s) {
     P.sweeps = h.pre_sweeps[T];
   }
   if (h.has32) {
-    if ((st = ensure_msg32(c)) != GABP_OK) return st;
+    if ((st = ensure_msg32(c, s)) != GABP_OK) return st;
     c->parity32 = 0;
     if ((st = put(c->msg32[0], E * sizeof(float)))) return st;
   }
