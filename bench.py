@@ -76,7 +76,11 @@ def main():
     ap.add_argument("--no-ttr", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sweeps", type=int, default=12)
+    ap.add_argument("--profile", action="store_true",
+                    help="short run for the profiler: few launches of each kernel")
     args = ap.parse_args()
+    if args.profile:
+        args.steps, args.warmup, args.no_ttr, args.no_cpu = 5, 1, True, True
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "layout is a design note, not part of this build", file=sys.stderr)
@@ -117,8 +121,18 @@ def main():
     value = edges * CE * args.steps / t_gpu
     log(f"[bench] timed {args.steps} steps: {ms_step:.3f} ms/step, {value/1e9:.2f} G edge-upd/s")
 
+    # attainable bandwidth: plain 16-byte-vector copy of 1 GiB
+    src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    gabp.copy_probe(src, dst)
+    NC = 3 if args.profile else 10
+    t_cp = _events_time(lambda k: [gabp.copy_probe(src, dst) for _ in range(k)], NC) / NC
+    copy_gbs = 2 * src.numel() * 8 / t_cp / 1e9
+    del src, dst
+    log(f"[bench] copy probe: {copy_gbs:.0f} GB/s (read + write of 1 GiB)")
+
     # dominant kernel: the joint FP64 sweep, back-to-back launches on the launch stream
-    NS = 200
+    NS = 20 if args.profile else 200
     sweeps_only = lambda k: sj.sweeps(bt, k, reset=False, x=x)
     sweeps_only(20)
     t_sw = _events_time(sweeps_only, NS) / NS
@@ -168,6 +182,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "k_joint (FP64 joint flood sweep)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac_of_copy": achieved / copy_gbs,
                      "algorithmic_bytes_per_launch": ab, "launch_us": t_sw * 1e6},
         "wall_s_timed": t_wall,
         "kernels": {
@@ -180,6 +195,8 @@ def main():
             "mean_f32_edge_updates_per_s": edges / t_m32,
             "mean_f32_GBs": sweep_bytes_mean32(lay["slots"], a.n) / t_m32 / 1e9,
             "residual_us": t_res * 1e6,
+            "residual_GBs": (12 * lay["slots"] + 32 * a.n) / t_res / 1e9,
+            "copy_probe_GBs": copy_gbs,
             "lambda_phase_sweeps_f32": lsw, "lambda_phase_sweeps_f64": lsw64,
         },
     }

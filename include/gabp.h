@@ -180,6 +180,12 @@ int gabp_set_state(gabp_ctx* ctx, const void* src, size_t bytes, hipStream_t str
 int gabp_layout_info(const gabp_ctx* ctx, int32_t* n, int64_t* nnz, int64_t* slots,
                      int64_t* padded_slots);
 
+/* Measurement helper: a plain streaming copy of `bytes` (a multiple of 16) from src to dst
+ * (DEVICE, non-overlapping) with 16-byte vector loads and stores. Used to measure the
+ * attainable HBM bandwidth and to calibrate the profiler's byte counters against a kernel
+ * whose traffic is known exactly (2 x bytes). */
+int gabp_copy_probe(const void* src, void* dst, int64_t bytes, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

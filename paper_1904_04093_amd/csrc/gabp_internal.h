@@ -151,6 +151,7 @@ hipError_t launch_residual(const Layout* L, const double* coef_row, const double
                            const double* x, const float* dx, const double* scale, double* r,
                            double* partials, int32_t nred, double* red, hipStream_t s);
 
+hipError_t launch_copy_probe(const void* src, void* dst, int64_t bytes, hipStream_t s);
 hipError_t launch_fill64(double* p, int64_t n, double v, hipStream_t s);
 hipError_t launch_fill32(float* p, int64_t n, float v, hipStream_t s);
 hipError_t launch_copy64(double* dst, const double* src, int64_t n, hipStream_t s);

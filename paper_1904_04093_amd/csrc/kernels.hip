@@ -10,6 +10,7 @@
 // per-row sums of Algorithm 1 are plain in-register accumulations and no cross-lane
 // traffic is needed. Reductions (residual norms, Lt convergence) go through wavefront
 // shuffles and LDS in a fixed order, so repeated runs give identical bits.
+#include <algorithm>
 #include <cmath>
 
 #include "gabp_internal.h"
@@ -270,7 +271,7 @@ __global__ __launch_bounds__(kBlock) void k_lambda_fin(
 // Residual r = b - A x (coef_row = val) or b - A^T x (coef_row = aT), optionally at
 // x + scale * dx, with per-block partial norms.
 // ---------------------------------------------------------------------------------------
-template <bool XADD>
+template <int KMAX, bool XADD>
 __global__ __launch_bounds__(kRedBlock) void k_residual(
     int n, const int32_t* __restrict__ sptr, const int32_t* __restrict__ col,
     const double* __restrict__ coef_row, const double* __restrict__ diag,
@@ -287,12 +288,33 @@ __global__ __launch_bounds__(kRedBlock) void k_residual(
     if (XADD) xj = fma(sc, static_cast<double>(dx[j]), xj);
     const double bj = b[j];
     double acc = fma(-diag[j], xj, bj);
-    for (int k = 0; k < w; ++k) {
-      const int p = p0 + 64 * k;
-      const int cc = col[p];
-      double xc = x[cc];
-      if (XADD) xc = fma(sc, static_cast<double>(dx[cc]), xc);
-      acc = fma(-coef_row[p], xc, acc);
+    if constexpr (KMAX > 0) {
+      // all index and coefficient loads first, then the gathers: more bytes in flight
+      int cc[KMAX];
+      double cf[KMAX];
+#pragma unroll
+      for (int k = 0; k < KMAX; ++k) {
+        if (k < w) {
+          cc[k] = col[p0 + 64 * k];
+          cf[k] = coef_row[p0 + 64 * k];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < KMAX; ++k) {
+        if (k < w) {
+          double xc = x[cc[k]];
+          if (XADD) xc = fma(sc, static_cast<double>(dx[cc[k]]), xc);
+          acc = fma(-cf[k], xc, acc);
+        }
+      }
+    } else {
+      for (int k = 0; k < w; ++k) {
+        const int p = p0 + 64 * k;
+        const int cc = col[p];
+        double xc = x[cc];
+        if (XADD) xc = fma(sc, static_cast<double>(dx[cc]), xc);
+        acc = fma(-coef_row[p], xc, acc);
+      }
     }
     if (r) r[j] = acc;
     rr = acc * acc;
@@ -321,6 +343,14 @@ __global__ __launch_bounds__(kRedBlock) void k_residual(
     partials[3 * blockIdx.x + 1] = s1;
     partials[3 * blockIdx.x + 2] = s2;
   }
+}
+
+// Plain streaming copy (16-byte vectors): attainable-bandwidth and counter calibration.
+__global__ __launch_bounds__(256) void k_copy_probe(const double2* __restrict__ src,
+                                                   double2* __restrict__ dst, int64_t n2) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n2;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
 }
 
 __global__ __launch_bounds__(kRedBlock) void k_finalize_norms(
@@ -541,13 +571,31 @@ hipError_t launch_residual(const Layout* Lp, const double* coef_row, const doubl
                            const double* x, const float* dx, const double* scale, double* r,
                            double* partials, int32_t nred, double* red, hipStream_t s) {
   const Layout& L = *Lp;
-  if (dx)
-    k_residual<true><<<nred, kRedBlock, 0, s>>>(L.n, L.sptr, L.col, coef_row, L.diag, b, x,
-                                                dx, scale, r, partials);
-  else
-    k_residual<false><<<nred, kRedBlock, 0, s>>>(L.n, L.sptr, L.col, coef_row, L.diag, b, x,
-                                                 nullptr, nullptr, r, partials);
+#define RES_ARGS(DX, SC) L.n, L.sptr, L.col, coef_row, L.diag, b, x, DX, SC, r, partials
+  if (dx) {
+    GABP_DISPATCH_WIDTH(L.max_width,
+                        (k_residual<4, true><<<nred, kRedBlock, 0, s>>>(RES_ARGS(dx, scale))),
+                        (k_residual<8, true><<<nred, kRedBlock, 0, s>>>(RES_ARGS(dx, scale))),
+                        (k_residual<16, true><<<nred, kRedBlock, 0, s>>>(RES_ARGS(dx, scale))),
+                        (k_residual<0, true><<<nred, kRedBlock, 0, s>>>(RES_ARGS(dx, scale))));
+  } else {
+    GABP_DISPATCH_WIDTH(L.max_width,
+                        (k_residual<4, false><<<nred, kRedBlock, 0, s>>>(RES_ARGS(nullptr, nullptr))),
+                        (k_residual<8, false><<<nred, kRedBlock, 0, s>>>(RES_ARGS(nullptr, nullptr))),
+                        (k_residual<16, false><<<nred, kRedBlock, 0, s>>>(RES_ARGS(nullptr, nullptr))),
+                        (k_residual<0, false><<<nred, kRedBlock, 0, s>>>(RES_ARGS(nullptr, nullptr))));
+  }
+#undef RES_ARGS
   k_finalize_norms<<<1, kRedBlock, 0, s>>>(nred, partials, red);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_probe(const void* src, void* dst, int64_t bytes, hipStream_t s) {
+  const int64_t n2 = bytes / 16;
+  if (n2 <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((n2 + 255) / 256, 256 * 64);
+  k_copy_probe<<<static_cast<int>(blocks), 256, 0, s>>>(static_cast<const double2*>(src),
+                                                        static_cast<double2*>(dst), n2);
   return hipGetLastError();
 }
 

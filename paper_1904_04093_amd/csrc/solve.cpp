@@ -506,4 +506,11 @@ int gabp_set_state(gabp_ctx* c, const void* src, size_t bytes, hipStream_t s) {
   return GABP_OK;
 }
 
+int gabp_copy_probe(const void* src, void* dst, int64_t bytes, hipStream_t s) {
+  if (!src || !dst || bytes < 0 || bytes % 16 != 0)
+    return fail(GABP_EINVAL, "copy probe needs non-NULL pointers and a multiple of 16 bytes");
+  GABP_HIP(launch_copy_probe(src, dst, bytes, s));
+  return GABP_OK;
+}
+
 }  // extern "C"

@@ -74,6 +74,7 @@ _SIGS = {
     "gabp_get_state": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_size_t), _P]),
     "gabp_set_state": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P]),
     "gabp_layout_info": (ctypes.c_int, [_P, _PI32, _PI64, _PI64, _PI64]),
+    "gabp_copy_probe": (ctypes.c_int, [_P, _P, _I64, _P]),
 }
 
 _lib = None
@@ -141,6 +142,14 @@ def _dev(t, n, dtype_name="float64"):
     if t.dtype != dt or not t.is_contiguous() or t.numel() != n:
         raise ValueError(f"expected a contiguous {dtype_name} tensor with {n} elements")
     return _P(t.data_ptr())
+
+
+def copy_probe(src, dst):
+    """dst <- src with the library's plain streaming copy kernel (CUDA tensors, same size)."""
+    nb = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nb or not (src.is_cuda and dst.is_cuda):
+        raise ValueError("copy_probe needs two CUDA tensors of the same byte size")
+    _check(load().gabp_copy_probe(_P(src.data_ptr()), _P(dst.data_ptr()), nb, _stream()))
 
 
 @dataclass
