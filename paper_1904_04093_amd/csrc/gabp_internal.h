@@ -85,7 +85,8 @@ struct gabp_ctx {
   // reductions
   int32_t nred = 0;           // blocks of the residual kernel
   double* partials = nullptr; // [3 * nred]
-  double* red = nullptr;      // [8] device scalars: 0 ||r||2^2, 1 max|r|, 2 ||b||2^2, 3 scale
+  double* red = nullptr;      // [8] device scalars: 0 ||r||2^2, 1 max|r|, 2 ||b||2^2,
+                              // 3 max|r| again, 4 refinement scale, 5 max|dLt|, 6 max|Lt|
   unsigned long long* lmax = nullptr;  // [2] max|dLt|, max|Lt| as ordered bit patterns
   double* host_red = nullptr;          // pinned [8]
 };
@@ -139,8 +140,10 @@ struct MeanArgs32 {
 };
 hipError_t launch_mean_sweep32(const MeanArgs32& a, hipStream_t s);
 
+// one Lt-only sweep; out[0] = max|dLt|, out[1] = max|Lt| over the sweep (device scalars);
+// partials needs 2 doubles per 256-row block
 hipError_t launch_lambda_sweep(const Layout* L, const double* coef, const double* lam_in,
-                               double* lam_out, double* lamout, unsigned long long* lmax,
+                               double* lam_out, double* lamout, double* partials, double* out,
                                hipStream_t s);
 hipError_t launch_lambda_finalize(const Layout* L, const double* coef, const double* lam_in,
                                   Precomp* P, hipStream_t s);

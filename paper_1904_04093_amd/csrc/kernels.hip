@@ -27,6 +27,31 @@ __device__ __forceinline__ int row_base(const int32_t* __restrict__ sptr, int j,
   return a + (j & 63);
 }
 
+// ---- streaming loads/stores ----------------------------------------------------------
+// Per-slot arrays are touched once per sweep and the sweep's footprint exceeds the
+// last-level cache, so they are read and written with non-temporal hints.
+#ifndef GABP_NO_STREAM_HINTS
+template <typename T>
+__device__ __forceinline__ T ld_s(const T* p) { return __builtin_nontemporal_load(p); }
+template <typename T>
+__device__ __forceinline__ void st_s(T v, T* p) { __builtin_nontemporal_store(v, p); }
+#else
+template <typename T>
+__device__ __forceinline__ T ld_s(const T* p) { return *p; }
+template <typename T>
+__device__ __forceinline__ void st_s(T v, T* p) { *p = v; }
+#endif
+// The FP32 mean sweep's footprint (16 B per slot) is small enough to live partly in the
+// last-level cache across sweeps; there the hints cost more than they save.
+template <typename T>
+__device__ __forceinline__ T ld_m(const T* p) {
+  if constexpr (sizeof(T) == 8) return ld_s(p); else return *p;
+}
+template <typename T>
+__device__ __forceinline__ void st_m(T v, T* p) {
+  if constexpr (sizeof(T) == 8) st_s(v, p); else *p = v;
+}
+
 // ---- wavefront / block reductions (deterministic) -------------------------------------
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -65,10 +90,10 @@ __global__ __launch_bounds__(kBlock) void k_joint(
     for (int k = 0; k < KMAX; ++k) {
       if (k < w) {
         const int p = p0 + 64 * k;
-        l[k] = lam_in[p];
-        m[k] = msg_in[p];
-        a[k] = coef[p];
-        r[k] = rev[p];
+        l[k] = ld_s(lam_in + p);
+        m[k] = ld_s(msg_in + p);
+        a[k] = ld_s(coef + p);
+        r[k] = ld_s(rev + p);
       }
     }
 #pragma unroll
@@ -83,8 +108,8 @@ __global__ __launch_bounds__(kBlock) void k_joint(
     for (int k = 0; k < KMAX; ++k) {
       if (k < w) {
         const double L = -a[k] / (S - l[k] * a[k]);
-        lam_out[r[k]] = L;
-        msg_out[r[k]] = L * (M - m[k]);
+        st_s(L, lam_out + r[k]);
+        st_s(L * (M - m[k]), msg_out + r[k]);
       }
     }
   } else {
@@ -141,9 +166,9 @@ __global__ __launch_bounds__(kBlock) void k_mean(
     for (int k = 0; k < KMAX; ++k) {
       if (k < w) {
         const int p = p0 + 64 * k;
-        m[k] = msg_in[p];
-        lo[k] = lamout[p];
-        r[k] = rev[p];
+        m[k] = ld_m(msg_in + p);
+        lo[k] = ld_m(lamout + p);
+        r[k] = sizeof(T) == 8 ? ld_s(rev + p) : rev[p];
       }
     }
 #pragma unroll
@@ -152,7 +177,7 @@ __global__ __launch_bounds__(kBlock) void k_mean(
     if (WX) x[j] = ReadOff<T>::f(M, Sx, j);
 #pragma unroll
     for (int k = 0; k < KMAX; ++k)
-      if (k < w) msg_out[r[k]] = lo[k] * (M - m[k]);
+      if (k < w) st_m(lo[k] * (M - m[k]), msg_out + r[k]);
   } else {
     for (int k = 0; k < w; ++k) M += msg_in[p0 + 64 * k];
     if (WX) x[j] = ReadOff<T>::f(M, Sx, j);
@@ -167,15 +192,11 @@ __global__ __launch_bounds__(kBlock) void k_mean(
 // Lt-only flood sweep for the precompute phase. Also records the outgoing value at the
 // sender's own slot (lamout) and the largest change / magnitude of this sweep.
 // ---------------------------------------------------------------------------------------
-__device__ __forceinline__ unsigned long long dbits(double v) {
-  return static_cast<unsigned long long>(__double_as_longlong(v));
-}
-
 template <int KMAX>
 __global__ __launch_bounds__(kBlock) void k_lambda(
     int n, const int32_t* __restrict__ sptr, const int32_t* __restrict__ rev,
     const double* __restrict__ coef, const double* __restrict__ diag, const double* lam_in,
-    double* lam_out, double* __restrict__ lamout, unsigned long long* __restrict__ lmax) {
+    double* lam_out, double* __restrict__ lamout, double* __restrict__ partials) {
   __shared__ double sh[2][kBlock / 64];
   const int j = blockIdx.x * kBlock + threadIdx.x;
   double dm = 0.0, lm = 0.0;
@@ -242,10 +263,39 @@ __global__ __launch_bounds__(kBlock) void k_lambda(
       d2 = fmax(d2, sh[0][q]);
       l2 = fmax(l2, sh[1][q]);
     }
-    atomicMax(&lmax[0], dbits(d2));
-    atomicMax(&lmax[1], dbits(l2));
+    partials[2 * blockIdx.x + 0] = d2;
+    partials[2 * blockIdx.x + 1] = l2;
   }
 }
+
+// max over the per-block partials of k_lambda -> out[0] = max|dLt|, out[1] = max|Lt|
+__global__ __launch_bounds__(1024) void k_lambda_reduce(int nblk, const double* __restrict__ partials,
+                                                        double* __restrict__ out) {
+  __shared__ double sh[2][16];
+  double d = 0.0, l = 0.0;
+  for (int q = threadIdx.x; q < nblk; q += 1024) {
+    d = fmax(d, partials[2 * q]);
+    l = fmax(l, partials[2 * q + 1]);
+  }
+  d = wave_max(d);
+  l = wave_max(l);
+  if ((threadIdx.x & 63) == 0) {
+    sh[0][threadIdx.x >> 6] = d;
+    sh[1][threadIdx.x >> 6] = l;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 1; q < 16; ++q) {
+      d = fmax(d, sh[0][q]);
+      l = fmax(l, sh[1][q]);
+    }
+    d = fmax(d, sh[0][0]);
+    l = fmax(l, sh[1][0]);
+    out[0] = d;
+    out[1] = l;
+  }
+}
+
 
 template <int KMAX>
 __global__ __launch_bounds__(kBlock) void k_lambda_fin(
@@ -345,19 +395,21 @@ __global__ __launch_bounds__(kRedBlock) void k_residual(
   }
 }
 
-// Plain streaming copy (16-byte vectors): attainable-bandwidth and counter calibration.
-__global__ __launch_bounds__(256) void k_copy_probe(const double2* __restrict__ src,
-                                                   double2* __restrict__ dst, int64_t n2) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n2;
-       i += (int64_t)gridDim.x * blockDim.x)
-    dst[i] = src[i];
+// Plain streaming copy: one 16-byte vector per thread with non-temporal hints, the fastest
+// of the copy shapes tried on gfx950 (grid-stride loops reach ~25% less).
+typedef double v2d __attribute__((ext_vector_type(2)));
+__global__ __launch_bounds__(256) void k_copy_probe(const v2d* __restrict__ src,
+                                                   v2d* __restrict__ dst, int64_t n2) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n2) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
-__global__ __launch_bounds__(kRedBlock) void k_finalize_norms(
+constexpr int kFinBlock = 1024;
+__global__ __launch_bounds__(kFinBlock) void k_finalize_norms(
     int nred, const double* __restrict__ partials, double* __restrict__ red) {
-  __shared__ double sh[3][kRedBlock / 64];
+  __shared__ double sh[3][kFinBlock / 64];
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-  for (int q = threadIdx.x; q < nred; q += kRedBlock) {
+  for (int q = threadIdx.x; q < nred; q += kFinBlock) {
     s0 += partials[3 * q + 0];
     s1 = fmax(s1, partials[3 * q + 1]);
     s2 += partials[3 * q + 2];
@@ -374,7 +426,7 @@ __global__ __launch_bounds__(kRedBlock) void k_finalize_norms(
   __syncthreads();
   if (threadIdx.x == 0) {
     double t0 = sh[0][0], t1 = sh[1][0], t2 = sh[2][0];
-    for (int q = 1; q < kRedBlock / 64; ++q) {
+    for (int q = 1; q < kFinBlock / 64; ++q) {
       t0 += sh[0][q];
       t1 = fmax(t1, sh[1][q]);
       t2 += sh[2][q];
@@ -545,17 +597,17 @@ hipError_t launch_mean_sweep32(const MeanArgs32& a, hipStream_t s) {
 }
 
 hipError_t launch_lambda_sweep(const Layout* Lp, const double* coef, const double* lam_in,
-                               double* lam_out, double* lamout, unsigned long long* lmax,
+                               double* lam_out, double* lamout, double* partials, double* out,
                                hipStream_t s) {
   const Layout& L = *Lp;
   const int g = nblocks(L.n);
-  k_fill<unsigned long long><<<1, 64, 0, s>>>(lmax, 2, 0ull);
   GABP_DISPATCH_WIDTH(
       L.max_width,
-      (k_lambda<4><<<g, kBlock, 0, s>>>(L.n, L.sptr, L.rev, coef, L.diag, lam_in, lam_out, lamout, lmax)),
-      (k_lambda<8><<<g, kBlock, 0, s>>>(L.n, L.sptr, L.rev, coef, L.diag, lam_in, lam_out, lamout, lmax)),
-      (k_lambda<16><<<g, kBlock, 0, s>>>(L.n, L.sptr, L.rev, coef, L.diag, lam_in, lam_out, lamout, lmax)),
-      (k_lambda<0><<<g, kBlock, 0, s>>>(L.n, L.sptr, L.rev, coef, L.diag, lam_in, lam_out, lamout, lmax)));
+      (k_lambda<4><<<g, kBlock, 0, s>>>(L.n, L.sptr, L.rev, coef, L.diag, lam_in, lam_out, lamout, partials)),
+      (k_lambda<8><<<g, kBlock, 0, s>>>(L.n, L.sptr, L.rev, coef, L.diag, lam_in, lam_out, lamout, partials)),
+      (k_lambda<16><<<g, kBlock, 0, s>>>(L.n, L.sptr, L.rev, coef, L.diag, lam_in, lam_out, lamout, partials)),
+      (k_lambda<0><<<g, kBlock, 0, s>>>(L.n, L.sptr, L.rev, coef, L.diag, lam_in, lam_out, lamout, partials)));
+  k_lambda_reduce<<<1, 1024, 0, s>>>(g, partials, out);
   return hipGetLastError();
 }
 
@@ -586,16 +638,18 @@ hipError_t launch_residual(const Layout* Lp, const double* coef_row, const doubl
                         (k_residual<0, false><<<nred, kRedBlock, 0, s>>>(RES_ARGS(nullptr, nullptr))));
   }
 #undef RES_ARGS
-  k_finalize_norms<<<1, kRedBlock, 0, s>>>(nred, partials, red);
+  k_finalize_norms<<<1, kFinBlock, 0, s>>>(nred, partials, red);
   return hipGetLastError();
 }
 
 hipError_t launch_copy_probe(const void* src, void* dst, int64_t bytes, hipStream_t s) {
   const int64_t n2 = bytes / 16;
-  if (n2 <= 0) return hipSuccess;
-  const int64_t blocks = std::min<int64_t>((n2 + 255) / 256, 256 * 64);
-  k_copy_probe<<<static_cast<int>(blocks), 256, 0, s>>>(static_cast<const double2*>(src),
-                                                        static_cast<double2*>(dst), n2);
+  for (int64_t off = 0; off < n2;) {   // grids of at most 2^31 - 1 threads
+    const int64_t chunk = std::min<int64_t>(n2 - off, int64_t(1) << 30);
+    k_copy_probe<<<static_cast<int>((chunk + 255) / 256), 256, 0, s>>>(
+        static_cast<const v2d*>(src) + off, static_cast<v2d*>(dst) + off, chunk);
+    off += chunk;
+  }
   return hipGetLastError();
 }
 

@@ -55,16 +55,15 @@ int ensure_pre(gabp_ctx* c, int T, hipStream_t s) {
   int par = 0, done = 0;
   const double tol = c->opt.tol_lambda;
   for (int it = 1; it <= c->opt.max_lambda_sweeps; ++it) {
-    GABP_HIP(launch_lambda_sweep(&L, coef, c->lam[par], c->lam[par ^ 1], P.lamout, c->lmax, s));
+    GABP_HIP(launch_lambda_sweep(&L, coef, c->lam[par], c->lam[par ^ 1], P.lamout, c->partials,
+                                 c->red + 5, s));
     par ^= 1;
     done = it;
     if (tol > 0.0) {
-      unsigned long long h[2];
-      GABP_HIP(hipMemcpyAsync(h, c->lmax, sizeof(h), hipMemcpyDeviceToHost, s));
+      GABP_HIP(hipMemcpyAsync(c->host_red + 5, c->red + 5, 2 * sizeof(double),
+                              hipMemcpyDeviceToHost, s));
       GABP_HIP(hipStreamSynchronize(s));
-      double dm, lm;
-      std::memcpy(&dm, &h[0], sizeof(double));
-      std::memcpy(&lm, &h[1], sizeof(double));
+      const double dm = c->host_red[5], lm = c->host_red[6];
       if (!std::isfinite(dm) || !std::isfinite(lm))
         return fail(GABP_ENUMERIC, "non-finite precision message in the Lt phase");
       if (dm <= tol * lm) break;
