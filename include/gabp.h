@@ -180,6 +180,33 @@ int gabp_set_state(gabp_ctx* ctx, const void* src, size_t bytes, hipStream_t str
 int gabp_layout_info(const gabp_ctx* ctx, int32_t* n, int64_t* nnz, int64_t* slots,
                      int64_t* padded_slots);
 
+/* ---- geometric multigrid (Sec. 4: GaBP as a multigrid smoother) ---------------------- */
+/* Build a V-cycle over `levels` contexts, finest first (level_ctx[l] owns the operator of
+ * level l: a rediscretisation on a vertex-centred side[l] x side[l] interior grid, rows x
+ * fastest, with side[l] = 2 side[l+1] + 1; the coarsest side must be <= 63). Transfers:
+ * full-weighting restriction and bilinear interpolation. The coarsest system is solved
+ * directly (its inverse is formed once here, by Gauss-Jordan with partial pivoting).
+ * smoother 0: GaBP as the error-correction smoother of Algorithm 3, run by each level's
+ * context with its own mode, schedule, precision and warm policy; smoother 1: red-black
+ * Gauss-Seidel (colour (ix + iy) mod 2, red first). nu1 / nu2: pre- / post-smoothing
+ * steps (GaBP: sweeps per smoother call; RB-GS: red+black sweeps). The contexts are
+ * borrowed and must outlive the multigrid context; their message state is used by the
+ * smoother. Operators must have the 5-point pattern (the RB-GS update is in place). */
+int mg_setup(mg_ctx** out, int32_t levels, gabp_ctx* const* level_ctx, const int32_t* side,
+             int32_t smoother, int32_t nu1, int32_t nu2, hipStream_t stream);
+
+/* One V(nu1, nu2) cycle on the finest level: x (DEVICE, in/out) is improved for A_0 x = b
+ * (b DEVICE). rel_res_out (host, may be NULL): ||b - A_0 x||_2 / ||b||_2 afterwards. */
+int mg_vcycle(mg_ctx* m, const double* b, double* x, double* rel_res_out, hipStream_t stream);
+
+/* x = 0, then V-cycles until ||b - A_0 x||_2 / ||b||_2 <= tol or max_cycles. Returns
+ * GABP_OK, GABP_MAXSWEEPS (cycle cap) or GABP_ENUMERIC (divergence to non-finite values).
+ * cycles_out / rel_res_out: host, may be NULL. */
+int mg_solve(mg_ctx* m, const double* b, double* x, double tol, int32_t max_cycles,
+             int32_t* cycles_out, double* rel_res_out, hipStream_t stream);
+
+void mg_destroy(mg_ctx* m);
+
 /* Measurement helper: a plain streaming copy of `bytes` (a multiple of 16) from src to dst
  * (DEVICE, non-overlapping) with 16-byte vector loads and stores. Used to measure the
  * attainable HBM bandwidth and to calibrate the profiler's byte counters against a kernel

@@ -360,3 +360,17 @@ def grid_colour(nx, ny=None):
     ny = nx if ny is None else ny
     iy, ix = np.divmod(np.arange(nx * ny), nx)
     return ((ix + iy) % 2).astype(np.uint8)
+
+
+def smooth_coloured(g: Graph, b, x, mu, colour, lam=None, m_state=None, Lt_state=None):
+    """Algorithm 3 with red-black sweeps: e^mu = the read-offs of the mu-th red-black sweep.
+
+    ``lam = (Lt*, S*)``: mean-only with precomputed Lambda~; otherwise joint from
+    ``Lt_state`` (zero if None). ``m_state``: warm mean messages. Returns (x_new, Lt, m).
+    """
+    r = g.residual(b, x)
+    m = np.zeros(g.E) if m_state is None else m_state.copy()
+    Lt = (np.zeros(g.E) if Lt_state is None else Lt_state.copy()) if lam is None else lam[0]
+    for _ in range(mu):
+        e, Lt, m = sweep_coloured(g, r, Lt, m, colour, lambda_fixed=lam)
+    return x + e, Lt, m

@@ -57,20 +57,26 @@ def rbgs(g: _g.Graph, b, x, n, sweeps):
 
 
 class Hierarchy:
-    """Per-level oracle state: graphs, grid sides, precomputed Lambda~ and warm messages."""
+    """Per-level oracle state: graphs, grid sides, precomputed Lambda~ and warm messages.
+
+    smoother: "rbgs" (red-black Gauss-Seidel) or "gabp" (Algorithm 3) with
+    gabp_mode "joint" | "precomp", schedule "flood" | "redblack" and warm "reset" | "all"
+    (mean messages -- and, in joint mode, precision messages -- carried between calls).
+    """
 
     def __init__(self, csrs, smoother="gabp", nu1=2, nu2=2, gabp_mode="precomp",
-                 warm="reset", tol_lambda=1e-14, max_lambda_sweeps=10000):
+                 warm="reset", tol_lambda=1e-14, max_lambda_sweeps=10000, schedule="flood"):
         self.graphs = [_g.Graph.from_csr(a) for a in csrs]
         self.sides = [int(round(np.sqrt(a.n))) for a in csrs]
         self.smoother, self.nu1, self.nu2 = smoother, nu1, nu2
-        self.gabp_mode, self.warm = gabp_mode, warm
+        self.gabp_mode, self.warm, self.schedule = gabp_mode, warm, schedule
         self.lam = [None] * len(csrs)
         if smoother == "gabp" and gabp_mode == "precomp":
             for l, g in enumerate(self.graphs[:-1]):
                 Lt, S, _ = _g.lambda_phase(g, tol_lambda, max_lambda_sweeps)
                 self.lam[l] = (Lt, S)
         self.m_state = [None] * len(csrs)
+        self.Lt_state = [None] * len(csrs)
         self.coarse = np.linalg.inv(self.graphs[-1].dense())
 
     def _smooth(self, l, b, x, nu):
@@ -79,10 +85,25 @@ class Hierarchy:
             return x
         if self.smoother == "rbgs":
             return rbgs(g, b, x, self.sides[l], nu)
-        m0 = self.m_state[l] if self.warm == "all" else None
-        x, m = _g.smooth(g, b, x, nu, lam=self.lam[l], m_state=m0)
-        if self.warm == "all":
+        warm = self.warm == "all"
+        m0 = self.m_state[l] if warm else None
+        if self.schedule == "redblack":
+            L0 = self.Lt_state[l] if warm else None
+            x, Lt, m = _g.smooth_coloured(g, b, x, nu, _g.grid_colour(self.sides[l]),
+                                          lam=self.lam[l], m_state=m0, Lt_state=L0)
+        elif self.lam[l] is None and warm:
+            r = g.residual(b, x)
+            Lt = np.zeros(g.E) if self.Lt_state[l] is None else self.Lt_state[l]
+            m = np.zeros(g.E) if m0 is None else m0
+            for _ in range(nu):
+                e, Lt, m, _, _ = _g.sweep(g, r, Lt, m)
+            x = x + e
+        else:
+            x, m = _g.smooth(g, b, x, nu, lam=self.lam[l], m_state=m0)
+            Lt = None
+        if warm:
             self.m_state[l] = m
+            self.Lt_state[l] = Lt if self.lam[l] is None else None
         return x
 
     def vcycle(self, b, x, l=0):

@@ -174,4 +174,12 @@ hipError_t launch_param_reduce(int32_t nparam, const int32_t* jptr, const int32_
                                const int32_t* row, const int32_t* col, double* dtheta,
                                hipStream_t s);
 
+// geometric multigrid (mg.cpp)
+hipError_t launch_restrict_fw(int nc, const double* rf, double* bc, hipStream_t s);
+hipError_t launch_prolong_add(int nc, const double* ec, double* xf, hipStream_t s);
+hipError_t launch_rbgs(const Layout* L, int side, int colour, const double* b, double* x,
+                       hipStream_t s);
+hipError_t launch_dense_matvec(int n, const double* inv, const double* b, double* x,
+                               hipStream_t s);
+
 }  // namespace gabp

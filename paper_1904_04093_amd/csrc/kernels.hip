@@ -512,6 +512,81 @@ __global__ void k_param_reduce(int np, const int32_t* __restrict__ jptr,
   out[p] = acc;
 }
 
+// ---- geometric multigrid on vertex-centred n x n interior grids (x fastest) ------------
+// Full weighting: b_c(I,J) = [1 2 1; 2 4 2; 1 2 1] / 16 around fine node (2I+1, 2J+1).
+__global__ void k_restrict_fw(int nc, const double* __restrict__ rf, double* __restrict__ bc) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nc * nc) return;
+  const int nf = 2 * nc + 1;
+  const int I = q % nc, J = q / nc;
+  const int fx = 2 * I + 1, fy = 2 * J + 1;
+  const double* c = rf + (int64_t)fy * nf + fx;
+  const double centre = c[0];
+  const double edges = c[-1] + c[1] + c[-nf] + c[nf];
+  const double corners = c[-nf - 1] + c[-nf + 1] + c[nf - 1] + c[nf + 1];
+  bc[q] = (4.0 * centre + 2.0 * edges + corners) * (1.0 / 16.0);
+}
+
+// Bilinear interpolation of the coarse correction (zero on the boundary), added to x_f.
+__device__ __forceinline__ double coarse_at(const double* ec, int nc, int cx, int cy) {
+  // cx, cy: coarse indices including the boundary ring (0 and nc + 1 are boundary)
+  return (cx < 1 || cy < 1 || cx > nc || cy > nc) ? 0.0 : ec[(int64_t)(cy - 1) * nc + (cx - 1)];
+}
+__global__ void k_prolong_add(int nc, const double* __restrict__ ec, double* __restrict__ xf) {
+  const int nf = 2 * nc + 1;
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nf * nf) return;
+  const int Fx = q % nf + 1, Fy = q / nf + 1;   // fine indices including the boundary ring
+  double v;
+  if ((Fy & 1) == 0) {
+    if ((Fx & 1) == 0) v = coarse_at(ec, nc, Fx / 2, Fy / 2);
+    else v = 0.5 * (coarse_at(ec, nc, Fx / 2, Fy / 2) + coarse_at(ec, nc, Fx / 2 + 1, Fy / 2));
+  } else {
+    double lo, hi;
+    if ((Fx & 1) == 0) {
+      lo = coarse_at(ec, nc, Fx / 2, Fy / 2);
+      hi = coarse_at(ec, nc, Fx / 2, Fy / 2 + 1);
+    } else {
+      lo = 0.5 * (coarse_at(ec, nc, Fx / 2, Fy / 2) + coarse_at(ec, nc, Fx / 2 + 1, Fy / 2));
+      hi = 0.5 * (coarse_at(ec, nc, Fx / 2, Fy / 2 + 1) + coarse_at(ec, nc, Fx / 2 + 1, Fy / 2 + 1));
+    }
+    v = 0.5 * (lo + hi);
+  }
+  xf[q] += v;
+}
+
+// One colour of red-black Gauss-Seidel: x_j = (b_j - sum_{k != j} A_jk x_k) / A_jj for the
+// rows with (ix + iy) % 2 == c, in place (the 5-point graph is bipartite in this colouring).
+template <int KMAX>
+__global__ __launch_bounds__(kBlock) void k_rbgs(int n, int side, int c,
+                                                 const int32_t* __restrict__ sptr,
+                                                 const int32_t* __restrict__ col,
+                                                 const double* __restrict__ val,
+                                                 const double* __restrict__ diag,
+                                                 const double* __restrict__ b, double* x) {
+  const int j = blockIdx.x * kBlock + threadIdx.x;
+  if (j >= n) return;
+  if (((j % side) + (j / side)) % 2 != c) return;
+  int w;
+  const int p0 = row_base(sptr, j, &w);
+  double s = 0.0;
+  for (int k = 0; k < w; ++k) {
+    const int p = p0 + 64 * k;
+    s = fma(val[p], x[col[p]], s);
+  }
+  x[j] = (b[j] - s) / diag[j];
+}
+
+// Coarsest level: x = A^{-1} b with the inverse formed once on the host.
+__global__ void k_dense_matvec(int n, const double* __restrict__ inv, const double* __restrict__ b,
+                               double* __restrict__ x) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double acc = 0.0;
+  for (int k = 0; k < n; ++k) acc = fma(inv[(int64_t)i * n + k], b[k], acc);
+  x[i] = acc;
+}
+
 int grid_for(int64_t n) {
   const int64_t b = (n + 255) / 256;
   return static_cast<int>(b < 65536 ? (b < 1 ? 1 : b) : 65536);
@@ -705,6 +780,28 @@ hipError_t launch_param_reduce(int32_t np, const int32_t* jptr, const int32_t* j
                                hipStream_t s) {
   if (np <= 0) return hipSuccess;
   k_param_reduce<<<nblocks(np), 256, 0, s>>>(np, jptr, jnnz, jw, lam, x, row, col, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_restrict_fw(int nc, const double* rf, double* bc, hipStream_t s) {
+  const int64_t m = (int64_t)nc * nc;
+  k_restrict_fw<<<nblocks(m), 256, 0, s>>>(nc, rf, bc);
+  return hipGetLastError();
+}
+hipError_t launch_prolong_add(int nc, const double* ec, double* xf, hipStream_t s) {
+  const int64_t m = (int64_t)(2 * nc + 1) * (2 * nc + 1);
+  k_prolong_add<<<nblocks(m), 256, 0, s>>>(nc, ec, xf);
+  return hipGetLastError();
+}
+hipError_t launch_rbgs(const Layout* Lp, int side, int colour, const double* b, double* x,
+                       hipStream_t s) {
+  const Layout& L = *Lp;
+  k_rbgs<0><<<nblocks(L.n), kBlock, 0, s>>>(L.n, side, colour, L.sptr, L.col, L.val, L.diag, b, x);
+  return hipGetLastError();
+}
+hipError_t launch_dense_matvec(int n, const double* inv, const double* b, double* x,
+                               hipStream_t s) {
+  k_dense_matvec<<<nblocks(n), 256, 0, s>>>(n, inv, b, x);
   return hipGetLastError();
 }
 

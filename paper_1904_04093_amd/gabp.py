@@ -75,6 +75,10 @@ _SIGS = {
     "gabp_set_state": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P]),
     "gabp_layout_info": (ctypes.c_int, [_P, _PI32, _PI64, _PI64, _PI64]),
     "gabp_copy_probe": (ctypes.c_int, [_P, _P, _I64, _P]),
+    "mg_setup": (ctypes.c_int, [ctypes.POINTER(_P), _I32, _P, _P, _I32, _I32, _I32, _P]),
+    "mg_vcycle": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(_D), _P]),
+    "mg_solve": (ctypes.c_int, [_P, _P, _P, _D, _I32, _PI32, ctypes.POINTER(_D), _P]),
+    "mg_destroy": (None, [_P]),
 }
 
 _lib = None
@@ -291,3 +295,52 @@ class Solver:
     @property
     def handle(self):
         return self._h
+
+
+SMOOTHERS = {"gabp": 0, "rbgs": 1}
+
+
+class Multigrid:
+    """V-cycle over per-level Solver contexts (finest first) with a GaBP or RB-GS smoother."""
+
+    def __init__(self, solvers, sides, smoother="gabp", nu1=2, nu2=2):
+        lib = load()
+        self._lib = lib
+        self.solvers = list(solvers)          # keep the borrowed contexts alive
+        self.sides = [int(s) for s in sides]
+        arr = (_P * len(self.solvers))(*[s.handle for s in self.solvers])
+        sd = (ctypes.c_int32 * len(self.sides))(*self.sides)
+        h = _P()
+        _check(lib.mg_setup(ctypes.byref(h), len(self.solvers), ctypes.cast(arr, _P),
+                            ctypes.cast(sd, _P), SMOOTHERS[smoother], int(nu1), int(nu2),
+                            _stream()))
+        self._h = h
+        self.n = self.solvers[0].n
+
+    def vcycle(self, b, x):
+        rel = ctypes.c_double(0.0)
+        _check(self._lib.mg_vcycle(self._h, _dev(b, self.n), _dev(x, self.n),
+                                   ctypes.byref(rel), _stream()))
+        return rel.value
+
+    def solve(self, b, tol, max_cycles, x=None):
+        import torch
+        x = torch.empty(self.n, dtype=torch.float64, device="cuda") if x is None else x
+        cyc = ctypes.c_int32(0)
+        rel = ctypes.c_double(0.0)
+        st = self._lib.mg_solve(self._h, _dev(b, self.n), _dev(x, self.n), float(tol),
+                                int(max_cycles), ctypes.byref(cyc), ctypes.byref(rel),
+                                _stream())
+        _check(st, allow=(OK, MAXSWEEPS, ENUMERIC))
+        return x, {"status": st, "cycles": cyc.value, "rel_res2": rel.value}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.mg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

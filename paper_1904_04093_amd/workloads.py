@@ -38,7 +38,7 @@ __all__ = [
     "small_upwind", "precision_at_scale", "batch_family", "anisotropic_mg",
     "mg_hierarchy", "theta_problem", "theta_jacobian",
     "random_walk_summable", "random_tridiagonal", "random_tree", "laplacian_5pt",
-    "toy_5x5", "csr_from_dense", "csr_to_dense",
+    "toy_5x5", "csr_from_dense", "csr_to_dense", "grid_colouring",
 ]
 
 
@@ -416,3 +416,9 @@ def toy_5x5(r: np.random.Generator) -> CSR:
     a = np.where(pat, r.uniform(-1.0, 1.0, (5, 5)), 0.0)
     np.fill_diagonal(a, r.uniform(3.0, 4.0, 5))
     return csr_from_dense(a)
+
+
+def grid_colouring(n: int) -> np.ndarray:
+    """Red-black colouring of the n x n grid (x fastest): 0 where ix + iy is even."""
+    iy, ix = np.divmod(np.arange(n * n), n)
+    return ((ix + iy) & 1).astype(np.uint8)

@@ -1,0 +1,93 @@
+"""Multigrid V-cycles on the GPU against the oracle's V-cycle (same smoother, transfers and
+coarse solve), and convergence of the working configurations."""
+import numpy as np
+import pytest
+
+from oracle import mg as MG
+from paper_1904_04093_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1904_04093_amd import gabp
+    gabp.load()
+    return gabp
+
+
+def _gpu_mg(B, levels, smoother, nu1, nu2, **kw):
+    sides = [int(round(np.sqrt(a.n))) for a in levels]
+    solvers = [B.Solver.from_csr(a, colour=W.grid_colouring(s), **kw)
+               for a, s in zip(levels, sides)]
+    return B.Multigrid(solvers, sides, smoother=smoother, nu1=nu1, nu2=nu2)
+
+
+CASES = [
+    ("rbgs", {}, {}),
+    ("gabp", dict(mode="joint"), dict(gabp_mode="joint")),
+    ("gabp", dict(mode="precomp", tol_lambda=0.0, max_lambda_sweeps=40),
+     dict(gabp_mode="precomp", tol_lambda=0.0, max_lambda_sweeps=40)),
+    ("gabp", dict(mode="joint", schedule="redblack"), dict(gabp_mode="joint", schedule="redblack")),
+    ("gabp", dict(mode="precomp", schedule="redblack", tol_lambda=0.0, max_lambda_sweeps=40),
+     dict(gabp_mode="precomp", schedule="redblack", tol_lambda=0.0, max_lambda_sweeps=40)),
+    ("gabp", dict(mode="precomp", schedule="redblack", warm="all", tol_lambda=0.0,
+                  max_lambda_sweeps=40),
+     dict(gabp_mode="precomp", schedule="redblack", warm="all", tol_lambda=0.0,
+          max_lambda_sweeps=40)),
+    ("gabp", dict(mode="joint", warm="all"), dict(gabp_mode="joint", warm="all")),
+]
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+@pytest.mark.parametrize("problem", ["poisson", "aniso"])
+def test_vcycle_matches_oracle(B, case, problem):
+    smoother, gkw, okw = CASES[case]
+    kw = dict(kx=1.0, ky=1.0, peclet=0.0) if problem == "poisson" else dict(kx=1.0, ky=0.01, peclet=4.0)
+    levels = W.mg_hierarchy(5, coarsest=3, **kw)
+    b = W.rng(500, case).uniform(-1, 1, levels[0].n)
+    mg = _gpu_mg(B, levels, smoother, 2, 1, **gkw)
+    ho = MG.Hierarchy(levels, smoother=smoother, nu1=2, nu2=1, **okw)
+    bt = torch.as_tensor(b).cuda()
+    x = torch.zeros(levels[0].n, dtype=torch.float64, device="cuda")
+    xo = np.zeros(levels[0].n)
+    for cycle in range(3):
+        mg.vcycle(bt, x)
+        xo = ho.vcycle(b, xo)
+        xg = x.cpu().numpy()
+        scale = max(np.abs(xo).max(), 1e-300)
+        assert np.abs(xg - xo).max() <= TOL * scale * (1 + cycle), (smoother, gkw, cycle)
+
+
+def test_rbgs_vcycle_poisson_converges(B):
+    levels = W.mg_hierarchy(7, coarsest=3, kx=1.0, ky=1.0, peclet=0.0)
+    b = W.rng(501, 0).uniform(-1, 1, levels[0].n)
+    mg = _gpu_mg(B, levels, "rbgs", 2, 2)
+    x, info = mg.solve(torch.as_tensor(b).cuda(), 1e-10, 30)
+    assert info["status"] == B.OK and info["cycles"] <= 12
+    assert info["rel_res2"] <= 1e-10
+
+
+def test_redblack_gabp_vcycle_poisson_converges(B):
+    levels = W.mg_hierarchy(7, coarsest=3, kx=1.0, ky=1.0, peclet=0.0)
+    b = W.rng(502, 0).uniform(-1, 1, levels[0].n)
+    mg = _gpu_mg(B, levels, "gabp", 2, 2, mode="precomp", schedule="redblack",
+                 precision="f32_ir", tol_lambda=1e-8)
+    x, info = mg.solve(torch.as_tensor(b).cuda(), 1e-8, 40)
+    assert info["status"] == B.OK, info
+    xs = np.linalg.solve(W.csr_to_dense(levels[0]), b) if levels[0].n <= 5000 else None
+    if xs is not None:
+        assert np.abs(x.cpu().numpy() - xs).max() <= 1e-6 * np.abs(xs).max()
+
+
+def test_mg_setup_rejects_bad_hierarchy(B):
+    levels = W.mg_hierarchy(4, coarsest=3)
+    solvers = [B.Solver.from_csr(a) for a in levels]
+    with pytest.raises(B.GaBPError):
+        B.Multigrid(solvers, [15, 6, 3], smoother="rbgs")
+    with pytest.raises(B.GaBPError):
+        B.Multigrid(solvers[:1], [15], smoother="rbgs")
