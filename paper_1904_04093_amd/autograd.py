@@ -46,7 +46,7 @@ class GaBPSolve(torch.autograd.Function):
         return G, lam, None, None, None
 
 
-def gabp_solve(values, b, solver, tol=1e-10, max_sweeps=10_000_000):
+def gabp_solve(values, b, solver, tol=1e-10, max_sweeps=2_000_000):
     return GaBPSolve.apply(values, b, solver, tol, max_sweeps)
 
 
