@@ -180,6 +180,31 @@ int gabp_set_state(gabp_ctx* ctx, const void* src, size_t bytes, hipStream_t str
 int gabp_layout_info(const gabp_ctx* ctx, int32_t* n, int64_t* nnz, int64_t* slots,
                      int64_t* padded_slots);
 
+/* ---- batches of independent systems ------------------------------------------------- */
+/* Build one context for nsys independent systems given as a block-diagonal CSR matrix
+ * (HOST arrays, n rows in total; system s owns rows sys_row_off[s] .. sys_row_off[s+1]-1
+ * and no entry may couple two systems), each with nrhs right-hand sides (1, 2 or 4).
+ * Every system is laid out from a 64-row slice boundary so that a wavefront never mixes
+ * two systems. The precision messages Lt* (b-independent, Sec. 2.3) are computed once per
+ * system and shared by its right-hand sides. opt as for gabp_setup (red-black schedules
+ * are not supported for batches). */
+int gabp_setup_batched(gabp_ctx** out, int32_t nsys, const int32_t* sys_row_off, int32_t n,
+                       int64_t nnz, const int32_t* rowptr, const int32_t* col,
+                       const double* val, int32_t nrhs, const gabp_options* opt,
+                       hipStream_t stream);
+
+/* Solve every system for every right-hand side. B, X: DEVICE, [nrhs][n] doubles (rhs-major,
+ * rows in the setup numbering). Each (system, rhs) pair stops on its own at
+ * ||b - A x||_2 / ||b||_2 <= tol (checked every opt.check_every sweeps), a finished
+ * system's wavefronts stop sweeping, and max_sweeps caps the sweeps of the whole batch.
+ * F64 precision: flood sweeps (joint or precomputed Lt), each pair keeping the read-off it
+ * converged with -- identical, for the same options, to a single-system gabp_solve.
+ * F32_IR precision: FP32 mean messages inside FP64 iterative refinement with the rules of
+ * gabp_solve applied per pair. infos (HOST, may be NULL): nsys * nrhs entries, pair
+ * (s, q) at s * nrhs + q. Returns the worst pair status (OK < MAXSWEEPS < ENUMERIC). */
+int gabp_solve_batched(gabp_ctx* ctx, const double* B, double* X, double tol,
+                       int32_t max_sweeps, gabp_info* infos, hipStream_t stream);
+
 /* ---- geometric multigrid (Sec. 4: GaBP as a multigrid smoother) ---------------------- */
 /* Build a V-cycle over `levels` contexts, finest first (level_ctx[l] owns the operator of
  * level l: a rediscretisation on a vertex-centred side[l] x side[l] interior grid, rows x

@@ -27,6 +27,7 @@
 
 namespace gabp {
 
+struct Batch;
 constexpr int kSlice = 64;      // rows per slice = wavefront size on CDNA
 constexpr int kBlock = 256;     // threads per block for row kernels (4 slices)
 constexpr int kRedBlock = 256;  // threads per block for reductions
@@ -89,6 +90,7 @@ struct gabp_ctx {
                               // 3 max|r| again, 4 refinement scale, 5 max|dLt|, 6 max|Lt|
   unsigned long long* lmax = nullptr;  // [2] max|dLt|, max|Lt| as ordered bit patterns
   double* host_red = nullptr;          // pinned [8]
+  gabp::Batch* batch = nullptr;        // set for contexts made by gabp_setup_batched
 };
 
 namespace gabp {
@@ -101,6 +103,9 @@ int hip_fail(hipError_t e, const char* what);
     hipError_t _e = (call);                                      \
     if (_e != hipSuccess) return ::gabp::hip_fail(_e, #call);    \
   } while (0)
+
+// Lt phase of the context (T = 1: for A^T), computed once and cached (solve.cpp)
+int precompute(gabp_ctx* c, int T, hipStream_t s);
 
 // ---- kernel launchers (kernels.hip) ----
 struct SweepArgs {

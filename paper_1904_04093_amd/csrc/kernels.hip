@@ -733,6 +733,11 @@ hipError_t launch_fill64(double* p, int64_t n, double v, hipStream_t s) {
   k_fill<double><<<grid_for(n), 256, 0, s>>>(p, n, v);
   return hipGetLastError();
 }
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_fill<int32_t><<<grid_for(n), 256, 0, s>>>(p, n, v);
+  return hipGetLastError();
+}
 hipError_t launch_fill32(float* p, int64_t n, float v, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   k_fill<float><<<grid_for(n), 256, 0, s>>>(p, n, v);

@@ -13,7 +13,7 @@
 #include <string>
 #include <vector>
 
-#include "gabp_internal.h"
+#include "gabp_batch.h"
 
 namespace gabp {
 
@@ -350,6 +350,10 @@ void gabp_destroy(gabp_ctx* c) {
   }
   F(c->r); F(c->r2); F(c->e); F(c->r32); F(c->d32); F(c->dbest32); F(c->partials); F(c->red); F(c->lmax);
   if (c->host_red) (void)hipHostFree(c->host_red);
+  if (c->batch) {
+    batch_free(c->batch);
+    delete c->batch;
+  }
   delete c;
 }
 

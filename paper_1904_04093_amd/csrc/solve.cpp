@@ -303,6 +303,10 @@ int solve_any(gabp_ctx* c, int T, const double* b, double* x, double tol, int32_
 
 }  // namespace
 
+namespace gabp {
+int precompute(gabp_ctx* c, int T, hipStream_t s) { return ensure_pre(c, T, s); }
+}  // namespace gabp
+
 extern "C" {
 
 int gabp_solve(gabp_ctx* c, const double* b, double* x, double tol, int32_t max_sweeps,

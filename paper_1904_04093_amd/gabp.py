@@ -75,6 +75,9 @@ _SIGS = {
     "gabp_set_state": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P]),
     "gabp_layout_info": (ctypes.c_int, [_P, _PI32, _PI64, _PI64, _PI64]),
     "gabp_copy_probe": (ctypes.c_int, [_P, _P, _I64, _P]),
+    "gabp_setup_batched": (ctypes.c_int, [ctypes.POINTER(_P), _I32, _P, _I32, _I64, _P, _P, _P,
+                                          _I32, ctypes.POINTER(Options), _P]),
+    "gabp_solve_batched": (ctypes.c_int, [_P, _P, _P, _D, _I32, _P, _P]),
     "mg_setup": (ctypes.c_int, [ctypes.POINTER(_P), _I32, _P, _P, _I32, _I32, _I32, _P]),
     "mg_vcycle": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(_D), _P]),
     "mg_solve": (ctypes.c_int, [_P, _P, _P, _D, _I32, _PI32, ctypes.POINTER(_D), _P]),
@@ -295,6 +298,78 @@ class Solver:
     @property
     def handle(self):
         return self._h
+
+
+def _options(mode="joint", precision="f64", check_every=16, tol_lambda=1e-14,
+             max_lambda_sweeps=100000, warm="reset", ir_inner_tol=1e-4, ir_max_inner=1000000,
+             schedule="flood"):
+    o = Options()
+    load().gabp_default_options(ctypes.byref(o))
+    o.mode, o.precision = MODES[mode], PRECISIONS[precision]
+    o.check_every, o.tol_lambda = int(check_every), float(tol_lambda)
+    o.max_lambda_sweeps, o.warm = int(max_lambda_sweeps), WARM[warm]
+    o.ir_inner_tol, o.ir_max_inner = float(ir_inner_tol), int(ir_max_inner)
+    o.schedule = SCHEDULES[schedule]
+    return o
+
+
+class BatchSolver:
+    """Independent systems (a list of CSR matrices) with nrhs right-hand sides each, solved
+    together by one block-diagonal context."""
+
+    def __init__(self, systems, nrhs=1, **opts):
+        lib = load()
+        self._lib = lib
+        sizes = [int(a.n) for a in systems]
+        off = np.zeros(len(systems) + 1, dtype=np.int64)
+        off[1:] = np.cumsum(sizes)
+        rps, cols, vals = [np.zeros(1, dtype=np.int64)], [], []
+        base = 0
+        for a, o in zip(systems, off[:-1]):
+            rps.append(a.rowptr[1:].astype(np.int64) + base)
+            cols.append(a.col.astype(np.int64) + o)
+            vals.append(a.val)
+            base += int(a.rowptr[-1])
+        rowptr = np.concatenate(rps)
+        col = np.concatenate(cols)
+        val = np.concatenate(vals)
+        if off[-1] >= 2**31 or rowptr[-1] >= 2**31:
+            raise ValueError("batch too large for int32 indices")
+        self.nsys, self.nrhs, self.n = len(systems), int(nrhs), int(off[-1])
+        self.offsets = off
+        o = _options(**opts)
+        self.options = o
+        so, pso = _host(off, np.int32)
+        rp, prp = _host(rowptr, np.int32)
+        c, pc = _host(col, np.int32)
+        v, pv = _host(val, np.float64)
+        h = _P()
+        _check(lib.gabp_setup_batched(ctypes.byref(h), self.nsys, pso, self.n, int(rp[-1]),
+                                      prp, pc, pv, self.nrhs, ctypes.byref(o), _stream()))
+        self._h = h
+
+    def solve(self, B, tol, max_sweeps, X=None):
+        """B, X: CUDA float64 tensors of shape (nrhs, n). Returns X and per-pair infos."""
+        import torch
+        X = torch.empty(self.nrhs, self.n, dtype=torch.float64, device="cuda") if X is None else X
+        infos = (Info * (self.nsys * self.nrhs))()
+        st = self._lib.gabp_solve_batched(self._h, _dev(B, self.nrhs * self.n),
+                                          _dev(X, self.nrhs * self.n), float(tol),
+                                          int(max_sweeps), infos, _stream())
+        _check(st, allow=(OK, MAXSWEEPS, ENUMERIC))
+        out = [SolveInfo(**i.as_dict()) for i in infos]
+        return X, out
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.gabp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 SMOOTHERS = {"gabp": 0, "rbgs": 1}
