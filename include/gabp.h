@@ -77,6 +77,8 @@ typedef struct {
                                                                   default 1e-4             */
   int32_t ir_max_inner;      /* IR: cap on inner sweeps per outer step  default 1000000   */
   int32_t schedule;          /* GABP_SCHED_*                      default FLOOD            */
+  int32_t use_graphs;        /* record each check block (sweeps + residual + readback) as a
+                                hipGraph once and replay it       default 1                */
 } gabp_options;
 
 typedef struct {

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "gabp_batch.h"
+#include "graph.h"
 
 using namespace gabp;
 
@@ -23,6 +24,7 @@ void batch_free(Batch* B) {
   };
   F(B->ext_off); F(B->int_off); F(B->slice_sys); F(B->sys_slice0); F(B->sys_on); F(B->sys_live);
   F(B->count); F(B->flags); F(B->stat); F(B->scale); F(B->best); F(B->rn); F(B->since);
+  F(B->inner);
   F(B->partials); F(B->norms); F(B->b); F(B->x); F(B->r); F(B->r32); F(B->d32); F(B->dbest32);
   for (int q = 0; q < 2; ++q) {
     F(B->msg64[q]);
@@ -93,21 +95,33 @@ int solve_plain(gabp_ctx* c, Batch* B, double tol, int max_sweeps, hipStream_t s
   int par = 0, done = 0, st;
   while (done < max_sweeps) {
     const int k = std::min(c->opt.check_every, max_sweeps - done);
-    for (int i = 0; i < k; ++i) {
-      double* x = i == k - 1 ? B->x : nullptr;
-      if (joint)
-        GABP_HIP(batch_joint64(c, B, c->lam[par], B->msg64[par], c->lam[par ^ 1], B->msg64[par ^ 1], x, s));
-      else
-        GABP_HIP(batch_mean64(c, B, B->msg64[par], B->msg64[par ^ 1], x, s));
-      par ^= 1;
-    }
+    const int start = par;
+    // one check block: k sweeps of every unfinished system, per-pair residual norms,
+    // per-pair decisions, the number of systems still sweeping to the host
+    st = run_block(c, *c->graphs, s, GraphKey{3, nullptr, nullptr, nullptr, start, k, 0, tol},
+                   [&](hipStream_t ss) -> int {
+                     int p = start;
+                     for (int i = 0; i < k; ++i) {
+                       double* x = i == k - 1 ? B->x : nullptr;
+                       if (joint)
+                         GABP_HIP(batch_joint64(c, B, c->lam[p], B->msg64[p], c->lam[p ^ 1],
+                                                B->msg64[p ^ 1], x, ss));
+                       else
+                         GABP_HIP(batch_mean64(c, B, B->msg64[p], B->msg64[p ^ 1], x, ss));
+                       p ^= 1;
+                     }
+                     GABP_HIP(launch_fill_i32(B->count, 1, 0, ss));
+                     GABP_HIP(batch_residual(c, B, B->sys_on, B->x, nullptr, nullptr, ss));
+                     GABP_HIP(batch_decide_plain(B, tol, k, ss));
+                     GABP_HIP(hipMemcpyAsync(B->host_count, B->count, sizeof(int32_t),
+                                             hipMemcpyDeviceToHost, ss));
+                     return GABP_OK;
+                   });
+    if (st != GABP_OK) return st;
+    par = start ^ (k & 1);
     done += k;
-    GABP_HIP(launch_fill_i32(B->count, 1, 0, s));
-    GABP_HIP(batch_residual(c, B, B->sys_on, B->x, nullptr, nullptr, s));
-    GABP_HIP(batch_decide_plain(B, tol, done, s));
-    int live = 0;
-    if ((st = read_count(B, s, &live)) != GABP_OK) return st;
-    if (live == 0) break;
+    GABP_HIP(hipStreamSynchronize(s));
+    if (*B->host_count == 0) break;
   }
   c->parity = 0;
   return GABP_OK;
@@ -129,22 +143,34 @@ int solve_ir(gabp_ctx* c, Batch* B, double tol, int max_sweeps, hipStream_t s) {
     int par = 0, inner = 0;
     while (true) {
       const int k = std::min({c->opt.check_every, max_sweeps - total, c->opt.ir_max_inner - inner});
-      for (int i = 0; i < k; ++i) {
-        GABP_HIP(batch_mean32(c, B, B->msg32[par], B->msg32[par ^ 1], i == k - 1 ? B->d32 : nullptr, s));
-        par ^= 1;
-      }
+      const int start = par;
+      // one inner block: k FP32 sweeps of the systems still inside their inner solve,
+      // per-pair FP64 residuals of x + s d, best-trial tracking, count to the host
+      st = run_block(c, *c->graphs, s, GraphKey{4, nullptr, nullptr, nullptr, start, k, 0, tol},
+                     [&](hipStream_t ss) -> int {
+                       int p = start;
+                       for (int i = 0; i < k; ++i) {
+                         GABP_HIP(batch_mean32(c, B, B->msg32[p], B->msg32[p ^ 1],
+                                               i == k - 1 ? B->d32 : nullptr, ss));
+                         p ^= 1;
+                       }
+                       GABP_HIP(launch_fill_i32(B->count, 1, 0, ss));
+                       GABP_HIP(batch_residual(c, B, B->sys_on, B->x, B->d32, nullptr, ss));
+                       GABP_HIP(batch_ir_inner_check(B, tol, c->opt.ir_inner_tol, patience, k,
+                                                     c->opt.ir_max_inner, ss));
+                       GABP_HIP(batch_copy_best(c, B, ss));
+                       GABP_HIP(hipMemcpyAsync(B->host_count, B->count, sizeof(int32_t),
+                                               hipMemcpyDeviceToHost, ss));
+                       return GABP_OK;
+                     });
+      if (st != GABP_OK) return st;
+      par = start ^ (k & 1);
       inner += k;
       total += k;
-      GABP_HIP(launch_fill_i32(B->count, 1, 0, s));
-      GABP_HIP(batch_residual(c, B, B->sys_on, B->x, B->d32, nullptr, s));
-      GABP_HIP(batch_ir_inner_check(B, tol, c->opt.ir_inner_tol, patience, inner,
-                                    c->opt.ir_max_inner, s));
-      GABP_HIP(batch_copy_best(c, B, s));
-      int on = 0;
-      if ((st = read_count(B, s, &on)) != GABP_OK) return st;
-      if (on == 0 || total >= max_sweeps) break;
+      GABP_HIP(hipStreamSynchronize(s));
+      if (*B->host_count == 0 || total >= max_sweeps) break;
     }
-    GABP_HIP(batch_ir_outer_end(B, total, s));
+    GABP_HIP(batch_ir_outer_end(B, s));
     GABP_HIP(batch_apply_best(c, B, s));
   }
   (void)ER;
@@ -231,7 +257,7 @@ int gabp_setup_batched(gabp_ctx** out, int32_t nsys, const int32_t* sys_row_off,
 #define DA(p, cnt) if ((st = dalloc(&(p), cnt)) != GABP_OK) return bail(st)
   DA(B->ext_off, nsys + 1); DA(B->int_off, nsys + 1); DA(B->slice_sys, nsl); DA(B->sys_slice0, nsys + 1);
   DA(B->sys_on, nsys); DA(B->sys_live, nsys); DA(B->count, 1); DA(B->flags, np); DA(B->stat, np);
-  DA(B->scale, np); DA(B->best, np); DA(B->rn, np); DA(B->since, np);
+  DA(B->scale, np); DA(B->best, np); DA(B->rn, np); DA(B->since, np); DA(B->inner, np);
   DA(B->partials, static_cast<int64_t>(nsl) * nrhs * 3); DA(B->norms, np * 3);
   DA(B->b, nR); DA(B->x, nR); DA(B->r, nR); DA(B->r32, nR); DA(B->d32, nR); DA(B->dbest32, nR);
   for (int k = 0; k < 2; ++k) {

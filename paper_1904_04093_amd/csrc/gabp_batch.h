@@ -39,6 +39,7 @@ struct Batch {
   double* best = nullptr;              // [nsys*R] best trial residual of the inner solve
   double* rn = nullptr;                // [nsys*R] residual norm at the outer step start
   int32_t* since = nullptr;            // [nsys*R] checks since the last new best
+  int32_t* inner = nullptr;            // [nsys*R] sweeps of the current inner solve
   double* partials = nullptr;          // [nslices*R*3]
   double* norms = nullptr;             // [nsys*R*3]: sum r^2, max|r|, sum b^2
   double* b = nullptr;                 // [n_int*R] internal right-hand sides
@@ -61,11 +62,11 @@ hipError_t batch_joint64(const gabp_ctx* c, const Batch* B, const double* lam_in
                          hipStream_t s);
 hipError_t batch_residual(const gabp_ctx* c, const Batch* B, const int32_t* gate,
                           const double* x, const float* dx, double* r, hipStream_t s);
-hipError_t batch_decide_plain(const Batch* B, double tol, int sweeps_now, hipStream_t s);
+hipError_t batch_decide_plain(const Batch* B, double tol, int k_swept, hipStream_t s);
 hipError_t batch_ir_outer_begin(const Batch* B, double tol, hipStream_t s);
 hipError_t batch_ir_inner_check(const Batch* B, double tol, double inner_tol, int patience,
-                                int inner_now, int inner_max, hipStream_t s);
-hipError_t batch_ir_outer_end(const Batch* B, int sweeps_now, hipStream_t s);
+                                int k_swept, int inner_max, hipStream_t s);
+hipError_t batch_ir_outer_end(const Batch* B, hipStream_t s);
 hipError_t batch_copy_best(const gabp_ctx* c, const Batch* B, hipStream_t s);
 hipError_t batch_apply_best(const gabp_ctx* c, const Batch* B, hipStream_t s);
 hipError_t batch_cast(const gabp_ctx* c, const Batch* B, hipStream_t s);

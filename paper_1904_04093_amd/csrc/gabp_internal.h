@@ -28,6 +28,7 @@
 namespace gabp {
 
 struct Batch;
+struct GraphCache;
 constexpr int kSlice = 64;      // rows per slice = wavefront size on CDNA
 constexpr int kBlock = 256;     // threads per block for row kernels (4 slices)
 constexpr int kRedBlock = 256;  // threads per block for reductions
@@ -91,6 +92,7 @@ struct gabp_ctx {
   unsigned long long* lmax = nullptr;  // [2] max|dLt|, max|Lt| as ordered bit patterns
   double* host_red = nullptr;          // pinned [8]
   gabp::Batch* batch = nullptr;        // set for contexts made by gabp_setup_batched
+  gabp::GraphCache* graphs = nullptr;  // recorded check blocks
 };
 
 namespace gabp {

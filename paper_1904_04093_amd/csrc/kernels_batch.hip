@@ -268,7 +268,7 @@ __device__ __forceinline__ double rel_of(const double* nm) {
 }
 
 // plain solves: a pair is done once its relative residual reaches tol
-__global__ void k_decide_plain(int nsys, int R, double tol, int sweeps_now,
+__global__ void k_decide_plain(int nsys, int R, double tol, int k_swept,
                                const double* __restrict__ norms, uint32_t* __restrict__ flags,
                                PairStat* __restrict__ stat, int32_t* __restrict__ sys_on,
                                int32_t* __restrict__ count) {
@@ -282,7 +282,7 @@ __global__ void k_decide_plain(int nsys, int R, double tol, int sweeps_now,
     const double rel = rel_of(nm);
     stat[i].rel_res2 = rel;
     stat[i].res_inf = nm[1];
-    stat[i].sweeps = sweeps_now;
+    stat[i].sweeps += k_swept;
     if (!(rel == rel) || !isfinite(nm[1])) {
       flags[i] |= kPairDone | kPairFailed;
     } else if (rel <= tol) {
@@ -301,6 +301,7 @@ __global__ void k_ir_outer_begin(int nsys, int R, double tol, const double* __re
                                  uint32_t* __restrict__ flags, PairStat* __restrict__ stat,
                                  double* __restrict__ scale, double* __restrict__ best,
                                  double* __restrict__ rn, int32_t* __restrict__ since,
+                                 int32_t* __restrict__ inner,
                                  int32_t* __restrict__ sys_live, int32_t* __restrict__ sys_on,
                                  int32_t* __restrict__ count) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -325,6 +326,7 @@ __global__ void k_ir_outer_begin(int nsys, int R, double tol, const double* __re
     rn[i] = sqrt(nm[0]);
     best[i] = rn[i];
     since[i] = 0;
+    inner[i] = 0;
     flags[i] &= ~(kPairHasBest | kPairInnerDone | kPairNewBest);
     ++live;
   }
@@ -336,18 +338,22 @@ __global__ void k_ir_outer_begin(int nsys, int R, double tol, const double* __re
 // refinement, inner check: track the best trial correction per pair; a system keeps
 // sweeping while one of its pairs is still inside its inner solve
 __global__ void k_ir_inner_check(int nsys, int R, double tol, double inner_tol, int patience,
-                                 int inner_now, int inner_max, const double* __restrict__ norms,
+                                 int k_swept, int inner_max, const double* __restrict__ norms,
                                  uint32_t* __restrict__ flags, PairStat* __restrict__ stat,
                                  double* __restrict__ best, const double* __restrict__ rn,
-                                 int32_t* __restrict__ since, int32_t* __restrict__ sys_on,
-                                 int32_t* __restrict__ count) {
+                                 int32_t* __restrict__ since, int32_t* __restrict__ inner,
+                                 int32_t* __restrict__ sys_on, int32_t* __restrict__ count) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= nsys || !sys_on[s]) return;
   int live = 0;
   for (int q = 0; q < R; ++q) {
     const int i = s * R + q;
     flags[i] &= ~kPairNewBest;
-    if (flags[i] & (kPairDone | kPairInnerDone)) continue;
+    if (flags[i] & kPairDone) continue;
+    // every pair of a sweeping system was swept k_swept more times
+    stat[i].sweeps += k_swept;
+    inner[i] += k_swept;
+    if (flags[i] & kPairInnerDone) continue;
     const double* nm = norms + i * 3;
     const double nt = sqrt(nm[0]);
     const double bn = sqrt(nm[2]);
@@ -363,7 +369,7 @@ __global__ void k_ir_inner_check(int nsys, int R, double tol, double inner_tol, 
       since[i] += 1;
     }
     const bool done = best[i] <= inner_tol * rn[i] || (bn > 0 ? best[i] / bn : best[i]) <= tol ||
-                      ((flags[i] & kPairHasBest) && since[i] >= patience) || inner_now >= inner_max;
+                      ((flags[i] & kPairHasBest) && since[i] >= patience) || inner[i] >= inner_max;
     if (done) flags[i] |= kPairInnerDone;
     else ++live;
   }
@@ -373,14 +379,12 @@ __global__ void k_ir_inner_check(int nsys, int R, double tol, double inner_tol, 
 
 // refinement, end of an outer step: pairs without any improving trial stagnated
 __global__ void k_ir_outer_end(int nsys, int R, uint32_t* __restrict__ flags,
-                               PairStat* __restrict__ stat, int32_t* __restrict__ sys_live,
-                               int sweeps_now) {
+                               PairStat* __restrict__ stat, int32_t* __restrict__ sys_live) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= nsys || !sys_live[s]) return;
   for (int q = 0; q < R; ++q) {
     const int i = s * R + q;
     if (flags[i] & kPairDone) continue;
-    stat[i].sweeps = sweeps_now;
     stat[i].outer += 1;
     if (!(flags[i] & kPairHasBest)) flags[i] |= kPairDone | kPairFailed;
   }
@@ -537,31 +541,30 @@ hipError_t batch_residual(const gabp_ctx* c, const Batch* B, const int32_t* gate
   return hipGetLastError();
 }
 
-hipError_t batch_decide_plain(const Batch* B, double tol, int sweeps_now, hipStream_t s) {
-  k_decide_plain<<<nb(B->nsys), kB, 0, s>>>(B->nsys, B->R, tol, sweeps_now, B->norms, B->flags,
+hipError_t batch_decide_plain(const Batch* B, double tol, int k_swept, hipStream_t s) {
+  k_decide_plain<<<nb(B->nsys), kB, 0, s>>>(B->nsys, B->R, tol, k_swept, B->norms, B->flags,
                                             B->stat, B->sys_on, B->count);
   return hipGetLastError();
 }
 
 hipError_t batch_ir_outer_begin(const Batch* B, double tol, hipStream_t s) {
   k_ir_outer_begin<<<nb(B->nsys), kB, 0, s>>>(B->nsys, B->R, tol, B->norms, B->flags, B->stat,
-                                              B->scale, B->best, B->rn, B->since, B->sys_live,
-                                              B->sys_on, B->count);
+                                              B->scale, B->best, B->rn, B->since, B->inner,
+                                              B->sys_live, B->sys_on, B->count);
   return hipGetLastError();
 }
 
 hipError_t batch_ir_inner_check(const Batch* B, double tol, double inner_tol, int patience,
-                                int inner_now, int inner_max, hipStream_t s) {
+                                int k_swept, int inner_max, hipStream_t s) {
   k_ir_inner_check<<<nb(B->nsys), kB, 0, s>>>(B->nsys, B->R, tol, inner_tol, patience,
-                                              inner_now, inner_max, B->norms, B->flags,
-                                              B->stat, B->best, B->rn, B->since, B->sys_on,
-                                              B->count);
+                                              k_swept, inner_max, B->norms, B->flags,
+                                              B->stat, B->best, B->rn, B->since, B->inner,
+                                              B->sys_on, B->count);
   return hipGetLastError();
 }
 
-hipError_t batch_ir_outer_end(const Batch* B, int sweeps_now, hipStream_t s) {
-  k_ir_outer_end<<<nb(B->nsys), kB, 0, s>>>(B->nsys, B->R, B->flags, B->stat, B->sys_live,
-                                            sweeps_now);
+hipError_t batch_ir_outer_end(const Batch* B, hipStream_t s) {
+  k_ir_outer_end<<<nb(B->nsys), kB, 0, s>>>(B->nsys, B->R, B->flags, B->stat, B->sys_live);
   return hipGetLastError();
 }
 

@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "gabp_batch.h"
+#include "graph.h"
 
 namespace gabp {
 
@@ -114,6 +115,7 @@ void gabp_default_options(gabp_options* o) {
   o->ir_inner_tol = 1e-4;
   o->ir_max_inner = 1000000;
   o->schedule = GABP_SCHED_FLOOD;
+  o->use_graphs = 1;
 }
 
 const char* gabp_strerror(int s) {
@@ -263,6 +265,7 @@ int gabp_setup(gabp_ctx** out, int32_t n, int64_t nnz, const int32_t* rowptr,
 
   gabp_ctx* c = new gabp_ctx();
   c->opt = o;
+  c->graphs = new GraphCache();
   GABP_HIP(hipGetDevice(&c->device));
   Layout& L = c->L;
   L.n = n;
@@ -332,6 +335,7 @@ int gabp_update_values(gabp_ctx* c, const double* val, hipStream_t stream) {
   GABP_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, stream));
   GABP_HIP(hipStreamSynchronize(stream));
   c->pre[0].valid = c->pre[1].valid = false;
+  c->graphs->clear();   // recorded blocks point at the precomputed-Lt buffers' values
   if (hbad) return fail(GABP_EZERODIAG, "zero or non-finite diagonal in updated values");
   return GABP_OK;
 }
@@ -354,6 +358,7 @@ void gabp_destroy(gabp_ctx* c) {
     batch_free(c->batch);
     delete c->batch;
   }
+  delete c->graphs;
   delete c;
 }
 

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "gabp_internal.h"
+#include "graph.h"
 
 using namespace gabp;
 
@@ -18,6 +19,12 @@ namespace {
 struct Norms {
   double r2, rinf, b2;
 };
+
+void host_norms(const gabp_ctx* c, Norms* nm) {
+  nm->r2 = std::sqrt(c->host_red[0]);
+  nm->rinf = c->host_red[1];
+  nm->b2 = std::sqrt(c->host_red[2]);
+}
 
 int read_norms(gabp_ctx* c, hipStream_t s, Norms* nm) {
   GABP_HIP(hipMemcpyAsync(c->host_red, c->red, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -184,13 +191,29 @@ int solve64(gabp_ctx* c, int T, const double* b, double* x, double tol, int max_
   if ((st = reset_messages64(c, s)) != GABP_OK) return st;
   Norms nm{0, 0, 0};
   int done = 0;
+  const bool rb = c->opt.schedule == GABP_SCHED_REDBLACK;
   while (done < max_sweeps) {
     const int k = std::min(c->opt.check_every, max_sweeps - done);
-    for (int i = 0; i < k; ++i)
-      if ((st = sweep64(c, T, b, i == k - 1 ? x : nullptr, s)) != GABP_OK) return st;
+    const int start = c->parity;
+    // one check block: k sweeps (read-off on the last), residual, norms to the host
+    st = run_block(c, *c->graphs, s, GraphKey{1, b, x, nullptr, start, k, T, 0.0},
+                   [&](hipStream_t ss) -> int {
+                     c->parity = start;
+                     for (int i = 0; i < k; ++i) {
+                       const int e = sweep64(c, T, b, i == k - 1 ? x : nullptr, ss);
+                       if (e != GABP_OK) return e;
+                     }
+                     const int e = residual(c, T, b, x, nullptr, nullptr, nullptr, ss);
+                     if (e != GABP_OK) return e;
+                     GABP_HIP(hipMemcpyAsync(c->host_red, c->red, 4 * sizeof(double),
+                                             hipMemcpyDeviceToHost, ss));
+                     return GABP_OK;
+                   });
+    if (st != GABP_OK) return st;
+    c->parity = rb ? start : start ^ (k & 1);
     done += k;
-    if ((st = residual(c, T, b, x, nullptr, nullptr, nullptr, s)) != GABP_OK) return st;
-    if ((st = read_norms(c, s, &nm)) != GABP_OK) return st;
+    GABP_HIP(hipStreamSynchronize(s));
+    host_norms(c, &nm);
     if (!std::isfinite(nm.r2) || !std::isfinite(nm.rinf)) {
       fill_info(info, GABP_ENUMERIC, done, lsw, 0, nm);
       return fail(GABP_ENUMERIC, "non-finite residual after sweep " + std::to_string(done));
@@ -246,15 +269,32 @@ int solve_ir(gabp_ctx* c, int T, const double* b, double* x, double tol, int max
     Norms nbest = nm;
     int ibest = -1, itry = (ir + 1) % 3;
     int inner = 0, since_best = 0;
+    const bool rb = c->opt.schedule == GABP_SCHED_REDBLACK;
     while (true) {
       const int k = std::min({c->opt.check_every, max_sweeps - total, c->opt.ir_max_inner - inner});
-      for (int i = 0; i < k; ++i)
-        if ((st = sweep32(c, T, c->r32, i == k - 1 ? c->d32 : nullptr, s)) != GABP_OK) return st;
+      const int start = c->parity32;
+      double* rt = buf[itry];
+      // one inner block: k FP32 sweeps, FP64 residual of x + s d, norms to the host
+      st = run_block(c, *c->graphs, s, GraphKey{2, b, x, rt, start, k, T, 0.0},
+                     [&](hipStream_t ss) -> int {
+                       c->parity32 = start;
+                       for (int i = 0; i < k; ++i) {
+                         const int e = sweep32(c, T, c->r32, i == k - 1 ? c->d32 : nullptr, ss);
+                         if (e != GABP_OK) return e;
+                       }
+                       const int e = residual(c, T, b, x, c->d32, scale, rt, ss);
+                       if (e != GABP_OK) return e;
+                       GABP_HIP(hipMemcpyAsync(c->host_red, c->red, 4 * sizeof(double),
+                                               hipMemcpyDeviceToHost, ss));
+                       return GABP_OK;
+                     });
+      if (st != GABP_OK) return st;
+      c->parity32 = rb ? start : start ^ (k & 1);
       inner += k;
       total += k;
       Norms nt;
-      if ((st = residual(c, T, b, x, c->d32, scale, buf[itry], s)) != GABP_OK) return st;
-      if ((st = read_norms(c, s, &nt)) != GABP_OK) return st;
+      GABP_HIP(hipStreamSynchronize(s));
+      host_norms(c, &nt);
       if (!std::isfinite(nt.r2)) {
         fill_info(info, GABP_ENUMERIC, total, lsw, outer, nt);
         return fail(GABP_ENUMERIC, "non-finite residual in iterative refinement");

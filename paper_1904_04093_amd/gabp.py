@@ -36,7 +36,7 @@ class Options(ctypes.Structure):
                 ("check_every", ctypes.c_int32), ("tol_lambda", ctypes.c_double),
                 ("max_lambda_sweeps", ctypes.c_int32), ("warm", ctypes.c_int32),
                 ("ir_inner_tol", ctypes.c_double), ("ir_max_inner", ctypes.c_int32),
-                ("schedule", ctypes.c_int32)]
+                ("schedule", ctypes.c_int32), ("use_graphs", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -175,7 +175,7 @@ class Solver:
     def __init__(self, n, rowptr, col, val, rev=None, colour=None, *, mode="joint",
                  precision="f64", check_every=16, tol_lambda=1e-14,
                  max_lambda_sweeps=100000, warm="reset", ir_inner_tol=1e-4,
-                 ir_max_inner=1000000, schedule="flood"):
+                 ir_max_inner=1000000, schedule="flood", use_graphs=True):
         lib = load()
         self._lib = lib
         o = Options()
@@ -185,6 +185,7 @@ class Solver:
         o.max_lambda_sweeps, o.warm = int(max_lambda_sweeps), WARM[warm]
         o.ir_inner_tol, o.ir_max_inner = float(ir_inner_tol), int(ir_max_inner)
         o.schedule = SCHEDULES[schedule]
+        o.use_graphs = int(bool(use_graphs))
         self.options = o
         rp, prp = _host(rowptr, np.int32)
         c, pc = _host(col, np.int32)
@@ -302,7 +303,7 @@ class Solver:
 
 def _options(mode="joint", precision="f64", check_every=16, tol_lambda=1e-14,
              max_lambda_sweeps=100000, warm="reset", ir_inner_tol=1e-4, ir_max_inner=1000000,
-             schedule="flood"):
+             schedule="flood", use_graphs=True):
     o = Options()
     load().gabp_default_options(ctypes.byref(o))
     o.mode, o.precision = MODES[mode], PRECISIONS[precision]
@@ -310,6 +311,7 @@ def _options(mode="joint", precision="f64", check_every=16, tol_lambda=1e-14,
     o.max_lambda_sweeps, o.warm = int(max_lambda_sweeps), WARM[warm]
     o.ir_inner_tol, o.ir_max_inner = float(ir_inner_tol), int(ir_max_inner)
     o.schedule = SCHEDULES[schedule]
+    o.use_graphs = int(bool(use_graphs))
     return o
 
 

@@ -363,3 +363,42 @@ def test_f32_mean_sweeps_track_fp64_oracle(B):
             for _ in range(sweeps):
                 xo, m = G.msweep(g, b, Lt, S, m)
             assert _rel_inf(x, xo) <= 2e-6 * (1 + sweeps), (name, sweeps)
+
+
+@pytest.mark.parametrize("kw", [dict(mode="joint"), dict(mode="precomp"),
+                                dict(mode="precomp", precision="f32_ir"),
+                                dict(mode="joint", schedule="redblack")])
+def test_graph_replays_match_eager(B, kw):
+    """Recorded check blocks replayed several times, with eager work in between, give the
+    eager result bit for bit."""
+    n = 24
+    a, b = W.small_upwind(n)
+    colour = G.grid_colour(n) if kw.get("schedule") == "redblack" else None
+    eager = B.Solver.from_csr(a, colour=colour, check_every=8, use_graphs=False, **kw)
+    graph = B.Solver.from_csr(a, colour=colour, check_every=8, use_graphs=True, **kw)
+    bt = _cuda(b)
+    xe, ie = eager.solve(bt, 1e-11, 20000)
+    xe = xe.cpu().numpy()
+    for rep in range(3):
+        xg, ig = graph.solve(bt, 1e-11, 20000)
+        assert np.array_equal(xg.cpu().numpy(), xe), rep
+        assert ig.sweeps == ie.sweeps and ig.rel_res2 == ie.rel_res2
+        eager.sweeps(bt, 5)                          # eager work between replays
+        torch.cuda.synchronize()
+
+
+def test_batched_graph_replays_match_eager(B):
+    fam = W.batch_family(nsys=5, nrhs=2, side_lo=8, side_hi=24, seed=33)
+    systems = [x for x, _ in fam]
+    rhs = np.stack([np.concatenate([bb[q] for _, bb in fam]) for q in range(2)])
+    Bt = torch.as_tensor(rhs).cuda()
+    res = []
+    for graphs in (False, True, True, True):
+        bs = B.BatchSolver(systems, nrhs=2, mode="precomp", precision="f32_ir",
+                           check_every=16, tol_lambda=1e-8, use_graphs=graphs)
+        X, infos = bs.solve(Bt, 1e-10, 200000)
+        X2, _ = bs.solve(Bt, 1e-10, 200000)          # replay on the same context
+        res.append((X.cpu().numpy(), X2.cpu().numpy(), [i.sweeps for i in infos]))
+    for X, X2, sw in res[1:]:
+        assert np.array_equal(X, res[0][0]) and np.array_equal(X2, res[0][0])
+        assert sw == res[0][2]
