@@ -203,7 +203,7 @@ int gabp_setup_batched(gabp_ctx** out, int32_t nsys, const int32_t* sys_row_off,
         if (col[e] < sys_row_off[s] || col[e] >= sys_row_off[s + 1])
           return fail(GABP_EINVAL, "entry couples two systems at row " + std::to_string(i));
   }
-  const int32_t n_int = int_off[nsys];
+  const int32_t n_int = int_off[nsys];   // a multiple of 64: kernels rely on it
   const int64_t nnz_int = nnz + (n_int - n);
   std::vector<int32_t> rp(n_int + 1, 0), cc(nnz_int);
   std::vector<double> vv(nnz_int);

@@ -145,6 +145,10 @@ __global__ __launch_bounds__(kB) void k_residual_b(
     const double* __restrict__ b, const double* __restrict__ x, const float* __restrict__ dx,
     const double* __restrict__ scale, double* __restrict__ r, double* __restrict__ partials) {
   const int j = blockIdx.x * kB + threadIdx.x;
+  // The internal row count n is a multiple of 64 (systems are slice-aligned), so this test
+  // retires whole wavefronts: the grid rounds up to 256 threads, and the extra wavefronts
+  // must not read slice_sys past its last slice.
+  if (j >= n) return;
   const int slice = j >> 6;
   // every lane of a wavefront has the same slice, hence the same system
   const int sys = slice_sys[slice];
