@@ -182,6 +182,19 @@ int gabp_set_state(gabp_ctx* ctx, const void* src, size_t bytes, hipStream_t str
 int gabp_layout_info(const gabp_ctx* ctx, int32_t* n, int64_t* nnz, int64_t* slots,
                      int64_t* padded_slots);
 
+/* Autotuner. Times the context's own sweep kernel (for its mode, precision and batch
+ * shape) with and without non-temporal hints on the per-slot streams, keeps the faster,
+ * then sets opt.check_every to the smallest power of two in [8, 256] for which one residual
+ * check (kernel, reduction, readback, host wait) costs at most 2% of the sweeps between
+ * checks. Results are cached per (architecture, sizes, mode) in memory and, when the
+ * environment variable GABP_AUTOTUNE_CACHE names a file, in that JSON-lines file. Runs
+ * sweeps on a zero right-hand side, so the context's message state is reset; computes the
+ * precomputed Lt first when the mode needs it. Outputs (host, may be NULL): the chosen
+ * check interval and hint setting (0/1). Because it changes check_every, later solves may
+ * stop at a different (rounded-up) sweep count than untuned ones. */
+int gabp_autotune(gabp_ctx* ctx, int32_t* check_every_out, int32_t* hints_out,
+                  hipStream_t stream);
+
 /* ---- batches of independent systems ------------------------------------------------- */
 /* Build one context for nsys independent systems given as a block-diagonal CSR matrix
  * (HOST arrays, n rows in total; system s owns rows sys_row_off[s] .. sys_row_off[s+1]-1

@@ -49,6 +49,10 @@ struct Layout {
   int64_t epad = 0;       // padded slot count; position epad is the trash slot
   int32_t nslices = 0;
   int32_t max_width = 0;  // max slots per row
+  // non-temporal hints on the per-slot streams of the FP64 / FP32 sweeps: they pay off
+  // once a sweep's footprint exceeds the last-level cache and cost time below it
+  bool stream_hints = false;
+  bool stream_hints32 = false;
   // device
   int32_t* sptr = nullptr;   // [nslices+1]
   int32_t* rev = nullptr;    // [epad]

@@ -30,26 +30,13 @@ __device__ __forceinline__ int row_base(const int32_t* __restrict__ sptr, int j,
 // ---- streaming loads/stores ----------------------------------------------------------
 // Per-slot arrays are touched once per sweep and the sweep's footprint exceeds the
 // last-level cache, so they are read and written with non-temporal hints.
-#ifndef GABP_NO_STREAM_HINTS
-template <typename T>
-__device__ __forceinline__ T ld_s(const T* p) { return __builtin_nontemporal_load(p); }
-template <typename T>
-__device__ __forceinline__ void st_s(T v, T* p) { __builtin_nontemporal_store(v, p); }
-#else
-template <typename T>
-__device__ __forceinline__ T ld_s(const T* p) { return *p; }
-template <typename T>
-__device__ __forceinline__ void st_s(T v, T* p) { *p = v; }
-#endif
-// The FP32 mean sweep's footprint (16 B per slot) is small enough to live partly in the
-// last-level cache across sweeps; there the hints cost more than they save.
-template <typename T>
-__device__ __forceinline__ T ld_m(const T* p) {
-  if constexpr (sizeof(T) == 8) return ld_s(p); else return *p;
+template <bool NT, typename T>
+__device__ __forceinline__ T ld_s(const T* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p); else return *p;
 }
-template <typename T>
-__device__ __forceinline__ void st_m(T v, T* p) {
-  if constexpr (sizeof(T) == 8) st_s(v, p); else *p = v;
+template <bool NT, typename T>
+__device__ __forceinline__ void st_s(T v, T* p) {
+  if constexpr (NT) __builtin_nontemporal_store(v, p); else *p = v;
 }
 
 // ---- wavefront / block reductions (deterministic) -------------------------------------
@@ -69,7 +56,7 @@ __device__ __forceinline__ double wave_max(double v) {
 // KMAX > 0: row held in registers; KMAX == 0: two passes over memory for wide rows.
 // colour >= 0: only rows of that colour work, in place (red-black schedule).
 // ---------------------------------------------------------------------------------------
-template <int KMAX, bool WX>
+template <int KMAX, bool WX, bool NT>
 __global__ __launch_bounds__(kBlock) void k_joint(
     int n, const int32_t* __restrict__ sptr, const int32_t* __restrict__ rev,
     const double* __restrict__ coef, const double* __restrict__ diag,
@@ -90,10 +77,10 @@ __global__ __launch_bounds__(kBlock) void k_joint(
     for (int k = 0; k < KMAX; ++k) {
       if (k < w) {
         const int p = p0 + 64 * k;
-        l[k] = ld_s(lam_in + p);
-        m[k] = ld_s(msg_in + p);
-        a[k] = ld_s(coef + p);
-        r[k] = ld_s(rev + p);
+        l[k] = ld_s<NT>(lam_in + p);
+        m[k] = ld_s<NT>(msg_in + p);
+        a[k] = ld_s<NT>(coef + p);
+        r[k] = ld_s<NT>(rev + p);
       }
     }
 #pragma unroll
@@ -108,8 +95,8 @@ __global__ __launch_bounds__(kBlock) void k_joint(
     for (int k = 0; k < KMAX; ++k) {
       if (k < w) {
         const double L = -a[k] / (S - l[k] * a[k]);
-        st_s(L, lam_out + r[k]);
-        st_s(L * (M - m[k]), msg_out + r[k]);
+        st_s<NT>(L, lam_out + r[k]);
+        st_s<NT>(L * (M - m[k]), msg_out + r[k]);
       }
     }
   } else {
@@ -147,7 +134,7 @@ struct ReadOff<float> {
   }
 };
 
-template <typename T, int KMAX, bool WX>
+template <typename T, int KMAX, bool WX, bool NT>
 __global__ __launch_bounds__(kBlock) void k_mean(
     int n, const int32_t* __restrict__ sptr, const int32_t* __restrict__ rev,
     const T* __restrict__ lamout, const T* __restrict__ Sx, const T* __restrict__ b,
@@ -166,9 +153,9 @@ __global__ __launch_bounds__(kBlock) void k_mean(
     for (int k = 0; k < KMAX; ++k) {
       if (k < w) {
         const int p = p0 + 64 * k;
-        m[k] = ld_m(msg_in + p);
-        lo[k] = ld_m(lamout + p);
-        r[k] = sizeof(T) == 8 ? ld_s(rev + p) : rev[p];
+        m[k] = ld_s<NT>(msg_in + p);
+        lo[k] = ld_s<NT>(lamout + p);
+        r[k] = ld_s<NT>(rev + p);
       }
     }
 #pragma unroll
@@ -177,7 +164,7 @@ __global__ __launch_bounds__(kBlock) void k_mean(
     if (WX) x[j] = ReadOff<T>::f(M, Sx, j);
 #pragma unroll
     for (int k = 0; k < KMAX; ++k)
-      if (k < w) st_m(lo[k] * (M - m[k]), msg_out + r[k]);
+      if (k < w) st_s<NT>(lo[k] * (M - m[k]), msg_out + r[k]);
   } else {
     for (int k = 0; k < w; ++k) M += msg_in[p0 + 64 * k];
     if (WX) x[j] = ReadOff<T>::f(M, Sx, j);
@@ -605,70 +592,64 @@ int grid_for(int64_t n) {
     else { CALL0; }                                         \
   } while (0)
 
+#define GABP_DISPATCH_NT(NTV, ...)                   \
+  if (NTV) { constexpr bool NTB = true; __VA_ARGS__; } \
+  else { constexpr bool NTB = false; __VA_ARGS__; }
+
 hipError_t launch_joint_sweep(const SweepArgs& a, hipStream_t s) {
   const Layout& L = *a.L;
   const int g = nblocks(L.n);
 #define JOINT_ARGS                                                                      \
   L.n, L.sptr, L.rev, a.coef, L.diag, a.b, a.lam_in, a.msg_in, a.lam_out, a.msg_out, a.x, \
       L.colour, a.colour
-  if (a.x) {
-    GABP_DISPATCH_WIDTH(L.max_width,
-                        (k_joint<4, true><<<g, kBlock, 0, s>>>(JOINT_ARGS)),
-                        (k_joint<8, true><<<g, kBlock, 0, s>>>(JOINT_ARGS)),
-                        (k_joint<16, true><<<g, kBlock, 0, s>>>(JOINT_ARGS)),
-                        (k_joint<0, true><<<g, kBlock, 0, s>>>(JOINT_ARGS)));
-  } else {
-    GABP_DISPATCH_WIDTH(L.max_width,
-                        (k_joint<4, false><<<g, kBlock, 0, s>>>(JOINT_ARGS)),
-                        (k_joint<8, false><<<g, kBlock, 0, s>>>(JOINT_ARGS)),
-                        (k_joint<16, false><<<g, kBlock, 0, s>>>(JOINT_ARGS)),
-                        (k_joint<0, false><<<g, kBlock, 0, s>>>(JOINT_ARGS)));
-  }
+  GABP_DISPATCH_NT(L.stream_hints, {
+    if (a.x) {
+      GABP_DISPATCH_WIDTH(L.max_width,
+                          (k_joint<4, true, NTB><<<g, kBlock, 0, s>>>(JOINT_ARGS)),
+                          (k_joint<8, true, NTB><<<g, kBlock, 0, s>>>(JOINT_ARGS)),
+                          (k_joint<16, true, NTB><<<g, kBlock, 0, s>>>(JOINT_ARGS)),
+                          (k_joint<0, true, NTB><<<g, kBlock, 0, s>>>(JOINT_ARGS)));
+    } else {
+      GABP_DISPATCH_WIDTH(L.max_width,
+                          (k_joint<4, false, NTB><<<g, kBlock, 0, s>>>(JOINT_ARGS)),
+                          (k_joint<8, false, NTB><<<g, kBlock, 0, s>>>(JOINT_ARGS)),
+                          (k_joint<16, false, NTB><<<g, kBlock, 0, s>>>(JOINT_ARGS)),
+                          (k_joint<0, false, NTB><<<g, kBlock, 0, s>>>(JOINT_ARGS)));
+    }
+  })
 #undef JOINT_ARGS
   return hipGetLastError();
 }
 
-hipError_t launch_mean_sweep64(const MeanArgs64& a, hipStream_t s) {
-  const Layout& L = *a.L;
+template <typename T, typename A>
+hipError_t mean_dispatch(const Layout& L, const A& a, const T* Sx, bool nt, hipStream_t s) {
   const int g = nblocks(L.n);
-#define MEAN_ARGS \
-  L.n, L.sptr, L.rev, a.lamout, a.S, a.b, a.msg_in, a.msg_out, a.x, L.colour, a.colour
-  if (a.x) {
-    GABP_DISPATCH_WIDTH(L.max_width,
-                        (k_mean<double, 4, true><<<g, kBlock, 0, s>>>(MEAN_ARGS)),
-                        (k_mean<double, 8, true><<<g, kBlock, 0, s>>>(MEAN_ARGS)),
-                        (k_mean<double, 16, true><<<g, kBlock, 0, s>>>(MEAN_ARGS)),
-                        (k_mean<double, 0, true><<<g, kBlock, 0, s>>>(MEAN_ARGS)));
-  } else {
-    GABP_DISPATCH_WIDTH(L.max_width,
-                        (k_mean<double, 4, false><<<g, kBlock, 0, s>>>(MEAN_ARGS)),
-                        (k_mean<double, 8, false><<<g, kBlock, 0, s>>>(MEAN_ARGS)),
-                        (k_mean<double, 16, false><<<g, kBlock, 0, s>>>(MEAN_ARGS)),
-                        (k_mean<double, 0, false><<<g, kBlock, 0, s>>>(MEAN_ARGS)));
-  }
+#define MEAN_ARGS L.n, L.sptr, L.rev, a.lamout, Sx, a.b, a.msg_in, a.msg_out, a.x, L.colour, a.colour
+  GABP_DISPATCH_NT(nt, {
+    if (a.x) {
+      GABP_DISPATCH_WIDTH(L.max_width,
+                          (k_mean<T, 4, true, NTB><<<g, kBlock, 0, s>>>(MEAN_ARGS)),
+                          (k_mean<T, 8, true, NTB><<<g, kBlock, 0, s>>>(MEAN_ARGS)),
+                          (k_mean<T, 16, true, NTB><<<g, kBlock, 0, s>>>(MEAN_ARGS)),
+                          (k_mean<T, 0, true, NTB><<<g, kBlock, 0, s>>>(MEAN_ARGS)));
+    } else {
+      GABP_DISPATCH_WIDTH(L.max_width,
+                          (k_mean<T, 4, false, NTB><<<g, kBlock, 0, s>>>(MEAN_ARGS)),
+                          (k_mean<T, 8, false, NTB><<<g, kBlock, 0, s>>>(MEAN_ARGS)),
+                          (k_mean<T, 16, false, NTB><<<g, kBlock, 0, s>>>(MEAN_ARGS)),
+                          (k_mean<T, 0, false, NTB><<<g, kBlock, 0, s>>>(MEAN_ARGS)));
+    }
+  })
+#undef MEAN_ARGS
   return hipGetLastError();
 }
 
+hipError_t launch_mean_sweep64(const MeanArgs64& a, hipStream_t s) {
+  return mean_dispatch<double>(*a.L, a, a.S, a.L->stream_hints, s);
+}
+
 hipError_t launch_mean_sweep32(const MeanArgs32& a, hipStream_t s) {
-  const Layout& L = *a.L;
-  const int g = nblocks(L.n);
-  const float* S = a.invS;
-  (void)S;
-  if (a.x) {
-    GABP_DISPATCH_WIDTH(L.max_width,
-                        (k_mean<float, 4, true><<<g, kBlock, 0, s>>>(L.n, L.sptr, L.rev, a.lamout, a.invS, a.b, a.msg_in, a.msg_out, a.x, L.colour, a.colour)),
-                        (k_mean<float, 8, true><<<g, kBlock, 0, s>>>(L.n, L.sptr, L.rev, a.lamout, a.invS, a.b, a.msg_in, a.msg_out, a.x, L.colour, a.colour)),
-                        (k_mean<float, 16, true><<<g, kBlock, 0, s>>>(L.n, L.sptr, L.rev, a.lamout, a.invS, a.b, a.msg_in, a.msg_out, a.x, L.colour, a.colour)),
-                        (k_mean<float, 0, true><<<g, kBlock, 0, s>>>(L.n, L.sptr, L.rev, a.lamout, a.invS, a.b, a.msg_in, a.msg_out, a.x, L.colour, a.colour)));
-  } else {
-    GABP_DISPATCH_WIDTH(L.max_width,
-                        (k_mean<float, 4, false><<<g, kBlock, 0, s>>>(L.n, L.sptr, L.rev, a.lamout, a.invS, a.b, a.msg_in, a.msg_out, a.x, L.colour, a.colour)),
-                        (k_mean<float, 8, false><<<g, kBlock, 0, s>>>(L.n, L.sptr, L.rev, a.lamout, a.invS, a.b, a.msg_in, a.msg_out, a.x, L.colour, a.colour)),
-                        (k_mean<float, 16, false><<<g, kBlock, 0, s>>>(L.n, L.sptr, L.rev, a.lamout, a.invS, a.b, a.msg_in, a.msg_out, a.x, L.colour, a.colour)),
-                        (k_mean<float, 0, false><<<g, kBlock, 0, s>>>(L.n, L.sptr, L.rev, a.lamout, a.invS, a.b, a.msg_in, a.msg_out, a.x, L.colour, a.colour)));
-  }
-#undef MEAN_ARGS
-  return hipGetLastError();
+  return mean_dispatch<float>(*a.L, a, a.invS, a.L->stream_hints32, s);
 }
 
 hipError_t launch_lambda_sweep(const Layout* Lp, const double* coef, const double* lam_in,

@@ -274,6 +274,11 @@ int gabp_setup(gabp_ctx** out, int32_t n, int64_t nnz, const int32_t* rowptr,
   L.epad = epad;
   L.nslices = nslices;
   L.max_width = max_w;
+  // footprint of one FP64 joint sweep (44 B per slot, 16 B per row) and one FP32 mean
+  // sweep (16 B per slot, 4 B per row) against the 256 MiB last-level cache
+  constexpr double kLLC = 256.0 * 1024 * 1024;
+  L.stream_hints = 44.0 * epad + 16.0 * n > kLLC;
+  L.stream_hints32 = 16.0 * epad + 4.0 * n > 2.0 * kLLC;
   auto cleanup_fail = [&](int code) {
     gabp_destroy(c);
     return code;

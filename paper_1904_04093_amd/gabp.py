@@ -75,6 +75,7 @@ _SIGS = {
     "gabp_set_state": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P]),
     "gabp_layout_info": (ctypes.c_int, [_P, _PI32, _PI64, _PI64, _PI64]),
     "gabp_copy_probe": (ctypes.c_int, [_P, _P, _I64, _P]),
+    "gabp_autotune": (ctypes.c_int, [_P, _PI32, _PI32, _P]),
     "gabp_setup_batched": (ctypes.c_int, [ctypes.POINTER(_P), _I32, _P, _I32, _I64, _P, _P, _P,
                                           _I32, ctypes.POINTER(Options), _P]),
     "gabp_solve_batched": (ctypes.c_int, [_P, _P, _P, _D, _I32, _P, _P]),
@@ -290,6 +291,12 @@ class Solver:
         buf = ctypes.create_string_buffer(blob, len(blob))
         _check(self._lib.gabp_set_state(self._h, buf, len(blob), _stream()))
 
+    def autotune(self):
+        """Pick streaming hints and the check interval by measurement (see gabp_autotune)."""
+        ce, hints = ctypes.c_int32(0), ctypes.c_int32(0)
+        _check(self._lib.gabp_autotune(self._h, ctypes.byref(ce), ctypes.byref(hints), _stream()))
+        return {"check_every": ce.value, "stream_hints": hints.value}
+
     def layout_info(self):
         n, nnz, slots, pad = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         _check(self._lib.gabp_layout_info(self._h, ctypes.byref(n), ctypes.byref(nnz),
@@ -349,6 +356,11 @@ class BatchSolver:
         _check(lib.gabp_setup_batched(ctypes.byref(h), self.nsys, pso, self.n, int(rp[-1]),
                                       prp, pc, pv, self.nrhs, ctypes.byref(o), _stream()))
         self._h = h
+
+    def autotune(self):
+        ce, hints = ctypes.c_int32(0), ctypes.c_int32(0)
+        _check(self._lib.gabp_autotune(self._h, ctypes.byref(ce), ctypes.byref(hints), _stream()))
+        return {"check_every": ce.value, "stream_hints": hints.value}
 
     def solve(self, B, tol, max_sweeps, X=None):
         """B, X: CUDA float64 tensors of shape (nrhs, n). Returns X and per-pair infos."""

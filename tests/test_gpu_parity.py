@@ -402,3 +402,28 @@ def test_batched_graph_replays_match_eager(B):
     for X, X2, sw in res[1:]:
         assert np.array_equal(X, res[0][0]) and np.array_equal(X2, res[0][0])
         assert sw == res[0][2]
+
+
+@pytest.mark.parametrize("kw", [dict(mode="joint"), dict(mode="precomp", precision="f32_ir")])
+def test_autotune_keeps_results_correct(B, kw):
+    a, b, _ = CASES["field45"]
+    s = B.Solver.from_csr(a, tol_lambda=1e-10, **kw)
+    t = s.autotune()
+    assert t["check_every"] in (8, 16, 32, 64, 128, 256) and t["stream_hints"] in (0, 1)
+    assert s.autotune() == t                       # cached
+    x, info = s.solve(_cuda(b), 1e-11, 200000)
+    assert info.status == B.OK and info.sweeps % t["check_every"] == 0 or info.outer_iters > 0
+    xs = np.linalg.solve(W.csr_to_dense(a), b)
+    assert _rel_inf(x.cpu().numpy(), xs) <= 1e-8
+
+
+def test_stream_hint_variants_agree(B):
+    """Both streaming variants of the sweep kernels compute the same bits."""
+    a, b, _ = CASES["upwind32"]
+    outs = []
+    for trial in range(2):
+        s = B.Solver.from_csr(a, mode="joint")
+        if trial:
+            s.autotune()
+        outs.append(s.sweeps(_cuda(b), 37).cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])
