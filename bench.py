@@ -94,7 +94,14 @@ def main():
     ap.add_argument("--cpu-sweeps", type=int, default=12)
     ap.add_argument("--profile", action="store_true",
                     help="short run for the profiler: few launches of each kernel")
+    ap.add_argument("--suite", action="store_true",
+                    help="also measure the multigrid, batching and adjoint configurations")
+    ap.add_argument("--suite-only", action="store_true")
     args = ap.parse_args()
+    if args.suite_only:
+        import torch  # noqa: F401
+        print(json.dumps(suite(lambda *a: print(*a, file=sys.stderr, flush=True))), flush=True)
+        return
     if args.profile:
         args.steps, args.warmup, args.no_ttr, args.no_cpu = 5, 1, True, True
     if args.gpus != 1:
@@ -224,6 +231,8 @@ def main():
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(a, b, args.cpu_sweeps, log)
+    if args.suite:
+        out["suite"] = suite(log)
     print(json.dumps(out), flush=True)
 
 
@@ -246,7 +255,8 @@ def time_to_residual(n, log):
     for name, kw in (("fp64_joint", dict(mode="joint")),
                      ("fp64_precomp", dict(mode="precomp", tol_lambda=1e-12)),
                      ("fp32_ir", dict(mode="precomp", precision="f32_ir", tol_lambda=1e-7))):
-        s = gabp.Solver.from_csr(a, check_every=64, **kw)
+        s = gabp.Solver.from_csr(a, **kw)
+        tuned = s.autotune()             # hints and check interval by measurement
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         x, info = s.solve(bt, 1e-8, 5_000_000)
@@ -254,7 +264,7 @@ def time_to_residual(n, log):
         dt = time.perf_counter() - t0
         entry = {"seconds": dt, "sweeps": info.sweeps, "lambda_sweeps": info.lambda_sweeps,
                  "outer_iters": info.outer_iters, "rel_res2": info.rel_res2,
-                 "status": info.status}
+                 "status": info.status, "autotuned": tuned}
         if xs is not None:
             xe = x.cpu().numpy()
             entry["x_rel_err_vs_" + "sparse_lu"] = float(np.linalg.norm(xe - xs) / np.linalg.norm(xs))
@@ -285,6 +295,198 @@ def cpu_baseline(a, b, sweeps, log):
             "sample": f"{sweeps} FP64 joint flood sweeps of the full {int(np.sqrt(a.n))}^2 grid "
                       f"(numpy, single-threaded; graph build {t_build:.1f}s excluded)",
             "host_cpus": os.cpu_count()}
+
+
+def suite(log):
+    """Measurements of the other configurations (sizes stated in each entry)."""
+    import torch
+    from paper_1904_04093_amd import gabp
+    from paper_1904_04093_amd import workloads as W
+    res = {}
+
+    # small plain case: 32 x 32 upwind operator, FP64 joint GaBP to rel.res 1e-10
+    a, b = W.small_upwind(32)
+    s = gabp.Solver.from_csr(a, mode="joint")
+    s.autotune()
+    bt = torch.as_tensor(b).cuda()
+    s.solve(bt, 1e-10, 10000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, info = s.solve(bt, 1e-10, 10000)
+    torch.cuda.synchronize()
+    xs = np.linalg.solve(W.csr_to_dense(a), b)
+    res["small_32x32_fp64"] = {"seconds": time.perf_counter() - t0, "sweeps": info.sweeps,
+                               "rel_res2": info.rel_res2,
+                               "x_rel_err_vs_dense": float(np.abs(x.cpu().numpy() - xs).max() / np.abs(xs).max())}
+    log(f"[suite] small: {res['small_32x32_fp64']}")
+    res["batch"] = suite_batch(log)
+    res["multigrid"] = suite_mg(log)
+    res["adjoint"] = suite_adjoint(log)
+    return res
+
+
+def suite_batch(log):
+    import torch
+    from paper_1904_04093_amd import gabp
+    from paper_1904_04093_amd import workloads as W
+    out = {}
+    # full shape: 512 systems, sides 48..384, 4 right-hand sides: batched FP32 sweep rate
+    t0 = time.perf_counter()
+    fam = W.batch_family(nsys=512, nrhs=4)
+    systems = [x for x, _ in fam]
+    rhs = np.stack([np.concatenate([bb[q] for _, bb in fam]) for q in range(4)])
+    del fam
+    gen = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    bs = gabp.BatchSolver(systems, nrhs=4, mode="precomp", precision="f32_ir", tol_lambda=1e-7)
+    setup = time.perf_counter() - t0
+    edges = sum(int(x.nnz - x.n) for x in systems)
+    Bt = torch.as_tensor(rhs).cuda()
+    # fixed work: 2 x 64 sweeps inside the refinement loop, tolerance unreachable
+    bs.solve(Bt, 1e-30, 64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    X, infos = bs.solve(Bt, 1e-30, 256)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    sw = infos[0].sweeps
+    out["full_shape"] = {"systems": 512, "sides": "48..384", "nrhs": 4,
+                         "unknowns": int(sum(x.n for x in systems)), "directed_edges": edges,
+                         "sweeps": sw, "seconds": dt,
+                         "edge_rhs_updates_per_s": edges * 4 * sw / dt,
+                         "generate_s": gen, "setup_s": setup}
+    log(f"[suite] batch full shape: {out['full_shape']}")
+    del bs, X, Bt
+    # reduced batch to rel.res 1e-8: 64 systems, sides 48..96, 4 rhs; batched vs loop
+    fam = W.batch_family(nsys=64, nrhs=4, side_lo=48, side_hi=96, seed=3)
+    systems = [x for x, _ in fam]
+    rhs_l = [bb for _, bb in fam]
+    rhs = np.stack([np.concatenate([r[q] for r in rhs_l]) for q in range(4)])
+    Bt = torch.as_tensor(rhs).cuda()
+    bs = gabp.BatchSolver(systems, nrhs=4, mode="precomp", precision="f32_ir", tol_lambda=1e-7)
+    bs.autotune()
+    bs.solve(Bt, 1e-8, 2_000_000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    X, infos = bs.solve(Bt, 1e-8, 2_000_000)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    ok = all(i.status == 0 for i in infos)
+    singles = [gabp.Solver.from_csr(x, mode="precomp", precision="f32_ir", tol_lambda=1e-7)
+               for x in systems]
+    for sgl in singles:
+        sgl.autotune()
+    rb = [[torch.as_tensor(r[q]).cuda() for q in range(4)] for r in rhs_l]
+    for sgl, r in zip(singles, rb):
+        sgl.solve(r[0], 1e-8, 2_000_000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    worst = 0.0
+    for sgl, r in zip(singles, rb):
+        for q in range(4):
+            _, inf = sgl.solve(r[q], 1e-8, 2_000_000)
+            worst = max(worst, inf.rel_res2)
+    torch.cuda.synchronize()
+    t_loop = time.perf_counter() - t0
+    out["reduced_to_1e-8"] = {"systems": 64, "sides": "48..96", "nrhs": 4,
+                              "batched_seconds": t_batch, "loop_of_single_solves_seconds": t_loop,
+                              "speedup": t_loop / t_batch, "all_converged": ok,
+                              "max_sweeps": max(i.sweeps for i in infos),
+                              "min_sweeps": min(i.sweeps for i in infos),
+                              "loop_worst_rel_res2": worst}
+    log(f"[suite] batch reduced: {out['reduced_to_1e-8']}")
+    return out
+
+
+def suite_mg(log, J=12):
+    import torch
+    from paper_1904_04093_amd import gabp
+    from paper_1904_04093_amd import workloads as W
+    out = {}
+    for name, kw in (("anisotropic", dict(kx=1.0, ky=0.01, peclet=4.0)),
+                     ("isotropic", dict(kx=1.0, ky=1.0, peclet=1.0))):
+        t0 = time.perf_counter()
+        levels = W.mg_hierarchy(J, coarsest=3, **kw)
+        sides = [int(round(np.sqrt(x.n))) for x in levels]
+        gen = time.perf_counter() - t0
+        b = W.rng(4, 1).uniform(-1, 1, levels[0].n)
+        bt = torch.as_tensor(b).cuda()
+        entry = {"grid": f"{sides[0]}x{sides[0]}", "levels": len(levels), "generate_s": gen}
+        for sm_name, smoother, kwg in (
+                ("rbgs_2_2", "rbgs", {}),
+                ("redblack_gabp_f32_warm_lambda_2_2", "gabp",
+                 dict(mode="precomp", precision="f32_ir", schedule="redblack", tol_lambda=1e-7)),
+                ("redblack_gabp_f64_joint_2_2", "gabp", dict(mode="joint", schedule="redblack")),
+                ("flood_gabp_f32_warm_lambda_2_2", "gabp",
+                 dict(mode="precomp", precision="f32_ir", tol_lambda=1e-7))):
+            t0 = time.perf_counter()
+            solvers = [gabp.Solver.from_csr(x, colour=W.grid_colouring(sd), **kwg)
+                       for x, sd in zip(levels, sides)]
+            mg = gabp.Multigrid(solvers, sides, smoother=smoother, nu1=2, nu2=2)
+            x = torch.zeros(levels[0].n, dtype=torch.float64, device="cuda")
+            mg.vcycle(bt, x)       # first cycle: Lt phases and recordings
+            torch.cuda.synchronize()
+            setup = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            x, info = mg.solve(bt, 1e-8, 60)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            entry[sm_name] = {"status": info["status"], "cycles": info["cycles"],
+                              "rel_res2": info["rel_res2"], "seconds": dt,
+                              "ms_per_cycle": 1e3 * dt / max(info["cycles"], 1),
+                              "setup_s": setup}
+            log(f"[suite] mg {name} {sm_name}: {entry[sm_name]}")
+            del mg, solvers
+        out[name] = entry
+    return out
+
+
+def suite_adjoint(log, n_full=1024, n_small=128, batch=8):
+    import torch
+    from paper_1904_04093_amd import autograd as AG
+    from paper_1904_04093_amd import gabp
+    from paper_1904_04093_amd import workloads as W
+    out = {}
+    for n in (n_small, n_full):
+        field = AG.ThetaField(n)
+        solver = gabp.Solver.from_csr(field.pattern, mode="precomp", precision="f32_ir",
+                                      tol_lambda=1e-7)
+        solver.autotune()
+        b = torch.as_tensor(W.rng(5, 101).uniform(-1, 1, n * n)).cuda()
+        xt = torch.as_tensor(W.rng(5, 100).uniform(-1, 1, n * n)).cuda()
+        if n == n_full:
+            # per-sweep rate of forward and adjoint FP32 sweeps on the full grid
+            th = torch.as_tensor(W.theta_problem(n, 0)).cuda()
+            solver.update_values(field.values(th).detach().contiguous())
+            solver.precompute_lambda()
+            solver.precompute_lambda(transposed=True)
+            xx = torch.zeros_like(b)
+            solver.sweeps(b, 2, x=xx)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            solver.sweeps(b, 401, reset=False, x=xx)
+            solver.sweeps(b, 401, reset=False, transposed=True, x=xx)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / 802
+            e = field.pattern.nnz - field.pattern.n
+            out[f"full_{n}x{n}"] = {"fp32_sweep_us": dt * 1e6, "edge_updates_per_s": e / dt,
+                                    "note": "gradient to 1e-8 at this size needs ~1.4M sweeps per solve"}
+            log(f"[suite] adjoint full: {out[f'full_{n}x{n}']}")
+            continue
+        t0 = time.perf_counter()
+        losses = []
+        for t in range(batch):
+            th = torch.tensor(W.theta_problem(n, t), device="cuda", requires_grad=True)
+            x = AG.gabp_solve(field.values(th), b, solver, tol=1e-8)
+            loss = 0.5 * ((x - xt) ** 2).sum()
+            loss.backward()
+            losses.append(float(loss))
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[f"gradients_{n}x{n}_batch{batch}"] = {"seconds": dt, "per_theta_s": dt / batch,
+                                                 "loss_mean": float(np.mean(losses))}
+        log(f"[suite] adjoint {n}: {out[f'gradients_{n}x{n}_batch{batch}']}")
+    return out
 
 
 if __name__ == "__main__":
