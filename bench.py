@@ -403,10 +403,11 @@ def suite_mg(log, J=12):
     from paper_1904_04093_amd import gabp
     from paper_1904_04093_amd import workloads as W
     out = {}
-    for name, kw in (("anisotropic", dict(kx=1.0, ky=0.01, peclet=4.0)),
-                     ("isotropic", dict(kx=1.0, ky=1.0, peclet=1.0))):
+    for name, JJ, kw in (("anisotropic_peclet4", J, dict(kx=1.0, ky=0.01, peclet=4.0)),
+                         ("poisson", J, dict(kx=1.0, ky=1.0, peclet=0.0)),
+                         ("anisotropic_peclet4_63x63", 6, dict(kx=1.0, ky=0.01, peclet=4.0))):
         t0 = time.perf_counter()
-        levels = W.mg_hierarchy(J, coarsest=3, **kw)
+        levels = W.mg_hierarchy(JJ, coarsest=3, **kw)
         sides = [int(round(np.sqrt(x.n))) for x in levels]
         gen = time.perf_counter() - t0
         b = W.rng(4, 1).uniform(-1, 1, levels[0].n)
