@@ -259,10 +259,11 @@ def time_to_residual(n, log):
         tuned = s.autotune()             # hints and check interval by measurement
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        lsw = s.precompute_lambda() if kw["mode"] == "precomp" else 0   # timed: Lt phase
         x, info = s.solve(bt, 1e-8, 5_000_000)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        entry = {"seconds": dt, "sweeps": info.sweeps, "lambda_sweeps": info.lambda_sweeps,
+        entry = {"seconds": dt, "sweeps": info.sweeps, "lambda_sweeps": lsw,
                  "outer_iters": info.outer_iters, "rel_res2": info.rel_res2,
                  "status": info.status, "autotuned": tuned}
         if xs is not None:

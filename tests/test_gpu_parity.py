@@ -427,3 +427,32 @@ def test_stream_hint_variants_agree(B):
             s.autotune()
         outs.append(s.sweeps(_cuda(b), 37).cpu().numpy())
     assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("density,kw", [(0.3, dict(mode="joint")),
+                                        (0.3, dict(mode="precomp", tol_lambda=0.0,
+                                                   max_lambda_sweeps=30)),
+                                        (0.12, dict(mode="joint"))])
+def test_wide_rows_two_pass_kernels(B, density, kw):
+    """Rows with more than 16 (and more than 8) neighbours take the wider register or the
+    two-pass kernel variants; they must agree with the oracle like the narrow ones."""
+    r = W.rng(310, int(density * 100))
+    a = W.random_walk_summable(150, density, r)
+    widths = np.diff(a.rowptr)
+    assert widths.max() > 9
+    b = r.uniform(-1, 1, a.n)
+    s = B.Solver.from_csr(a, **kw)
+    g = G.Graph.from_csr(a)
+    bt = _cuda(b)
+    lam = G.lambda_phase(g, 0.0, 30) if kw["mode"] == "precomp" else None
+    for sweeps in (1, 4, 25):
+        x = s.sweeps(bt, sweeps).cpu().numpy()
+        if lam is None:
+            xo, _, _ = G.run(g, b, sweeps)
+        else:
+            m = np.zeros(g.E)
+            for _ in range(sweeps):
+                xo, m = G.msweep(g, b, lam[0], lam[1], m)
+        assert _rel_inf(x, xo) <= TOL, sweeps
+    r_, (n2, _, _) = s.residual(bt, torch.as_tensor(x).cuda())
+    assert _rel_inf(r_.cpu().numpy(), g.residual(b, x)) <= 1e-13

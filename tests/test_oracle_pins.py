@@ -364,3 +364,52 @@ def test_redblack_fixed_point_is_dense_solution(precomp):
     for _ in range(400):
         x, Lt, m = G.sweep_coloured(g, b, Lt, m, colour, lambda_fixed=lam)
     assert _relerr(x, np.linalg.solve(_dense(a), b)) < 1e-12
+
+
+# --------------------------------------------------------------------------------------
+# The pins catch plausible mistakes: each mutation of the sweep below breaks some pin
+# (planted in a copy of the oracle's sweep on the CPU; the oracle itself is untouched)
+# --------------------------------------------------------------------------------------
+
+def _mutated_sweep(kind):
+    def sweep(g, b, Lt, m, lambda_fixed=False):
+        S, M = G.node_totals(g, b, Lt, m)
+        if kind == "aji_in_sigma":          # transposed operand in the precision sum
+            S = g.diag + np.bincount(g.dst, weights=Lt * g.a_ij, minlength=g.n)
+        x = M / S
+        back_L = G._gather(Lt, g.rev)
+        back_m = G._gather(m, g.rev)
+        if kind == "no_cavity":             # dropped term: reverse message not excluded
+            back_L = 0 * back_L
+            back_m = 0 * back_m
+        a = g.a_ji if kind == "aji_numerator" else g.a_ij
+        Lt_new = -a / (S[g.src] - back_L * g.a_ij)
+        if kind == "sign":                  # wrong sign
+            Lt_new = -Lt_new
+        m_new = Lt_new * (M[g.src] - back_m)
+        if kind == "receiver_total":        # wrong index: receiver's totals instead of sender's
+            m_new = Lt_new * (M[g.dst] - back_m)
+        return x, Lt_new, m_new, S, M
+    return sweep
+
+
+@pytest.mark.parametrize("kind", ["aji_in_sigma", "no_cavity", "aji_numerator", "sign",
+                                  "receiver_total"])
+def test_pins_detect_planted_mistakes(kind, monkeypatch):
+    monkeypatch.setattr(G, "sweep", _mutated_sweep(kind))
+    failures = 0
+    # pin 1: tree exactness (nonsymmetric tridiagonal)
+    a = W.random_tridiagonal(12, W.rng(101, 0))
+    b = W.rng(102, 0).uniform(-1, 1, 12)
+    with np.errstate(all="ignore"):
+        x, _, _ = G.run(_graph(a), b, 12)
+    failures += not (_relerr(x, np.linalg.solve(_dense(a), b)) < 1e-13)
+    # pin 2: LFA two-sweep stencil
+    n = 16
+    lap = W.laplacian_5pt(n)
+    bb = np.zeros(lap.n)
+    bb[8 * n + 8] = 1.0
+    with np.errstate(all="ignore"):
+        x2, _, _ = G.run(_graph(lap), bb, 2)
+    failures += not (abs(x2[8 * n + 8] - 1 / 3) < 1e-15 and abs(x2[8 * n + 9] - 1 / 12) < 1e-15)
+    assert failures >= 1, f"planted mistake {kind} passed every pin"
