@@ -37,20 +37,20 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
 
 
-def sweep_bytes_joint64(slots, n):
-    # per slot: Lt_in, m_in, coefficient (8 B each), reverse index (4 B), Lt_out, m_out (8 B each)
-    # per row: diagonal and b (8 B each)
-    return 44 * slots + 16 * n
+def sweep_bytes_joint64(slots, n, rb=4):
+    # per slot: Lt_in, m_in, coefficient (8 B each), reverse index (rb B), Lt_out, m_out
+    # (8 B each); per row: diagonal and b (8 B each)
+    return (40 + rb) * slots + 16 * n
 
 
-def sweep_bytes_mean32(slots, n):
-    # per slot: m_in, Lt* (FP32), reverse index, m_out (4 B each); per row: FP32 rhs
-    return 16 * slots + 4 * n
+def sweep_bytes_mean32(slots, n, rb=4):
+    # per slot: m_in, Lt* (FP32), reverse index (rb B), m_out; per row: FP32 rhs
+    return (12 + rb) * slots + 4 * n
 
 
-def sweep_bytes_mean64(slots, n):
-    # per slot: m_in, Lt* (8 B), reverse index (4 B), m_out (8 B); per row: b (8 B)
-    return 28 * slots + 8 * n
+def sweep_bytes_mean64(slots, n, rb=4):
+    # per slot: m_in, Lt* (8 B), reverse index (rb B), m_out (8 B); per row: b (8 B)
+    return (24 + rb) * slots + 8 * n
 
 
 def measured_traffic(kernel):
@@ -159,7 +159,8 @@ def main():
     sweeps_only = lambda k: sj.sweeps(bt, k, reset=False, x=x)
     sweeps_only(20)
     t_sw = _events_time(sweeps_only, NS) / NS
-    ab = sweep_bytes_joint64(lay["slots"], a.n)
+    rb = lay["rev_bytes"]
+    ab = sweep_bytes_joint64(lay["slots"], a.n, rb)
     achieved = ab / t_sw / 1e9
     log(f"[bench] joint sweep {t_sw*1e6:.1f} us, {achieved:.0f} GB/s algorithmic")
 
@@ -207,17 +208,18 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic("k_joint<4, false>"),
                      "frac_of_copy": achieved / copy_gbs,
-                     "algorithmic_bytes_per_launch": ab, "launch_us": t_sw * 1e6},
+                     "algorithmic_bytes_per_launch": ab, "launch_us": t_sw * 1e6,
+                     "reverse_index_bytes": rb},
         "wall_s_timed": t_wall,
         "kernels": {
             "joint_f64_sweep_us": t_sw * 1e6,
             "joint_f64_edge_updates_per_s": edges / t_sw,
             "mean_f64_sweep_us": t_m64 * 1e6,
             "mean_f64_edge_updates_per_s": edges / t_m64,
-            "mean_f64_GBs": sweep_bytes_mean64(lay["slots"], a.n) / t_m64 / 1e9,
+            "mean_f64_GBs": sweep_bytes_mean64(lay["slots"], a.n, rb) / t_m64 / 1e9,
             "mean_f32_sweep_us": t_m32 * 1e6,
             "mean_f32_edge_updates_per_s": edges / t_m32,
-            "mean_f32_GBs": sweep_bytes_mean32(lay["slots"], a.n) / t_m32 / 1e9,
+            "mean_f32_GBs": sweep_bytes_mean32(lay["slots"], a.n, rb) / t_m32 / 1e9,
             "residual_us": t_res * 1e6,
             "residual_GBs": (12 * lay["slots"] + 32 * a.n) / t_res / 1e9,
             "copy_probe_GBs": copy_gbs,

@@ -178,9 +178,11 @@ int gabp_get_state(gabp_ctx* ctx, void* dst, size_t* bytes, hipStream_t stream);
 int gabp_set_state(gabp_ctx* ctx, const void* src, size_t bytes, hipStream_t stream);
 
 /* Sizes of the internal layout (host outputs, any may be NULL): number of rows, stored
- * nonzeros, directed message slots (2 x off-diagonal pairs), padded slot count. */
+ * nonzeros, directed message slots (2 x off-diagonal pairs), padded slot count, and the
+ * bytes per slot of the reverse index the single-system sweeps read (2 when every slot's
+ * reverse lies within +-32767 positions, as for grid matrices, else 4). */
 int gabp_layout_info(const gabp_ctx* ctx, int32_t* n, int64_t* nnz, int64_t* slots,
-                     int64_t* padded_slots);
+                     int64_t* padded_slots, int32_t* rev_bytes);
 
 /* Autotuner. Times the context's own sweep kernel (for its mode, precision and batch
  * shape) with and without non-temporal hints on the per-slot streams, keeps the faster,

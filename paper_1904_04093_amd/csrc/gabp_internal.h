@@ -56,6 +56,8 @@ struct Layout {
   // device
   int32_t* sptr = nullptr;   // [nslices+1]
   int32_t* rev = nullptr;    // [epad]
+  int16_t* rev16 = nullptr;  // [epad] rev[p] - p when every real slot's reverse lies within
+                             // int16 range (grid matrices); padding slots hold 0 (self)
   int32_t* col = nullptr;    // [epad]
   double* val = nullptr;     // [epad] A_ji at slot (j,i)
   double* aT = nullptr;      // [epad] A_ij at slot (j,i)

@@ -56,9 +56,19 @@ __device__ __forceinline__ double wave_max(double v) {
 // KMAX > 0: row held in registers; KMAX == 0: two passes over memory for wide rows.
 // colour >= 0: only rows of that colour work, in place (red-black schedule).
 // ---------------------------------------------------------------------------------------
-template <int KMAX, bool WX, bool NT>
+// Reverse slot of p: rev[p] (int32) or p + rev16[p] (int16 delta; padding slots point at
+// themselves and write zeros there).
+template <bool NT, bool R16>
+__device__ __forceinline__ int rev_of(const int32_t* __restrict__ rev,
+                                      const int16_t* __restrict__ rev16, int p) {
+  if constexpr (R16) return p + static_cast<int>(ld_s<NT>(rev16 + p));
+  else return ld_s<NT>(rev + p);
+}
+
+template <int KMAX, bool WX, bool NT, bool R16>
 __global__ __launch_bounds__(kBlock) void k_joint(
     int n, const int32_t* __restrict__ sptr, const int32_t* __restrict__ rev,
+    const int16_t* __restrict__ rev16,
     const double* __restrict__ coef, const double* __restrict__ diag,
     const double* __restrict__ b, const double* lam_in, const double* msg_in,
     double* lam_out, double* msg_out, double* __restrict__ x,
@@ -80,7 +90,7 @@ __global__ __launch_bounds__(kBlock) void k_joint(
         l[k] = ld_s<NT>(lam_in + p);
         m[k] = ld_s<NT>(msg_in + p);
         a[k] = ld_s<NT>(coef + p);
-        r[k] = ld_s<NT>(rev + p);
+        r[k] = rev_of<NT, R16>(rev, rev16, p);
       }
     }
 #pragma unroll
@@ -109,7 +119,7 @@ __global__ __launch_bounds__(kBlock) void k_joint(
     for (int k = 0; k < w; ++k) {
       const int p = p0 + 64 * k;
       const double l = lam_in[p], a = coef[p], m = msg_in[p];
-      const int r = rev[p];
+      const int r = rev_of<false, R16>(rev, rev16, p);
       const double L = -a / (S - l * a);
       lam_out[r] = L;
       msg_out[r] = L * (M - m);
@@ -134,9 +144,10 @@ struct ReadOff<float> {
   }
 };
 
-template <typename T, int KMAX, bool WX, bool NT>
+template <typename T, int KMAX, bool WX, bool NT, bool R16>
 __global__ __launch_bounds__(kBlock) void k_mean(
     int n, const int32_t* __restrict__ sptr, const int32_t* __restrict__ rev,
+    const int16_t* __restrict__ rev16,
     const T* __restrict__ lamout, const T* __restrict__ Sx, const T* __restrict__ b,
     const T* msg_in, T* msg_out, T* __restrict__ x, const uint8_t* __restrict__ colour,
     int c) {
@@ -155,7 +166,7 @@ __global__ __launch_bounds__(kBlock) void k_mean(
         const int p = p0 + 64 * k;
         m[k] = ld_s<NT>(msg_in + p);
         lo[k] = ld_s<NT>(lamout + p);
-        r[k] = ld_s<NT>(rev + p);
+        r[k] = rev_of<NT, R16>(rev, rev16, p);
       }
     }
 #pragma unroll
@@ -170,7 +181,7 @@ __global__ __launch_bounds__(kBlock) void k_mean(
     if (WX) x[j] = ReadOff<T>::f(M, Sx, j);
     for (int k = 0; k < w; ++k) {
       const int p = p0 + 64 * k;
-      msg_out[rev[p]] = lamout[p] * (M - msg_in[p]);
+      msg_out[rev_of<false, R16>(rev, rev16, p)] = lamout[p] * (M - msg_in[p]);
     }
   }
 }
@@ -595,28 +606,31 @@ int grid_for(int64_t n) {
 #define GABP_DISPATCH_NT(NTV, ...)                   \
   if (NTV) { constexpr bool NTB = true; __VA_ARGS__; } \
   else { constexpr bool NTB = false; __VA_ARGS__; }
+#define GABP_DISPATCH_R16(RV, ...)                     \
+  if (RV) { constexpr bool R16B = true; __VA_ARGS__; } \
+  else { constexpr bool R16B = false; __VA_ARGS__; }
 
 hipError_t launch_joint_sweep(const SweepArgs& a, hipStream_t s) {
   const Layout& L = *a.L;
   const int g = nblocks(L.n);
 #define JOINT_ARGS                                                                      \
-  L.n, L.sptr, L.rev, a.coef, L.diag, a.b, a.lam_in, a.msg_in, a.lam_out, a.msg_out, a.x, \
-      L.colour, a.colour
-  GABP_DISPATCH_NT(L.stream_hints, {
+  L.n, L.sptr, L.rev, L.rev16, a.coef, L.diag, a.b, a.lam_in, a.msg_in, a.lam_out,       \
+      a.msg_out, a.x, L.colour, a.colour
+  GABP_DISPATCH_NT(L.stream_hints, GABP_DISPATCH_R16(L.rev16 != nullptr, {
     if (a.x) {
       GABP_DISPATCH_WIDTH(L.max_width,
-                          (k_joint<4, true, NTB><<<g, kBlock, 0, s>>>(JOINT_ARGS)),
-                          (k_joint<8, true, NTB><<<g, kBlock, 0, s>>>(JOINT_ARGS)),
-                          (k_joint<16, true, NTB><<<g, kBlock, 0, s>>>(JOINT_ARGS)),
-                          (k_joint<0, true, NTB><<<g, kBlock, 0, s>>>(JOINT_ARGS)));
+                          (k_joint<4, true, NTB, R16B><<<g, kBlock, 0, s>>>(JOINT_ARGS)),
+                          (k_joint<8, true, NTB, R16B><<<g, kBlock, 0, s>>>(JOINT_ARGS)),
+                          (k_joint<16, true, NTB, R16B><<<g, kBlock, 0, s>>>(JOINT_ARGS)),
+                          (k_joint<0, true, NTB, R16B><<<g, kBlock, 0, s>>>(JOINT_ARGS)));
     } else {
       GABP_DISPATCH_WIDTH(L.max_width,
-                          (k_joint<4, false, NTB><<<g, kBlock, 0, s>>>(JOINT_ARGS)),
-                          (k_joint<8, false, NTB><<<g, kBlock, 0, s>>>(JOINT_ARGS)),
-                          (k_joint<16, false, NTB><<<g, kBlock, 0, s>>>(JOINT_ARGS)),
-                          (k_joint<0, false, NTB><<<g, kBlock, 0, s>>>(JOINT_ARGS)));
+                          (k_joint<4, false, NTB, R16B><<<g, kBlock, 0, s>>>(JOINT_ARGS)),
+                          (k_joint<8, false, NTB, R16B><<<g, kBlock, 0, s>>>(JOINT_ARGS)),
+                          (k_joint<16, false, NTB, R16B><<<g, kBlock, 0, s>>>(JOINT_ARGS)),
+                          (k_joint<0, false, NTB, R16B><<<g, kBlock, 0, s>>>(JOINT_ARGS)));
     }
-  })
+  }))
 #undef JOINT_ARGS
   return hipGetLastError();
 }
@@ -624,22 +638,23 @@ hipError_t launch_joint_sweep(const SweepArgs& a, hipStream_t s) {
 template <typename T, typename A>
 hipError_t mean_dispatch(const Layout& L, const A& a, const T* Sx, bool nt, hipStream_t s) {
   const int g = nblocks(L.n);
-#define MEAN_ARGS L.n, L.sptr, L.rev, a.lamout, Sx, a.b, a.msg_in, a.msg_out, a.x, L.colour, a.colour
-  GABP_DISPATCH_NT(nt, {
+#define MEAN_ARGS \
+  L.n, L.sptr, L.rev, L.rev16, a.lamout, Sx, a.b, a.msg_in, a.msg_out, a.x, L.colour, a.colour
+  GABP_DISPATCH_NT(nt, GABP_DISPATCH_R16(L.rev16 != nullptr, {
     if (a.x) {
       GABP_DISPATCH_WIDTH(L.max_width,
-                          (k_mean<T, 4, true, NTB><<<g, kBlock, 0, s>>>(MEAN_ARGS)),
-                          (k_mean<T, 8, true, NTB><<<g, kBlock, 0, s>>>(MEAN_ARGS)),
-                          (k_mean<T, 16, true, NTB><<<g, kBlock, 0, s>>>(MEAN_ARGS)),
-                          (k_mean<T, 0, true, NTB><<<g, kBlock, 0, s>>>(MEAN_ARGS)));
+                          (k_mean<T, 4, true, NTB, R16B><<<g, kBlock, 0, s>>>(MEAN_ARGS)),
+                          (k_mean<T, 8, true, NTB, R16B><<<g, kBlock, 0, s>>>(MEAN_ARGS)),
+                          (k_mean<T, 16, true, NTB, R16B><<<g, kBlock, 0, s>>>(MEAN_ARGS)),
+                          (k_mean<T, 0, true, NTB, R16B><<<g, kBlock, 0, s>>>(MEAN_ARGS)));
     } else {
       GABP_DISPATCH_WIDTH(L.max_width,
-                          (k_mean<T, 4, false, NTB><<<g, kBlock, 0, s>>>(MEAN_ARGS)),
-                          (k_mean<T, 8, false, NTB><<<g, kBlock, 0, s>>>(MEAN_ARGS)),
-                          (k_mean<T, 16, false, NTB><<<g, kBlock, 0, s>>>(MEAN_ARGS)),
-                          (k_mean<T, 0, false, NTB><<<g, kBlock, 0, s>>>(MEAN_ARGS)));
+                          (k_mean<T, 4, false, NTB, R16B><<<g, kBlock, 0, s>>>(MEAN_ARGS)),
+                          (k_mean<T, 8, false, NTB, R16B><<<g, kBlock, 0, s>>>(MEAN_ARGS)),
+                          (k_mean<T, 16, false, NTB, R16B><<<g, kBlock, 0, s>>>(MEAN_ARGS)),
+                          (k_mean<T, 0, false, NTB, R16B><<<g, kBlock, 0, s>>>(MEAN_ARGS)));
     }
-  })
+  }))
 #undef MEAN_ARGS
   return hipGetLastError();
 }

@@ -257,6 +257,21 @@ int gabp_setup(gabp_ctx** out, int32_t n, int64_t nnz, const int32_t* rowptr,
                                        std::to_string(j));
     }
   }
+  // int16 reverse deltas when every real slot's reverse is within +-32767 positions
+  std::vector<int16_t> h_rev16;
+  {
+    bool fits = true;
+    for (int64_t p = 0; p < epad && fits; ++p)
+      if (h_rev[p] != epad) {
+        const int64_t d = static_cast<int64_t>(h_rev[p]) - p;
+        fits = d >= -32767 && d <= 32767;
+      }
+    if (fits) {
+      h_rev16.resize(epad);
+      for (int64_t p = 0; p < epad; ++p)
+        h_rev16[p] = h_rev[p] == epad ? int16_t(0) : static_cast<int16_t>(h_rev[p] - p);
+    }
+  }
   std::vector<int32_t> h_sptr(nslices + 1);
   for (int32_t s = 0; s <= nslices; ++s) h_sptr[s] = static_cast<int32_t>(sptr64[s]);
   std::vector<int32_t> h_row(nnz), h_ccol(col, col + nnz);
@@ -289,6 +304,7 @@ int gabp_setup(gabp_ctx** out, int32_t n, int64_t nnz, const int32_t* rowptr,
   if ((st = alloc(&(dst), cnt)) != GABP_OK) return cleanup_fail(st)
   UP(L.sptr, h_sptr);
   UP(L.rev, h_rev);
+  if (!h_rev16.empty()) UP(L.rev16, h_rev16);
   UP(L.col, h_col);
   UP(L.val, h_val);
   UP(L.aT, h_aT);
@@ -351,7 +367,7 @@ void gabp_destroy(gabp_ctx* c) {
     if (p) (void)hipFree(p);
   };
   Layout& L = c->L;
-  F(L.sptr); F(L.rev); F(L.col); F(L.val); F(L.aT); F(L.diag); F(L.val_src); F(L.aT_src);
+  F(L.sptr); F(L.rev); F(L.rev16); F(L.col); F(L.val); F(L.aT); F(L.diag); F(L.val_src); F(L.aT_src);
   F(L.diag_src); F(L.csr_row); F(L.csr_col); F(L.colour);
   for (int q = 0; q < 2; ++q) {
     F(c->lam[q]); F(c->msg[q]); F(c->msg32[q]);
@@ -368,12 +384,13 @@ void gabp_destroy(gabp_ctx* c) {
 }
 
 int gabp_layout_info(const gabp_ctx* c, int32_t* n, int64_t* nnz, int64_t* slots,
-                     int64_t* padded) {
+                     int64_t* padded, int32_t* rev_bytes) {
   if (!c) return fail(GABP_EINVAL, "NULL context");
   if (n) *n = c->L.n;
   if (nnz) *nnz = c->L.nnz;
   if (slots) *slots = c->L.slots;
   if (padded) *padded = c->L.epad;
+  if (rev_bytes) *rev_bytes = c->L.rev16 ? 2 : 4;
   return GABP_OK;
 }
 

@@ -73,7 +73,7 @@ _SIGS = {
     "gabp_adjoint_scatter": (ctypes.c_int, [_P, _P, _P, _P, _I32, _P, _P, _P, _P, _P]),
     "gabp_get_state": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_size_t), _P]),
     "gabp_set_state": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P]),
-    "gabp_layout_info": (ctypes.c_int, [_P, _PI32, _PI64, _PI64, _PI64]),
+    "gabp_layout_info": (ctypes.c_int, [_P, _PI32, _PI64, _PI64, _PI64, _PI32]),
     "gabp_copy_probe": (ctypes.c_int, [_P, _P, _I64, _P]),
     "gabp_autotune": (ctypes.c_int, [_P, _PI32, _PI32, _P]),
     "gabp_setup_batched": (ctypes.c_int, [ctypes.POINTER(_P), _I32, _P, _I32, _I64, _P, _P, _P,
@@ -299,9 +299,11 @@ class Solver:
 
     def layout_info(self):
         n, nnz, slots, pad = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        rb = ctypes.c_int32()
         _check(self._lib.gabp_layout_info(self._h, ctypes.byref(n), ctypes.byref(nnz),
-                                          ctypes.byref(slots), ctypes.byref(pad)))
-        return {"n": n.value, "nnz": nnz.value, "slots": slots.value, "padded_slots": pad.value}
+                                          ctypes.byref(slots), ctypes.byref(pad), ctypes.byref(rb)))
+        return {"n": n.value, "nnz": nnz.value, "slots": slots.value, "padded_slots": pad.value,
+                "rev_bytes": rb.value}
 
     @property
     def handle(self):

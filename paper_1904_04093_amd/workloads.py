@@ -38,7 +38,7 @@ __all__ = [
     "small_upwind", "precision_at_scale", "batch_family", "anisotropic_mg",
     "mg_hierarchy", "theta_problem", "theta_jacobian",
     "random_walk_summable", "random_tridiagonal", "random_tree", "laplacian_5pt",
-    "toy_5x5", "csr_from_dense", "csr_to_dense", "grid_colouring",
+    "toy_5x5", "csr_from_dense", "csr_to_dense", "grid_colouring", "random_sparse_dominant",
 ]
 
 
@@ -422,3 +422,27 @@ def grid_colouring(n: int) -> np.ndarray:
     """Red-black colouring of the n x n grid (x fastest): 0 where ix + iy is even."""
     iy, ix = np.divmod(np.arange(n * n), n)
     return ((ix + iy) & 1).astype(np.uint8)
+
+
+def random_sparse_dominant(n: int, per_row: int, r: np.random.Generator,
+                           margin: float = 0.3) -> CSR:
+    """Sparse nonsymmetric matrix with ``per_row`` random off-diagonals per row (arbitrary,
+    long-range columns) and a strictly dominant diagonal, built without a dense array."""
+    rows = np.repeat(np.arange(n), per_row)
+    cols = r.integers(0, n, size=n * per_row)
+    keep = cols != rows
+    rows, cols = rows[keep], cols[keep]
+    key = np.unique(rows.astype(np.int64) * n + cols)
+    rows, cols = (key // n).astype(np.int64), (key % n).astype(np.int64)
+    vals = r.uniform(-1.0, 1.0, size=len(rows))
+    s = np.bincount(rows, weights=np.abs(vals), minlength=n)
+    s[s == 0] = 1.0
+    d = np.where(r.random(n) < 0.5, -1.0, 1.0) * (1.0 + margin) * s
+    rows = np.concatenate([rows, np.arange(n)])
+    cols = np.concatenate([cols, np.arange(n)])
+    vals = np.concatenate([vals, d])
+    order = np.lexsort((cols, rows))
+    rows, cols, vals = rows[order], cols[order], vals[order]
+    rowptr = np.zeros(n + 1, dtype=np.int32)
+    rowptr[1:] = np.cumsum(np.bincount(rows, minlength=n))
+    return CSR(n, rowptr, cols.astype(np.int32), vals)

@@ -458,3 +458,23 @@ def test_wide_rows_two_pass_kernels(B, density, kw):
         assert _rel_inf(x, xo) <= TOL, sweeps
     r_, (n2, _, _) = s.residual(bt, torch.as_tensor(x).cuda())
     assert _rel_inf(r_.cpu().numpy(), g.residual(b, x)) <= 1e-13
+
+
+def test_long_range_pattern_int32_reverse_index(B):
+    """Long-range couplings put reverse slots far apart: the 4-byte reverse index is used and
+    the sweeps still match the oracle; grid matrices get the 2-byte deltas."""
+    r = W.rng(311, 0)
+    a = W.random_sparse_dominant(40000, 3, r)
+    b = r.uniform(-1, 1, a.n)
+    s = B.Solver.from_csr(a)
+    assert s.layout_info()["rev_bytes"] == 4
+    g = G.Graph.from_csr(a)
+    bt = _cuda(b)
+    for sweeps in (1, 3, 20):
+        x = s.sweeps(bt, sweeps).cpu().numpy()
+        xo, _, _ = G.run(g, b, sweeps)
+        assert _rel_inf(x, xo) <= TOL
+    p = B.Solver.from_csr(a, mode="precomp", precision="f32_ir", tol_lambda=1e-9)
+    x, info = p.solve(bt, 1e-10, 100000)
+    assert info.status == B.OK
+    assert B.Solver.from_csr(W.small_upwind(32)[0]).layout_info()["rev_bytes"] == 2
