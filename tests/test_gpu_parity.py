@@ -456,8 +456,9 @@ def test_wide_rows_two_pass_kernels(B, density, kw):
             for _ in range(sweeps):
                 xo, m = G.msweep(g, b, lam[0], lam[1], m)
         assert _rel_inf(x, xo) <= TOL, sweeps
-    r_, (n2, _, _) = s.residual(bt, torch.as_tensor(x).cuda())
-    assert _rel_inf(r_.cpu().numpy(), g.residual(b, x)) <= 1e-13
+    xr = r.uniform(-1, 1, a.n)          # residual kernel on wide rows, at a non-solution
+    r_, _ = s.residual(bt, _cuda(xr))
+    assert _rel_inf(r_.cpu().numpy(), g.residual(b, xr)) <= 1e-13
 
 
 def test_long_range_pattern_int32_reverse_index(B):
