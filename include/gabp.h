@@ -233,7 +233,10 @@ int gabp_solve_batched(gabp_ctx* ctx, const double* B, double* X, double tol,
  * Gauss-Seidel (colour (ix + iy) mod 2, red first). nu1 / nu2: pre- / post-smoothing
  * steps (GaBP: sweeps per smoother call; RB-GS: red+black sweeps). The contexts are
  * borrowed and must outlive the multigrid context; their message state is used by the
- * smoother. Operators must have the 5-point pattern (the RB-GS update is in place). */
+ * smoother. Operators must have the 5-point pattern (the RB-GS update is in place).
+ * When every level context has opt.use_graphs set, each cycle after the first (which runs
+ * eagerly, so that all precomputed-Lt phases and buffers exist) is recorded once as a
+ * hipGraph -- the whole V-cycle plus the finest residual's norms -- and replayed. */
 int mg_setup(mg_ctx** out, int32_t levels, gabp_ctx* const* level_ctx, const int32_t* side,
              int32_t smoother, int32_t nu1, int32_t nu2, hipStream_t stream);
 

@@ -12,8 +12,19 @@
 #include <vector>
 
 #include "gabp_internal.h"
+#include "graph.h"
 
 using namespace gabp;
+
+// A recorded V-cycle (+ residual norms to the host) and the message-buffer parities of the
+// level contexts before and after it: replaying it must leave the contexts exactly as the
+// eager cycle would.
+struct MgGraph {
+  const double* b = nullptr;
+  const double* x = nullptr;
+  std::vector<int> before, after;
+  hipGraphExec_t exec = nullptr;
+};
 
 struct mg_ctx {
   int levels = 0;
@@ -23,6 +34,10 @@ struct mg_ctx {
   std::vector<double*> b, x, r;   // per level: rhs and iterate (levels >= 1), residual
   double* inv = nullptr;          // dense inverse of the coarsest operator, row-major
   int nc = 0;
+  int cycles_run = 0;
+  bool use_graphs = true;
+  hipStream_t capture_stream = nullptr;
+  std::vector<MgGraph> graphs;
 };
 
 namespace {
@@ -108,12 +123,80 @@ int vcycle(mg_ctx* m, int l, const double* b, double* x, hipStream_t s) {
   return smooth(m, l, b, x, m->nu2, s);
 }
 
-int rel_residual(mg_ctx* m, const double* b, const double* x, double* rel, hipStream_t s) {
-  gabp_ctx* c = m->lv[0];
-  double norms[3];
-  int st = gabp_residual(c, b, x, nullptr, 0, norms, s);
+std::vector<int> parities(const mg_ctx* m) {
+  std::vector<int> p;
+  for (const gabp_ctx* c : m->lv) {
+    p.push_back(c->parity);
+    p.push_back(c->parity32);
+  }
+  return p;
+}
+
+void set_parities(mg_ctx* m, const std::vector<int>& p) {
+  for (size_t l = 0; l < m->lv.size(); ++l) {
+    m->lv[l]->parity = p[2 * l];
+    m->lv[l]->parity32 = p[2 * l + 1];
+  }
+}
+
+// one V-cycle followed by the finest residual's norms copied to the host (no wait)
+int enqueue_cycle(mg_ctx* m, const double* b, double* x, hipStream_t s) {
+  int st = vcycle(m, 0, b, x, s);
   if (st != GABP_OK) return st;
-  *rel = norms[2] > 0 ? norms[0] / norms[2] : norms[0];
+  gabp_ctx* c = m->lv[0];
+  GABP_HIP(launch_residual(&c->L, c->L.val, b, x, nullptr, nullptr, nullptr, c->partials,
+                           c->nred, c->red, s));
+  GABP_HIP(hipMemcpyAsync(c->host_red, c->red, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+  return GABP_OK;
+}
+
+// Run one cycle; from the second cycle on (every Lt phase done, every buffer allocated) the
+// cycle is recorded once per starting state and replayed. Returns the relative residual.
+int run_cycle(mg_ctx* m, const double* b, double* x, double* rel, hipStream_t s) {
+  int st;
+  if (!m->use_graphs || m->cycles_run == 0) {
+    if ((st = enqueue_cycle(m, b, x, s)) != GABP_OK) return st;
+  } else {
+    const std::vector<int> before = parities(m);
+    MgGraph* g = nullptr;
+    for (auto& e : m->graphs)
+      if (e.b == b && e.x == x && e.before == before) g = &e;
+    if (!g) {
+      if (m->graphs.size() >= 4) {
+        (void)hipGraphExecDestroy(m->graphs.front().exec);
+        m->graphs.erase(m->graphs.begin());
+      }
+      if (!m->capture_stream)
+        GABP_HIP(hipStreamCreateWithFlags(&m->capture_stream, hipStreamNonBlocking));
+      GABP_HIP(hipStreamBeginCapture(m->capture_stream, hipStreamCaptureModeThreadLocal));
+      st = enqueue_cycle(m, b, x, m->capture_stream);
+      hipGraph_t graph = nullptr;
+      const hipError_t e = hipStreamEndCapture(m->capture_stream, &graph);
+      if (st != GABP_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        set_parities(m, before);
+        return st;
+      }
+      if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture (V-cycle)");
+      MgGraph ng;
+      ng.b = b;
+      ng.x = x;
+      ng.before = before;
+      ng.after = parities(m);
+      const hipError_t e2 = hipGraphInstantiate(&ng.exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (e2 != hipSuccess) return hip_fail(e2, "hipGraphInstantiate (V-cycle)");
+      m->graphs.push_back(ng);
+      g = &m->graphs.back();
+    }
+    GABP_HIP(hipGraphLaunch(g->exec, s));
+    set_parities(m, g->after);
+  }
+  ++m->cycles_run;
+  GABP_HIP(hipStreamSynchronize(s));
+  const double* h = m->lv[0]->host_red;
+  const double r2 = std::sqrt(h[0]), b2 = std::sqrt(h[2]);
+  *rel = b2 > 0 ? r2 / b2 : r2;
   return GABP_OK;
 }
 
@@ -138,6 +221,7 @@ int mg_setup(mg_ctx** out, int32_t levels, gabp_ctx* const* level_ctx, const int
   if (side[levels - 1] > 63) return fail(GABP_ENOTSUPP, "coarsest grid above 63 x 63");
   mg_ctx* m = new mg_ctx();
   m->levels = levels;
+  for (int l = 0; l < levels; ++l) m->use_graphs = m->use_graphs && level_ctx[l]->opt.use_graphs;
   m->lv.assign(level_ctx, level_ctx + levels);
   m->side.assign(side, side + levels);
   m->smoother = smoother;
@@ -175,9 +259,10 @@ int mg_setup(mg_ctx** out, int32_t levels, gabp_ctx* const* level_ctx, const int
 
 int mg_vcycle(mg_ctx* m, const double* b, double* x, double* rel_res_out, hipStream_t s) {
   if (!m || !b || !x) return fail(GABP_EINVAL, "NULL argument");
-  int st = vcycle(m, 0, b, x, s);
+  double rel = 0.0;
+  const int st = run_cycle(m, b, x, &rel, s);
   if (st != GABP_OK) return st;
-  if (rel_res_out) return rel_residual(m, b, x, rel_res_out, s);
+  if (rel_res_out) *rel_res_out = rel;
   return GABP_OK;
 }
 
@@ -189,9 +274,8 @@ int mg_solve(mg_ctx* m, const double* b, double* x, double tol, int32_t max_cycl
   double rel = 1.0;
   int k = 0, st;
   while (k < max_cycles) {
-    if ((st = vcycle(m, 0, b, x, s)) != GABP_OK) return st;
+    if ((st = run_cycle(m, b, x, &rel, s)) != GABP_OK) return st;
     ++k;
-    if ((st = rel_residual(m, b, x, &rel, s)) != GABP_OK) return st;
     if (!std::isfinite(rel)) {
       if (cycles_out) *cycles_out = k;
       if (rel_res_out) *rel_res_out = rel;
@@ -206,6 +290,8 @@ int mg_solve(mg_ctx* m, const double* b, double* x, double tol, int32_t max_cycl
 
 void mg_destroy(mg_ctx* m) {
   if (!m) return;
+  for (auto& g : m->graphs) (void)hipGraphExecDestroy(g.exec);
+  if (m->capture_stream) (void)hipStreamDestroy(m->capture_stream);
   for (double* p : m->b) if (p) (void)hipFree(p);
   for (double* p : m->x) if (p) (void)hipFree(p);
   for (double* p : m->r) if (p) (void)hipFree(p);
