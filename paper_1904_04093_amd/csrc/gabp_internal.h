@@ -68,6 +68,11 @@ struct Layout {
   int32_t* csr_row = nullptr;   // [nnz] row of each stored entry (adjoint scatter)
   int32_t* csr_col = nullptr;   // [nnz]
   uint8_t* colour = nullptr;    // [n] or null
+  // With a colouring, each slice stores its rows colour-sorted (colour 0 first, ascending
+  // rows within a colour), so a red or black half-sweep reads one contiguous part of every
+  // 64-slot run. perm[t] = row held by lane t & 63 of slice t >> 6 (null: identity).
+  int32_t* perm = nullptr;      // [nslices * 64] or null
+  std::vector<int32_t> lane_of_row;   // host copy of the inverse (empty: identity)
 };
 
 }  // namespace gabp

@@ -20,6 +20,12 @@ namespace {
 
 inline int nblocks(int64_t n, int b = kBlock) { return static_cast<int>((n + b - 1) / b); }
 
+// Thread t serves lane t & 63 of slice t >> 6; that lane holds row perm[t] when the context
+// stores colour-sorted slices (red rows first), else row t.
+__device__ __forceinline__ int row_of(const int32_t* __restrict__ perm, int t) {
+  return perm ? perm[t] : t;
+}
+
 __device__ __forceinline__ int row_base(const int32_t* __restrict__ sptr, int j, int* w) {
   const int s = j >> 6;
   const int a = sptr[s];
@@ -72,12 +78,13 @@ __global__ __launch_bounds__(kBlock) void k_joint(
     const double* __restrict__ coef, const double* __restrict__ diag,
     const double* __restrict__ b, const double* lam_in, const double* msg_in,
     double* lam_out, double* msg_out, double* __restrict__ x,
-    const uint8_t* __restrict__ colour, int c) {
-  const int j = blockIdx.x * kBlock + threadIdx.x;
-  if (j >= n) return;
+    const uint8_t* __restrict__ colour, int c, const int32_t* __restrict__ perm) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= n) return;
+  const int j = row_of(perm, t);
   if (c >= 0 && colour[j] != c) return;
   int w;
-  const int p0 = row_base(sptr, j, &w);
+  const int p0 = row_base(sptr, t, &w);
   double S = diag[j];
   double M = b[j];
   if constexpr (KMAX > 0) {
@@ -150,12 +157,13 @@ __global__ __launch_bounds__(kBlock) void k_mean(
     const int16_t* __restrict__ rev16,
     const T* __restrict__ lamout, const T* __restrict__ Sx, const T* __restrict__ b,
     const T* msg_in, T* msg_out, T* __restrict__ x, const uint8_t* __restrict__ colour,
-    int c) {
-  const int j = blockIdx.x * kBlock + threadIdx.x;
-  if (j >= n) return;
+    int c, const int32_t* __restrict__ perm) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= n) return;
+  const int j = row_of(perm, t);
   if (c >= 0 && colour[j] != c) return;
   int w;
-  const int p0 = row_base(sptr, j, &w);
+  const int p0 = row_base(sptr, t, &w);
   T M = b[j];
   if constexpr (KMAX > 0) {
     T m[KMAX], lo[KMAX];
@@ -194,13 +202,15 @@ template <int KMAX>
 __global__ __launch_bounds__(kBlock) void k_lambda(
     int n, const int32_t* __restrict__ sptr, const int32_t* __restrict__ rev,
     const double* __restrict__ coef, const double* __restrict__ diag, const double* lam_in,
-    double* lam_out, double* __restrict__ lamout, double* __restrict__ partials) {
+    double* lam_out, double* __restrict__ lamout, double* __restrict__ partials,
+    const int32_t* __restrict__ perm) {
   __shared__ double sh[2][kBlock / 64];
-  const int j = blockIdx.x * kBlock + threadIdx.x;
+  const int t = blockIdx.x * kBlock + threadIdx.x;
   double dm = 0.0, lm = 0.0;
-  if (j < n) {
+  if (t < n) {
+    const int j = row_of(perm, t);
     int w;
-    const int p0 = row_base(sptr, j, &w);
+    const int p0 = row_base(sptr, t, &w);
     double S = diag[j];
     if constexpr (KMAX > 0) {
       double l[KMAX], a[KMAX];
@@ -300,11 +310,12 @@ __global__ __launch_bounds__(kBlock) void k_lambda_fin(
     int n, const int32_t* __restrict__ sptr, const double* __restrict__ coef,
     const double* __restrict__ diag, const double* __restrict__ lam_in,
     const double* __restrict__ lamout, double* __restrict__ Sout, float* __restrict__ lamout32,
-    float* __restrict__ invS32) {
-  const int j = blockIdx.x * kBlock + threadIdx.x;
-  if (j >= n) return;
+    float* __restrict__ invS32, const int32_t* __restrict__ perm) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= n) return;
+  const int j = row_of(perm, t);
   int w;
-  const int p0 = row_base(sptr, j, &w);
+  const int p0 = row_base(sptr, t, &w);
   double S = diag[j];
   for (int k = 0; k < w; ++k) {
     const int p = p0 + 64 * k;
@@ -324,13 +335,15 @@ __global__ __launch_bounds__(kRedBlock) void k_residual(
     int n, const int32_t* __restrict__ sptr, const int32_t* __restrict__ col,
     const double* __restrict__ coef_row, const double* __restrict__ diag,
     const double* __restrict__ b, const double* __restrict__ x, const float* __restrict__ dx,
-    const double* __restrict__ scale, double* __restrict__ r, double* __restrict__ partials) {
+    const double* __restrict__ scale, double* __restrict__ r, double* __restrict__ partials,
+    const int32_t* __restrict__ perm) {
   __shared__ double sh[3][kRedBlock / 64];
-  const int j = blockIdx.x * kRedBlock + threadIdx.x;
+  const int t = blockIdx.x * kRedBlock + threadIdx.x;
   double rr = 0.0, ra = 0.0, bb = 0.0;
-  if (j < n) {
+  if (t < n) {
+    const int j = row_of(perm, t);
     int w;
-    const int p0 = row_base(sptr, j, &w);
+    const int p0 = row_base(sptr, t, &w);
     const double sc = XADD ? scale[0] : 0.0;
     double xj = x[j];
     if (XADD) xj = fma(sc, static_cast<double>(dx[j]), xj);
@@ -561,12 +574,14 @@ __global__ __launch_bounds__(kBlock) void k_rbgs(int n, int side, int c,
                                                  const int32_t* __restrict__ col,
                                                  const double* __restrict__ val,
                                                  const double* __restrict__ diag,
-                                                 const double* __restrict__ b, double* x) {
-  const int j = blockIdx.x * kBlock + threadIdx.x;
-  if (j >= n) return;
+                                                 const double* __restrict__ b, double* x,
+                                                 const int32_t* __restrict__ perm) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= n) return;
+  const int j = row_of(perm, t);
   if (((j % side) + (j / side)) % 2 != c) return;
   int w;
-  const int p0 = row_base(sptr, j, &w);
+  const int p0 = row_base(sptr, t, &w);
   double s = 0.0;
   for (int k = 0; k < w; ++k) {
     const int p = p0 + 64 * k;
@@ -615,7 +630,7 @@ hipError_t launch_joint_sweep(const SweepArgs& a, hipStream_t s) {
   const int g = nblocks(L.n);
 #define JOINT_ARGS                                                                      \
   L.n, L.sptr, L.rev, L.rev16, a.coef, L.diag, a.b, a.lam_in, a.msg_in, a.lam_out,       \
-      a.msg_out, a.x, L.colour, a.colour
+      a.msg_out, a.x, L.colour, a.colour, L.perm
   GABP_DISPATCH_NT(L.stream_hints, GABP_DISPATCH_R16(L.rev16 != nullptr, {
     if (a.x) {
       GABP_DISPATCH_WIDTH(L.max_width,
@@ -639,7 +654,8 @@ template <typename T, typename A>
 hipError_t mean_dispatch(const Layout& L, const A& a, const T* Sx, bool nt, hipStream_t s) {
   const int g = nblocks(L.n);
 #define MEAN_ARGS \
-  L.n, L.sptr, L.rev, L.rev16, a.lamout, Sx, a.b, a.msg_in, a.msg_out, a.x, L.colour, a.colour
+  L.n, L.sptr, L.rev, L.rev16, a.lamout, Sx, a.b, a.msg_in, a.msg_out, a.x, L.colour, a.colour, \
+      L.perm
   GABP_DISPATCH_NT(nt, GABP_DISPATCH_R16(L.rev16 != nullptr, {
     if (a.x) {
       GABP_DISPATCH_WIDTH(L.max_width,
@@ -674,10 +690,10 @@ hipError_t launch_lambda_sweep(const Layout* Lp, const double* coef, const doubl
   const int g = nblocks(L.n);
   GABP_DISPATCH_WIDTH(
       L.max_width,
-      (k_lambda<4><<<g, kBlock, 0, s>>>(L.n, L.sptr, L.rev, coef, L.diag, lam_in, lam_out, lamout, partials)),
-      (k_lambda<8><<<g, kBlock, 0, s>>>(L.n, L.sptr, L.rev, coef, L.diag, lam_in, lam_out, lamout, partials)),
-      (k_lambda<16><<<g, kBlock, 0, s>>>(L.n, L.sptr, L.rev, coef, L.diag, lam_in, lam_out, lamout, partials)),
-      (k_lambda<0><<<g, kBlock, 0, s>>>(L.n, L.sptr, L.rev, coef, L.diag, lam_in, lam_out, lamout, partials)));
+      (k_lambda<4><<<g, kBlock, 0, s>>>(L.n, L.sptr, L.rev, coef, L.diag, lam_in, lam_out, lamout, partials, L.perm)),
+      (k_lambda<8><<<g, kBlock, 0, s>>>(L.n, L.sptr, L.rev, coef, L.diag, lam_in, lam_out, lamout, partials, L.perm)),
+      (k_lambda<16><<<g, kBlock, 0, s>>>(L.n, L.sptr, L.rev, coef, L.diag, lam_in, lam_out, lamout, partials, L.perm)),
+      (k_lambda<0><<<g, kBlock, 0, s>>>(L.n, L.sptr, L.rev, coef, L.diag, lam_in, lam_out, lamout, partials, L.perm)));
   k_lambda_reduce<<<1, 1024, 0, s>>>(g, partials, out);
   return hipGetLastError();
 }
@@ -686,7 +702,8 @@ hipError_t launch_lambda_finalize(const Layout* Lp, const double* coef, const do
                                   Precomp* P, hipStream_t s) {
   const Layout& L = *Lp;
   k_lambda_fin<0><<<nblocks(L.n), kBlock, 0, s>>>(L.n, L.sptr, coef, L.diag, lam_in,
-                                                  P->lamout, P->S, P->lamout32, P->invS32);
+                                                  P->lamout, P->S, P->lamout32, P->invS32,
+                                                  L.perm);
   return hipGetLastError();
 }
 
@@ -694,7 +711,7 @@ hipError_t launch_residual(const Layout* Lp, const double* coef_row, const doubl
                            const double* x, const float* dx, const double* scale, double* r,
                            double* partials, int32_t nred, double* red, hipStream_t s) {
   const Layout& L = *Lp;
-#define RES_ARGS(DX, SC) L.n, L.sptr, L.col, coef_row, L.diag, b, x, DX, SC, r, partials
+#define RES_ARGS(DX, SC) L.n, L.sptr, L.col, coef_row, L.diag, b, x, DX, SC, r, partials, L.perm
   if (dx) {
     GABP_DISPATCH_WIDTH(L.max_width,
                         (k_residual<4, true><<<nred, kRedBlock, 0, s>>>(RES_ARGS(dx, scale))),
@@ -797,7 +814,8 @@ hipError_t launch_prolong_add(int nc, const double* ec, double* xf, hipStream_t 
 hipError_t launch_rbgs(const Layout* Lp, int side, int colour, const double* b, double* x,
                        hipStream_t s) {
   const Layout& L = *Lp;
-  k_rbgs<0><<<nblocks(L.n), kBlock, 0, s>>>(L.n, side, colour, L.sptr, L.col, L.val, L.diag, b, x);
+  k_rbgs<0><<<nblocks(L.n), kBlock, 0, s>>>(L.n, side, colour, L.sptr, L.col, L.val, L.diag, b, x,
+                                            L.perm);
   return hipGetLastError();
 }
 hipError_t launch_dense_matvec(int n, const double* inv, const double* b, double* x,

@@ -90,7 +90,8 @@ int dense_of(gabp_ctx* c, std::vector<double>& A, hipStream_t s) {
     const int sl = j / kSlice;
     const int w = (sptr[sl + 1] - sptr[sl]) / kSlice;
     for (int k = 0; k < w; ++k) {
-      const int p = sptr[sl] + k * kSlice + (j % kSlice);
+      const int lane = L.lane_of_row.empty() ? (j % kSlice) : L.lane_of_row[j];
+      const int p = sptr[sl] + k * kSlice + lane;
       if (val[p] != 0.0) A[static_cast<size_t>(j) * n + col[p]] += val[p];
     }
   }

@@ -217,8 +217,31 @@ int gabp_setup(gabp_ctx** out, int32_t n, int64_t nnz, const int32_t* rowptr,
   const int64_t epad = sptr64[nslices];
   if (epad + 1 >= std::numeric_limits<int32_t>::max())
     return fail(GABP_ENOTSUPP, "more than 2^31-1 padded message slots");
+  // lane of every row: identity, or colour-sorted within each slice when colours are given
+  std::vector<int32_t> lane_of_row, row_of_lane;
+  if (colour) {
+    for (int32_t j = 0; j < n; ++j)
+      if (colour[j] > 1) return fail(GABP_EINVAL, "colour must be 0 or 1");
+    lane_of_row.resize(n);
+    row_of_lane.resize(static_cast<size_t>(nslices) * kSlice);
+    for (int32_t s = 0; s < nslices; ++s) {
+      int32_t lane = 0;
+      const int32_t r0 = s * kSlice, r1 = std::min(n, r0 + kSlice);
+      for (int c = 0; c < 2; ++c)
+        for (int32_t j = r0; j < r1; ++j)
+          if (colour[j] == c) {
+            lane_of_row[j] = lane;
+            row_of_lane[r0 + lane] = j;
+            ++lane;
+          }
+      for (; lane < kSlice; ++lane) row_of_lane[r0 + lane] = r0 + lane;   // rows >= n
+    }
+  }
+  auto lane = [&](int32_t j) -> int64_t {
+    return lane_of_row.empty() ? (j % kSlice) : lane_of_row[j];
+  };
   auto pos = [&](int32_t j, int64_t k) -> int64_t {
-    return sptr64[j / kSlice] + k * kSlice + (j % kSlice);
+    return sptr64[j / kSlice] + k * kSlice + lane(j);
   };
   std::vector<int32_t> h_rev(epad, static_cast<int32_t>(epad)), h_col(epad, 0);
   std::vector<int32_t> h_vsrc(epad, -1), h_asrc(epad, -1);
@@ -317,6 +340,8 @@ int gabp_setup(gabp_ctx** out, int32_t n, int64_t nnz, const int32_t* rowptr,
   if (colour) {
     std::vector<uint8_t> hc(colour, colour + n);
     UP(L.colour, hc);
+    UP(L.perm, row_of_lane);
+    L.lane_of_row = lane_of_row;
   }
   for (int q = 0; q < 2; ++q) {
     AL(c->lam[q], epad + 1);
@@ -368,7 +393,7 @@ void gabp_destroy(gabp_ctx* c) {
   };
   Layout& L = c->L;
   F(L.sptr); F(L.rev); F(L.rev16); F(L.col); F(L.val); F(L.aT); F(L.diag); F(L.val_src); F(L.aT_src);
-  F(L.diag_src); F(L.csr_row); F(L.csr_col); F(L.colour);
+  F(L.diag_src); F(L.csr_row); F(L.csr_col); F(L.colour); F(L.perm);
   for (int q = 0; q < 2; ++q) {
     F(c->lam[q]); F(c->msg[q]); F(c->msg32[q]);
     F(c->pre[q].lamout); F(c->pre[q].S); F(c->pre[q].lamout32); F(c->pre[q].invS32);
