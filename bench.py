@@ -206,7 +206,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "k_joint (FP64 joint flood sweep)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic("k_joint<4, false>"),
+                     "traffic": measured_traffic("k_joint<4, false, true, true>"),
                      "frac_of_copy": achieved / copy_gbs,
                      "algorithmic_bytes_per_launch": ab, "launch_us": t_sw * 1e6,
                      "reverse_index_bytes": rb},

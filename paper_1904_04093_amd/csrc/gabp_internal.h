@@ -92,6 +92,8 @@ struct gabp_ctx {
   double* r = nullptr;        // [n]
   double* r2 = nullptr;       // [n]
   double* e = nullptr;        // [n]
+  double* bsol = nullptr;     // [n] staged right-hand side of gabp_solve*
+  double* xsol = nullptr;     // [n] staged iterate of gabp_solve*
   float* r32 = nullptr;       // [n]
   float* d32 = nullptr;       // [n]
   float* dbest32 = nullptr;   // [n] best inner correction of the current refinement step

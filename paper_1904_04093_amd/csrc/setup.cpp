@@ -380,8 +380,9 @@ int gabp_update_values(gabp_ctx* c, const double* val, hipStream_t stream) {
   int hbad = 0;
   GABP_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, stream));
   GABP_HIP(hipStreamSynchronize(stream));
+  // recorded blocks read the coefficient and precomputed-Lt buffers in place, so they stay
+  // valid; only the precomputed Lt must be recomputed for the new values
   c->pre[0].valid = c->pre[1].valid = false;
-  c->graphs->clear();   // recorded blocks point at the precomputed-Lt buffers' values
   if (hbad) return fail(GABP_EZERODIAG, "zero or non-finite diagonal in updated values");
   return GABP_OK;
 }
@@ -398,7 +399,7 @@ void gabp_destroy(gabp_ctx* c) {
     F(c->lam[q]); F(c->msg[q]); F(c->msg32[q]);
     F(c->pre[q].lamout); F(c->pre[q].S); F(c->pre[q].lamout32); F(c->pre[q].invS32);
   }
-  F(c->r); F(c->r2); F(c->e); F(c->r32); F(c->d32); F(c->dbest32); F(c->partials); F(c->red); F(c->lmax);
+  F(c->r); F(c->r2); F(c->e); F(c->bsol); F(c->xsol); F(c->r32); F(c->d32); F(c->dbest32); F(c->partials); F(c->red); F(c->lmax);
   if (c->host_red) (void)hipHostFree(c->host_red);
   if (c->batch) {
     batch_free(c->batch);

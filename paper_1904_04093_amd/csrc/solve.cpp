@@ -332,13 +332,26 @@ int solve_ir(gabp_ctx* c, int T, const double* b, double* x, double tol, int max
   return GABP_MAXSWEEPS;
 }
 
+// The caller's b and x are staged through context-owned buffers, so the recorded check
+// blocks (which bake in their buffer addresses) are reused across calls whatever tensors
+// the caller passes.
 int solve_any(gabp_ctx* c, int T, const double* b, double* x, double tol, int32_t max_sweeps,
               gabp_info* info, hipStream_t s) {
   if (!c || !b || !x) return fail(GABP_EINVAL, "NULL argument");
   if (max_sweeps < 1 || !(tol >= 0.0)) return fail(GABP_EINVAL, "max_sweeps < 1 or tol < 0");
   GABP_HIP(hipSetDevice(c->device));
-  if (c->opt.precision == GABP_F32_IR) return solve_ir(c, T, b, x, tol, max_sweeps, info, s);
-  return solve64(c, T, b, x, tol, max_sweeps, info, s);
+  const int64_t n = c->L.n;
+  if (!c->bsol) {
+    GABP_HIP(hipMalloc(reinterpret_cast<void**>(&c->bsol), n * sizeof(double)));
+    GABP_HIP(hipMalloc(reinterpret_cast<void**>(&c->xsol), n * sizeof(double)));
+  }
+  GABP_HIP(hipMemcpyAsync(c->bsol, b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  const int st = c->opt.precision == GABP_F32_IR
+                     ? solve_ir(c, T, c->bsol, c->xsol, tol, max_sweeps, info, s)
+                     : solve64(c, T, c->bsol, c->xsol, tol, max_sweeps, info, s);
+  if (st == GABP_OK || st == GABP_MAXSWEEPS || st == GABP_ENUMERIC)
+    GABP_HIP(hipMemcpyAsync(x, c->xsol, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  return st;
 }
 
 }  // namespace

@@ -387,6 +387,29 @@ def test_graph_replays_match_eager(B, kw):
         torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("kw", [dict(mode="joint"), dict(mode="precomp", tol_lambda=1e-12),
+                                dict(mode="precomp", precision="f32_ir", tol_lambda=1e-10)])
+def test_recorded_solves_follow_new_values_and_tensors(B, kw):
+    """A recorded solve reads the coefficients in place and stages b and x through the
+    context, so it stays correct when the values change and when every call passes fresh
+    tensors (the autograd pattern)."""
+    n = 20
+    ops = [W.theta_operator(n, W.theta_problem(n, q)) for q in range(3)]
+    eager = B.Solver.from_csr(ops[0], check_every=8, use_graphs=False, **kw)
+    graph = B.Solver.from_csr(ops[0], check_every=8, use_graphs=True, **kw)
+    for q, a in enumerate(ops + ops[:1]):
+        b = W.rng(305, q).uniform(-1, 1, a.n)
+        for s in (eager, graph):
+            s.update_values(_cuda(a.val))
+        xe, ie = eager.solve(_cuda(b), 1e-10, 200000)
+        xg, ig = graph.solve(_cuda(b), 1e-10, 200000)
+        assert np.array_equal(xg.cpu().numpy(), xe.cpu().numpy()), q
+        assert ig.sweeps == ie.sweeps, q
+        xt, _ = graph.solve_transposed(_cuda(b), 1e-10, 200000)
+        At = W.csr_to_dense(a).T
+        assert np.abs(At @ xt.cpu().numpy() - b).max() < 1e-8 * np.abs(b).max() * 10, q
+
+
 def test_batched_graph_replays_match_eager(B):
     fam = W.batch_family(nsys=5, nrhs=2, side_lo=8, side_hi=24, seed=33)
     systems = [x for x, _ in fam]
