@@ -17,6 +17,7 @@ from __future__ import annotations
 import numpy as np
 
 from . import gabp as _g
+from . import regions as _rg
 
 
 def restrict_fw(r, n_f):
@@ -60,8 +61,11 @@ class Hierarchy:
     """Per-level oracle state: graphs, grid sides, precomputed Lambda~ and warm messages.
 
     smoother: "rbgs" (red-black Gauss-Seidel) or "gabp" (Algorithm 3) with
-    gabp_mode "joint" | "precomp", schedule "flood" | "redblack" and warm "reset" | "all"
-    (mean messages -- and, in joint mode, precision messages -- carried between calls).
+    gabp_mode "joint" | "precomp", schedule "flood" | "redblack" | "lines" | "lines_alt" and
+    warm "reset" | "all" (mean messages -- and, for point GaBP in joint mode, precision
+    messages -- carried between calls). "lines" is the two-layer region iteration on the
+    grid's rows and columns (Algorithm 2 with the partition of Fig. two_layers_network, line
+    GaBP) in the flood schedule; "lines_alt" updates all rows, then all columns.
     """
 
     def __init__(self, csrs, smoother="gabp", nu1=2, nu2=2, gabp_mode="precomp",
@@ -71,7 +75,18 @@ class Hierarchy:
         self.smoother, self.nu1, self.nu2 = smoother, nu1, nu2
         self.gabp_mode, self.warm, self.schedule = gabp_mode, warm, schedule
         self.lam = [None] * len(csrs)
-        if smoother == "gabp" and gabp_mode == "precomp":
+        self.rgs = None
+        if smoother == "gabp" and schedule in ("lines", "lines_alt"):
+            self.rgs = [_rg.RegionGraph(a, _rg.grid_lines(s, s))
+                        for a, s in zip(csrs[:-1], self.sides[:-1])]
+            self.groups = [None if schedule == "lines" else _rg.line_groups(s, s)
+                           for s in self.sides[:-1]]
+            if gabp_mode == "precomp":
+                for l, rg in enumerate(self.rgs):
+                    lam, invs, _ = _rg.lambda_phase(rg, tol_lambda, max_lambda_sweeps,
+                                                    groups=self.groups[l])
+                    self.lam[l] = (lam, invs)
+        elif smoother == "gabp" and gabp_mode == "precomp":
             for l, g in enumerate(self.graphs[:-1]):
                 Lt, S, _ = _g.lambda_phase(g, tol_lambda, max_lambda_sweeps)
                 self.lam[l] = (Lt, S)
@@ -87,6 +102,12 @@ class Hierarchy:
             return rbgs(g, b, x, self.sides[l], nu)
         warm = self.warm == "all"
         m0 = self.m_state[l] if warm else None
+        if self.schedule in ("lines", "lines_alt"):
+            x, m = _rg.smooth(self.rgs[l], b, x, nu, precomp=self.lam[l], m_state=m0,
+                              groups=self.groups[l])
+            if warm:
+                self.m_state[l] = m
+            return x
         if self.schedule == "redblack":
             L0 = self.Lt_state[l] if warm else None
             x, Lt, m = _g.smooth_coloured(g, b, x, nu, _g.grid_colour(self.sides[l]),

@@ -446,3 +446,30 @@ def random_sparse_dominant(n: int, per_row: int, r: np.random.Generator,
     rowptr = np.zeros(n + 1, dtype=np.int32)
     rowptr[1:] = np.cumsum(np.bincount(rows, minlength=n))
     return CSR(n, rowptr, cols.astype(np.int32), vals)
+
+
+def random_grid_5pt(nx: int, ny: int, r: np.random.Generator, margin: float = 0.3,
+                    kx: float = 1.0, ky: float = 1.0, one_way: float = 0.0,
+                    flip: float = 0.0) -> CSR:
+    """Random 5-point operator on an nx x ny grid (node (x, y) has index y * nx + x; rows list
+    S, W, diagonal, E, N). Horizontal couplings have magnitude kx * U(0.5, 1), vertical ones
+    ky * U(0.5, 1); they are negative except for a fraction ``flip`` of positive ones, and a
+    fraction ``one_way`` of them is zero (structurally nonsymmetric). Zero couplings are not
+    stored. The diagonal is (1 + margin) times the row's absolute off-diagonal sum (1 where
+    that sum is 0)."""
+    n = nx * ny
+    iy, ix = np.divmod(np.arange(n), nx)
+    mag = np.stack([ky * r.uniform(0.5, 1.0, n), kx * r.uniform(0.5, 1.0, n),
+                    np.zeros(n), kx * r.uniform(0.5, 1.0, n), ky * r.uniform(0.5, 1.0, n)], -1)
+    sign = np.where(r.random((n, 5)) < flip, 1.0, -1.0)
+    coef = mag * sign * (r.random((n, 5)) >= one_way)
+    exists = np.stack([iy > 0, ix > 0, np.ones(n, bool), ix < nx - 1, iy < ny - 1], -1)
+    coef = np.where(exists, coef, 0.0)
+    s = np.abs(coef).sum(1)
+    coef[:, 2] = np.where(s > 0, (1.0 + margin) * s, 1.0)
+    keep = exists & ((coef != 0.0) | (np.arange(5) == 2))
+    cols = (np.arange(n)[:, None] + np.array([-nx, -1, 0, 1, nx]))[keep].astype(np.int32)
+    vals = coef[keep]
+    rowptr = np.zeros(n + 1, dtype=np.int32)
+    rowptr[1:] = np.cumsum(keep.sum(1))
+    return CSR(n, rowptr, cols, vals, {"grid": (nx, ny)})
