@@ -62,6 +62,12 @@ extern "C" {
 #define GABP_SCHED_FLOOD 0   /* all nodes send every sweep (Sec. 2.2)                       */
 #define GABP_SCHED_REDBLACK 1/* red nodes send, then black nodes, using the newest messages
                                 (the paper's red-black GaBP, Sec. 5); needs node colours    */
+#define GABP_SCHED_LINES 2   /* line GaBP: the two-layer region iteration of Algorithm 2 whose
+                                large regions are the grid's rows and columns and whose small
+                                regions are the nodes (Fig. two_layers_network), every line
+                                from the previous messages; needs grid_nx, grid_ny          */
+#define GABP_SCHED_LINES_ALT 3 /* line GaBP with all rows updated first, then all columns from
+                                the new row messages (one chain of the flood iteration)     */
 #define GABP_WARM_RESET_M 0  /* smoother: mean messages restart from zero every call        */
 #define GABP_WARM_ALL 1      /* smoother: mean messages carry over between calls            */
 
@@ -79,6 +85,10 @@ typedef struct {
   int32_t schedule;          /* GABP_SCHED_*                      default FLOOD            */
   int32_t use_graphs;        /* record each check block (sweeps + residual + readback) as a
                                 hipGraph once and replay it       default 1                */
+  int32_t grid_nx, grid_ny;  /* line schedules: node (x, y) is row y*grid_nx + x, and A may
+                                couple a node only with its horizontal and vertical
+                                neighbours (5-point pattern); lines of at most 4096 nodes
+                                                                  default 0, 0             */
 } gabp_options;
 
 typedef struct {

@@ -114,6 +114,7 @@ extern "C" {
 
 int gabp_autotune(gabp_ctx* c, int32_t* check_every_out, int32_t* hints_out, hipStream_t s) {
   if (!c) return fail(GABP_EINVAL, "NULL context");
+  if (c->lines) return fail(GABP_ENOTSUPP, "the autotuner covers the point schedules");
   const std::string key = key_of(c);
   Tuned t{};
   const bool f32 = c->opt.precision == GABP_F32_IR;

@@ -29,6 +29,7 @@ namespace gabp {
 
 struct Batch;
 struct GraphCache;
+struct LineLayout;
 constexpr int kSlice = 64;      // rows per slice = wavefront size on CDNA
 constexpr int kBlock = 256;     // threads per block for row kernels (4 slices)
 constexpr int kRedBlock = 256;  // threads per block for reductions
@@ -106,6 +107,7 @@ struct gabp_ctx {
   double* host_red = nullptr;          // pinned [8]
   gabp::Batch* batch = nullptr;        // set for contexts made by gabp_setup_batched
   gabp::GraphCache* graphs = nullptr;  // recorded check blocks
+  gabp::LineLayout* lines = nullptr;   // set for the line schedules
 };
 
 namespace gabp {
@@ -175,6 +177,8 @@ hipError_t launch_residual(const Layout* L, const double* coef_row, const double
                            double* partials, int32_t nred, double* red, hipStream_t s);
 
 hipError_t launch_copy_probe(const void* src, void* dst, int64_t bytes, hipStream_t s);
+// out[0] = max of partials[2q], out[1] = max of partials[2q+1] over q < nblk
+hipError_t launch_max_pairs(int nblk, const double* partials, double* out, hipStream_t s);
 hipError_t launch_fill64(double* p, int64_t n, double v, hipStream_t s);
 hipError_t launch_fill32(float* p, int64_t n, float v, hipStream_t s);
 hipError_t launch_copy64(double* dst, const double* src, int64_t n, hipStream_t s);

@@ -698,6 +698,11 @@ hipError_t launch_lambda_sweep(const Layout* Lp, const double* coef, const doubl
   return hipGetLastError();
 }
 
+hipError_t launch_max_pairs(int nblk, const double* partials, double* out, hipStream_t s) {
+  k_lambda_reduce<<<1, 1024, 0, s>>>(nblk, partials, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_lambda_finalize(const Layout* Lp, const double* coef, const double* lam_in,
                                   Precomp* P, hipStream_t s) {
   const Layout& L = *Lp;

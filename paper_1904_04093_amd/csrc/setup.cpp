@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "gabp_batch.h"
+#include "gabp_line.h"
 #include "graph.h"
 
 namespace gabp {
@@ -116,6 +117,8 @@ void gabp_default_options(gabp_options* o) {
   o->ir_max_inner = 1000000;
   o->schedule = GABP_SCHED_FLOOD;
   o->use_graphs = 1;
+  o->grid_nx = 0;
+  o->grid_ny = 0;
 }
 
 const char* gabp_strerror(int s) {
@@ -152,7 +155,7 @@ int gabp_setup(gabp_ctx** out, int32_t n, int64_t nnz, const int32_t* rowptr,
   if (o.check_every < 1 || o.max_lambda_sweeps < 0 || o.tol_lambda < 0 ||
       (o.mode != GABP_MODE_JOINT && o.mode != GABP_MODE_PRECOMP) ||
       (o.precision != GABP_F64 && o.precision != GABP_F32_IR) ||
-      (o.schedule != GABP_SCHED_FLOOD && o.schedule != GABP_SCHED_REDBLACK) ||
+      (o.schedule < GABP_SCHED_FLOOD || o.schedule > GABP_SCHED_LINES_ALT) ||
       (o.warm != GABP_WARM_RESET_M && o.warm != GABP_WARM_ALL) || o.ir_max_inner < 1 ||
       !(o.ir_inner_tol > 0.0))
     return fail(GABP_EINVAL, "invalid options");
@@ -366,6 +369,10 @@ int gabp_setup(gabp_ctx** out, int32_t n, int64_t nnz, const int32_t* rowptr,
     hipError_t e2 = launch_fill64(c->msg[q], epad + 1, 0.0, stream);
     if (e1 != hipSuccess || e2 != hipSuccess) return cleanup_fail(hip_fail(e1 != hipSuccess ? e1 : e2, "fill"));
   }
+  if (o.schedule == GABP_SCHED_LINES || o.schedule == GABP_SCHED_LINES_ALT) {
+    const int lst = line_setup(c, o.grid_nx, o.grid_ny, rowptr, col, val);
+    if (lst != GABP_OK) return cleanup_fail(lst);
+  }
   hipError_t e = hipStreamSynchronize(stream);
   if (e != hipSuccess) return cleanup_fail(hip_fail(e, "hipStreamSynchronize(setup)"));
   *out = c;
@@ -377,6 +384,10 @@ int gabp_update_values(gabp_ctx* c, const double* val, hipStream_t stream) {
   int* bad = reinterpret_cast<int*>(c->lmax);   // reuse 16 bytes of scratch as a flag
   GABP_HIP(hipMemsetAsync(bad, 0, sizeof(int), stream));
   GABP_HIP(launch_update_values(&c->L, val, bad, stream));
+  if (c->lines) {
+    const int lst = line_update_values(c, val, stream);
+    if (lst != GABP_OK) return lst;
+  }
   int hbad = 0;
   GABP_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, stream));
   GABP_HIP(hipStreamSynchronize(stream));
@@ -405,6 +416,7 @@ void gabp_destroy(gabp_ctx* c) {
     batch_free(c->batch);
     delete c->batch;
   }
+  line_destroy(c->lines);
   delete c->graphs;
   delete c;
 }

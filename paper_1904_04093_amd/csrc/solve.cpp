@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "gabp_internal.h"
+#include "gabp_line.h"
 #include "graph.h"
 
 using namespace gabp;
@@ -46,6 +47,7 @@ int residual(gabp_ctx* c, int T, const double* b, const double* x, const float* 
 }
 
 int ensure_pre(gabp_ctx* c, int T, hipStream_t s) {
+  if (c->lines) return line_precompute(c, T, s);
   Precomp& P = c->pre[T];
   if (P.valid) return GABP_OK;
   const Layout& L = c->L;
@@ -88,6 +90,10 @@ int ensure_pre(gabp_ctx* c, int T, hipStream_t s) {
 // Both FP32 message buffers start at zero: padding slots (short rows inside a slice) are
 // read by every sweep but never written, so they must hold zeros in both buffers.
 int ensure_msg32(gabp_ctx* c, hipStream_t s) {
+  if (c->lines) {
+    if (!c->dbest32) GABP_HIP(hipMalloc(reinterpret_cast<void**>(&c->dbest32), c->L.n * sizeof(float)));
+    return line_ensure32(c, s);
+  }
   if (c->msg32[0]) return GABP_OK;
   for (int q = 0; q < 2; ++q) {
     GABP_HIP(hipMalloc(reinterpret_cast<void**>(&c->msg32[q]), (c->L.epad + 1) * sizeof(float)));
@@ -100,6 +106,7 @@ int ensure_msg32(gabp_ctx* c, hipStream_t s) {
 // One FP64 sweep of the configured mode and schedule on right-hand side b.
 // x != null: the read-off of this sweep is written there.
 int sweep64(gabp_ctx* c, int T, const double* b, double* x, hipStream_t s) {
+  if (c->lines) return line_sweep64(c, T, b, x, s);
   const bool rb = c->opt.schedule == GABP_SCHED_REDBLACK;
   if (c->opt.mode == GABP_MODE_JOINT) {
     SweepArgs a{&c->L, sweep_coef(c, T), b, nullptr, nullptr, nullptr, nullptr, x, -1};
@@ -138,6 +145,7 @@ int sweep64(gabp_ctx* c, int T, const double* b, double* x, hipStream_t s) {
 }
 
 int sweep32(gabp_ctx* c, int T, const float* b, float* x, hipStream_t s) {
+  if (c->lines) return line_sweep32(c, T, b, x, s);
   const Precomp& P = c->pre[T];
   MeanArgs32 a{&c->L, P.lamout32, P.invS32, b, nullptr, nullptr, x, -1};
   if (c->opt.schedule != GABP_SCHED_REDBLACK) {
@@ -157,6 +165,7 @@ int sweep32(gabp_ctx* c, int T, const float* b, float* x, hipStream_t s) {
 
 int reset_messages64(gabp_ctx* c, hipStream_t s) {
   c->parity = 0;
+  if (c->lines) return line_reset64(c, s);
   GABP_HIP(launch_fill64(c->msg[0], c->L.epad + 1, 0.0, s));
   if (c->opt.mode == GABP_MODE_JOINT) GABP_HIP(launch_fill64(c->lam[0], c->L.epad + 1, 0.0, s));
   return GABP_OK;
@@ -164,9 +173,26 @@ int reset_messages64(gabp_ctx* c, hipStream_t s) {
 
 int reset_messages32(gabp_ctx* c, hipStream_t s) {
   c->parity32 = 0;
+  if (c->lines) return line_reset32(c, s);
   GABP_HIP(launch_fill32(c->msg32[0], c->L.epad + 1, 0.0f, s));
   return GABP_OK;
 }
+
+// Line schedules read the right-hand side in both the row and the column layout: these
+// refresh the column copy (no-ops for point schedules).
+int prep_rhs64(gabp_ctx* c, const double* b, hipStream_t s) {
+  return c->lines ? line_rhs64(c, b, s) : GABP_OK;
+}
+int prep_rhs32(gabp_ctx* c, const float* b, hipStream_t s) {
+  return c->lines ? line_rhs32(c, b, s) : GABP_OK;
+}
+
+// in-place schedules keep one message buffer (no ping-pong parity)
+inline bool in_place(const gabp_ctx* c) {
+  return c->opt.schedule == GABP_SCHED_REDBLACK || c->lines != nullptr;
+}
+
+bool has_msg32(const gabp_ctx* c) { return c->lines ? line_has32(c) : c->msg32[0] != nullptr; }
 
 void fill_info(gabp_info* info, int status, int sweeps, int lsweeps, int outer,
                const Norms& nm) {
@@ -189,9 +215,10 @@ int solve64(gabp_ctx* c, int T, const double* b, double* x, double tol, int max_
     lsw = had ? 0 : c->pre[T].sweeps;
   }
   if ((st = reset_messages64(c, s)) != GABP_OK) return st;
+  if ((st = prep_rhs64(c, b, s)) != GABP_OK) return st;
   Norms nm{0, 0, 0};
   int done = 0;
-  const bool rb = c->opt.schedule == GABP_SCHED_REDBLACK;
+  const bool rb = in_place(c);
   while (done < max_sweeps) {
     const int k = std::min(c->opt.check_every, max_sweeps - done);
     const int start = c->parity;
@@ -263,13 +290,14 @@ int solve_ir(gabp_ctx* c, int T, const double* b, double* x, double tol, int max
     if (total >= max_sweeps) break;
     GABP_HIP(launch_copy64(scale, c->red + 3, 1, s));   // s = ||r||_inf
     GABP_HIP(launch_cast_scaled(c->r32, buf[ir], scale, n, s));
+    if ((st = prep_rhs32(c, c->r32, s)) != GABP_OK) return st;
     if ((st = reset_messages32(c, s)) != GABP_OK) return st;
     const double rn = nm.r2;
     double best = rn;
     Norms nbest = nm;
     int ibest = -1, itry = (ir + 1) % 3;
     int inner = 0, since_best = 0;
-    const bool rb = c->opt.schedule == GABP_SCHED_REDBLACK;
+    const bool rb = in_place(c);
     while (true) {
       const int k = std::min({c->opt.check_every, max_sweeps - total, c->opt.ir_max_inner - inner});
       const int start = c->parity32;
@@ -393,9 +421,10 @@ int gabp_sweeps(gabp_ctx* c, const double* b, double* x, int32_t sweeps, int32_t
   if (c->opt.precision == GABP_F32_IR) {
     // FP32 mean-only sweeps on fp32(b) with the FP32 copy of the precomputed Lt
     if ((st = ensure_pre(c, T, s)) != GABP_OK) return st;
-    const bool fresh = !c->msg32[0];
+    const bool fresh = !has_msg32(c);
     if ((st = ensure_msg32(c, s)) != GABP_OK) return st;
     GABP_HIP(launch_cast_scaled(c->r32, b, nullptr, c->L.n, s));
+    if ((st = prep_rhs32(c, c->r32, s)) != GABP_OK) return st;
     if ((reset || fresh) && (st = reset_messages32(c, s)) != GABP_OK) return st;
     for (int i = 0; i < sweeps; ++i)
       if ((st = sweep32(c, T, c->r32, i == sweeps - 1 ? c->d32 : nullptr, s)) != GABP_OK) return st;
@@ -405,6 +434,7 @@ int gabp_sweeps(gabp_ctx* c, const double* b, double* x, int32_t sweeps, int32_t
   }
   if (c->opt.mode == GABP_MODE_PRECOMP && (st = ensure_pre(c, T, s)) != GABP_OK) return st;
   if (reset && (st = reset_messages64(c, s)) != GABP_OK) return st;
+  if ((st = prep_rhs64(c, b, s)) != GABP_OK) return st;
   for (int i = 0; i < sweeps; ++i)
     if ((st = sweep64(c, T, b, i == sweeps - 1 ? x : nullptr, s)) != GABP_OK) return st;
   return GABP_OK;
@@ -419,9 +449,10 @@ int gabp_smooth(gabp_ctx* c, const double* b, double* x, int32_t mu, hipStream_t
   if ((st = residual(c, 0, b, x, nullptr, nullptr, c->r, s)) != GABP_OK) return st;
   if (c->opt.precision == GABP_F32_IR) {
     if ((st = ensure_pre(c, 0, s)) != GABP_OK) return st;
-    const bool fresh = !c->msg32[0];
+    const bool fresh = !has_msg32(c);
     if ((st = ensure_msg32(c, s)) != GABP_OK) return st;
     GABP_HIP(launch_cast_scaled(c->r32, c->r, nullptr, n, s));
+    if ((st = prep_rhs32(c, c->r32, s)) != GABP_OK) return st;
     if ((!warm || fresh) && (st = reset_messages32(c, s)) != GABP_OK) return st;
     for (int i = 0; i < mu; ++i)
       if ((st = sweep32(c, 0, c->r32, i == mu - 1 ? c->d32 : nullptr, s)) != GABP_OK) return st;
@@ -430,6 +461,7 @@ int gabp_smooth(gabp_ctx* c, const double* b, double* x, int32_t mu, hipStream_t
   }
   if (c->opt.mode == GABP_MODE_PRECOMP && (st = ensure_pre(c, 0, s)) != GABP_OK) return st;
   if (!warm && (st = reset_messages64(c, s)) != GABP_OK) return st;
+  if ((st = prep_rhs64(c, c->r, s)) != GABP_OK) return st;
   for (int i = 0; i < mu; ++i)
     if ((st = sweep64(c, 0, c->r, i == mu - 1 ? c->e : nullptr, s)) != GABP_OK) return st;
   GABP_HIP(launch_axpy64(x, c->e, n, s));
@@ -477,6 +509,7 @@ constexpr uint64_t kMagic = 0x6761627073743031ull;  // "gabpst01"
 
 int gabp_get_state(gabp_ctx* c, void* dst, size_t* bytes, hipStream_t s) {
   if (!c || !bytes) return fail(GABP_EINVAL, "NULL argument");
+  if (c->lines) return fail(GABP_ENOTSUPP, "checkpoints of line schedules are not supported");
   const Layout& L = c->L;
   const size_t E = static_cast<size_t>(L.epad + 1), N = static_cast<size_t>(L.n);
   size_t need = sizeof(StateHeader) + 2 * E * sizeof(double);
@@ -515,6 +548,7 @@ int gabp_get_state(gabp_ctx* c, void* dst, size_t* bytes, hipStream_t s) {
 
 int gabp_set_state(gabp_ctx* c, const void* src, size_t bytes, hipStream_t s) {
   if (!c || !src || bytes < sizeof(StateHeader)) return fail(GABP_EINVAL, "bad state");
+  if (c->lines) return fail(GABP_ENOTSUPP, "checkpoints of line schedules are not supported");
   StateHeader h;
   std::memcpy(&h, src, sizeof(h));
   const Layout& L = c->L;

@@ -21,7 +21,7 @@ OK, MAXSWEEPS = 0, 1
 EINVAL, ENOMEM, EZERODIAG, ENUMERIC, EDEVICE, ENOTSUPP = -1, -2, -3, -4, -5, -6
 MODES = {"joint": 0, "precomp": 1}
 PRECISIONS = {"f64": 0, "f32_ir": 1}
-SCHEDULES = {"flood": 0, "redblack": 1}
+SCHEDULES = {"flood": 0, "redblack": 1, "lines": 2, "lines_alt": 3}
 WARM = {"reset": 0, "all": 1}
 
 
@@ -36,7 +36,8 @@ class Options(ctypes.Structure):
                 ("check_every", ctypes.c_int32), ("tol_lambda", ctypes.c_double),
                 ("max_lambda_sweeps", ctypes.c_int32), ("warm", ctypes.c_int32),
                 ("ir_inner_tol", ctypes.c_double), ("ir_max_inner", ctypes.c_int32),
-                ("schedule", ctypes.c_int32), ("use_graphs", ctypes.c_int32)]
+                ("schedule", ctypes.c_int32), ("use_graphs", ctypes.c_int32),
+                ("grid_nx", ctypes.c_int32), ("grid_ny", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -176,7 +177,7 @@ class Solver:
     def __init__(self, n, rowptr, col, val, rev=None, colour=None, *, mode="joint",
                  precision="f64", check_every=16, tol_lambda=1e-14,
                  max_lambda_sweeps=100000, warm="reset", ir_inner_tol=1e-4,
-                 ir_max_inner=1000000, schedule="flood", use_graphs=True):
+                 ir_max_inner=1000000, schedule="flood", use_graphs=True, grid=None):
         lib = load()
         self._lib = lib
         o = Options()
@@ -187,6 +188,8 @@ class Solver:
         o.ir_inner_tol, o.ir_max_inner = float(ir_inner_tol), int(ir_max_inner)
         o.schedule = SCHEDULES[schedule]
         o.use_graphs = int(bool(use_graphs))
+        if grid is not None:                  # (nx, ny) of the line schedules
+            o.grid_nx, o.grid_ny = int(grid[0]), int(grid[1])
         self.options = o
         rp, prp = _host(rowptr, np.int32)
         c, pc = _host(col, np.int32)
