@@ -97,10 +97,17 @@ def main():
     ap.add_argument("--suite", action="store_true",
                     help="also measure the multigrid, batching and adjoint configurations")
     ap.add_argument("--suite-only", action="store_true")
+    ap.add_argument("--suite-part", default="all",
+                    choices=["all", "small", "batch", "mg", "adjoint", "lines"],
+                    help="with --suite-only: run one part of the suite")
+    ap.add_argument("--line-sweeps", type=int, default=50,
+                    help="timed sweeps per variant in the line-sweep part")
     args = ap.parse_args()
     if args.suite_only:
         import torch  # noqa: F401
-        print(json.dumps(suite(lambda *a: print(*a, file=sys.stderr, flush=True))), flush=True)
+        print(json.dumps(suite(lambda *a: print(*a, file=sys.stderr, flush=True),
+                               part=args.suite_part, line_sweeps=args.line_sweeps)),
+              flush=True)
         return
     if args.profile:
         args.steps, args.warmup, args.no_ttr, args.no_cpu = 5, 1, True, True
@@ -300,13 +307,30 @@ def cpu_baseline(a, b, sweeps, log):
             "host_cpus": os.cpu_count()}
 
 
-def suite(log):
+def suite(log, part="all", line_sweeps=50):
     """Measurements of the other configurations (sizes stated in each entry)."""
     import torch
     from paper_1904_04093_amd import gabp
     from paper_1904_04093_amd import workloads as W
     res = {}
+    if part != "all":
+        fn = {"small": lambda: suite_small(log), "batch": lambda: suite_batch(log),
+              "mg": lambda: suite_mg(log), "adjoint": lambda: suite_adjoint(log),
+              "lines": lambda: suite_lines(log, sweeps=line_sweeps)}[part]
+        res[part] = fn()
+        return res
+    res["small_32x32_fp64"] = suite_small(log)
+    res["batch"] = suite_batch(log)
+    res["multigrid"] = suite_mg(log)
+    res["lines"] = suite_lines(log, sweeps=line_sweeps)
+    res["adjoint"] = suite_adjoint(log)
+    return res
 
+
+def suite_small(log):
+    import torch
+    from paper_1904_04093_amd import gabp
+    from paper_1904_04093_amd import workloads as W
     # small plain case: 32 x 32 upwind operator, FP64 joint GaBP to rel.res 1e-10
     a, b = W.small_upwind(32)
     s = gabp.Solver.from_csr(a, mode="joint")
@@ -318,14 +342,60 @@ def suite(log):
     x, info = s.solve(bt, 1e-10, 10000)
     torch.cuda.synchronize()
     xs = np.linalg.solve(W.csr_to_dense(a), b)
-    res["small_32x32_fp64"] = {"seconds": time.perf_counter() - t0, "sweeps": info.sweeps,
-                               "rel_res2": info.rel_res2,
-                               "x_rel_err_vs_dense": float(np.abs(x.cpu().numpy() - xs).max() / np.abs(xs).max())}
-    log(f"[suite] small: {res['small_32x32_fp64']}")
-    res["batch"] = suite_batch(log)
-    res["multigrid"] = suite_mg(log)
-    res["adjoint"] = suite_adjoint(log)
-    return res
+    out = {"seconds": time.perf_counter() - t0, "sweeps": info.sweeps,
+           "rel_res2": info.rel_res2,
+           "x_rel_err_vs_dense": float(np.abs(x.cpu().numpy() - xs).max() / np.abs(xs).max())}
+    log(f"[suite] small: {out}")
+    return out
+
+
+# algorithmic bytes per grid node of one line sweep (both orientations): the line update
+# reads diag, lo, hi, b and the other orientation's two messages and writes two messages
+# (64 B per orientation in FP64 joint mode); each orientation's messages are then
+# transposed into the other layout (read + write); mean-only sweeps move alpha, beta, b,
+# one incoming and one outgoing mean (40 B / 20 B per orientation) plus one transposed mean
+LINE_BYTES_PER_NODE = {"joint_f64": 2 * 64 + 2 * 32, "mean_f64": 2 * 40 + 2 * 16,
+                       "mean_f32": 2 * 20 + 2 * 8}
+
+
+def suite_lines(log, n=4095, sweeps=50):
+    """Line GaBP sweep rates on the anisotropic convection-diffusion fine grid."""
+    import torch
+    from paper_1904_04093_amd import gabp
+    from paper_1904_04093_amd import workloads as W
+    t0 = time.perf_counter()
+    a = W.anisotropic_mg(n, kx=1.0, ky=0.01, peclet=4.0, scaled=False)
+    b = torch.as_tensor(W.rng(4, 2).uniform(-1, 1, a.n)).cuda()
+    out = {"grid": f"{n}x{n}", "nodes": a.n, "generate_s": time.perf_counter() - t0,
+           "bytes_per_node": LINE_BYTES_PER_NODE}
+    # the plain copy kernel on 1 GiB: the attainable-bandwidth reference of this run, and
+    # the calibration kernel of the HBM byte counters
+    src = torch.empty(2 ** 27, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    gabp.copy_probe(src, dst)
+    t_cp = _events_time(lambda k: [gabp.copy_probe(src, dst) for _ in range(k)], 4) / 4
+    out["copy_probe_GBps"] = 2 * src.numel() * 8 / t_cp / 1e9
+    del src, dst
+    variants = (("joint_f64", dict(mode="joint")),
+                ("mean_f64", dict(mode="precomp", tol_lambda=1e-12)),
+                ("mean_f32", dict(mode="precomp", precision="f32_ir", tol_lambda=1e-7)))
+    for sched in ("lines", "lines_alt"):
+        for name, kw in variants:
+            s = gabp.Solver.from_csr(a, schedule=sched, grid=(n, n), **kw)
+            lsw = s.precompute_lambda() if kw["mode"] == "precomp" else 0
+            x = torch.zeros(a.n, dtype=torch.float64, device="cuda")
+            s.sweeps(b, 2, x=x)
+            torch.cuda.synchronize()
+            dt = _events_time(lambda k: s.sweeps(b, sweeps, reset=False, x=x), 1) / sweeps
+            bpn = LINE_BYTES_PER_NODE[name]
+            rec = {"sweep_us": dt * 1e6, "lambda_sweeps": lsw,
+                   "algorithmic_GBps": bpn * a.n / dt / 1e9,
+                   "frac_of_hbm_peak": bpn * a.n / dt / 1e9 / HBM_PEAK_GBS,
+                   "frac_of_copy": bpn * a.n / dt / 1e9 / out["copy_probe_GBps"]}
+            out[f"{sched}_{name}"] = rec
+            log(f"[suite] lines {sched} {name}: {rec}")
+            del s
+    return out
 
 
 def suite_batch(log):
@@ -422,9 +492,14 @@ def suite_mg(log, J=12):
                  dict(mode="precomp", precision="f32_ir", schedule="redblack", tol_lambda=1e-7)),
                 ("redblack_gabp_f64_joint_2_2", "gabp", dict(mode="joint", schedule="redblack")),
                 ("flood_gabp_f32_warm_lambda_2_2", "gabp",
-                 dict(mode="precomp", precision="f32_ir", tol_lambda=1e-7))):
+                 dict(mode="precomp", precision="f32_ir", tol_lambda=1e-7)),
+                ("lines_alt_gabp_f32_warm_lambda_2_2", "gabp",
+                 dict(mode="precomp", precision="f32_ir", schedule="lines_alt", tol_lambda=1e-7)),
+                ("lines_alt_gabp_f64_joint_2_2", "gabp", dict(mode="joint", schedule="lines_alt"))):
             t0 = time.perf_counter()
-            solvers = [gabp.Solver.from_csr(x, colour=W.grid_colouring(sd), **kwg)
+            lines = kwg.get("schedule", "").startswith("lines")
+            solvers = [gabp.Solver.from_csr(x, colour=None if lines else W.grid_colouring(sd),
+                                            grid=(sd, sd) if lines else None, **kwg)
                        for x, sd in zip(levels, sides)]
             mg = gabp.Multigrid(solvers, sides, smoother=smoother, nu1=2, nu2=2)
             x = torch.zeros(levels[0].n, dtype=torch.float64, device="cuda")

@@ -100,70 +100,85 @@ __device__ inline PM pm_shfl(const PM& P, int off) {
             shfl<DOWN>(P.g, off)};
 }
 
-// Incoming state of every thread from the per-thread maps P (thread order = processing
-// order, reversed for REV): the start vector (1, 0, 0) pushed through the maps of all
-// threads before this one. `tot` is LDS for one map per wave.
-template <bool REV>
-__device__ V3 pm_block_scan(PM P, PM* tot) {
+// Forward (from the low threads) and backward (from the high threads) scans at once, so
+// the two shuffle/multiply chains overlap.
+__device__ void pm_block_scan2(PM F, PM Bk, PM* totf, PM* totb, V3* vf, V3* vb) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   for (int off = 1; off < 64; off <<= 1) {
-    const PM Y = pm_shfl<REV>(P, off);
-    if (REV ? (lane + off < 64) : (lane >= off)) {
-      P = pm_mul(P, Y);
-      pm_scale(P);
+    const PM Yf = pm_shfl<false>(F, off);
+    const PM Yb = pm_shfl<true>(Bk, off);
+    if (lane >= off) {
+      F = pm_mul(F, Yf);
+      pm_scale(F);
+    }
+    if (lane + off < 64) {
+      Bk = pm_mul(Bk, Yb);
+      pm_scale(Bk);
     }
   }
-  if (lane == (REV ? 0 : 63)) tot[w] = P;
+  if (lane == 63) totf[w] = F;
+  if (lane == 0) totb[w] = Bk;
   __syncthreads();
-  V3 v{1.0, 0.0, 0.0};
-  if (!REV) {
-    for (int q = 0; q < w; ++q) {
-      v = pm_apply(tot[q], v);
-      v3_scale(v);
-    }
-  } else {
-    for (int q = kLWaves - 1; q > w; --q) {
-      v = pm_apply(tot[q], v);
-      v3_scale(v);
-    }
+  V3 a{1.0, 0.0, 0.0}, c{1.0, 0.0, 0.0};
+  for (int q = 0; q < w; ++q) {
+    a = pm_apply(totf[q], a);
+    v3_scale(a);
   }
-  PM E = pm_shfl<REV>(P, 1);
-  if (lane == (REV ? 63 : 0)) E = pm_identity();
-  v = pm_apply(E, v);
+  for (int q = kLWaves - 1; q > w; --q) {
+    c = pm_apply(totb[q], c);
+    v3_scale(c);
+  }
+  PM Ef = pm_shfl<false>(F, 1);
+  PM Eb = pm_shfl<true>(Bk, 1);
+  if (lane == 0) Ef = pm_identity();
+  if (lane == 63) Eb = pm_identity();
+  *vf = pm_apply(Ef, a);
+  *vb = pm_apply(Eb, c);
   __syncthreads();
-  return v;
 }
 
-// affine maps g -> A g + B, same scan for the mean-only recurrences
-template <typename T, bool REV>
-__device__ T affine_block_scan(T A, T B, T* totA, T* totB) {
+// Affine maps g -> A g + B of the mean-only recurrences: forward and backward scans at once.
+// Returns every thread's incoming g (from the low threads) and q (from the high threads).
+template <typename T>
+__device__ void affine_block_scan2(T Af, T Bf, T Ab, T Bb, T* tot, T* gin, T* qin) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   for (int off = 1; off < 64; off <<= 1) {
-    const T Ya = shfl<REV>(A, off), Yb = shfl<REV>(B, off);
-    if (REV ? (lane + off < 64) : (lane >= off)) {
-      B = fma(A, Yb, B);
-      A = A * Ya;
+    const T Yfa = shfl<false>(Af, off), Yfb = shfl<false>(Bf, off);
+    const T Yba = shfl<true>(Ab, off), Ybb = shfl<true>(Bb, off);
+    if (lane >= off) {
+      Bf = fma(Af, Yfb, Bf);
+      Af = Af * Yfa;
+    }
+    if (lane + off < 64) {
+      Bb = fma(Ab, Ybb, Bb);
+      Ab = Ab * Yba;
     }
   }
-  if (lane == (REV ? 0 : 63)) {
-    totA[w] = A;
-    totB[w] = B;
+  if (lane == 63) {
+    tot[4 * w] = Af;
+    tot[4 * w + 1] = Bf;
+  }
+  if (lane == 0) {
+    tot[4 * w + 2] = Ab;
+    tot[4 * w + 3] = Bb;
   }
   __syncthreads();
-  T g = T(0);
-  if (!REV) {
-    for (int q = 0; q < w; ++q) g = fma(totA[q], g, totB[q]);
-  } else {
-    for (int q = kLWaves - 1; q > w; --q) g = fma(totA[q], g, totB[q]);
+  T g = T(0), q = T(0);
+  for (int k = 0; k < w; ++k) g = fma(tot[4 * k], g, tot[4 * k + 1]);
+  for (int k = kLWaves - 1; k > w; --k) q = fma(tot[4 * k + 2], q, tot[4 * k + 3]);
+  T Efa = shfl<false>(Af, 1), Efb = shfl<false>(Bf, 1);
+  T Eba = shfl<true>(Ab, 1), Ebb = shfl<true>(Bb, 1);
+  if (lane == 0) {
+    Efa = T(1);
+    Efb = T(0);
   }
-  T Ea = shfl<REV>(A, 1), Eb = shfl<REV>(B, 1);
-  if (lane == (REV ? 63 : 0)) {
-    Ea = T(1);
-    Eb = T(0);
+  if (lane == 63) {
+    Eba = T(1);
+    Ebb = T(0);
   }
-  g = fma(Ea, g, Eb);
+  *gin = fma(Efa, g, Efb);
+  *qin = fma(Eba, q, Ebb);
   __syncthreads();
-  return g;
 }
 
 __device__ inline double wave_max64(double v) {
@@ -171,18 +186,13 @@ __device__ inline double wave_max64(double v) {
   return v;
 }
 
-// Coalesced (striped) load of one line array (optionally plus a second one) into LDS.
+// Striped registers (position threadIdx.x + j * kLT in slot j) into LDS.
 template <int NPL, typename T>
-__device__ inline void stage_in(T* sh, const T* __restrict__ g0, const T* __restrict__ g1,
-                                int64_t base, int len) {
+__device__ inline void stage_regs(T* sh, const T* vals, int len) {
 #pragma unroll
   for (int j = 0; j < NPL; ++j) {
     const int t = threadIdx.x + j * kLT;
-    if (t < len) {
-      T v = g0[base + t];
-      if (g1) v += g1[base + t];
-      sh[pidx<NPL>(t)] = v;
-    }
+    if (t < len) sh[pidx<NPL>(t)] = vals[j];
   }
   __syncthreads();
 }
@@ -208,9 +218,9 @@ __device__ inline void stage_out(T* sh, const T* vals, int t0, int len) {
 // precision messages. One block per line; blocks [0, nblk0) take side a0, the rest a1.
 // ---------------------------------------------------------------------------------------
 template <int NPL, bool FIN>
-__global__ __launch_bounds__(kLT) void k_line_joint(LineArgs a0, LineArgs a1, int nblk0) {
+__global__ __launch_bounds__(kLT, 2) void k_line_joint(LineArgs a0, LineArgs a1, int nblk0) {
   __shared__ double sh[kLT * (NPL + 1)];
-  __shared__ PM tot[kLWaves];
+  __shared__ PM totf[kLWaves], totb[kLWaves];
   __shared__ double red[2][kLWaves];
   const bool second = static_cast<int>(blockIdx.x) >= nblk0;
   const LineArgs A = second ? a1 : a0;
@@ -219,34 +229,63 @@ __global__ __launch_bounds__(kLT) void k_line_joint(LineArgs a0, LineArgs a1, in
   const int64_t base = static_cast<int64_t>(line) * len;
   const int t0 = threadIdx.x * NPL;
 
+  // every global load of the line is issued before the first LDS round (striped order,
+  // coalesced); the LDS rounds then hand each thread its NPL consecutive positions
   double d[NPL], c[NPL], lo[NPL], h[NPL + 1];
   double lo_next;
-  stage_in<NPL>(sh, A.diag, A.lam_in, base, len);
-  stage_take<NPL>(sh, t0, len, 1.0, d);
-  __syncthreads();
-  stage_in<NPL>(sh, A.b, A.m_in, base, len);
-  stage_take<NPL>(sh, t0, len, 0.0, c);
-  __syncthreads();
-  stage_in<NPL>(sh, A.lo, static_cast<const double*>(nullptr), base, len);
-  stage_take<NPL>(sh, t0, len, 0.0, lo);
-  lo_next = t0 + NPL < len ? sh[pidx<NPL>(t0 + NPL)] : 0.0;
-  __syncthreads();
-  stage_in<NPL>(sh, A.hi, static_cast<const double*>(nullptr), base, len);
+  {
+    double gd[NPL], gc[NPL], gl[NPL], gh[NPL];
 #pragma unroll
-  for (int k = 0; k < NPL; ++k) h[k + 1] = t0 + k < len ? sh[pidx<NPL>(t0 + k)] : 0.0;
-  h[0] = (t0 > 0 && t0 - 1 < len) ? sh[pidx<NPL>(t0 - 1)] : 0.0;
-  __syncthreads();
+    for (int j = 0; j < NPL; ++j) {
+      const int t = threadIdx.x + j * kLT;
+      if (t < len) {
+        const int64_t i = base + t;
+        gd[j] = A.diag[i] + A.lam_in[i];
+        gc[j] = A.b[i] + A.m_in[i];
+        gl[j] = A.lo[i];
+        gh[j] = A.hi[i];
+      }
+    }
+    stage_regs<NPL>(sh, gd, len);
+    stage_take<NPL>(sh, t0, len, 1.0, d);
+    __syncthreads();
+    stage_regs<NPL>(sh, gc, len);
+    stage_take<NPL>(sh, t0, len, 0.0, c);
+    __syncthreads();
+    stage_regs<NPL>(sh, gl, len);
+    stage_take<NPL>(sh, t0, len, 0.0, lo);
+    lo_next = t0 + NPL < len ? sh[pidx<NPL>(t0 + NPL)] : 0.0;
+    __syncthreads();
+    stage_regs<NPL>(sh, gh, len);
+#pragma unroll
+    for (int k = 0; k < NPL; ++k) h[k + 1] = t0 + k < len ? sh[pidx<NPL>(t0 + k)] : 0.0;
+    h[0] = (t0 > 0 && t0 - 1 < len) ? sh[pidx<NPL>(t0 - 1)] : 0.0;
+    __syncthreads();
+  }
+
+  // per-thread maps of the forward (f_t, g_t) and backward (h_t, q_t) eliminations, and
+  // every thread's incoming state from both ends of the line
+  V3 vf, vb;
+  {
+    PM Pf = pm_identity(), Pb = pm_identity();
+#pragma unroll
+    for (int k = 0; k < NPL; ++k)
+      if (t0 + k < len) Pf = pm_step(Pf, d[k], lo[k] * h[k], c[k], lo[k]);
+#pragma unroll
+    for (int k = NPL - 1; k >= 0; --k)
+      if (t0 + k < len) {
+        const double lnx = k + 1 < NPL ? lo[k + 1] : lo_next;
+        Pb = pm_step(Pb, d[k], lnx * h[k + 1], c[k], h[k + 1]);
+      }
+    pm_scale(Pf);
+    pm_scale(Pb);
+    pm_block_scan2(Pf, Pb, totf, totb, &vf, &vb);
+  }
 
   // forward elimination: f_t, g_t
   double Fl[NPL], Fm[NPL];
   {
-    PM P = pm_identity();
-#pragma unroll
-    for (int k = 0; k < NPL; ++k)
-      if (t0 + k < len) P = pm_step(P, d[k], lo[k] * h[k], c[k], lo[k]);
-    pm_scale(P);
-    const V3 v = pm_block_scan<false>(P, tot);
-    double fp = v.x / v.y, gp = v.z / v.y;   // f_{t0-1}, g_{t0-1} (unused when t0 == 0)
+    double fp = vf.x / vf.y, gp = vf.z / vf.y;   // f_{t0-1}, g_{t0-1} (unused when t0 == 0)
 #pragma unroll
     for (int k = 0; k < NPL; ++k) {
       const int t = t0 + k;
@@ -265,16 +304,7 @@ __global__ __launch_bounds__(kLT) void k_line_joint(LineArgs a0, LineArgs a1, in
   }
   // backward elimination: h_t, q_t
   {
-    PM P = pm_identity();
-#pragma unroll
-    for (int k = NPL - 1; k >= 0; --k)
-      if (t0 + k < len) {
-        const double lnx = k + 1 < NPL ? lo[k + 1] : lo_next;
-        P = pm_step(P, d[k], lnx * h[k + 1], c[k], h[k + 1]);
-      }
-    pm_scale(P);
-    const V3 v = pm_block_scan<true>(P, tot);
-    double hn = v.x / v.y, qn = v.z / v.y;   // h_{t0+NPL}, q_{t0+NPL}
+    double hn = vb.x / vb.y, qn = vb.z / vb.y;   // h_{t0+NPL}, q_{t0+NPL}
 #pragma unroll
     for (int k = NPL - 1; k >= 0; --k) {
       const int t = t0 + k;
@@ -374,7 +404,7 @@ template <typename T, int NPL>
 __global__ __launch_bounds__(kLT) void k_line_mean(LineMeanArgs<T> a0, LineMeanArgs<T> a1,
                                                    int nblk0) {
   __shared__ T sh[kLT * (NPL + 1)];
-  __shared__ T totA[kLWaves], totB[kLWaves];
+  __shared__ T tot[4 * kLWaves];
   const bool second = static_cast<int>(blockIdx.x) >= nblk0;
   const LineMeanArgs<T> A = second ? a1 : a0;
   const int line = second ? blockIdx.x - nblk0 : blockIdx.x;
@@ -383,47 +413,57 @@ __global__ __launch_bounds__(kLT) void k_line_mean(LineMeanArgs<T> a0, LineMeanA
   const int t0 = threadIdx.x * NPL;
 
   T al[NPL], be[NPL], c[NPL], out[NPL];
-  stage_in<NPL>(sh, A.alpha, static_cast<const T*>(nullptr), base, len);
-  stage_take<NPL>(sh, t0, len, T(0), al);
-  __syncthreads();
-  stage_in<NPL>(sh, A.beta, static_cast<const T*>(nullptr), base, len);
-  stage_take<NPL>(sh, t0, len, T(0), be);
-  __syncthreads();
-  stage_in<NPL>(sh, A.b, A.m_in, base, len);
-  stage_take<NPL>(sh, t0, len, T(0), c);
-  __syncthreads();
-
   {
-    T Am = T(1), Bm = T(0);
+    T ga[NPL], gb[NPL], gc[NPL];
+#pragma unroll
+    for (int j = 0; j < NPL; ++j) {
+      const int t = threadIdx.x + j * kLT;
+      if (t < len) {
+        const int64_t i = base + t;
+        ga[j] = A.alpha[i];
+        gb[j] = A.beta[i];
+        gc[j] = A.b[i] + A.m_in[i];
+      }
+    }
+    stage_regs<NPL>(sh, ga, len);
+    stage_take<NPL>(sh, t0, len, T(0), al);
+    __syncthreads();
+    stage_regs<NPL>(sh, gb, len);
+    stage_take<NPL>(sh, t0, len, T(0), be);
+    __syncthreads();
+    stage_regs<NPL>(sh, gc, len);
+    stage_take<NPL>(sh, t0, len, T(0), c);
+    __syncthreads();
+  }
+
+  T g, q;
+  {
+    T Af = T(1), Bf = T(0), Ab = T(1), Bb = T(0);
 #pragma unroll
     for (int k = 0; k < NPL; ++k)
       if (t0 + k < len) {
-        Bm = fma(-al[k], Bm, c[k]);
-        Am = -al[k] * Am;
+        Bf = fma(-al[k], Bf, c[k]);
+        Af = -al[k] * Af;
       }
-    T g = affine_block_scan<T, false>(Am, Bm, totA, totB);
-#pragma unroll
-    for (int k = 0; k < NPL; ++k) {
-      const T f = -al[k] * g;
-      g = c[k] + f;
-      out[k] = f;
-    }
-  }
-  {
-    T Am = T(1), Bm = T(0);
 #pragma unroll
     for (int k = NPL - 1; k >= 0; --k)
       if (t0 + k < len) {
-        Bm = fma(-be[k], Bm, c[k]);
-        Am = -be[k] * Am;
+        Bb = fma(-be[k], Bb, c[k]);
+        Ab = -be[k] * Ab;
       }
-    T q = affine_block_scan<T, true>(Am, Bm, totA, totB);
+    affine_block_scan2<T>(Af, Bf, Ab, Bb, tot, &g, &q);
+  }
 #pragma unroll
-    for (int k = NPL - 1; k >= 0; --k) {
-      const T bk = -be[k] * q;
-      q = c[k] + bk;
-      out[k] += bk;
-    }
+  for (int k = 0; k < NPL; ++k) {
+    const T f = -al[k] * g;
+    g = c[k] + f;
+    out[k] = f;
+  }
+#pragma unroll
+  for (int k = NPL - 1; k >= 0; --k) {
+    const T bk = -be[k] * q;
+    q = c[k] + bk;
+    out[k] += bk;
   }
   stage_out<NPL>(sh, out, t0, len);
 #pragma unroll
