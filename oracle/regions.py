@@ -24,13 +24,14 @@ tridiagonal recurrences that a line region allows are deliberately not used here
 Readings of points the paper leaves open (also listed in the design notes):
 
 * initial messages are zero (as for Algorithm 1);
-* one sweep = read off, then update every message, as for Algorithm 1: the s-th read-off
-  uses s-1 updates. The read-off is the belief of the small region {l}:
-  x_l = (b_l + sum of all m_{L l}) / (A_ll + sum of all Lambda_{L l}) -- it uses every
-  parent's message once, so it does not depend on the order in which the regions are
-  visited. Algorithm 2 writes [x]_L region by region; at a fixed point every region's
-  [x]_L equals this belief (and A^{-1} b, Theorem prop:generalized_GaBP_Consistency), and
-  ``sweep`` returns the per-region solutions too;
+* the read-off is Algorithm 2's own: every region L writes [x]_L = Lambda~_0^{-1} b~_0 when
+  it is updated, so a node keeps the solution of the last region containing it in the
+  processing order (regions in list order, groups in group order). For the line partition
+  (rows listed before columns) that is the node's column solution. ``sweep`` returns it
+  with the per-region solutions; ``readoff`` gives the single-node belief
+  (b_l + sum m_{L l}) / (A_ll + sum Lambda_{L l}) of a message state instead, which is what
+  the Bethe-region reduction to Algorithm 1 compares. At a fixed point both equal A^{-1} b
+  (Theorem prop:generalized_GaBP_Consistency);
 * Lambda converged: max|dLambda| <= tol_lambda * max|Lambda| between consecutive updates;
 * schedules: "flood" (every region from the previous iteration's messages, the literal
   all-regions-in-parallel reading) and, with ``groups``, region groups updated one after
@@ -132,15 +133,15 @@ def readoff(rg, b, lam, m):
 def sweep(rg, b, lam, m, lam_fixed=None, groups=None):
     """One iteration. Returns (x, x_regions, lam_new, m_new).
 
-    x is the read-off from the incoming messages; x_regions[k] = [x]_L of region k computed
-    in this iteration. ``lam_fixed = (lam*, inverses)`` freezes the precision messages and
+    x_regions[k] = [x]_L of region k computed in this iteration; x is Algorithm 2's read-off
+    (every node takes the [x]_L of the last region written that contains it). ``lam_fixed = (lam*, inverses)`` freezes the precision messages and
     reuses the region inverses (precomputed Lambda, Sec. 4.2 applied to Algorithm 2).
     ``groups`` (lists of region indices): update group by group from the newest messages;
     None: flood, every region from the incoming messages.
     """
     b = np.asarray(b, dtype=np.float64)
     tl, tm = _totals(rg, lam, m)
-    x = (b + tm) / (rg.diag + tl)
+    x = np.full(rg.n, np.nan)
     lam_new, m_new = list(lam), list(m)
     xr = [None] * len(rg.regions)
     for grp in (groups if groups is not None else [range(len(rg.regions))]):
@@ -160,8 +161,12 @@ def sweep(rg, b, lam, m, lam_fixed=None, groups=None):
             upd.append((k, s - rg.diag[r] - other_l if lam_fixed is None else lam[k],
                         s * xl - b[r] - other_m))
             xr[k] = xl
+            x[r] = xl
         for k, lk, mk in upd:
             lam_new[k], m_new[k] = lk, mk
+    # nodes in no region keep the belief of their (message-free) small region
+    lone = np.isnan(x)
+    x[lone] = b[lone] / rg.diag[lone]
     return x, xr, lam_new, m_new
 
 

@@ -9,6 +9,9 @@
 //   Lambda_out(t) = (f_t - d_t) + (h_t - d_t),   m_out(t) = (g_t - c_t) + (q_t - c_t)
 //
 // (lo_t / hi_t: coupling of position t to its predecessor / successor along the line).
+// The read-off is Algorithm 2's [x]_L of the last line updated that contains the node, its
+// column: x = (c_t + m_out(t)) / (d_t + Lambda_out(t)) of the column update, formed in the
+// column layout right after that update and transposed into the row layout.
 // f_t + h_t - d_t is 1 / (T^{-1})_tt of the line's tridiagonal matrix T and g_t + q_t - c_t
 // is that Schur complement times x_t, so these are eq. Two_layers_GaBP_rules with the
 // line's own diagonal and incoming messages removed. With frozen precision messages the
@@ -66,8 +69,10 @@ struct LineLayout {
   double* bcol = nullptr;                  // [n] right-hand side in the column layout
   float* bcol32 = nullptr;
   double* zero = nullptr;                  // [n] zeros (right-hand side of the Lt phase)
-  double* invS[2] = {nullptr, nullptr};    // [T][n] 1 / (A_ii + Lambda*_row + Lambda*_col)
-  float* invS32[2] = {nullptr, nullptr};
+  double* invS[2] = {nullptr, nullptr};    // [T][n] 1 / (T^{-1})_tt of the frozen column
+  float* invS32[2] = {nullptr, nullptr};   //   systems, column layout (frozen read-off)
+  double* xcol = nullptr;                  // [n] read-off in the column layout
+  float* xcol32 = nullptr;
   double* partials = nullptr;              // [2 * (nx + ny)] per-line max|dLambda|, max|Lambda|
 };
 
@@ -86,6 +91,8 @@ struct LineArgs {
   double* beta;
   float* alpha32;
   float* beta32;
+  double* invS;           // with alpha: also 1 / (T^{-1})_tt = 1 / (f_t + h_t - d_t), if non-null
+  float* invS32;
   double* partials;       // non-null: per line max|Lambda_out - old|, max|Lambda_out|
 };
 
@@ -118,8 +125,6 @@ hipError_t launch_line_readoff64(int64_t n, const double* b, const double* diag,
                                  hipStream_t s);
 hipError_t launch_line_readoff32(int64_t n, const float* b, const float* m_r, const float* m_c,
                                  const float* invS, float* x, hipStream_t s);
-hipError_t launch_line_invS(int64_t n, const double* diag, const double* lam_r,
-                            const double* lam_c, double* invS, float* invS32, hipStream_t s);
 hipError_t launch_gather_values(int64_t n, const int32_t* src, const double* val, double* dst,
                                 hipStream_t s);
 

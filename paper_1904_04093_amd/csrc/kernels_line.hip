@@ -284,6 +284,7 @@ __global__ __launch_bounds__(kLT, 2) void k_line_joint(LineArgs a0, LineArgs a1,
 
   // forward elimination: f_t, g_t
   double Fl[NPL], Fm[NPL];
+  double Sf[FIN ? NPL : 1];   // FIN: f_t + h_t - d_t, the line's Schur complement at t
   {
     double fp = vf.x / vf.y, gp = vf.z / vf.y;   // f_{t0-1}, g_{t0-1} (unused when t0 == 0)
 #pragma unroll
@@ -300,6 +301,7 @@ __global__ __launch_bounds__(kLT, 2) void k_line_joint(LineArgs a0, LineArgs a1,
       gp = c[k] + fm;
       Fl[k] = FIN ? al : fl;
       Fm[k] = fm;
+      if constexpr (FIN) Sf[k] = fp;
     }
   }
   // backward elimination: h_t, q_t
@@ -318,8 +320,9 @@ __global__ __launch_bounds__(kLT, 2) void k_line_joint(LineArgs a0, LineArgs a1,
       }
       hn = d[k] + bl;
       qn = c[k] + bm;
-      if (FIN) {
+      if constexpr (FIN) {
         Fm[k] = be;
+        Sf[k] += bl;
       } else {
         Fl[k] += bl;
         Fm[k] += bm;
@@ -327,7 +330,7 @@ __global__ __launch_bounds__(kLT, 2) void k_line_joint(LineArgs a0, LineArgs a1,
     }
   }
 
-  if (FIN) {
+  if constexpr (FIN) {
     stage_out<NPL>(sh, Fl, t0, len);
 #pragma unroll
     for (int j = 0; j < NPL; ++j) {
@@ -347,6 +350,19 @@ __global__ __launch_bounds__(kLT, 2) void k_line_joint(LineArgs a0, LineArgs a1,
         const double v = sh[pidx<NPL>(t)];
         A.beta[base + t] = v;
         A.beta32[base + t] = static_cast<float>(v);
+      }
+    }
+    if (A.invS) {
+      __syncthreads();
+      stage_out<NPL>(sh, Sf, t0, len);
+#pragma unroll
+      for (int j = 0; j < NPL; ++j) {
+        const int t = threadIdx.x + j * kLT;
+        if (t < len) {
+          const double v = 1.0 / sh[pidx<NPL>(t)];
+          A.invS[base + t] = v;
+          A.invS32[base + t] = static_cast<float>(v);
+        }
       }
     }
     return;
@@ -524,16 +540,6 @@ __global__ void k_line_readoff32(int64_t n, const float* __restrict__ b, const f
   x[i] = (b[i] + m_r[i] + m_c[i]) * invS[i];
 }
 
-__global__ void k_line_invS(int64_t n, const double* __restrict__ diag, const double* __restrict__ lam_r,
-                            const double* __restrict__ lam_c, double* __restrict__ invS,
-                            float* __restrict__ invS32) {
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-  if (i >= n) return;
-  const double v = 1.0 / (diag[i] + lam_r[i] + lam_c[i]);
-  invS[i] = v;
-  invS32[i] = static_cast<float>(v);
-}
-
 __global__ void k_gather_values(int64_t n, const int32_t* __restrict__ src,
                                 const double* __restrict__ val, double* __restrict__ dst) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
@@ -657,13 +663,6 @@ hipError_t launch_line_readoff32(int64_t n, const float* b, const float* m_r, co
                                  const float* invS, float* x, hipStream_t s) {
   if (n == 0) return hipSuccess;
   k_line_readoff32<<<elem_blocks(n), 256, 0, s>>>(n, b, m_r, m_c, invS, x);
-  return hipGetLastError();
-}
-
-hipError_t launch_line_invS(int64_t n, const double* diag, const double* lam_r,
-                            const double* lam_c, double* invS, float* invS32, hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  k_line_invS<<<elem_blocks(n), 256, 0, s>>>(n, diag, lam_r, lam_c, invS, invS32);
   return hipGetLastError();
 }
 

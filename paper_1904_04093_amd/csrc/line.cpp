@@ -65,24 +65,41 @@ void joint_args(const LineLayout& G, int T, const double* b_row, const double* b
   const LineSide& R = G.side[0];
   const LineSide& C = G.side[1];
   a[0] = LineArgs{R.nlines, R.len, R.diag, R.lo[T], R.hi[T], b_row, C.lam_x, C.m_x,
-                  R.lam_own, R.m_own, nullptr, nullptr, nullptr, nullptr, nullptr};
+                  R.lam_own, R.m_own, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                  nullptr};
   a[1] = LineArgs{C.nlines, C.len, C.diag, C.lo[T], C.hi[T], b_col, R.lam_x, R.m_x,
-                  C.lam_own, C.m_own, nullptr, nullptr, nullptr, nullptr, nullptr};
+                  C.lam_own, C.m_own, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                  nullptr};
+}
+
+// Read-off of the column update just made (before the column messages move to the row
+// layout): x = (b + m_row + m_col) / (A_ii + Lambda_row + Lambda_col) in the column layout
+// with the row messages that update used (flood: previous sweep; alt: this sweep), then
+// transposed into x (row layout). invS: frozen 1/Sigma* in the column layout, or null.
+int readoff_col64(const LineLayout& G, const double* invS, double* x, hipStream_t s) {
+  const LineSide& R = G.side[0];
+  const LineSide& C = G.side[1];
+  GABP_HIP(launch_line_readoff64(G.n, G.bcol, C.diag, R.lam_x, R.m_x, C.lam_own, C.m_own, invS,
+                                 G.xcol, s));
+  TransposeJob<double> j{G.xcol, x, G.nx, G.ny};
+  GABP_HIP(launch_transpose64(&j, 1, s));
+  return GABP_OK;
 }
 
 // one joint update of every line (flood: both orientations from the previous messages;
-// alt: rows, then columns from the new row messages)
-int joint_update(const LineLayout& G, LineArgs a[2], hipStream_t s) {
+// alt: rows, then columns from the new row messages); x != null: the read-off
+int joint_update(const LineLayout& G, LineArgs a[2], double* x, hipStream_t s) {
+  int st;
   if (!G.alt) {
     GABP_HIP(launch_line_joint(a, 2, s));
-    int st = transpose_side(G, 0, true, s);
-    if (st != GABP_OK) return st;
+    if (x && (st = readoff_col64(G, nullptr, x, s)) != GABP_OK) return st;
+    if ((st = transpose_side(G, 0, true, s)) != GABP_OK) return st;
     return transpose_side(G, 1, true, s);
   }
   for (int o = 0; o < 2; ++o) {
     GABP_HIP(launch_line_joint(&a[o], 1, s));
-    const int st = transpose_side(G, o, true, s);
-    if (st != GABP_OK) return st;
+    if (o == 1 && x && (st = readoff_col64(G, nullptr, x, s)) != GABP_OK) return st;
+    if ((st = transpose_side(G, o, true, s)) != GABP_OK) return st;
   }
   return GABP_OK;
 }
@@ -166,6 +183,7 @@ int line_setup(gabp_ctx* c, int nx, int ny, const int32_t* rowptr, const int32_t
   }
   int st;
   if ((st = dev_zeros(&G->bcol, n)) || (st = dev_zeros(&G->zero, n)) ||
+      (st = dev_zeros(&G->xcol, n)) ||
       (st = dev_zeros(&G->partials, 2 * static_cast<int64_t>(nx + ny))))
     return st;
   return GABP_OK;
@@ -184,7 +202,7 @@ void line_destroy(LineLayout* G) {
       F(S.alpha[T]); F(S.beta[T]); F(S.alpha32[T]); F(S.beta32[T]);
     }
   }
-  F(G->bcol); F(G->bcol32); F(G->zero); F(G->partials);
+  F(G->bcol); F(G->bcol32); F(G->zero); F(G->partials); F(G->xcol); F(G->xcol32);
   for (int T = 0; T < 2; ++T) {
     F(G->invS[T]); F(G->invS32[T]);
   }
@@ -219,7 +237,7 @@ int line_ensure32(gabp_ctx* c, hipStream_t s) {
   int st;
   for (auto& S : G.side)
     if ((st = dev_zeros(&S.m32_own, G.n)) || (st = dev_zeros(&S.m32_x, G.n))) return st;
-  if ((st = dev_zeros(&G.bcol32, G.n))) return st;
+  if ((st = dev_zeros(&G.bcol32, G.n)) || (st = dev_zeros(&G.xcol32, G.n))) return st;
   (void)s;
   return GABP_OK;
 }
@@ -253,28 +271,25 @@ int line_sweep64(gabp_ctx* c, int T, const double* b, double* x, hipStream_t s) 
   const LineLayout& G = *c->lines;
   const LineSide& R = G.side[0];
   const LineSide& C = G.side[1];
-  const bool pre = c->opt.mode == GABP_MODE_PRECOMP;
-  if (x)
-    GABP_HIP(launch_line_readoff64(G.n, b, R.diag, R.lam_own, R.m_own, C.lam_x, C.m_x,
-                                   pre ? G.invS[T] : nullptr, x, s));
-  if (!pre) {
+  if (c->opt.mode != GABP_MODE_PRECOMP) {
     LineArgs a[2];
     joint_args(G, T, b, G.bcol, a);
-    return joint_update(G, a, s);
+    return joint_update(G, a, x, s);
   }
   LineMeanArgs<double> m[2] = {
       {R.nlines, R.len, R.alpha[T], R.beta[T], b, C.m_x, R.m_own},
       {C.nlines, C.len, C.alpha[T], C.beta[T], G.bcol, R.m_x, C.m_own}};
+  int st;
   if (!G.alt) {
     GABP_HIP(launch_line_mean64(m, 2, s));
-    int st = transpose_side(G, 0, false, s);
-    if (st != GABP_OK) return st;
+    if (x && (st = readoff_col64(G, G.invS[T], x, s)) != GABP_OK) return st;
+    if ((st = transpose_side(G, 0, false, s)) != GABP_OK) return st;
     return transpose_side(G, 1, false, s);
   }
   for (int o = 0; o < 2; ++o) {
     GABP_HIP(launch_line_mean64(&m[o], 1, s));
-    const int st = transpose_side(G, o, false, s);
-    if (st != GABP_OK) return st;
+    if (o == 1 && x && (st = readoff_col64(G, G.invS[T], x, s)) != GABP_OK) return st;
+    if ((st = transpose_side(G, o, false, s)) != GABP_OK) return st;
   }
   return GABP_OK;
 }
@@ -283,20 +298,26 @@ int line_sweep32(gabp_ctx* c, int T, const float* b, float* x, hipStream_t s) {
   const LineLayout& G = *c->lines;
   const LineSide& R = G.side[0];
   const LineSide& C = G.side[1];
-  if (x) GABP_HIP(launch_line_readoff32(G.n, b, R.m32_own, C.m32_x, G.invS32[T], x, s));
+  auto readoff = [&]() -> int {
+    GABP_HIP(launch_line_readoff32(G.n, G.bcol32, R.m32_x, C.m32_own, G.invS32[T], G.xcol32, s));
+    TransposeJob<float> j{G.xcol32, x, G.nx, G.ny};
+    GABP_HIP(launch_transpose32(&j, 1, s));
+    return GABP_OK;
+  };
   LineMeanArgs<float> m[2] = {
       {R.nlines, R.len, R.alpha32[T], R.beta32[T], b, C.m32_x, R.m32_own},
       {C.nlines, C.len, C.alpha32[T], C.beta32[T], G.bcol32, R.m32_x, C.m32_own}};
+  int st;
   if (!G.alt) {
     GABP_HIP(launch_line_mean32(m, 2, s));
-    int st = transpose_side32(G, 0, s);
-    if (st != GABP_OK) return st;
+    if (x && (st = readoff()) != GABP_OK) return st;
+    if ((st = transpose_side32(G, 0, s)) != GABP_OK) return st;
     return transpose_side32(G, 1, s);
   }
   for (int o = 0; o < 2; ++o) {
     GABP_HIP(launch_line_mean32(&m[o], 1, s));
-    const int st = transpose_side32(G, o, s);
-    if (st != GABP_OK) return st;
+    if (o == 1 && x && (st = readoff()) != GABP_OK) return st;
+    if ((st = transpose_side32(G, o, s)) != GABP_OK) return st;
   }
   return GABP_OK;
 }
@@ -326,7 +347,7 @@ int line_precompute(gabp_ctx* c, int T, hipStream_t s) {
   const double tol = c->opt.tol_lambda;
   int done = 0;
   for (int it = 1; it <= c->opt.max_lambda_sweeps; ++it) {
-    if ((st = joint_update(G, a, s)) != GABP_OK) return st;
+    if ((st = joint_update(G, a, nullptr, s)) != GABP_OK) return st;
     GABP_HIP(launch_max_pairs(R.nlines + C.nlines, G.partials, c->red + 5, s));
     done = it;
     if (tol > 0.0) {
@@ -339,7 +360,8 @@ int line_precompute(gabp_ctx* c, int T, hipStream_t s) {
       if (dm <= tol * lm) break;
     }
   }
-  // frozen multipliers from the final messages (both orientations, one launch)
+  // frozen multipliers from the final messages (both orientations, one launch), and the
+  // read-off factor of the frozen column systems, 1 / (T^{-1})_tt, in the column layout
   LineArgs f[2];
   joint_args(G, T, G.zero, G.zero, f);
   for (int o = 0; o < 2; ++o) {
@@ -351,8 +373,9 @@ int line_precompute(gabp_ctx* c, int T, hipStream_t s) {
     f[o].alpha32 = S.alpha32[T];
     f[o].beta32 = S.beta32[T];
   }
+  f[1].invS = G.invS[T];
+  f[1].invS32 = G.invS32[T];
   GABP_HIP(launch_line_joint(f, 2, s));
-  GABP_HIP(launch_line_invS(G.n, R.diag, R.lam_own, C.lam_x, G.invS[T], G.invS32[T], s));
   if ((st = zero_joint(G, s)) != GABP_OK) return st;
   P.sweeps = done;
   P.valid = true;

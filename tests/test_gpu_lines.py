@@ -231,3 +231,77 @@ def test_line_setup_rejects_what_it_cannot_run(B):
     with pytest.raises(B.GaBPError) as e:
         s.get_state()
     assert e.value.status == B.ENOTSUPP
+
+
+# --------------------------------------------------------------------------------------
+# full size (4095 x 4095 fine grid of the multigrid configuration): properties that hold at
+# any size, in the launch configuration the benchmark times
+# --------------------------------------------------------------------------------------
+
+def _banded_rows(A_rows, b_rows):
+    """Solve independent tridiagonal systems (one per row) with LAPACK's banded solver."""
+    import scipy.linalg
+    out = np.empty_like(b_rows)
+    for r in range(b_rows.shape[0]):
+        lo, d, hi = A_rows[r]
+        ab = np.zeros((3, len(d)))
+        ab[0, 1:] = hi[:-1]
+        ab[1] = d
+        ab[2, :-1] = lo[1:]
+        out[r] = scipy.linalg.solve_banded((1, 1), ab, b_rows[r])
+    return out
+
+
+@pytest.mark.parametrize("decoupled", ["columns", "rows"])
+def test_full_size_decoupled_lines_are_exact_after_one_update(B, decoupled):
+    # with one direction's couplings absent every line is an independent tridiagonal system:
+    # the second read-off (one update) is its exact solution (the region graph is a forest)
+    n = 4095
+    kw = dict(ky=0.0) if decoupled == "columns" else dict(kx=0.0)
+    a = W.random_grid_5pt(n, n, W.rng(507, 2), margin=0.05, flip=0.1, one_way=0.05, **kw)
+    b = W.rng(507, 0).uniform(-1, 1, a.n)
+    s = B.Solver.from_csr(a, schedule="lines", grid=(n, n))
+    x = s.sweeps(_cuda(b), 2).cpu().numpy()
+    # sampled lines solved on the CPU
+    lines = np.sort(W.rng(507, 1).choice(n, size=24, replace=False))
+    step = 1 if decoupled == "columns" else n
+    A_rows, b_rows, idx_rows = [], [], []
+    for ln in lines:
+        idx = ln * n + np.arange(n) if decoupled == "columns" else ln + n * np.arange(n)
+        dg, lo, hi = np.zeros(n), np.zeros(n), np.zeros(n)
+        for t, i in enumerate(idx):
+            for e in range(a.rowptr[i], a.rowptr[i + 1]):
+                j = a.col[e]
+                if j == i:
+                    dg[t] = a.val[e]
+                elif j == i - step:
+                    lo[t] = a.val[e]
+                elif j == i + step:
+                    hi[t] = a.val[e]
+        A_rows.append((lo, dg, hi))
+        b_rows.append(b[idx])
+        idx_rows.append(idx)
+    want = _banded_rows(A_rows, np.array(b_rows))
+    for k, idx in enumerate(idx_rows):
+        assert _rel_inf(x[idx], want[k]) < 1e-12, (decoupled, lines[k])
+
+
+@pytest.mark.parametrize("schedule", ["lines", "lines_alt"])
+def test_full_size_line_sweeps_are_linear_and_scale_invariant(B, schedule):
+    # the precision messages do not depend on b and the mean messages are linear in it, so
+    # the read-off is linear in b; scaling row i of (A, b) by d_i leaves every line solution
+    # unchanged (each line system is scaled row by row), and so does (A, b) -> (-A, -b)
+    n = 4095
+    a = W.anisotropic_mg(n, kx=1.0, ky=0.01, peclet=4.0, scaled=False)
+    r = W.rng(508, 0)
+    b1, b2 = r.uniform(-1, 1, a.n), r.uniform(-1, 1, a.n)
+    s = B.Solver.from_csr(a, schedule=schedule, grid=(n, n))
+    x1 = s.sweeps(_cuda(b1), 5).cpu().numpy()
+    x2 = s.sweeps(_cuda(b2), 5).cpu().numpy()
+    x12 = s.sweeps(_cuda(b1 + b2), 5).cpu().numpy()
+    assert _rel_inf(x12, x1 + x2) < 1e-12
+    d = r.uniform(0.5, 2.0, a.n) * np.where(r.random(a.n) < 0.5, -1.0, 1.0)
+    rows = np.repeat(np.arange(a.n), np.diff(a.rowptr))
+    ds = B.Solver(a.n, a.rowptr, a.col, a.val * d[rows], schedule=schedule, grid=(n, n))
+    xs = ds.sweeps(_cuda(d * b1), 5).cpu().numpy()
+    assert _rel_inf(xs, x1) < 1e-12

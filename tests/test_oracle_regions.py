@@ -35,7 +35,8 @@ def _bethe_vs_gabp(a_csr, b, sweeps):
     Lt, mm = np.zeros(g.E), np.zeros(g.E)
     worst = 0.0
     for s in range(sweeps):
-        x_r, _, lam, m = RG.sweep(rg, b, lam, m)
+        x_r = RG.readoff(rg, b, lam, m)           # belief of the single-node regions
+        _, _, lam, m = RG.sweep(rg, b, lam, m)
         x_g, Lt, mm, _, _ = G.sweep(g, b, Lt, mm)
         worst = max(worst, _relerr(x_r, x_g))
         for k, (i, j) in enumerate(rg.regions):
@@ -67,17 +68,25 @@ def test_bethe_regions_reduce_to_gabp_on_a_grid():
 # exactness when the region graph is a tree
 # --------------------------------------------------------------------------------------
 
+@pytest.mark.parametrize("grouped", [False, True])
 @pytest.mark.parametrize("shape", [(17, 1), (1, 13)])
-def test_single_line_is_exact_after_one_update(shape):
+def test_single_line_is_solved_exactly(shape, grouped):
+    # the read-off is the node's column solution: a single column is solved by the first
+    # sweep; a single row needs the row's messages first (flood: the second sweep; rows
+    # then columns: the first)
     nx, ny = shape
     a = W.random_grid_5pt(nx, ny, W.rng(402, nx), one_way=0.1, flip=0.2)
     b = W.rng(402, 7).uniform(-1, 1, a.n)
     rg = _lines(a, nx, ny)
     A = W.csr_to_dense(a)
-    x1, _, _ = RG.run(rg, b, 1)
-    assert np.allclose(x1, b / np.diag(A), rtol=1e-15, atol=0)    # zero messages: Jacobi
-    x2, _, _ = RG.run(rg, b, 2)
-    assert _relerr(x2, np.linalg.solve(A, b)) < 1e-13
+    grp = RG.line_groups(nx, ny) if grouped else None
+    x1, _, _ = RG.run(rg, b, 1, groups=grp)
+    if ny == 1 and not grouped:
+        assert np.allclose(x1, b / np.diag(A), rtol=1e-15, atol=0)    # zero messages: Jacobi
+        x2, _, _ = RG.run(rg, b, 2, groups=grp)
+        assert _relerr(x2, np.linalg.solve(A, b)) < 1e-13
+    else:
+        assert _relerr(x1, np.linalg.solve(A, b)) < 1e-13
 
 
 @pytest.mark.parametrize("decouple", ["vertical", "horizontal"])
@@ -87,8 +96,11 @@ def test_decoupled_lines_are_exact_after_one_update(decouple):
     a = W.random_grid_5pt(nx, ny, W.rng(403, 0), flip=0.2, **kw)
     b = W.rng(403, 1).uniform(-1, 1, a.n)
     rg = _lines(a, nx, ny)
+    want = np.linalg.solve(W.csr_to_dense(a), b)
     x2, _, _ = RG.run(rg, b, 2)
-    assert _relerr(x2, np.linalg.solve(W.csr_to_dense(a), b)) < 1e-13
+    assert _relerr(x2, want) < 1e-13
+    x1, _, _ = RG.run(rg, b, 1, groups=RG.line_groups(nx, ny))   # rows, then columns
+    assert _relerr(x1, want) < 1e-13
 
 
 def test_coupled_grid_is_not_exact_after_one_update():
@@ -216,10 +228,13 @@ def test_grid_transpose_is_equivariant():
     At[np.ix_(p, p)] = A
     bt = np.zeros_like(b)
     bt[p] = b
+    rg, rgt = _lines(a, nx, ny), _lines(W.csr_from_dense(At), ny, nx)
     for s in (2, 3, 5):
-        x, _, _ = RG.run(_lines(a, nx, ny), b, s)
-        xt, _, _ = RG.run(_lines(W.csr_from_dense(At), ny, nx), bt, s)
-        assert _relerr(xt[p], x) < 1e-13
+        # the message state is equivariant (the read-off is not: it takes the column
+        # solution, and columns become rows)
+        _, lam, m = RG.run(rg, b, s)
+        _, lamt, mt = RG.run(rgt, bt, s)
+        assert _relerr(RG.readoff(rgt, bt, lamt, mt)[p], RG.readoff(rg, b, lam, m)) < 1e-13
 
 
 # --------------------------------------------------------------------------------------
