@@ -98,7 +98,7 @@ def main():
                     help="also measure the multigrid, batching and adjoint configurations")
     ap.add_argument("--suite-only", action="store_true")
     ap.add_argument("--suite-part", default="all",
-                    choices=["all", "small", "batch", "mg", "adjoint", "lines"],
+                    choices=["all", "small", "batch", "mg", "adjoint", "lines", "sec5"],
                     help="with --suite-only: run one part of the suite")
     ap.add_argument("--line-sweeps", type=int, default=50,
                     help="timed sweeps per variant in the line-sweep part")
@@ -316,15 +316,73 @@ def suite(log, part="all", line_sweeps=50):
     if part != "all":
         fn = {"small": lambda: suite_small(log), "batch": lambda: suite_batch(log),
               "mg": lambda: suite_mg(log), "adjoint": lambda: suite_adjoint(log),
-              "lines": lambda: suite_lines(log, sweeps=line_sweeps)}[part]
+              "lines": lambda: suite_lines(log, sweeps=line_sweeps),
+              "sec5": lambda: suite_sec5(log)}[part]
         res[part] = fn()
         return res
     res["small_32x32_fp64"] = suite_small(log)
     res["batch"] = suite_batch(log)
     res["multigrid"] = suite_mg(log)
     res["lines"] = suite_lines(log, sweeps=line_sweeps)
+    res["sec5"] = suite_sec5(log)
     res["adjoint"] = suite_adjoint(log)
     return res
+
+
+def _sec5_printed():
+    """V-cycle counts printed in the paper's Sec. 5 tables (tests/golden/sec5_iterations.txt)."""
+    out = []
+    for line in open(os.path.join(ROOT, "tests", "golden", "sec5_iterations.txt")):
+        f = line.split("#")[0].split()
+        if not f:
+            continue
+        kw = {k: float(v) if ("." in v or "e" in v) else int(v)
+              for k, v in (p.split("=") for p in f[1].split(","))}
+        nu = (2, 2) if f[3] == "any" else (int(f[3]), int(f[4]))
+        out.append((f[0], kw, f[1], f[2], nu, None if f[-2] == "div" else int(f[-2])))
+    return out
+
+
+def suite_sec5(log, cap=100):
+    """The paper's Sec. 5 multigrid problems on the 63 x 63 grid: V-cycles (down to one point)
+    until ||r||_inf <= 2e-4, next to the counts the paper prints."""
+    import torch
+    from paper_1904_04093_amd import gabp
+    from paper_1904_04093_amd import workloads as W
+    smoothers = {"redblack_gabp": ("gabp", dict(mode="joint", schedule="redblack")),
+                 "line_gabp": ("gabp", dict(mode="joint", schedule="lines_alt")),
+                 "redblack_gs": ("rbgs", dict())}
+    rows = []
+    for prob, kw, pname, smoother, nu, printed in _sec5_printed():
+        levels, b = W.sec5_hierarchy(prob, 6, 1, **kw)
+        sides = [int(round(np.sqrt(a.n))) for a in levels]
+        sm, skw = smoothers[smoother]
+        lines = skw.get("schedule", "").startswith("lines")
+        solvers = [gabp.Solver.from_csr(a, colour=None if lines else W.grid_colouring(sd),
+                                        grid=(sd, sd) if lines else None, **skw)
+                   for a, sd in zip(levels, sides)]
+        mg = gabp.Multigrid(solvers, sides, smoother=sm, nu1=nu[0], nu2=nu[1])
+        bt = torch.as_tensor(b).cuda()
+        x = torch.zeros(levels[0].n, dtype=torch.float64, device="cuda")
+        t0 = time.perf_counter()
+        ours, rinf = None, float("nan")
+        for k in range(1, cap + 1):
+            mg.vcycle(bt, x)
+            _, (_, rinf, _) = solvers[0].residual(bt, x, want_r=False)
+            if not np.isfinite(rinf) or rinf > 1e30:
+                break
+            if rinf <= 2e-4:
+                ours = k
+                break
+        dt = time.perf_counter() - t0
+        rec = {"problem": prob, "params": pname, "smoother": smoother, "pre_post": list(nu),
+               "paper_cycles": printed if printed is not None else "diverges",
+               "cycles": ours if ours is not None else "diverges" if not rinf <= 1e30 else f"cap {cap}",
+               "seconds": dt}
+        rows.append(rec)
+        log(f"[suite] sec5 {rec}")
+        del mg, solvers
+    return rows
 
 
 def suite_small(log):

@@ -473,3 +473,114 @@ def random_grid_5pt(nx: int, ny: int, r: np.random.Generator, margin: float = 0.
     rowptr = np.zeros(n + 1, dtype=np.int32)
     rowptr[1:] = np.cumsum(keep.sum(1))
     return CSR(n, rowptr, cols, vals, {"grid": (nx, ny)})
+
+
+# ---------------------------------------------------------------------------------------
+# The analytic test problems of the paper's numerical section (Sec. 5): variable-coefficient
+# operators a phi_xx + b phi_yy + alpha phi_x + beta phi_y on the unit square with Dirichlet
+# data and source from a manufactured solution. Discretised here by second-order central
+# differences on the vertex-centred n x n interior grid, h = 1/(n+1), unscaled (1/h^2).
+# ---------------------------------------------------------------------------------------
+
+def _sec5_stand_alone():
+    pi = np.pi
+    coef = (lambda x, y: np.exp(-x * (y + 2.0)) + 10.0,
+            lambda x, y: np.exp(-2.0 * x + 2.0 * y) * np.cos(2 * pi * (2 * x + y / 2)) ** 2 + 3.0,
+            lambda x, y: np.cos(pi * (x + y / 2)) * np.cos(2 * pi * x) + 4.0,
+            lambda x, y: np.exp(2.0 * x - 2.0 * y))
+    phi = lambda x, y: np.cos(pi * x) * np.cos(pi * y)
+    d = {"x": lambda x, y: -pi * np.sin(pi * x) * np.cos(pi * y),
+         "y": lambda x, y: -pi * np.cos(pi * x) * np.sin(pi * y),
+         "xx": lambda x, y: -pi * pi * phi(x, y),
+         "yy": lambda x, y: -pi * pi * phi(x, y)}
+    return coef, phi, d
+
+
+def _sec5_boundary_layers(eps):
+    one = lambda x, y: np.ones(np.broadcast(x, y).shape)
+    coef = (lambda x, y: -eps * one(x, y), lambda x, y: -eps * one(x, y), one, one)
+    den = np.exp(-1.0 / eps) - 1.0
+    phi = lambda x, y: (2 * np.exp(-1.0 / eps) - np.exp((x - 1) / eps) - np.exp((y - 1) / eps)) / den
+    d = {"x": lambda x, y: -np.exp((x - 1) / eps) / eps / den + 0 * y,
+         "y": lambda x, y: -np.exp((y - 1) / eps) / eps / den + 0 * x,
+         "xx": lambda x, y: -np.exp((x - 1) / eps) / eps ** 2 / den + 0 * y,
+         "yy": lambda x, y: -np.exp((y - 1) / eps) / eps ** 2 / den + 0 * x}
+    return coef, phi, d
+
+
+def _sec5_inner_layers(eps):
+    one = lambda x, y: np.ones(np.broadcast(x, y).shape)
+    coef = (lambda x, y: eps * one(x, y), lambda x, y: eps * one(x, y),
+            lambda x, y: x + 0 * y, lambda x, y: y + 0 * x)
+    phi = lambda x, y: np.exp(-(x + y - 1) ** 2 / eps)
+    d1 = lambda x, y: -2 * (x + y - 1) / eps * phi(x, y)
+    d2 = lambda x, y: (-2 / eps + 4 * (x + y - 1) ** 2 / eps ** 2) * phi(x, y)
+    return coef, phi, {"x": d1, "y": d1, "xx": d2, "yy": d2}
+
+
+def _sec5_stretched(p, eta, eps):
+    u = lambda t: 1.0 + ((t - 0.5) ** 2 + eta) ** p / eps
+    zero = lambda x, y: np.zeros(np.broadcast(x, y).shape)
+    coef = (lambda x, y: u(x) + 0 * y, lambda x, y: u(y) + 0 * x, zero, zero)
+    pi = np.pi
+    phi = lambda x, y: np.cos(2 * pi * (x + y)) * np.sin(2 * pi * (x - y))
+    d = {"x": lambda x, y: 2 * pi * np.cos(4 * pi * x) + 0 * y,
+         "y": lambda x, y: -2 * pi * np.cos(4 * pi * y) + 0 * x,
+         "xx": lambda x, y: -8 * pi * pi * np.sin(4 * pi * x) + 0 * y,
+         "yy": lambda x, y: 8 * pi * pi * np.sin(4 * pi * y) + 0 * x}
+    return coef, phi, d
+
+
+SEC5_PROBLEMS = {
+    "stand_alone": lambda: _sec5_stand_alone(),
+    "boundary_layers": lambda eps=0.02: _sec5_boundary_layers(eps),
+    "inner_layers": lambda eps=0.015: _sec5_inner_layers(eps),
+    "stretched": lambda p=20, eta=0.5, eps=1e-6: _sec5_stretched(p, eta, eps),
+}
+
+
+def sec5_problem(name: str, n: int = 63, **params):
+    """Operator, right-hand side and exact nodal solution of one Sec. 5 problem on an
+    n x n interior grid. Rows list S, W, diagonal, E, N (zeros kept: the pattern is the full
+    5-point stencil); boundary neighbours move to the right-hand side with the exact
+    solution's values."""
+    coef, phi, d = SEC5_PROBLEMS[name](**params)
+    x, y, h = _grid_xy(n)
+    a, bb, al, be = (f(x, y) for f in coef)
+    g = a * d["xx"](x, y) + bb * d["yy"](x, y) + al * d["x"](x, y) + be * d["y"](x, y)
+    st = np.stack([bb / h ** 2 - be / (2 * h), a / h ** 2 - al / (2 * h),
+                   -2 * (a + bb) / h ** 2, a / h ** 2 + al / (2 * h),
+                   bb / h ** 2 + be / (2 * h)], axis=-1)
+    rhs = g.copy()
+    rhs[0, :] -= st[0, :, 0] * phi(x[0, :], 0.0)
+    rhs[:, 0] -= st[:, 0, 1] * phi(0.0, y[:, 0])
+    rhs[:, -1] -= st[:, -1, 3] * phi(1.0, y[:, -1])
+    rhs[-1, :] -= st[-1, :, 4] * phi(x[-1, :], 1.0)
+    iy, ix = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    exists = np.stack([iy > 0, ix > 0, np.ones_like(ix, bool), ix < n - 1, iy < n - 1], -1)
+    idx = (iy * n + ix)[..., None] + np.array([-n, -1, 0, 1, n])
+    exists = exists.reshape(n * n, 5)
+    cols = idx.reshape(n * n, 5)[exists].astype(np.int32)
+    vals = st.reshape(n * n, 5)[exists]
+    rowptr = np.zeros(n * n + 1, dtype=np.int32)
+    rowptr[1:] = np.cumsum(exists.sum(1))
+    A = CSR(n * n, rowptr, cols, vals, {"grid": (n, n), "h": h, "problem": name, **params})
+    return A, rhs.reshape(-1), phi(x, y).reshape(-1)
+
+
+def sec5_hierarchy(name: str, J: int = 6, coarsest: int = 1, **params):
+    """Rediscretised operators of one Sec. 5 problem on nested grids 2^l - 1 (finest first,
+    down to ``coarsest`` points per side), and the fine right-hand side."""
+    levels = []
+    lvl = J
+    b = None
+    while True:
+        n = 2 ** lvl - 1
+        A, rhs, _ = sec5_problem(name, n, **params)
+        if b is None:
+            b = rhs
+        levels.append(A)
+        if n <= coarsest:
+            break
+        lvl -= 1
+    return levels, b

@@ -1,0 +1,78 @@
+"""The HIP multigrid on the Sec. 5 test problems (63 x 63 grid, V-cycles down to one point,
+stopping rule ||r||_inf <= 2e-4): every V-cycle count equals the oracle's, which reproduces
+the counts printed in the paper's tables where the design notes say so."""
+import numpy as np
+import pytest
+
+from oracle import mg as MG
+from paper_1904_04093_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1904_04093_amd import gabp
+    gabp.load()
+    return gabp
+
+
+CASES = [("boundary_layers", dict(eps=0.02)), ("boundary_layers", dict(eps=0.01)),
+         ("inner_layers", dict(eps=0.015)), ("inner_layers", dict(eps=0.01)),
+         ("stretched", dict(p=20, eta=0.5, eps=1e-6)), ("stretched", dict(p=20, eta=0.5, eps=8e-8))]
+SMOOTHERS = {"redblack_gabp": ("gabp", dict(mode="joint", schedule="redblack")),
+             "line_gabp": ("gabp", dict(mode="joint", schedule="lines_alt")),
+             "redblack_gs": ("rbgs", dict())}
+NU = {("boundary_layers", "redblack_gabp"): (5, 0), ("inner_layers", "redblack_gabp"): (3, 0),
+      ("stretched", "redblack_gabp"): (3, 0), ("stretched", "redblack_gs"): (3, 0)}
+
+
+def _oracle_cycles(levels, b, nu, smoother, kw, cap=100):
+    okw = dict(smoother=smoother)
+    if smoother == "gabp":
+        okw.update(gabp_mode=kw["mode"], schedule=kw["schedule"])
+    h = MG.Hierarchy(levels, nu1=nu[0], nu2=nu[1], **okw)
+    g = h.graphs[0]
+    x = np.zeros(g.n)
+    for k in range(1, cap + 1):
+        x = h.vcycle(b, x)
+        r = float(np.abs(g.residual(b, x)).max())
+        if not np.isfinite(r) or r > 1e30:
+            return None
+        if r <= 2e-4:
+            return k
+    return None
+
+
+def _gpu_cycles(Bm, levels, b, nu, smoother, kw, cap=100):
+    sides = [int(round(np.sqrt(a.n))) for a in levels]
+    lines = kw.get("schedule", "").startswith("lines")
+    solvers = [Bm.Solver.from_csr(a, colour=None if lines else W.grid_colouring(sd),
+                                  grid=(sd, sd) if lines else None, **kw)
+               for a, sd in zip(levels, sides)]
+    mg = Bm.Multigrid(solvers, sides, smoother=smoother, nu1=nu[0], nu2=nu[1])
+    bt = torch.as_tensor(b).cuda()
+    x = torch.zeros(levels[0].n, dtype=torch.float64, device="cuda")
+    for k in range(1, cap + 1):
+        mg.vcycle(bt, x)
+        _, (r2, rinf, _) = solvers[0].residual(bt, x, want_r=False)
+        if not np.isfinite(rinf) or rinf > 1e30:
+            return None
+        if rinf <= 2e-4:
+            return k
+    return None
+
+
+@pytest.mark.parametrize("smoother", list(SMOOTHERS))
+@pytest.mark.parametrize("case", CASES, ids=[f"{c[0]}-{list(c[1].values())[-1]}" for c in CASES])
+def test_sec5_cycle_counts_match_oracle(B, case, smoother):
+    prob, kw = case
+    levels, b = W.sec5_hierarchy(prob, 6, 1, **kw)
+    nu = NU.get((prob, smoother), (0, 2) if smoother == "line_gabp" else (2, 2))
+    sm, skw = SMOOTHERS[smoother]
+    want = _oracle_cycles(levels, b, nu, sm, skw)
+    got = _gpu_cycles(B, levels, b, nu, sm, skw)
+    assert got == want, (prob, kw, smoother, want, got)
