@@ -350,6 +350,7 @@ def suite_sec5(log, cap=100):
     from paper_1904_04093_amd import gabp
     from paper_1904_04093_amd import workloads as W
     smoothers = {"redblack_gabp": ("gabp", dict(mode="joint", schedule="redblack")),
+                 "colour4_gabp": ("gabp", dict(mode="joint", schedule="redblack")),
                  "line_gabp": ("gabp", dict(mode="joint", schedule="lines_alt")),
                  "redblack_gs": ("rbgs", dict())}
     rows = []
@@ -358,7 +359,8 @@ def suite_sec5(log, cap=100):
         sides = [int(round(np.sqrt(a.n))) for a in levels]
         sm, skw = smoothers[smoother]
         lines = skw.get("schedule", "").startswith("lines")
-        solvers = [gabp.Solver.from_csr(a, colour=None if lines else W.grid_colouring(sd),
+        colouring = W.grid_colouring4 if smoother == "colour4_gabp" else W.grid_colouring
+        solvers = [gabp.Solver.from_csr(a, colour=None if lines else colouring(sd),
                                         grid=(sd, sd) if lines else None, **skw)
                    for a, sd in zip(levels, sides)]
         mg = gabp.Multigrid(solvers, sides, smoother=sm, nu1=nu[0], nu2=nu[1])

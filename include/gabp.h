@@ -60,8 +60,10 @@ extern "C" {
                                 FP64 iterative refinement: r = b - A x and x += d are the
                                 only FP64 steps                                             */
 #define GABP_SCHED_FLOOD 0   /* all nodes send every sweep (Sec. 2.2)                       */
-#define GABP_SCHED_REDBLACK 1/* red nodes send, then black nodes, using the newest messages
-                                (the paper's red-black GaBP, Sec. 5); needs node colours    */
+#define GABP_SCHED_REDBLACK 1/* coloured schedule: the nodes of colour 0 send, then those of
+                                colour 1, ..., each from the newest messages (the paper's
+                                red-black GaBP with two colours, its 4-colour GaBP with four,
+                                Sec. 5); needs node colours                                 */
 #define GABP_SCHED_LINES 2   /* line GaBP: the two-layer region iteration of Algorithm 2 whose
                                 large regions are the grid's rows and columns and whose small
                                 regions are the nodes (Fig. two_layers_network), every line
@@ -119,8 +121,9 @@ int gabp_validate_csr(int32_t n, int64_t nnz, const int32_t* rowptr, const int32
  * col, val, rev: HOST pointers as in gabp_validate_csr (rev NULL: built here). The matrix
  * is copied into context-owned device memory in slice-of-64-rows, column-major order over
  * the symmetrised pattern; the caller may free its arrays on return. opt NULL = defaults.
- * `colour` (host, may be NULL): one byte per row, 0 = red, 1 = black; required by
- * GABP_SCHED_REDBLACK, and no edge may join two nodes of one colour.
+ * `colour` (host, may be NULL): one byte per row, the row's colour class 0..7 (red-black:
+ * 0 = red, 1 = black); required by GABP_SCHED_REDBLACK, and no edge may join two nodes of
+ * one colour (EINVAL otherwise).
  * The context belongs to the current HIP device. */
 int gabp_setup(gabp_ctx** out, int32_t n, int64_t nnz, const int32_t* rowptr,
                const int32_t* col, const double* val, const int32_t* rev,

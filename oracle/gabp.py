@@ -324,7 +324,9 @@ def ir_solve(g: Graph, b, tol, lam32, check_every=16, inner_tol=1e-4, max_sweeps
 # ----------------------------------------------------------------------------------------
 
 def sweep_coloured(g: Graph, b, Lt, m, colour, lambda_fixed=None):
-    """One red-black sweep. colour: 0 (red) / 1 (black) per node, a proper 2-colouring.
+    """One coloured sweep (red-black, or the 4-colour schedule of Sec. 5): colour classes
+    0, 1, ... in turn; each class reads off its nodes and sends their messages from the
+    newest messages. colour: a proper colouring (no edge inside a class).
 
     ``lambda_fixed = (Lt*, S*)``: mean-only with frozen Lambda~ (x = M / S*).
     Returns (x, Lt, m) with x the read-off of each node at its visit.
@@ -333,7 +335,7 @@ def sweep_coloured(g: Graph, b, Lt, m, colour, lambda_fixed=None):
     x = np.zeros(g.n)
     Lt = Lt.copy()
     m = m.copy()
-    for c in (0, 1):
+    for c in range(int(colour.max()) + 1 if len(colour) else 0):
         if lambda_fixed is None:
             S, M = node_totals(g, b, Lt, m)
         else:
@@ -360,6 +362,14 @@ def grid_colour(nx, ny=None):
     ny = nx if ny is None else ny
     iy, ix = np.divmod(np.arange(nx * ny), nx)
     return ((ix + iy) % 2).astype(np.uint8)
+
+
+def grid_colour4(nx, ny=None):
+    """Four-colouring of an nx x ny grid proper for 9-point stencils: colour =
+    (ix mod 2) + 2 (iy mod 2)."""
+    ny = nx if ny is None else ny
+    iy, ix = np.divmod(np.arange(nx * ny), nx)
+    return ((ix % 2) + 2 * (iy % 2)).astype(np.uint8)
 
 
 def smooth_coloured(g: Graph, b, x, mu, colour, lam=None, m_state=None, Lt_state=None):

@@ -61,7 +61,8 @@ class Hierarchy:
     """Per-level oracle state: graphs, grid sides, precomputed Lambda~ and warm messages.
 
     smoother: "rbgs" (red-black Gauss-Seidel) or "gabp" (Algorithm 3) with
-    gabp_mode "joint" | "precomp", schedule "flood" | "redblack" | "lines" | "lines_alt" and
+    gabp_mode "joint" | "precomp", schedule "flood" | "redblack" | "colour4" | "lines" |
+    "lines_alt" and
     warm "reset" | "all" (mean messages -- and, for point GaBP in joint mode, precision
     messages -- carried between calls). "lines" is the two-layer region iteration on the
     grid's rows and columns (Algorithm 2 with the partition of Fig. two_layers_network, line
@@ -108,10 +109,11 @@ class Hierarchy:
             if warm:
                 self.m_state[l] = m
             return x
-        if self.schedule == "redblack":
+        if self.schedule in ("redblack", "colour4"):
             L0 = self.Lt_state[l] if warm else None
-            x, Lt, m = _g.smooth_coloured(g, b, x, nu, _g.grid_colour(self.sides[l]),
-                                          lam=self.lam[l], m_state=m0, Lt_state=L0)
+            col = (_g.grid_colour if self.schedule == "redblack" else _g.grid_colour4)(self.sides[l])
+            x, Lt, m = _g.smooth_coloured(g, b, x, nu, col, lam=self.lam[l], m_state=m0,
+                                          Lt_state=L0)
         elif self.lam[l] is None and warm:
             r = g.residual(b, x)
             Lt = np.zeros(g.E) if self.Lt_state[l] is None else self.Lt_state[l]

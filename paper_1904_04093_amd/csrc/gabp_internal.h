@@ -33,6 +33,7 @@ struct LineLayout;
 constexpr int kSlice = 64;      // rows per slice = wavefront size on CDNA
 constexpr int kBlock = 256;     // threads per block for row kernels (4 slices)
 constexpr int kRedBlock = 256;  // threads per block for reductions
+constexpr int kMaxColours = 8;  // colour classes of the coloured schedule
 
 struct Precomp {
   bool valid = false;
@@ -69,6 +70,7 @@ struct Layout {
   int32_t* csr_row = nullptr;   // [nnz] row of each stored entry (adjoint scatter)
   int32_t* csr_col = nullptr;   // [nnz]
   uint8_t* colour = nullptr;    // [n] or null
+  int32_t ncolours = 0;         // colour classes (1 + the largest colour), 0 without colours
   // With a colouring, each slice stores its rows colour-sorted (colour 0 first, ascending
   // rows within a colour), so a red or black half-sweep reads one contiguous part of every
   // 64-slot run. perm[t] = row held by lane t & 63 of slice t >> 6 (null: identity).

@@ -222,15 +222,19 @@ int gabp_setup(gabp_ctx** out, int32_t n, int64_t nnz, const int32_t* rowptr,
     return fail(GABP_ENOTSUPP, "more than 2^31-1 padded message slots");
   // lane of every row: identity, or colour-sorted within each slice when colours are given
   std::vector<int32_t> lane_of_row, row_of_lane;
+  int ncolours = 0;
   if (colour) {
-    for (int32_t j = 0; j < n; ++j)
-      if (colour[j] > 1) return fail(GABP_EINVAL, "colour must be 0 or 1");
+    for (int32_t j = 0; j < n; ++j) {
+      if (colour[j] >= kMaxColours)
+        return fail(GABP_EINVAL, "colour must be below " + std::to_string(kMaxColours));
+      ncolours = std::max(ncolours, colour[j] + 1);
+    }
     lane_of_row.resize(n);
     row_of_lane.resize(static_cast<size_t>(nslices) * kSlice);
     for (int32_t s = 0; s < nslices; ++s) {
       int32_t lane = 0;
       const int32_t r0 = s * kSlice, r1 = std::min(n, r0 + kSlice);
-      for (int c = 0; c < 2; ++c)
+      for (int c = 0; c < ncolours; ++c)
         for (int32_t j = r0; j < r1; ++j)
           if (colour[j] == c) {
             lane_of_row[j] = lane;
@@ -276,7 +280,6 @@ int gabp_setup(gabp_ctx** out, int32_t n, int64_t nnz, const int32_t* rowptr,
   }
   if (colour) {
     for (int32_t j = 0; j < n; ++j) {
-      if (colour[j] > 1) return fail(GABP_EINVAL, "colour must be 0 or 1");
       for (int64_t u = uptr[j]; u < uptr[j + 1]; ++u)
         if (colour[unbr[u]] == colour[j])
           return fail(GABP_EINVAL, "colouring is not proper: edge inside one colour at row " +
@@ -345,6 +348,7 @@ int gabp_setup(gabp_ctx** out, int32_t n, int64_t nnz, const int32_t* rowptr,
     UP(L.colour, hc);
     UP(L.perm, row_of_lane);
     L.lane_of_row = lane_of_row;
+    L.ncolours = ncolours;
   }
   for (int q = 0; q < 2; ++q) {
     AL(c->lam[q], epad + 1);

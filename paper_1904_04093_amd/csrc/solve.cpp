@@ -103,7 +103,8 @@ int ensure_msg32(gabp_ctx* c, hipStream_t s) {
   return GABP_OK;
 }
 
-// One FP64 sweep of the configured mode and schedule on right-hand side b.
+// One FP64 sweep of the configured mode and schedule on right-hand side b (coloured
+// schedule: the colour classes 0, 1, ... in turn, in place).
 // x != null: the read-off of this sweep is written there.
 int sweep64(gabp_ctx* c, int T, const double* b, double* x, hipStream_t s) {
   if (c->lines) return line_sweep64(c, T, b, x, s);
@@ -120,7 +121,7 @@ int sweep64(gabp_ctx* c, int T, const double* b, double* x, hipStream_t s) {
     } else {
       a.lam_in = a.lam_out = c->lam[c->parity];
       a.msg_in = a.msg_out = c->msg[c->parity];
-      for (int col = 0; col < 2; ++col) {
+      for (int col = 0; col < c->L.ncolours; ++col) {
         a.colour = col;
         GABP_HIP(launch_joint_sweep(a, s));
       }
@@ -135,7 +136,7 @@ int sweep64(gabp_ctx* c, int T, const double* b, double* x, hipStream_t s) {
       c->parity ^= 1;
     } else {
       a.msg_in = a.msg_out = c->msg[c->parity];
-      for (int col = 0; col < 2; ++col) {
+      for (int col = 0; col < c->L.ncolours; ++col) {
         a.colour = col;
         GABP_HIP(launch_mean_sweep64(a, s));
       }
@@ -155,7 +156,7 @@ int sweep32(gabp_ctx* c, int T, const float* b, float* x, hipStream_t s) {
     c->parity32 ^= 1;
   } else {
     a.msg_in = a.msg_out = c->msg32[c->parity32];
-    for (int col = 0; col < 2; ++col) {
+    for (int col = 0; col < c->L.ncolours; ++col) {
       a.colour = col;
       GABP_HIP(launch_mean_sweep32(a, s));
     }

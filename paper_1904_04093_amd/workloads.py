@@ -424,6 +424,33 @@ def grid_colouring(n: int) -> np.ndarray:
     return ((ix + iy) & 1).astype(np.uint8)
 
 
+def random_grid_9pt(nx: int, ny: int, r: np.random.Generator, margin: float = 0.2,
+                    flip: float = 0.1) -> CSR:
+    """Random 9-point operator on an nx x ny grid (node (x, y) has index y * nx + x):
+    couplings of magnitude U(0.2, 1), negative except a fraction ``flip``, diagonal
+    (1 + margin) times the row's absolute off-diagonal sum."""
+    n = nx * ny
+    iy, ix = np.divmod(np.arange(n), nx)
+    offs = [(-1, -1), (0, -1), (1, -1), (-1, 0), (0, 0), (1, 0), (-1, 1), (0, 1), (1, 1)]
+    coef = -r.uniform(0.2, 1.0, (n, 9)) * np.where(r.random((n, 9)) < flip, -1.0, 1.0)
+    exists = np.stack([(ix + dx >= 0) & (ix + dx < nx) & (iy + dy >= 0) & (iy + dy < ny)
+                       for dx, dy in offs], -1)
+    coef = np.where(exists, coef, 0.0)
+    coef[:, 4] = 0.0
+    coef[:, 4] = (1.0 + margin) * np.abs(coef).sum(1)
+    cols = (np.arange(n)[:, None] + np.array([dy * nx + dx for dx, dy in offs]))[exists]
+    rowptr = np.zeros(n + 1, dtype=np.int32)
+    rowptr[1:] = np.cumsum(exists.sum(1))
+    return CSR(n, rowptr, cols.astype(np.int32), coef[exists], {"grid": (nx, ny)})
+
+
+def grid_colouring4(n: int) -> np.ndarray:
+    """Four-colouring of the n x n grid (x fastest) that is proper for 9-point stencils:
+    (ix mod 2) + 2 (iy mod 2)."""
+    iy, ix = np.divmod(np.arange(n * n), n)
+    return ((ix & 1) + 2 * (iy & 1)).astype(np.uint8)
+
+
 def random_sparse_dominant(n: int, per_row: int, r: np.random.Generator,
                            margin: float = 0.3) -> CSR:
     """Sparse nonsymmetric matrix with ``per_row`` random off-diagonals per row (arbitrary,
@@ -531,7 +558,19 @@ def _sec5_stretched(p, eta, eps):
     return coef, phi, d
 
 
+def _sec5_mixed_derivative(eps):
+    one = lambda x, y: np.ones(np.broadcast(x, y).shape)
+    zero = lambda x, y: np.zeros(np.broadcast(x, y).shape)
+    coef = (one, one, zero, zero, lambda x, y: (2.0 - eps) * one(x, y))
+    phi = lambda x, y: 2 * x ** 3 * y ** 4
+    d = {"x": lambda x, y: 6 * x ** 2 * y ** 4, "y": lambda x, y: 8 * x ** 3 * y ** 3,
+         "xx": lambda x, y: 12 * x * y ** 4, "yy": lambda x, y: 24 * x ** 3 * y ** 2,
+         "xy": lambda x, y: 24 * x ** 2 * y ** 3}
+    return coef, phi, d
+
+
 SEC5_PROBLEMS = {
+    "mixed_derivative": lambda eps=0.01: _sec5_mixed_derivative(eps),
     "stand_alone": lambda: _sec5_stand_alone(),
     "boundary_layers": lambda eps=0.02: _sec5_boundary_layers(eps),
     "inner_layers": lambda eps=0.015: _sec5_inner_layers(eps),
@@ -541,27 +580,39 @@ SEC5_PROBLEMS = {
 
 def sec5_problem(name: str, n: int = 63, **params):
     """Operator, right-hand side and exact nodal solution of one Sec. 5 problem on an
-    n x n interior grid. Rows list S, W, diagonal, E, N (zeros kept: the pattern is the full
-    5-point stencil); boundary neighbours move to the right-hand side with the exact
-    solution's values."""
+    n x n interior grid. Rows list their stencil columns in ascending order (S, W, diagonal,
+    E, N; with a mixed derivative term the 9-point stencil SW, S, SE, W, diagonal, E, NW, N,
+    NE, phi_xy by the centred 4-point formula); zeros are kept, so the pattern is the full
+    stencil. Boundary neighbours move to the right-hand side with the exact solution's
+    values."""
     coef, phi, d = SEC5_PROBLEMS[name](**params)
     x, y, h = _grid_xy(n)
-    a, bb, al, be = (f(x, y) for f in coef)
+    a, bb, al, be = (f(x, y) for f in coef[:4])
+    cxy = coef[4](x, y) if len(coef) > 4 else None
     g = a * d["xx"](x, y) + bb * d["yy"](x, y) + al * d["x"](x, y) + be * d["y"](x, y)
-    st = np.stack([bb / h ** 2 - be / (2 * h), a / h ** 2 - al / (2 * h),
-                   -2 * (a + bb) / h ** 2, a / h ** 2 + al / (2 * h),
-                   bb / h ** 2 + be / (2 * h)], axis=-1)
-    rhs = g.copy()
-    rhs[0, :] -= st[0, :, 0] * phi(x[0, :], 0.0)
-    rhs[:, 0] -= st[:, 0, 1] * phi(0.0, y[:, 0])
-    rhs[:, -1] -= st[:, -1, 3] * phi(1.0, y[:, -1])
-    rhs[-1, :] -= st[-1, :, 4] * phi(x[-1, :], 1.0)
+    # stencil offsets (dx, dy) and coefficients
+    offs = [(0, -1), (-1, 0), (0, 0), (1, 0), (0, 1)]
+    st = [bb / h ** 2 - be / (2 * h), a / h ** 2 - al / (2 * h), -2 * (a + bb) / h ** 2,
+          a / h ** 2 + al / (2 * h), bb / h ** 2 + be / (2 * h)]
+    if cxy is not None:
+        g = g + cxy * d["xy"](x, y)
+        q = cxy / (4 * h ** 2)
+        offs = [(-1, -1), (0, -1), (1, -1), (-1, 0), (0, 0), (1, 0), (-1, 1), (0, 1), (1, 1)]
+        st = [q, st[0], -q, st[1], st[2], st[3], -q, st[4], q]
+    st = np.stack(st, axis=-1)
     iy, ix = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
-    exists = np.stack([iy > 0, ix > 0, np.ones_like(ix, bool), ix < n - 1, iy < n - 1], -1)
-    idx = (iy * n + ix)[..., None] + np.array([-n, -1, 0, 1, n])
-    exists = exists.reshape(n * n, 5)
-    cols = idx.reshape(n * n, 5)[exists].astype(np.int32)
-    vals = st.reshape(n * n, 5)[exists]
+    rhs = g.copy()
+    exists = []
+    for k, (dx, dy) in enumerate(offs):
+        jx, jy = ix + dx, iy + dy
+        inside = (jx >= 0) & (jx < n) & (jy >= 0) & (jy < n)
+        bnd = ~inside
+        rhs[bnd] -= st[..., k][bnd] * phi((jx[bnd] + 1) * h, (jy[bnd] + 1) * h)
+        exists.append(inside)
+    exists = np.stack(exists, -1).reshape(n * n, len(offs))
+    idx = (iy * n + ix)[..., None] + np.array([dy * n + dx for dx, dy in offs])
+    cols = idx.reshape(n * n, len(offs))[exists].astype(np.int32)
+    vals = st.reshape(n * n, len(offs))[exists]
     rowptr = np.zeros(n * n + 1, dtype=np.int32)
     rowptr[1:] = np.cumsum(exists.sum(1))
     A = CSR(n * n, rowptr, cols, vals, {"grid": (n, n), "h": h, "problem": name, **params})

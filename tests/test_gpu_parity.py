@@ -119,6 +119,54 @@ def test_redblack_rejects_improper_colouring(B):
     with pytest.raises(B.GaBPError) as e:
         B.Solver.from_csr(a, colour=np.zeros(64, np.uint8), schedule="redblack")
     assert e.value.status == B.EINVAL
+    # the red-black colouring is not proper for a 9-point stencil; colours stop at 7
+    m, _, _ = W.sec5_problem("mixed_derivative", 8, eps=0.01)
+    with pytest.raises(B.GaBPError) as e:
+        B.Solver.from_csr(m, colour=G.grid_colour(8), schedule="redblack")
+    assert e.value.status == B.EINVAL
+    with pytest.raises(B.GaBPError) as e:
+        B.Solver.from_csr(a, colour=np.full(64, 8, np.uint8), schedule="redblack")
+    assert e.value.status == B.EINVAL
+
+
+@pytest.mark.parametrize("mode", ["joint", "precomp"])
+@pytest.mark.parametrize("n", [31, 45])
+def test_four_colour_sweeps_on_a_nine_point_grid_match_oracle(B, mode, n):
+    # the paper's 4-colour GaBP: colour classes (ix mod 2) + 2 (iy mod 2) in turn, on a
+    # dominant random 9-point operator (GaBP alone diverges on the mixed-derivative one,
+    # where only the first few sweeps are comparable; see below)
+    a = W.random_grid_9pt(n, n, W.rng(309, n))
+    b = W.rng(309, 1).uniform(-1, 1, a.n)
+    colour = G.grid_colour4(n)
+    kw = dict(mode=mode, schedule="redblack")
+    if mode == "precomp":
+        kw.update(tol_lambda=0.0, max_lambda_sweeps=30)
+    s = B.Solver.from_csr(a, colour=colour, **kw)
+    g = G.Graph.from_csr(a)
+    lam = None
+    if mode == "precomp":
+        Lt, S, _ = G.lambda_phase(g, 0.0, 30)
+        lam = (Lt, S)
+    for sweeps in (1, 2, 7, 30):
+        x = s.sweeps(_cuda(b), sweeps).cpu().numpy()
+        Lt0 = np.zeros(g.E) if lam is None else lam[0]
+        m = np.zeros(g.E)
+        for _ in range(sweeps):
+            xo, Lt0, m = G.sweep_coloured(g, b, Lt0, m, colour, lambda_fixed=lam)
+        assert _rel_inf(x, xo) <= TOL, (mode, n, sweeps)
+
+
+def test_four_colour_sweeps_on_the_mixed_derivative_problem(B):
+    a, b, _ = W.sec5_problem("mixed_derivative", 31, eps=0.01)
+    colour = G.grid_colour4(31)
+    s = B.Solver.from_csr(a, colour=colour, schedule="redblack")
+    g = G.Graph.from_csr(a)
+    for sweeps in (1, 2, 5):
+        x = s.sweeps(_cuda(b), sweeps).cpu().numpy()
+        Lt0, m = np.zeros(g.E), np.zeros(g.E)
+        for _ in range(sweeps):
+            xo, Lt0, m = G.sweep_coloured(g, b, Lt0, m, colour)
+        assert _rel_inf(x, xo) <= TOL, sweeps
 
 
 @pytest.mark.parametrize("mode", ["joint", "precomp"])

@@ -366,6 +366,38 @@ def test_redblack_fixed_point_is_dense_solution(precomp):
     assert _relerr(x, np.linalg.solve(_dense(a), b)) < 1e-12
 
 
+def test_four_colour_schedule_first_class_reads_jacobi_and_fixed_point():
+    # 4-colour GaBP (Sec. 5, mixed-derivative problem) on a 9-point stencil: the first colour
+    # class reads off from zero messages (a Jacobi step); the fixed point is A^-1 b
+    n = 15
+    a, b, _ = W.sec5_problem("mixed_derivative", n, eps=0.01)
+    A = _dense(a)
+    colour = G.grid_colour4(n)
+    g = _graph(a)
+    # proper for the 9-point stencil: no stored coupling inside a colour class
+    assert not np.any(colour[g.dst] == colour[g.src])
+    x, Lt, m = G.sweep_coloured(g, b, np.zeros(g.E), np.zeros(g.E), colour)
+    first = colour == 0
+    assert np.allclose(x[first], b[first] / np.diag(A)[first], rtol=1e-15, atol=0)
+    # fixed point on a dominant 9-point operator (the mixed-derivative one is nearly
+    # non-elliptic and GaBP alone does not converge on it)
+    r = W.rng(120, 0)
+    D = np.zeros((n * n, n * n))
+    for i in range(n * n):
+        iy, ix = divmod(i, n)
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                jx, jy = ix + dx, iy + dy
+                if (dx or dy) and 0 <= jx < n and 0 <= jy < n:
+                    D[i, jy * n + jx] = -r.uniform(0.2, 1.0)
+        D[i, i] = 1.2 * np.abs(D[i]).sum()
+    g = _graph(W.csr_from_dense(D))
+    x, Lt, m = G.sweep_coloured(g, b, np.zeros(g.E), np.zeros(g.E), colour)
+    for _ in range(400):
+        x, Lt, m = G.sweep_coloured(g, b, Lt, m, colour)
+    assert _relerr(x, np.linalg.solve(D, b)) < 1e-10
+
+
 # --------------------------------------------------------------------------------------
 # The pins catch plausible mistakes: each mutation of the sweep below breaks some pin
 # (planted in a copy of the oracle's sweep on the CPU; the oracle itself is untouched)
