@@ -252,13 +252,15 @@ class Solver:
                                      _stream()))
         return x
 
-    def residual(self, b, x, transposed=False, want_r=True):
+    def residual(self, b, x, transposed=False, want_r=True, want_norms=True):
+        """r = b - A x (or b - A^T x) and, with want_norms, (||r||_2, ||r||_inf, ||b||_2)
+        read back to the host (which waits for the stream); without, only enqueued."""
         r = self._new() if want_r else None
-        norms = (ctypes.c_double * 3)()
+        norms = (ctypes.c_double * 3)() if want_norms else None
         _check(self._lib.gabp_residual(self._h, _dev(b, self.n), _dev(x, self.n),
                                        _dev(r, self.n) if want_r else None,
                                        int(bool(transposed)), norms, _stream()))
-        return r, tuple(norms)
+        return r, tuple(norms) if want_norms else None
 
     def adjoint_scatter(self, lam, x, jac=None, want_G=True):
         import torch
