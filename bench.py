@@ -112,8 +112,8 @@ def main():
     if args.profile:
         args.steps, args.warmup, args.no_ttr, args.no_cpu = 5, 1, True, True
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "layout is a design note, not part of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the library has "
+              "no multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -48,7 +48,7 @@ extern "C" {
 #define GABP_EZERODIAG -3  /* a diagonal entry A_ii is missing or zero                      */
 #define GABP_ENUMERIC -4   /* non-finite read-off or residual (zero cavity precision, ...) */
 #define GABP_EDEVICE -5    /* a HIP runtime call failed                                     */
-#define GABP_ENOTSUPP -6   /* valid request this build does not support                     */
+#define GABP_ENOTSUPP -6   /* valid request the library does not support                     */
 
 /* ---- options ------------------------------------------------------------------------- */
 #define GABP_MODE_JOINT 0    /* Algorithm 1 literally: Lt and m updated every sweep        */
