@@ -102,7 +102,16 @@ def main():
                     help="with --suite-only: run one part of the suite")
     ap.add_argument("--line-sweeps", type=int, default=50,
                     help="timed sweeps per variant in the line-sweep part")
+    ap.add_argument("--ttr-full", default=None,
+                    help="only time to rel.res 1e-8 on the --grid workload, driven in chunks "
+                         "with progress lines: comma list of fp64_joint, fp64_precomp, fp32_ir")
     args = ap.parse_args()
+    if args.ttr_full:
+        import torch  # noqa: F401
+        lg = lambda *a: print(*a, file=sys.stderr, flush=True)
+        print(json.dumps([ttr_chunked(args.grid, v, lg) for v in args.ttr_full.split(",")]),
+              flush=True)
+        return
     if args.suite_only:
         import torch  # noqa: F401
         print(json.dumps(suite(lambda *a: print(*a, file=sys.stderr, flush=True),
@@ -288,6 +297,82 @@ def time_to_residual(n, log):
     if res["fp64_joint"]["seconds"] > 0:
         res["speedup_fp32_ir_vs_fp64_joint"] = res["fp64_joint"]["seconds"] / res["fp32_ir"]["seconds"]
     return res
+
+
+def ttr_chunked(n, variant, log, tol=1e-8, chunk=256, max_sweeps=30_000_000):
+    """Time to rel.res ``tol`` on the n x n workload, driven through the library's sweep and
+    residual entry points in chunks of ``chunk`` sweeps (the same checks a solve makes every
+    ``chunk`` sweeps), so that a run of many minutes reports its progress. fp32_ir mirrors
+    the library's refinement: FP32 mean-only sweeps on A d = r / ||r||_inf from zero
+    messages, the FP64 residual of x + s d after every chunk, best trial kept, inner solve
+    ended at 1e-4 of ||r||, at tol, or 8 checks without a new best once one was found."""
+    import torch
+    from paper_1904_04093_amd import gabp
+    from paper_1904_04093_amd import workloads as W
+    a, b = W.precision_at_scale(n)
+    bt = torch.as_tensor(b).cuda()
+    kw = {"fp64_joint": dict(mode="joint"),
+          "fp64_precomp": dict(mode="precomp", tol_lambda=1e-12),
+          "fp32_ir": dict(mode="precomp", precision="f32_ir", tol_lambda=1e-7)}[variant]
+    s = gabp.Solver.from_csr(a, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lsw = s.precompute_lambda() if kw["mode"] == "precomp" else 0
+    total, outer, last = 0, 0, t0
+    _, (rn2, rinf, bn) = s.residual(bt, torch.zeros_like(bt), want_r=False)
+
+    def progress(rel):
+        nonlocal last
+        if time.perf_counter() - last > 20.0:
+            last = time.perf_counter()
+            log(f"[ttr] {variant} n={n}: {total} sweeps, rel.res {rel:.3e}, "
+                f"{last - t0:.0f} s")
+
+    if variant != "fp32_ir":
+        x = torch.zeros_like(bt)
+        rel = 1.0
+        while total < max_sweeps:
+            s.sweeps(bt, chunk, reset=(total == 0), x=x)
+            total += chunk
+            _, (r2, _, _) = s.residual(bt, x, want_r=False)
+            rel = r2 / bn
+            if rel <= tol or not np.isfinite(rel):
+                break
+            progress(rel)
+    else:
+        x = torch.zeros_like(bt)
+        r, (rn2, rinf, _) = s.residual(bt, x)
+        rel = rn2 / bn
+        while rel > tol and total < max_sweeps:
+            scale = rinf
+            rs = r / scale
+            d = torch.zeros_like(bt)
+            best, dbest, since, first = rn2, None, 0, True
+            while total < max_sweeps:
+                s.sweeps(rs, chunk, reset=first, x=d)
+                first = False
+                total += chunk
+                _, (t2, _, _) = s.residual(bt, x + scale * d, want_r=False)
+                if t2 < best:
+                    best, dbest, since = t2, d.clone(), 0
+                else:
+                    since += 1
+                progress(t2 / bn)
+                if best <= 1e-4 * rn2 or best / bn <= tol or (dbest is not None and since >= 8):
+                    break
+            if dbest is None:
+                break
+            x = x + scale * dbest
+            outer += 1
+            r, (rn2, rinf, _) = s.residual(bt, x)
+            rel = rn2 / bn
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out = {"variant": variant, "grid": n, "unknowns": a.n, "tol": tol, "seconds": dt,
+           "sweeps": total, "lambda_sweeps": lsw, "outer_iters": outer, "rel_res2": rel,
+           "check_every": chunk, "converged": bool(rel <= tol)}
+    log(f"[ttr] {out}")
+    return out
 
 
 def cpu_baseline(a, b, sweeps, log):
