@@ -221,12 +221,18 @@ int line_update_values(gabp_ctx* c, const double* val, hipStream_t s) {
   return GABP_OK;
 }
 
+// Zero messages: only the incoming copies a sweep reads before anything writes them -- the
+// column messages in the row layout, and (flood) the row messages in the column layout; the
+// rows-then-columns schedule rewrites the latter before the columns read them, and every
+// outgoing array is written by its own update before anything reads it. With precomputed
+// Lambda only the mean messages restart.
 int line_reset64(gabp_ctx* c, hipStream_t s) {
   const LineLayout& G = *c->lines;
-  if (c->opt.mode == GABP_MODE_JOINT) return zero_joint(G, s);
-  for (const auto& S : G.side) {   // precomputed Lambda: only the mean messages restart
-    GABP_HIP(launch_fill64(S.m_own, G.n, 0.0, s));
+  const bool joint = c->opt.mode == GABP_MODE_JOINT;
+  for (int o = 1; o >= (G.alt ? 1 : 0); --o) {   // columns' messages (row layout), then rows'
+    const LineSide& S = G.side[o];
     GABP_HIP(launch_fill64(S.m_x, G.n, 0.0, s));
+    if (joint) GABP_HIP(launch_fill64(S.lam_x, G.n, 0.0, s));
   }
   return GABP_OK;
 }
@@ -244,12 +250,9 @@ int line_ensure32(gabp_ctx* c, hipStream_t s) {
 
 bool line_has32(const gabp_ctx* c) { return c->lines->side[0].m32_own != nullptr; }
 
-int line_reset32(gabp_ctx* c, hipStream_t s) {
+int line_reset32(gabp_ctx* c, hipStream_t s) {   // as line_reset64
   const LineLayout& G = *c->lines;
-  for (const auto& S : G.side) {
-    GABP_HIP(launch_fill32(S.m32_own, G.n, 0.0f, s));
-    GABP_HIP(launch_fill32(S.m32_x, G.n, 0.0f, s));
-  }
+  for (int o = 1; o >= (G.alt ? 1 : 0); --o) GABP_HIP(launch_fill32(G.side[o].m32_x, G.n, 0.0f, s));
   return GABP_OK;
 }
 
