@@ -104,8 +104,13 @@ class Hierarchy:
         warm = self.warm == "all"
         m0 = self.m_state[l] if warm else None
         if self.schedule in ("lines", "lines_alt"):
-            x, m = _rg.smooth(self.rgs[l], b, x, nu, precomp=self.lam[l], m_state=m0,
-                              groups=self.groups[l])
+            rg, grp = self.rgs[l], self.groups[l]
+            if warm and self.lam[l] is None:     # joint: the precision messages carry over too
+                L0 = self.Lt_state[l] if self.Lt_state[l] is not None else rg.zeros()
+                x, m, lam = _rg.smooth(rg, b, x, nu, m_state=m0, groups=grp, lam_state=L0)
+                self.Lt_state[l] = lam
+            else:
+                x, m = _rg.smooth(rg, b, x, nu, precomp=self.lam[l], m_state=m0, groups=grp)
             if warm:
                 self.m_state[l] = m
             return x

@@ -30,8 +30,9 @@ def _loss_dense(n, theta, b, xt):
     return 0.5 * float((x - xt) @ (x - xt))
 
 
-@pytest.mark.parametrize("precision", ["f32_ir", "f64"])
-def test_theta_gradient_matches_fd_and_dense_adjoint(mods, precision):
+@pytest.mark.parametrize("precision,schedule", [("f32_ir", "flood"), ("f64", "flood"),
+                                                 ("f64", "lines_alt")])
+def test_theta_gradient_matches_fd_and_dense_adjoint(mods, precision, schedule):
     gabp, AG = mods
     n = 16
     theta0 = W.theta_problem(n, 0)
@@ -46,8 +47,11 @@ def test_theta_gradient_matches_fd_and_dense_adjoint(mods, precision):
     # FP64 messages: joint mode (a frozen Lt* with error e shifts the fixed point by ~e, so
     # precomputed Lt alone cannot reach 1e-13; refinement removes that floor)
     mode = "precomp" if precision == "f32_ir" else "joint"
+    # line GaBP as the solver too: its transposed solve runs the line recurrences on A^T
+    grid = (n, n) if schedule.startswith("lines") else None
     solver = gabp.Solver.from_csr(field.pattern, mode=mode, precision=precision,
-                                  check_every=16, tol_lambda=1e-12)
+                                  check_every=16, tol_lambda=1e-12, schedule=schedule,
+                                  grid=grid)
     bt = torch.as_tensor(b, device="cuda")
     x = AG.gabp_solve(vals, bt, solver, tol=1e-13)
     loss = 0.5 * ((x - torch.as_tensor(xt, device="cuda")) ** 2).sum()
