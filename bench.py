@@ -468,7 +468,7 @@ def suite_sec5(log, cap=100):
         rec = {"problem": prob, "params": pname, "smoother": smoother, "pre_post": list(nu),
                "paper_cycles": printed if printed is not None else "diverges",
                "cycles": ours if ours is not None else "diverges" if not rinf <= 1e30 else f"cap {cap}",
-               "seconds": dt}
+               "seconds": dt, "cpu_baseline": cpu_baseline_sec5(levels, b, smoother, nu, cap)}
         rows.append(rec)
         log(f"[suite] sec5 {rec}")
         del mg, solvers
@@ -543,7 +543,60 @@ def suite_lines(log, n=4095, sweeps=50):
             out[f"{sched}_{name}"] = rec
             log(f"[suite] lines {sched} {name}: {rec}")
             del s
+    out["cpu_baseline"] = cpu_baseline_lines(log)
     return out
+
+
+def cpu_baseline_sec5(levels, b, smoother, nu, cap):
+    """The oracle's multigrid (numpy, one thread) on the same problem: cycles and seconds."""
+    from oracle import mg as MG
+    okw = {"redblack_gabp": dict(smoother="gabp", gabp_mode="joint", schedule="redblack"),
+           "colour4_gabp": dict(smoother="gabp", gabp_mode="joint", schedule="colour4"),
+           "line_gabp": dict(smoother="gabp", gabp_mode="joint", schedule="lines_alt"),
+           "redblack_gs": dict(smoother="rbgs")}[smoother]
+    t0 = time.perf_counter()
+    h = MG.Hierarchy(levels, nu1=nu[0], nu2=nu[1], **okw)
+    g = h.graphs[0]
+    x = np.zeros(g.n)
+    cycles = None
+    for k in range(1, cap + 1):
+        x = h.vcycle(b, x)
+        r = float(np.abs(g.residual(b, x)).max())
+        if not np.isfinite(r) or r > 1e30:
+            cycles = "diverges"
+            break
+        if r <= 2e-4:
+            cycles = k
+            break
+    return {"cycles": cycles if cycles is not None else f"cap {cap}", "cores": 1,
+            "seconds": time.perf_counter() - t0, "kind": "oracle"}
+
+
+def cpu_baseline_lines(log, n=256, sweeps=3):
+    """The region oracle (dense LU per line, numpy, one thread) against the HIP flood line
+    sweep on the same n x n anisotropic operator."""
+    import torch
+    from oracle import regions as RG
+    from paper_1904_04093_amd import gabp
+    from paper_1904_04093_amd import workloads as W
+    a = W.anisotropic_mg(n, kx=1.0, ky=0.01, peclet=4.0, scaled=False)
+    b = W.rng(4, 2).uniform(-1, 1, a.n)
+    t0 = time.perf_counter()
+    rg = RG.RegionGraph(a, RG.grid_lines(n, n))
+    t_build = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    RG.run(rg, b, sweeps)
+    t_cpu = (time.perf_counter() - t0) / sweeps
+    s = gabp.Solver.from_csr(a, schedule="lines", grid=(n, n))
+    bt = torch.as_tensor(b).cuda()
+    x = torch.zeros_like(bt)
+    s.sweeps(bt, 2, x=x)
+    t_gpu = _events_time(lambda k: s.sweeps(bt, k, reset=False, x=x), 200) / 200
+    rec = {"grid": f"{n}x{n}", "cpu_sweep_s": t_cpu, "cpu_build_s": t_build, "cores": 1,
+           "gpu_sweep_us": t_gpu * 1e6, "gpu_over_cpu": t_cpu / t_gpu,
+           "sample": f"{sweeps} joint flood line sweeps, region oracle (dense LU per line)"}
+    log(f"[suite] lines cpu baseline (oracle): {rec}")
+    return rec
 
 
 def suite_batch(log):
