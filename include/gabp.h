@@ -206,7 +206,8 @@ int gabp_layout_info(const gabp_ctx* ctx, int32_t* n, int64_t* nnz, int64_t* slo
  * sweeps on a zero right-hand side, so the context's message state is reset; computes the
  * precomputed Lt first when the mode needs it. Outputs (host, may be NULL): the chosen
  * check interval and hint setting (0/1). Because it changes check_every, later solves may
- * stop at a different (rounded-up) sweep count than untuned ones. */
+ * stop at a different (rounded-up) sweep count than untuned ones. Line schedules have no
+ * hint variants: only the check interval is tuned (from one line sweep), hints_out is 0. */
 int gabp_autotune(gabp_ctx* ctx, int32_t* check_every_out, int32_t* hints_out,
                   hipStream_t stream);
 

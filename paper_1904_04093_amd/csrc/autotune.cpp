@@ -12,6 +12,7 @@
 #include <string>
 
 #include "gabp_batch.h"
+#include "gabp_line.h"
 #include "graph.h"
 
 using namespace gabp;
@@ -108,13 +109,60 @@ int time_it(hipStream_t s, int reps, F&& fn, double* out) {
   return st;
 }
 
+// Line schedules have no stream-hint variants: only the check interval is tuned, from the
+// time of one line sweep and of one residual check on a zero right-hand side.
+int autotune_lines(gabp_ctx* c, int32_t* check_every_out, int32_t* hints_out, hipStream_t s) {
+  const std::string key = key_of(c);
+  Tuned t{};
+  if (!cache_lookup(key, &t)) {
+    int st;
+    const bool f32 = c->opt.precision == GABP_F32_IR;
+    if ((f32 || c->opt.mode == GABP_MODE_PRECOMP) && (st = precompute(c, 0, s)) != GABP_OK)
+      return st;
+    const int64_t n = c->L.n;
+    GABP_HIP(launch_fill64(c->r, n, 0.0, s));
+    if (f32) {
+      if ((st = line_ensure32(c, s)) != GABP_OK) return st;
+      GABP_HIP(launch_fill32(c->r32, n, 0.0f, s));
+      if ((st = line_rhs32(c, c->r32, s)) != GABP_OK) return st;
+      if ((st = line_reset32(c, s)) != GABP_OK) return st;
+    } else {
+      if ((st = line_rhs64(c, c->r, s)) != GABP_OK) return st;
+      if ((st = line_reset64(c, s)) != GABP_OK) return st;
+    }
+    auto one_sweep = [&]() -> int {
+      return f32 ? line_sweep32(c, 0, c->r32, nullptr, s) : line_sweep64(c, 0, c->r, nullptr, s);
+    };
+    double t_sweep = 0.0, t_check = 0.0;
+    if ((st = time_it(s, 10, one_sweep, &t_sweep)) != GABP_OK) return st;
+    auto one_check = [&]() -> int {
+      GABP_HIP(launch_residual(&c->L, c->L.val, c->r, c->r, nullptr, nullptr, nullptr,
+                               c->partials, c->nred, c->red, s));
+      GABP_HIP(hipMemcpyAsync(c->host_red, c->red, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+      GABP_HIP(hipStreamSynchronize(s));
+      return GABP_OK;
+    };
+    if ((st = time_it(s, 10, one_check, &t_check)) != GABP_OK) return st;
+    int ce = 8;
+    while (ce < 256 && t_check > 0.02 * ce * t_sweep) ce *= 2;
+    t.hints = 0;
+    t.check_every = ce;
+    cache_store(key, t);
+  }
+  c->opt.check_every = t.check_every;
+  c->graphs->clear();
+  if (check_every_out) *check_every_out = t.check_every;
+  if (hints_out) *hints_out = 0;
+  return GABP_OK;
+}
+
 }  // namespace
 
 extern "C" {
 
 int gabp_autotune(gabp_ctx* c, int32_t* check_every_out, int32_t* hints_out, hipStream_t s) {
   if (!c) return fail(GABP_EINVAL, "NULL context");
-  if (c->lines) return fail(GABP_ENOTSUPP, "the autotuner covers the point schedules");
+  if (c->lines) return autotune_lines(c, check_every_out, hints_out, s);
   const std::string key = key_of(c);
   Tuned t{};
   const bool f32 = c->opt.precision == GABP_F32_IR;

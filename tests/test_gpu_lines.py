@@ -204,6 +204,22 @@ def test_recorded_line_solves_match_eager(B):
             torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("kw", [dict(mode="joint"),
+                                dict(mode="precomp", precision="f32_ir", tol_lambda=1e-10)])
+def test_line_autotune_sets_the_check_interval_only(B, kw):
+    a, b, nx, ny = _problem("130x65", 5)
+    s = B.Solver.from_csr(a, schedule="lines_alt", grid=(nx, ny), **kw)
+    t = s.autotune()
+    assert t["check_every"] in (8, 16, 32, 64, 128, 256) and t["stream_hints"] == 0
+    assert s.autotune() == t                       # cached
+    x, info = s.solve(_cuda(b), 1e-11, 200000)
+    assert info.status == B.OK
+    assert _rel_inf(x.cpu().numpy(), np.linalg.solve(W.csr_to_dense(a), b)) < 1e-8
+    ref = B.Solver.from_csr(a, schedule="lines_alt", grid=(nx, ny), **kw)
+    assert np.array_equal(s.sweeps(_cuda(b), 7).cpu().numpy(),
+                          ref.sweeps(_cuda(b), 7).cpu().numpy())
+
+
 def test_line_update_values_matches_fresh_setup(B):
     n = 24
     a0 = W.theta_operator(n, W.theta_problem(n, 0))
