@@ -16,6 +16,31 @@ constexpr int kLWaves = kLT / 64;
 template <int NPL>
 __device__ inline int pidx(int t) { return t + t / NPL; }
 
+// The same index for the striped position threadIdx.x + j * kLT and for the thread's own
+// position t0 + k (0 <= k < NPL): one base register plus immediate offsets.
+template <int NPL>
+__device__ inline int sidx(int j) {
+  const int tid = threadIdx.x;
+  return tid + tid / NPL + j * (kLT + kLT / NPL);
+}
+template <int NPL>
+__device__ inline int bidx(int k) { return static_cast<int>(threadIdx.x) * (NPL + 1) + k; }
+
+// Striped positions threadIdx.x + j * kLT of a line of len >= 1 positions. Whether stripe
+// j is whole is uniform (j is a compile-time index), so the per-lane tests need no
+// register per stripe. In the one partial stripe every lane still loads (its index
+// clamped to the last position; the value past the end is never used): no load sits in a
+// branch whose end would make the wave wait for it.
+__device__ inline bool in_stripe(int j, int len) {
+  return (j + 1) * kLT <= len || (j * kLT < len && static_cast<int>(threadIdx.x) < len - j * kLT);
+}
+template <typename T>
+__device__ inline T ld_stripe(const T* __restrict__ p, int j, int len) {
+  const unsigned t = threadIdx.x + j * kLT;
+  if ((j + 1) * kLT <= len) return p[t];
+  return p[min(t, static_cast<unsigned>(len) - 1u)];
+}
+
 // ---- 3x3 projective maps with the sparsity [[a b 0] [c d 0] [e f g]] -------------------
 struct PM {
   double a, b, c, d, e, f, g;
@@ -190,17 +215,15 @@ __device__ inline double wave_max64(double v) {
 template <int NPL, typename T>
 __device__ inline void stage_regs(T* sh, const T* vals, int len) {
 #pragma unroll
-  for (int j = 0; j < NPL; ++j) {
-    const int t = threadIdx.x + j * kLT;
-    if (t < len) sh[pidx<NPL>(t)] = vals[j];
-  }
+  for (int j = 0; j < NPL; ++j)
+    if (in_stripe(j, len)) sh[sidx<NPL>(j)] = vals[j];
   __syncthreads();
 }
 
 template <int NPL, typename T>
 __device__ inline void stage_take(const T* sh, int t0, int len, T pad, T* out) {
 #pragma unroll
-  for (int k = 0; k < NPL; ++k) out[k] = t0 + k < len ? sh[pidx<NPL>(t0 + k)] : pad;
+  for (int k = 0; k < NPL; ++k) out[k] = t0 + k < len ? sh[bidx<NPL>(k)] : pad;
 }
 
 // Blocked values of every thread to a line array through LDS (coalesced stores).
@@ -208,7 +231,7 @@ template <int NPL, typename T>
 __device__ inline void stage_out(T* sh, const T* vals, int t0, int len) {
 #pragma unroll
   for (int k = 0; k < NPL; ++k)
-    if (t0 + k < len) sh[pidx<NPL>(t0 + k)] = vals[k];
+    if (t0 + k < len) sh[bidx<NPL>(k)] = vals[k];
   __syncthreads();
 }
 
@@ -237,14 +260,10 @@ __global__ __launch_bounds__(kLT, 2) void k_line_joint(LineArgs a0, LineArgs a1,
     double gd[NPL], gc[NPL], gl[NPL], gh[NPL];
 #pragma unroll
     for (int j = 0; j < NPL; ++j) {
-      const int t = threadIdx.x + j * kLT;
-      if (t < len) {
-        const int64_t i = base + t;
-        gd[j] = A.diag[i] + A.lam_in[i];
-        gc[j] = A.b[i] + A.m_in[i];
-        gl[j] = A.lo[i];
-        gh[j] = A.hi[i];
-      }
+      gd[j] = ld_stripe(A.diag + base, j, len) + ld_stripe(A.lam_in + base, j, len);
+      gc[j] = ld_stripe(A.b + base, j, len) + ld_stripe(A.m_in + base, j, len);
+      gl[j] = ld_stripe(A.lo + base, j, len);
+      gh[j] = ld_stripe(A.hi + base, j, len);
     }
     stage_regs<NPL>(sh, gd, len);
     stage_take<NPL>(sh, t0, len, 1.0, d);
@@ -258,7 +277,7 @@ __global__ __launch_bounds__(kLT, 2) void k_line_joint(LineArgs a0, LineArgs a1,
     __syncthreads();
     stage_regs<NPL>(sh, gh, len);
 #pragma unroll
-    for (int k = 0; k < NPL; ++k) h[k + 1] = t0 + k < len ? sh[pidx<NPL>(t0 + k)] : 0.0;
+    for (int k = 0; k < NPL; ++k) h[k + 1] = t0 + k < len ? sh[bidx<NPL>(k)] : 0.0;
     h[0] = (t0 > 0 && t0 - 1 < len) ? sh[pidx<NPL>(t0 - 1)] : 0.0;
     __syncthreads();
   }
@@ -336,7 +355,7 @@ __global__ __launch_bounds__(kLT, 2) void k_line_joint(LineArgs a0, LineArgs a1,
     for (int j = 0; j < NPL; ++j) {
       const int t = threadIdx.x + j * kLT;
       if (t < len) {
-        const double v = sh[pidx<NPL>(t)];
+        const double v = sh[sidx<NPL>(j)];
         A.alpha[base + t] = v;
         A.alpha32[base + t] = static_cast<float>(v);
       }
@@ -347,7 +366,7 @@ __global__ __launch_bounds__(kLT, 2) void k_line_joint(LineArgs a0, LineArgs a1,
     for (int j = 0; j < NPL; ++j) {
       const int t = threadIdx.x + j * kLT;
       if (t < len) {
-        const double v = sh[pidx<NPL>(t)];
+        const double v = sh[sidx<NPL>(j)];
         A.beta[base + t] = v;
         A.beta32[base + t] = static_cast<float>(v);
       }
@@ -359,7 +378,7 @@ __global__ __launch_bounds__(kLT, 2) void k_line_joint(LineArgs a0, LineArgs a1,
       for (int j = 0; j < NPL; ++j) {
         const int t = threadIdx.x + j * kLT;
         if (t < len) {
-          const double v = 1.0 / sh[pidx<NPL>(t)];
+          const double v = 1.0 / sh[sidx<NPL>(j)];
           A.invS[base + t] = v;
           A.invS32[base + t] = static_cast<float>(v);
         }
@@ -369,14 +388,19 @@ __global__ __launch_bounds__(kLT, 2) void k_line_joint(LineArgs a0, LineArgs a1,
   }
 
   double dmax = 0.0, lmax = 0.0;
+  double prev[NPL];   // the messages being replaced (Lt phase: the change per sweep)
+  if (A.partials) {
+#pragma unroll
+    for (int j = 0; j < NPL; ++j) prev[j] = ld_stripe(A.lam_out + base, j, len);
+  }
   stage_out<NPL>(sh, Fl, t0, len);
 #pragma unroll
   for (int j = 0; j < NPL; ++j) {
     const int t = threadIdx.x + j * kLT;
     if (t < len) {
-      const double v = sh[pidx<NPL>(t)];
+      const double v = sh[sidx<NPL>(j)];
       if (A.partials) {
-        const double dv = fabs(v - A.lam_out[base + t]);
+        const double dv = fabs(v - prev[j]);
         // a non-finite message must stop the Lt phase (fmax would drop a NaN)
         dmax = fmax(dmax, dv <= 1.7976931348623157e308 ? dv : __builtin_inf());
         lmax = fmax(lmax, fabs(v) <= 1.7976931348623157e308 ? fabs(v) : __builtin_inf());
@@ -389,7 +413,7 @@ __global__ __launch_bounds__(kLT, 2) void k_line_joint(LineArgs a0, LineArgs a1,
 #pragma unroll
   for (int j = 0; j < NPL; ++j) {
     const int t = threadIdx.x + j * kLT;
-    if (t < len) A.m_out[base + t] = sh[pidx<NPL>(t)];
+    if (t < len) A.m_out[base + t] = sh[sidx<NPL>(j)];
   }
   if (A.partials) {
     dmax = wave_max64(dmax);
@@ -417,7 +441,7 @@ __global__ __launch_bounds__(kLT, 2) void k_line_joint(LineArgs a0, LineArgs a1,
 // beta_t q_{t+1}, c_t = b_t + m_in(t).
 // ---------------------------------------------------------------------------------------
 template <typename T, int NPL>
-__global__ __launch_bounds__(kLT) void k_line_mean(LineMeanArgs<T> a0, LineMeanArgs<T> a1,
+__global__ __launch_bounds__(kLT, 3) void k_line_mean(LineMeanArgs<T> a0, LineMeanArgs<T> a1,
                                                    int nblk0) {
   __shared__ T sh[kLT * (NPL + 1)];
   __shared__ T tot[4 * kLWaves];
@@ -433,13 +457,9 @@ __global__ __launch_bounds__(kLT) void k_line_mean(LineMeanArgs<T> a0, LineMeanA
     T ga[NPL], gb[NPL], gc[NPL];
 #pragma unroll
     for (int j = 0; j < NPL; ++j) {
-      const int t = threadIdx.x + j * kLT;
-      if (t < len) {
-        const int64_t i = base + t;
-        ga[j] = A.alpha[i];
-        gb[j] = A.beta[i];
-        gc[j] = A.b[i] + A.m_in[i];
-      }
+      ga[j] = ld_stripe(A.alpha + base, j, len);
+      gb[j] = ld_stripe(A.beta + base, j, len);
+      gc[j] = ld_stripe(A.b + base, j, len) + ld_stripe(A.m_in + base, j, len);
     }
     stage_regs<NPL>(sh, ga, len);
     stage_take<NPL>(sh, t0, len, T(0), al);
@@ -483,10 +503,8 @@ __global__ __launch_bounds__(kLT) void k_line_mean(LineMeanArgs<T> a0, LineMeanA
   }
   stage_out<NPL>(sh, out, t0, len);
 #pragma unroll
-  for (int j = 0; j < NPL; ++j) {
-    const int t = threadIdx.x + j * kLT;
-    if (t < len) A.m_out[base + t] = sh[pidx<NPL>(t)];
-  }
+  for (int j = 0; j < NPL; ++j)
+    if (in_stripe(j, len)) A.m_out[base + threadIdx.x + j * kLT] = sh[sidx<NPL>(j)];
 }
 
 // ---------------------------------------------------------------------------------------
