@@ -183,12 +183,24 @@ int gabp_adjoint_scatter(gabp_ctx* ctx, const double* lambda, const double* x, d
                          int32_t nparam, const int32_t* jptr, const int32_t* jnnz,
                          const double* jw, double* dtheta, hipStream_t stream);
 
-/* Checkpoint: the complete iteration state (messages, precomputed Lt, sweep parity).
- * gabp_get_state with dst == NULL stores the needed size in *bytes; otherwise dst (host)
- * must hold *bytes. gabp_set_state restores a state taken from a context with the same
- * matrix pattern and options. */
+/* Checkpoint: the complete iteration state (messages, precomputed Lt, sweep parity; for
+ * line schedules the messages of both orientations and both layouts, the FP32 messages and
+ * the frozen multipliers and read-off factors). gabp_get_state with dst == NULL stores the
+ * needed size in *bytes; otherwise dst (host) must hold *bytes. gabp_set_state restores a
+ * state taken from a context with the same matrix pattern and options (EINVAL for a blob
+ * of another layout or schedule family, or a truncated one). */
 int gabp_get_state(gabp_ctx* ctx, void* dst, size_t* bytes, hipStream_t stream);
 int gabp_set_state(gabp_ctx* ctx, const void* src, size_t bytes, hipStream_t stream);
+
+/* Residual history of the context's last gabp_solve / gabp_solve_transposed: the
+ * ||b - A x||_2 / ||b||_2 read at every check (FP32 refinement: of every trial x + s d),
+ * in order. *count (host) receives the number of checks; out (host, may be NULL) receives
+ * the first min(cap, count) values. Fault injection for tests of the failure path: when the
+ * environment variable GABP_FAULT_INJECT reads nan@sweep:<k> at gabp_setup, the first
+ * single-system solve check block that starts at or after sweep k begins with every
+ * incoming mean message set to NaN (once), so the check reports GABP_ENUMERIC; gabp_setup
+ * returns GABP_EINVAL for any other value of the variable. */
+int gabp_residual_history(const gabp_ctx* ctx, double* out, int32_t cap, int32_t* count);
 
 /* Sizes of the internal layout (host outputs, any may be NULL): number of rows, stored
  * nonzeros, directed message slots (2 x off-diagonal pairs), padded slot count, and the

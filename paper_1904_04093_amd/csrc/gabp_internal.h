@@ -110,6 +110,11 @@ struct gabp_ctx {
   gabp::Batch* batch = nullptr;        // set for contexts made by gabp_setup_batched
   gabp::GraphCache* graphs = nullptr;  // recorded check blocks
   gabp::LineLayout* lines = nullptr;   // set for the line schedules
+  // fault injection (environment GABP_FAULT_INJECT=nan@sweep:k, read at set-up): before the
+  // first check block that starts at or after sweep k, the incoming mean messages are
+  // overwritten with NaN; -1 when off or already done
+  int32_t inject_nan_at = -1;
+  std::vector<double> history;         // ||r||_2 / ||b||_2 at every check of the last solve
 };
 
 namespace gabp {

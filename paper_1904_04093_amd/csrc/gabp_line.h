@@ -29,6 +29,8 @@
 // into the other layout by a tiled LDS transpose after each update.
 #pragma once
 
+#include <vector>
+
 #include "gabp_internal.h"
 
 namespace gabp {
@@ -142,5 +144,16 @@ int line_rhs32(gabp_ctx* c, const float* b, hipStream_t s);
 int line_sweep64(gabp_ctx* c, int T, const double* b, double* x, hipStream_t s);
 int line_sweep32(gabp_ctx* c, int T, const float* b, float* x, hipStream_t s);
 int line_precompute(gabp_ctx* c, int T, hipStream_t s);
+
+// Checkpoint: the device arrays of the iteration state in a fixed order -- the joint FP64
+// messages of both orientations (own layout and the other layout's copy), the FP32 mean
+// messages if has32, and per transposition T with pre[T] the frozen multipliers (FP64 and
+// FP32) and read-off factors. alloc: allocate what a restore needs and is missing.
+struct StateArray {
+  void* p;
+  size_t bytes;
+};
+int line_state_arrays(gabp_ctx* c, bool has32, const bool pre[2], bool alloc,
+                      std::vector<StateArray>* out);
 
 }  // namespace gabp

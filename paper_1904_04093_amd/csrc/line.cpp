@@ -325,13 +325,7 @@ int line_sweep32(gabp_ctx* c, int T, const float* b, float* x, hipStream_t s) {
   return GABP_OK;
 }
 
-// Precision phase: iterate the Lambda messages alone (zero right-hand side, so the mean
-// messages stay zero) until max|dLambda| <= tol_lambda * max|Lambda|, then the frozen
-// multipliers alpha, beta from the final messages and 1/Sigma* for the read-off.
-int line_precompute(gabp_ctx* c, int T, hipStream_t s) {
-  Precomp& P = c->pre[T];
-  if (P.valid) return GABP_OK;
-  LineLayout& G = *c->lines;
+static int alloc_pre(LineLayout& G, int T) {
   int st;
   for (auto& S : G.side)
     if (!S.alpha[T] &&
@@ -340,6 +334,48 @@ int line_precompute(gabp_ctx* c, int T, hipStream_t s) {
       return st;
   if (!G.invS[T] && ((st = dev_alloc(&G.invS[T], G.n)) || (st = dev_alloc(&G.invS32[T], G.n))))
     return st;
+  return GABP_OK;
+}
+
+int line_state_arrays(gabp_ctx* c, bool has32, const bool pre[2], bool alloc,
+                      std::vector<StateArray>* out) {
+  LineLayout& G = *c->lines;
+  const size_t n = static_cast<size_t>(G.n);
+  int st;
+  out->clear();
+  for (auto& S : G.side)
+    for (double* p : {S.lam_own, S.m_own, S.lam_x, S.m_x}) out->push_back({p, n * sizeof(double)});
+  if (has32) {
+    if (alloc && (st = line_ensure32(c, nullptr)) != GABP_OK) return st;
+    for (auto& S : G.side)
+      for (float* p : {S.m32_own, S.m32_x}) out->push_back({p, n * sizeof(float)});
+  }
+  for (int T = 0; T < 2; ++T) {
+    if (!pre[T]) continue;
+    if (alloc && (st = alloc_pre(G, T)) != GABP_OK) return st;
+    for (auto& S : G.side) {
+      out->push_back({S.alpha[T], n * sizeof(double)});
+      out->push_back({S.beta[T], n * sizeof(double)});
+      out->push_back({S.alpha32[T], n * sizeof(float)});
+      out->push_back({S.beta32[T], n * sizeof(float)});
+    }
+    out->push_back({G.invS[T], n * sizeof(double)});
+    out->push_back({G.invS32[T], n * sizeof(float)});
+  }
+  for (const auto& a : *out)
+    if (!a.p) return fail(GABP_EINVAL, "line state array missing");
+  return GABP_OK;
+}
+
+// Precision phase: iterate the Lambda messages alone (zero right-hand side, so the mean
+// messages stay zero) until max|dLambda| <= tol_lambda * max|Lambda|, then the frozen
+// multipliers alpha, beta from the final messages and 1/Sigma* for the read-off.
+int line_precompute(gabp_ctx* c, int T, hipStream_t s) {
+  Precomp& P = c->pre[T];
+  if (P.valid) return GABP_OK;
+  LineLayout& G = *c->lines;
+  int st;
+  if ((st = alloc_pre(G, T)) != GABP_OK) return st;
   if ((st = zero_joint(G, s)) != GABP_OK) return st;
   const LineSide& R = G.side[0];
   const LineSide& C = G.side[1];

@@ -7,6 +7,8 @@
 // other coefficient is zero, so the message through it is identically zero (Sec. 2.3,
 // remark after Algorithm 1), which is how structurally nonsymmetric A is handled.
 #include <algorithm>
+#include <cstdlib>
+#include <cstdio>
 #include <cmath>
 #include <cstring>
 #include <limits>
@@ -161,6 +163,14 @@ int gabp_setup(gabp_ctx** out, int32_t n, int64_t nnz, const int32_t* rowptr,
     return fail(GABP_EINVAL, "invalid options");
   if (o.schedule == GABP_SCHED_REDBLACK && !colour)
     return fail(GABP_EINVAL, "red-black schedule needs node colours");
+  int32_t inject_at = -1;
+  if (const char* fi = std::getenv("GABP_FAULT_INJECT")) {
+    int k = -1;
+    char tail = 0;
+    if (std::sscanf(fi, "nan@sweep:%d%c", &k, &tail) != 1 || k < 0)
+      return fail(GABP_EINVAL, "GABP_FAULT_INJECT must read nan@sweep:<k>, k >= 0");
+    inject_at = k;
+  }
 
   // --- transposed pattern (counting sort): tptr/trow/tidx list entries (i, j) by column j
   std::vector<int64_t> tptr(n + 1, 0);
@@ -309,6 +319,7 @@ int gabp_setup(gabp_ctx** out, int32_t n, int64_t nnz, const int32_t* rowptr,
 
   gabp_ctx* c = new gabp_ctx();
   c->opt = o;
+  c->inject_nan_at = inject_at;
   c->graphs = new GraphCache();
   GABP_HIP(hipGetDevice(&c->device));
   Layout& L = c->L;

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <limits>
 #include <vector>
 
 #include "gabp_internal.h"
@@ -206,6 +207,24 @@ void fill_info(gabp_info* info, int status, int sweeps, int lsweeps, int outer,
   info->res_inf = nm.rinf;
 }
 
+// Fault injection: NaN into every incoming mean message of the current sweep (FP64, or the
+// FP32 inner messages of the refinement), once, when the solve reaches the chosen sweep.
+static int maybe_inject(gabp_ctx* c, int done, bool f32, hipStream_t s) {
+  if (c->inject_nan_at < 0 || done < c->inject_nan_at) return GABP_OK;
+  c->inject_nan_at = -1;
+  const double nan = std::numeric_limits<double>::quiet_NaN();
+  if (c->lines) {
+    for (const auto& S : c->lines->side) {
+      if (f32) GABP_HIP(launch_fill32(S.m32_x, c->lines->n, static_cast<float>(nan), s));
+      else GABP_HIP(launch_fill64(S.m_x, c->lines->n, nan, s));
+    }
+    return GABP_OK;
+  }
+  if (f32) GABP_HIP(launch_fill32(c->msg32[c->parity32], c->L.epad + 1, static_cast<float>(nan), s));
+  else GABP_HIP(launch_fill64(c->msg[c->parity], c->L.epad + 1, nan, s));
+  return GABP_OK;
+}
+
 // Plain FP64 solve (JOINT or PRECOMP, flood or red-black).
 int solve64(gabp_ctx* c, int T, const double* b, double* x, double tol, int max_sweeps,
             gabp_info* info, hipStream_t s) {
@@ -220,8 +239,10 @@ int solve64(gabp_ctx* c, int T, const double* b, double* x, double tol, int max_
   Norms nm{0, 0, 0};
   int done = 0;
   const bool rb = in_place(c);
+  c->history.clear();
   while (done < max_sweeps) {
     const int k = std::min(c->opt.check_every, max_sweeps - done);
+    if ((st = maybe_inject(c, done, false, s)) != GABP_OK) return st;
     const int start = c->parity;
     // one check block: k sweeps (read-off on the last), residual, norms to the host
     st = run_block(c, *c->graphs, s, GraphKey{1, b, x, nullptr, start, k, T, 0.0},
@@ -242,11 +263,12 @@ int solve64(gabp_ctx* c, int T, const double* b, double* x, double tol, int max_
     done += k;
     GABP_HIP(hipStreamSynchronize(s));
     host_norms(c, &nm);
+    const double rel = nm.b2 > 0 ? nm.r2 / nm.b2 : nm.r2;
+    c->history.push_back(rel);
     if (!std::isfinite(nm.r2) || !std::isfinite(nm.rinf)) {
       fill_info(info, GABP_ENUMERIC, done, lsw, 0, nm);
       return fail(GABP_ENUMERIC, "non-finite residual after sweep " + std::to_string(done));
     }
-    const double rel = nm.b2 > 0 ? nm.r2 / nm.b2 : nm.r2;
     if (rel <= tol) {
       fill_info(info, GABP_OK, done, lsw, 0, nm);
       return GABP_OK;
@@ -281,6 +303,7 @@ int solve_ir(gabp_ctx* c, int T, const double* b, double* x, double tol, int max
   if (!std::isfinite(nm.r2)) return fail(GABP_EINVAL, "non-finite right-hand side");
   const double bn = nm.b2;
   int total = 0, outer = 0;
+  c->history.clear();
   double* scale = c->red + 4;   // device copy of s for this outer step
   while (true) {
     const double rel = bn > 0 ? nm.r2 / bn : nm.r2;
@@ -301,6 +324,7 @@ int solve_ir(gabp_ctx* c, int T, const double* b, double* x, double tol, int max
     const bool rb = in_place(c);
     while (true) {
       const int k = std::min({c->opt.check_every, max_sweeps - total, c->opt.ir_max_inner - inner});
+      if ((st = maybe_inject(c, total, true, s)) != GABP_OK) return st;
       const int start = c->parity32;
       double* rt = buf[itry];
       // one inner block: k FP32 sweeps, FP64 residual of x + s d, norms to the host
@@ -324,6 +348,7 @@ int solve_ir(gabp_ctx* c, int T, const double* b, double* x, double tol, int max
       Norms nt;
       GABP_HIP(hipStreamSynchronize(s));
       host_norms(c, &nt);
+      c->history.push_back(bn > 0 ? nt.r2 / bn : nt.r2);
       if (!std::isfinite(nt.r2)) {
         fill_info(info, GABP_ENUMERIC, total, lsw, outer, nt);
         return fail(GABP_ENUMERIC, "non-finite residual in iterative refinement");
@@ -505,12 +530,62 @@ struct StateHeader {
   int32_t pre_valid[2], pre_sweeps[2];
   int32_t has32, pad;
 };
-constexpr uint64_t kMagic = 0x6761627073743031ull;  // "gabpst01"
+constexpr uint64_t kMagic = 0x6761627073743031ull;      // "gabpst01"
+constexpr uint64_t kLineMagic = 0x676162706c6e3031ull;  // "gabpln01"
+
+// Line schedules: the header, then the arrays listed by line_state_arrays.
+int line_get_state(gabp_ctx* c, void* dst, size_t* bytes, hipStream_t s) {
+  const bool pre[2] = {c->pre[0].valid, c->pre[1].valid};
+  const bool has32 = line_has32(c);
+  std::vector<StateArray> arr;
+  int st;
+  if ((st = line_state_arrays(c, has32, pre, false, &arr)) != GABP_OK) return st;
+  size_t need = sizeof(StateHeader);
+  for (const auto& a : arr) need += a.bytes;
+  if (!dst) {
+    *bytes = need;
+    return GABP_OK;
+  }
+  if (*bytes < need) return fail(GABP_EINVAL, "state buffer too small");
+  StateHeader h{kLineMagic, c->L.n, c->L.epad, {pre[0], pre[1]},
+                {c->pre[0].sweeps, c->pre[1].sweeps}, has32, 0};
+  char* p = static_cast<char*>(dst);
+  std::memcpy(p, &h, sizeof(h));
+  p += sizeof(h);
+  for (const auto& a : arr) {
+    GABP_HIP(hipMemcpyAsync(p, a.p, a.bytes, hipMemcpyDeviceToHost, s));
+    p += a.bytes;
+  }
+  GABP_HIP(hipStreamSynchronize(s));
+  *bytes = need;
+  return GABP_OK;
+}
+
+int line_set_state(gabp_ctx* c, const StateHeader& h, const char* p, size_t bytes,
+                   hipStream_t s) {
+  const bool pre[2] = {h.pre_valid[0] != 0, h.pre_valid[1] != 0};
+  std::vector<StateArray> arr;
+  int st;
+  if ((st = line_state_arrays(c, h.has32 != 0, pre, true, &arr)) != GABP_OK) return st;
+  size_t need = sizeof(StateHeader);
+  for (const auto& a : arr) need += a.bytes;
+  if (bytes < need) return fail(GABP_EINVAL, "state blob truncated");
+  for (const auto& a : arr) {
+    GABP_HIP(hipMemcpyAsync(a.p, p, a.bytes, hipMemcpyHostToDevice, s));
+    p += a.bytes;
+  }
+  for (int T = 0; T < 2; ++T) {
+    c->pre[T].valid = pre[T];
+    c->pre[T].sweeps = pre[T] ? h.pre_sweeps[T] : 0;
+  }
+  GABP_HIP(hipStreamSynchronize(s));
+  return GABP_OK;
+}
 }  // namespace
 
 int gabp_get_state(gabp_ctx* c, void* dst, size_t* bytes, hipStream_t s) {
   if (!c || !bytes) return fail(GABP_EINVAL, "NULL argument");
-  if (c->lines) return fail(GABP_ENOTSUPP, "checkpoints of line schedules are not supported");
+  if (c->lines) return line_get_state(c, dst, bytes, s);
   const Layout& L = c->L;
   const size_t E = static_cast<size_t>(L.epad + 1), N = static_cast<size_t>(L.n);
   size_t need = sizeof(StateHeader) + 2 * E * sizeof(double);
@@ -549,12 +624,13 @@ int gabp_get_state(gabp_ctx* c, void* dst, size_t* bytes, hipStream_t s) {
 
 int gabp_set_state(gabp_ctx* c, const void* src, size_t bytes, hipStream_t s) {
   if (!c || !src || bytes < sizeof(StateHeader)) return fail(GABP_EINVAL, "bad state");
-  if (c->lines) return fail(GABP_ENOTSUPP, "checkpoints of line schedules are not supported");
   StateHeader h;
   std::memcpy(&h, src, sizeof(h));
   const Layout& L = c->L;
-  if (h.magic != kMagic || h.n != L.n || h.epad != L.epad)
-    return fail(GABP_EINVAL, "state was taken from a different layout");
+  if (h.magic != (c->lines ? kLineMagic : kMagic) || h.n != L.n || h.epad != L.epad)
+    return fail(GABP_EINVAL, "state was taken from a different layout or schedule");
+  if (c->lines)
+    return line_set_state(c, h, static_cast<const char*>(src) + sizeof(h), bytes, s);
   const size_t E = static_cast<size_t>(L.epad + 1), N = static_cast<size_t>(L.n);
   size_t need = sizeof(StateHeader) + 2 * E * sizeof(double);
   for (int T = 0; T < 2; ++T)
@@ -594,6 +670,16 @@ int gabp_set_state(gabp_ctx* c, const void* src, size_t bytes, hipStream_t s) {
     if ((st = put(c->msg32[0], E * sizeof(float)))) return st;
   }
   GABP_HIP(hipStreamSynchronize(s));
+  return GABP_OK;
+}
+
+int gabp_residual_history(const gabp_ctx* c, double* out, int32_t cap, int32_t* count) {
+  if (!c || !count) return fail(GABP_EINVAL, "NULL argument");
+  if (cap < 0) return fail(GABP_EINVAL, "cap < 0");
+  const int32_t m = static_cast<int32_t>(c->history.size());
+  *count = m;
+  if (out)
+    for (int32_t i = 0; i < std::min(m, cap); ++i) out[i] = c->history[i];
   return GABP_OK;
 }
 

@@ -74,6 +74,7 @@ _SIGS = {
     "gabp_adjoint_scatter": (ctypes.c_int, [_P, _P, _P, _P, _I32, _P, _P, _P, _P, _P]),
     "gabp_get_state": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_size_t), _P]),
     "gabp_set_state": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P]),
+    "gabp_residual_history": (ctypes.c_int, [_P, _P, _I32, _PI32]),
     "gabp_layout_info": (ctypes.c_int, [_P, _PI32, _PI64, _PI64, _PI64, _PI32]),
     "gabp_copy_probe": (ctypes.c_int, [_P, _P, _I64, _P]),
     "gabp_autotune": (ctypes.c_int, [_P, _PI32, _PI32, _P]),
@@ -295,6 +296,17 @@ class Solver:
     def set_state(self, blob: bytes):
         buf = ctypes.create_string_buffer(blob, len(blob))
         _check(self._lib.gabp_set_state(self._h, buf, len(blob), _stream()))
+
+    def residual_history(self):
+        """||r||_2 / ||b||_2 at every check of the last solve (numpy array)."""
+        import numpy as np
+        cnt = ctypes.c_int32(0)
+        _check(self._lib.gabp_residual_history(self._h, None, 0, ctypes.byref(cnt)))
+        out = np.zeros(cnt.value, dtype=np.float64)
+        if cnt.value:
+            _check(self._lib.gabp_residual_history(
+                self._h, out.ctypes.data_as(_P), cnt.value, ctypes.byref(cnt)))
+        return out
 
     def autotune(self):
         """Pick streaming hints and the check interval by measurement (see gabp_autotune)."""

@@ -246,9 +246,31 @@ def test_line_setup_rejects_what_it_cannot_run(B):
         B.Solver.from_csr(long_row, schedule="lines", grid=(5000, 1))
     assert e.value.status == B.ENOTSUPP
     s = B.Solver.from_csr(a, schedule="lines", grid=(nx, ny))
-    with pytest.raises(B.GaBPError) as e:
-        s.get_state()
-    assert e.value.status == B.ENOTSUPP
+    blob = s.get_state()
+    with pytest.raises(B.GaBPError) as e:            # a line state does not fit a point context
+        B.Solver.from_csr(a).set_state(blob)
+    assert e.value.status == B.EINVAL
+
+
+@pytest.mark.parametrize("schedule", ["lines", "lines_alt"])
+@pytest.mark.parametrize("kw", [dict(mode="joint"),
+                                dict(mode="precomp", precision="f32_ir", tol_lambda=1e-10)])
+def test_line_checkpoint_resumes_bit_for_bit(B, schedule, kw):
+    """k sweeps, export, import into a fresh context, more sweeps = the uninterrupted run."""
+    a, b, nx, ny = _problem("130x65", 6)
+    bt = _cuda(b)
+    s = B.Solver.from_csr(a, schedule=schedule, grid=(nx, ny), **kw)
+    s.sweeps(bt, 5)
+    blob = s.get_state()
+    want = s.sweeps(bt, 7, reset=False).cpu().numpy()
+    r = B.Solver.from_csr(a, schedule=schedule, grid=(nx, ny), **kw)
+    r.set_state(blob)
+    got = r.sweeps(bt, 7, reset=False).cpu().numpy()
+    assert np.array_equal(got, want)
+    assert np.array_equal(s.sweeps(bt, 12).cpu().numpy(), want)   # 5 + 7 sweeps from zero
+    with pytest.raises(B.GaBPError) as e:            # truncated blob
+        r.set_state(blob[:-8])
+    assert e.value.status == B.EINVAL
 
 
 # --------------------------------------------------------------------------------------

@@ -351,6 +351,43 @@ def test_failure_modes(B):
         s.solve(_cuda(b), 1e-14, 0)
 
 
+@pytest.mark.parametrize("kw,at", [(dict(mode="joint"), 8),
+                                   (dict(mode="precomp", precision="f32_ir", tol_lambda=1e-10), 16),
+                                   (dict(mode="joint", schedule="lines_alt", grid=(32, 32)), 8)])
+def test_injected_nan_is_reported(B, monkeypatch, kw, at):
+    """A NaN forced into the messages from the host (GABP_FAULT_INJECT) reaches the check
+    that follows it and ends the solve with ENUMERIC; the checks before it stay finite."""
+    a, b, _ = CASES["upwind32"]
+    monkeypatch.setenv("GABP_FAULT_INJECT", f"nan@sweep:{at}")
+    s = B.Solver.from_csr(a, check_every=4, **kw)
+    monkeypatch.delenv("GABP_FAULT_INJECT")
+    with pytest.raises(B.GaBPError) as e:
+        s.solve(_cuda(b), 1e-14, 4000)
+    assert e.value.status == B.ENUMERIC
+    h = s.residual_history()
+    assert len(h) >= 2 and np.isnan(h[-1]) and np.all(np.isfinite(h[:-1]))
+    if "precision" not in kw:
+        assert len(h) == at // 4 + 1                 # the block that starts at sweep `at`
+    # injection happens once: the same context solves normally afterwards
+    x, info = s.solve(_cuda(b), 1e-10, 40000)
+    assert info.status == B.OK
+    monkeypatch.setenv("GABP_FAULT_INJECT", "inf@7")
+    with pytest.raises(B.GaBPError) as e:
+        B.Solver.from_csr(a)
+    assert e.value.status == B.EINVAL
+
+
+def test_residual_history_records_every_check(B):
+    a, b, _ = CASES["upwind32"]
+    s = B.Solver.from_csr(a, check_every=8)
+    x, info = s.solve(_cuda(b), 1e-10, 40000)
+    h = s.residual_history()
+    assert info.status == B.OK and len(h) == info.sweeps // 8
+    assert h[-1] == info.rel_res2 and h[-1] <= 1e-10 and np.all(h[:-1] > 1e-10)
+    s.solve(_cuda(b), 1e-3, 40000)                   # the next solve replaces the history
+    assert len(s.residual_history()) < len(h)
+
+
 def _ball(a, centre, radius):
     seen = {int(centre)}
     frontier = [int(centre)]
