@@ -114,6 +114,9 @@ struct gabp_ctx {
   // first check block that starts at or after sweep k, the incoming mean messages are
   // overwritten with NaN; -1 when off or already done
   int32_t inject_nan_at = -1;
+  // GABP_FAULT_INJECT=poison-outputs: every ping-pong sweep first fills its output message
+  // buffers with NaN, so a slot the sweep does not write shows up in the next read-off
+  bool poison_outputs = false;
   std::vector<double> history;         // ||r||_2 / ||b||_2 at every check of the last solve
 };
 

@@ -3,6 +3,7 @@
 // layouts built from a 5-point grid matrix, the sweep drivers for the flood and the
 // rows-then-columns schedules, the precision-message phase and the frozen multipliers.
 #include <cmath>
+#include <limits>
 #include <string>
 #include <vector>
 
@@ -270,10 +271,29 @@ int line_rhs32(gabp_ctx* c, const float* b, hipStream_t s) {
   return GABP_OK;
 }
 
+// GABP_FAULT_INJECT=poison-outputs: NaN into the arrays a line update only writes (the
+// messages in the sender's own layout) before the update.
+static int poison_own(gabp_ctx* c, bool f32, hipStream_t s) {
+  if (!c->poison_outputs) return GABP_OK;
+  const LineLayout& G = *c->lines;
+  const double nan = std::numeric_limits<double>::quiet_NaN();
+  for (const auto& S : G.side) {
+    if (f32) {
+      GABP_HIP(launch_fill32(S.m32_own, G.n, static_cast<float>(nan), s));
+      continue;
+    }
+    GABP_HIP(launch_fill64(S.m_own, G.n, nan, s));
+    if (c->opt.mode != GABP_MODE_PRECOMP) GABP_HIP(launch_fill64(S.lam_own, G.n, nan, s));
+  }
+  return GABP_OK;
+}
+
 int line_sweep64(gabp_ctx* c, int T, const double* b, double* x, hipStream_t s) {
   const LineLayout& G = *c->lines;
   const LineSide& R = G.side[0];
   const LineSide& C = G.side[1];
+  int st;
+  if ((st = poison_own(c, false, s)) != GABP_OK) return st;
   if (c->opt.mode != GABP_MODE_PRECOMP) {
     LineArgs a[2];
     joint_args(G, T, b, G.bcol, a);
@@ -282,7 +302,6 @@ int line_sweep64(gabp_ctx* c, int T, const double* b, double* x, hipStream_t s) 
   LineMeanArgs<double> m[2] = {
       {R.nlines, R.len, R.alpha[T], R.beta[T], b, C.m_x, R.m_own},
       {C.nlines, C.len, C.alpha[T], C.beta[T], G.bcol, R.m_x, C.m_own}};
-  int st;
   if (!G.alt) {
     GABP_HIP(launch_line_mean64(m, 2, s));
     if (x && (st = readoff_col64(G, G.invS[T], x, s)) != GABP_OK) return st;
@@ -301,6 +320,8 @@ int line_sweep32(gabp_ctx* c, int T, const float* b, float* x, hipStream_t s) {
   const LineLayout& G = *c->lines;
   const LineSide& R = G.side[0];
   const LineSide& C = G.side[1];
+  int st;
+  if ((st = poison_own(c, true, s)) != GABP_OK) return st;
   auto readoff = [&]() -> int {
     GABP_HIP(launch_line_readoff32(G.n, G.bcol32, R.m32_x, C.m32_own, G.invS32[T], G.xcol32, s));
     TransposeJob<float> j{G.xcol32, x, G.nx, G.ny};
@@ -310,7 +331,6 @@ int line_sweep32(gabp_ctx* c, int T, const float* b, float* x, hipStream_t s) {
   LineMeanArgs<float> m[2] = {
       {R.nlines, R.len, R.alpha32[T], R.beta32[T], b, C.m32_x, R.m32_own},
       {C.nlines, C.len, C.alpha32[T], C.beta32[T], G.bcol32, R.m32_x, C.m32_own}};
-  int st;
   if (!G.alt) {
     GABP_HIP(launch_line_mean32(m, 2, s));
     if (x && (st = readoff()) != GABP_OK) return st;

@@ -164,12 +164,17 @@ int gabp_setup(gabp_ctx** out, int32_t n, int64_t nnz, const int32_t* rowptr,
   if (o.schedule == GABP_SCHED_REDBLACK && !colour)
     return fail(GABP_EINVAL, "red-black schedule needs node colours");
   int32_t inject_at = -1;
+  bool poison = false;
   if (const char* fi = std::getenv("GABP_FAULT_INJECT")) {
     int k = -1;
     char tail = 0;
-    if (std::sscanf(fi, "nan@sweep:%d%c", &k, &tail) != 1 || k < 0)
-      return fail(GABP_EINVAL, "GABP_FAULT_INJECT must read nan@sweep:<k>, k >= 0");
-    inject_at = k;
+    if (std::strcmp(fi, "poison-outputs") == 0)
+      poison = true;
+    else if (std::sscanf(fi, "nan@sweep:%d%c", &k, &tail) == 1 && k >= 0)
+      inject_at = k;
+    else
+      return fail(GABP_EINVAL, "GABP_FAULT_INJECT must read nan@sweep:<k> (k >= 0) or "
+                               "poison-outputs");
   }
 
   // --- transposed pattern (counting sort): tptr/trow/tidx list entries (i, j) by column j
@@ -320,6 +325,7 @@ int gabp_setup(gabp_ctx** out, int32_t n, int64_t nnz, const int32_t* rowptr,
   gabp_ctx* c = new gabp_ctx();
   c->opt = o;
   c->inject_nan_at = inject_at;
+  c->poison_outputs = poison;
   c->graphs = new GraphCache();
   GABP_HIP(hipGetDevice(&c->device));
   Layout& L = c->L;

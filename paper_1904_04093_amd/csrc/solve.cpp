@@ -104,6 +104,9 @@ int ensure_msg32(gabp_ctx* c, hipStream_t s) {
   return GABP_OK;
 }
 
+// (the slot past the padded slots is the zero message of one-way edges: never poisoned)
+constexpr double kPoison = std::numeric_limits<double>::quiet_NaN();
+
 // One FP64 sweep of the configured mode and schedule on right-hand side b (coloured
 // schedule: the colour classes 0, 1, ... in turn, in place).
 // x != null: the read-off of this sweep is written there.
@@ -117,6 +120,10 @@ int sweep64(gabp_ctx* c, int T, const double* b, double* x, hipStream_t s) {
       a.msg_in = c->msg[c->parity];
       a.lam_out = c->lam[c->parity ^ 1];
       a.msg_out = c->msg[c->parity ^ 1];
+      if (c->poison_outputs) {
+        GABP_HIP(launch_fill64(a.lam_out, c->L.epad, kPoison, s));
+        GABP_HIP(launch_fill64(a.msg_out, c->L.epad, kPoison, s));
+      }
       GABP_HIP(launch_joint_sweep(a, s));
       c->parity ^= 1;
     } else {
@@ -133,6 +140,7 @@ int sweep64(gabp_ctx* c, int T, const double* b, double* x, hipStream_t s) {
     if (!rb) {
       a.msg_in = c->msg[c->parity];
       a.msg_out = c->msg[c->parity ^ 1];
+      if (c->poison_outputs) GABP_HIP(launch_fill64(a.msg_out, c->L.epad, kPoison, s));
       GABP_HIP(launch_mean_sweep64(a, s));
       c->parity ^= 1;
     } else {
@@ -153,6 +161,8 @@ int sweep32(gabp_ctx* c, int T, const float* b, float* x, hipStream_t s) {
   if (c->opt.schedule != GABP_SCHED_REDBLACK) {
     a.msg_in = c->msg32[c->parity32];
     a.msg_out = c->msg32[c->parity32 ^ 1];
+    if (c->poison_outputs)
+      GABP_HIP(launch_fill32(a.msg_out, c->L.epad, static_cast<float>(kPoison), s));
     GABP_HIP(launch_mean_sweep32(a, s));
     c->parity32 ^= 1;
   } else {

@@ -377,6 +377,48 @@ def test_injected_nan_is_reported(B, monkeypatch, kw, at):
     assert e.value.status == B.EINVAL
 
 
+@pytest.mark.parametrize("kw", [dict(mode="joint"),
+                                dict(mode="precomp", precision="f64", tol_lambda=1e-12),
+                                dict(mode="precomp", precision="f32_ir", tol_lambda=1e-10),
+                                dict(mode="joint", schedule="lines", grid=(32, 32)),
+                                dict(mode="precomp", precision="f32_ir", tol_lambda=1e-10,
+                                     schedule="lines_alt", grid=(32, 32))])
+def test_every_output_slot_is_written(B, monkeypatch, kw):
+    """Race/coverage check: with every sweep's output buffers filled with NaN first
+    (GABP_FAULT_INJECT=poison-outputs), sweeps and solves give the same bits as without."""
+    a, b, _ = CASES["upwind32"]
+    bt = _cuda(b)
+    clean = B.Solver.from_csr(a, check_every=8, **kw)
+    monkeypatch.setenv("GABP_FAULT_INJECT", "poison-outputs")
+    poisoned = B.Solver.from_csr(a, check_every=8, **kw)
+    monkeypatch.delenv("GABP_FAULT_INJECT")
+    for tr in (False, True):
+        want = clean.sweeps(bt, 9, transposed=tr).cpu().numpy()
+        got = poisoned.sweeps(bt, 9, transposed=tr).cpu().numpy()
+        assert np.all(np.isfinite(got)) and np.array_equal(got, want), tr
+    xw, iw = clean.solve(bt, 1e-9, 40000)
+    xg, ig = poisoned.solve(bt, 1e-9, 40000)
+    assert ig.status == B.OK and ig.sweeps == iw.sweeps
+    assert np.array_equal(xg.cpu().numpy(), xw.cpu().numpy())
+
+
+@pytest.mark.parametrize("name", ["walk200", "tree150", "upwind9", "n1"])
+@pytest.mark.parametrize("mode", ["joint", "precomp"])
+def test_every_output_slot_is_written_ragged(B, monkeypatch, name, mode):
+    """The same check on ragged, one-way and tiny graphs (padding lanes, missing reverses)."""
+    a, b, _ = CASES[name]
+    bt = _cuda(b)
+    kw = dict(mode=mode, tol_lambda=0.0, max_lambda_sweeps=40)
+    clean = B.Solver.from_csr(a, **kw)
+    monkeypatch.setenv("GABP_FAULT_INJECT", "poison-outputs")
+    poisoned = B.Solver.from_csr(a, **kw)
+    monkeypatch.delenv("GABP_FAULT_INJECT")
+    for k in (1, 2, 7):
+        want = clean.sweeps(bt, k).cpu().numpy()
+        got = poisoned.sweeps(bt, k).cpu().numpy()
+        assert np.array_equal(got, want), k
+
+
 def test_residual_history_records_every_check(B):
     a, b, _ = CASES["upwind32"]
     s = B.Solver.from_csr(a, check_every=8)
