@@ -125,6 +125,9 @@ namespace gabp {
 // ---- error reporting ----
 int fail(int code, const std::string& msg);
 int hip_fail(hipError_t e, const char* what);
+// CSR check of gabp_validate_csr (host only, validate.cpp)
+int validate(int32_t n, int64_t nnz, const int32_t* rowptr, const int32_t* col,
+             const double* val, const int32_t* rev);
 #define GABP_HIP(call)                                           \
   do {                                                           \
     hipError_t _e = (call);                                      \
