@@ -91,14 +91,15 @@ def main():
     ap.add_argument("--ttr-grid", type=int, default=512)
     ap.add_argument("--no-ttr", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-sweeps", type=int, default=12)
+    ap.add_argument("--cpu-sweeps", type=int, default=60)
     ap.add_argument("--profile", action="store_true",
                     help="short run for the profiler: few launches of each kernel")
     ap.add_argument("--suite", action="store_true",
                     help="also measure the multigrid, batching and adjoint configurations")
     ap.add_argument("--suite-only", action="store_true")
     ap.add_argument("--suite-part", default="all",
-                    choices=["all", "small", "batch", "mg", "adjoint", "lines", "sec5"],
+                    choices=["all", "small", "batch", "mg", "adjoint", "lines", "sec5",
+                             "colours"],
                     help="with --suite-only: run one part of the suite")
     ap.add_argument("--line-sweeps", type=int, default=50,
                     help="timed sweeps per variant in the line-sweep part")
@@ -225,7 +226,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "k_joint (FP64 joint flood sweep)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic("k_joint<4, false, true, true>"),
+                     "traffic": measured_traffic("k_joint<4, false, true, true, false>"),
                      "frac_of_copy": achieved / copy_gbs,
                      "algorithmic_bytes_per_launch": ab, "launch_us": t_sw * 1e6,
                      "reverse_index_bytes": rb},
@@ -405,7 +406,7 @@ def suite(log, part="all", line_sweeps=50):
         fn = {"small": lambda: suite_small(log), "batch": lambda: suite_batch(log),
               "mg": lambda: suite_mg(log), "adjoint": lambda: suite_adjoint(log),
               "lines": lambda: suite_lines(log, sweeps=line_sweeps),
-              "sec5": lambda: suite_sec5(log)}[part]
+              "sec5": lambda: suite_sec5(log), "colours": lambda: suite_colours(log)}[part]
         res[part] = fn()
         return res
     res["small_32x32_fp64"] = suite_small(log)
@@ -413,6 +414,7 @@ def suite(log, part="all", line_sweeps=50):
     res["multigrid"] = suite_mg(log)
     res["lines"] = suite_lines(log, sweeps=line_sweeps)
     res["sec5"] = suite_sec5(log)
+    res["colours"] = suite_colours(log)
     res["adjoint"] = suite_adjoint(log)
     return res
 
@@ -544,6 +546,64 @@ def suite_lines(log, n=4095, sweeps=50):
             log(f"[suite] lines {sched} {name}: {rec}")
             del s
     out["cpu_baseline"] = cpu_baseline_lines(log)
+    return out
+
+
+def suite_colours(log, n=2048, sweeps=40):
+    """Sweep rates of the coloured schedules at n x n: red-black on the benchmark's 5-point
+    upwind operator next to its flood sweep, and the 4-colour schedule on a dominant random
+    9-point operator next to its flood sweep. A coloured sweep updates every directed slot
+    once (one launch per colour class, in place), so its algorithmic bytes are the flood
+    kernel's: joint (40 + rb) B per slot + 16 B per row, frozen-Lt FP64 (24 + rb) + 8, FP32
+    (12 + rb) + 4 (rb = bytes of the reverse index)."""
+    import torch
+    from paper_1904_04093_amd import gabp
+    from paper_1904_04093_amd import workloads as W
+    t0 = time.perf_counter()
+    a5, b5 = W.precision_at_scale(n)
+    a9 = W.random_grid_9pt(n, n, W.rng(6, 0))
+    b9 = W.rng(6, 1).uniform(-1, 1, a9.n)
+    out = {"grid": f"{n}x{n}", "generate_s": time.perf_counter() - t0}
+    src = torch.empty(2 ** 27, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    gabp.copy_probe(src, dst)
+    t_cp = _events_time(lambda k: [gabp.copy_probe(src, dst) for _ in range(k)], 4) / 4
+    out["copy_probe_GBps"] = 2 * src.numel() * 8 / t_cp / 1e9
+    del src, dst
+    rb5, c4 = W.grid_colouring(n), W.grid_colouring4(n)
+    joint, m64 = dict(mode="joint"), dict(mode="precomp", tol_lambda=1e-12)
+    m32 = dict(mode="precomp", precision="f32_ir", tol_lambda=1e-7)
+    variants = (("upwind5", "flood", "joint_f64", joint, None),
+                ("upwind5", "redblack", "joint_f64", joint, rb5),
+                ("upwind5", "redblack", "mean_f64", m64, rb5),
+                ("upwind5", "flood", "mean_f32", m32, None),
+                ("upwind5", "redblack", "mean_f32", m32, rb5),
+                ("grid9", "flood", "joint_f64", joint, None),
+                ("grid9", "colour4", "joint_f64", joint, c4),
+                ("grid9", "colour4", "mean_f32", m32, c4))
+    for op, sched, var, kw, colour in variants:
+        a, b = (a5, b5) if op == "upwind5" else (a9, b9)
+        s = gabp.Solver.from_csr(a, colour=colour,
+                                 schedule="flood" if colour is None else "redblack", **kw)
+        if kw["mode"] == "precomp":
+            s.precompute_lambda()
+        li = s.layout_info()
+        slots, nn, rb = li["slots"], li["n"], li["rev_bytes"]
+        per = {"joint_f64": (40 + rb) * slots + 16 * nn, "mean_f64": (24 + rb) * slots + 8 * nn,
+               "mean_f32": (12 + rb) * slots + 4 * nn}[var]
+        bt = torch.as_tensor(b).cuda()
+        x = torch.zeros(a.n, dtype=torch.float64, device="cuda")
+        s.sweeps(bt, 2, x=x)
+        torch.cuda.synchronize()
+        dt = _events_time(lambda k: s.sweeps(bt, sweeps, reset=False, x=x), 1) / sweeps
+        rec = {"sweep_us": dt * 1e6, "colours": 1 if colour is None else int(colour.max()) + 1,
+               "slots": slots, "algorithmic_MB": per / 1e6,
+               "algorithmic_GBps": per / dt / 1e9, "frac_of_hbm_peak": per / dt / 1e9 / HBM_PEAK_GBS,
+               "frac_of_copy": per / dt / 1e9 / out["copy_probe_GBps"],
+               "edge_updates_per_s": slots / dt}
+        out[f"{op}_{sched}_{var}"] = rec
+        log(f"[suite] colours {op} {sched} {var}: {rec}")
+        del s
     return out
 
 

@@ -254,8 +254,10 @@ int gabp_autotune(gabp_ctx* c, int32_t* check_every_out, int32_t* hints_out, hip
     while (ce < 256 && t_check > 0.02 * ce * t_sweep) ce *= 2;
     t.check_every = ce;
     cache_store(key, t);
-    c->parity = 0;
+    c->parity = 0;   // the timing runs leave the buffers in use: logically zero again
     c->parity32 = 0;
+    c->fresh64 = true;
+    c->fresh32 = true;
   }
   hints = t.hints != 0;
   c->opt.check_every = t.check_every;

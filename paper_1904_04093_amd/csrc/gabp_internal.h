@@ -7,11 +7,13 @@
 //    used by r = b - A x) and aT = A_ij (the coefficient of the message j -> i that row j
 //    *sends*, and of Lt_ij in Sigma_j). A missing entry is stored as 0, which makes the
 //    corresponding message exactly zero (Sec. 2.3: if A_jk = 0, x_k is not eliminated).
-//  * Rows are grouped into slices of 64 (one wavefront); slice s occupies
-//    [sptr[s], sptr[s+1]) and stores slot k of row 64 s + lane at sptr[s] + 64 k + lane,
-//    so the 64 lanes of a wavefront touch 64 consecutive elements for every k.
-//  * rev[p] is the position of the reverse slot (i,j); padding slots point at a trash
-//    position `epad` that nobody reads.
+//  * Rows are grouped into slices of 64 lanes (one wavefront); slice s occupies
+//    [sptr[s], sptr[s+1]) and stores slot k of the row at lane 64 s + l at
+//    sptr[s] + 64 k + l, so the 64 lanes of a wavefront touch 64 consecutive elements for
+//    every k. Lane t holds row t, or with a colouring the colour-major order of Layout.
+//  * rev[p] is the position of the reverse slot (i,j); padding slots are their own
+//    reverse (a zero message is written there every sweep). Position epad (one past the
+//    padded slots) is allocated but holds no message.
 //  * The sweep is written "push" style, as Algorithm 1 is: the thread of row j reads its
 //    own incoming messages (contiguous), forms Sigma_j and M_j, reads off x_j and writes
 //    every outgoing message j -> i straight into the receiver's slot rev[p].
@@ -48,7 +50,7 @@ struct Layout {
   int32_t n = 0;
   int64_t nnz = 0;
   int64_t slots = 0;      // directed message slots (symmetrised pattern)
-  int64_t epad = 0;       // padded slot count; position epad is the trash slot
+  int64_t epad = 0;       // padded slot count
   int32_t nslices = 0;
   int32_t max_width = 0;  // max slots per row
   // non-temporal hints on the per-slot streams of the FP64 / FP32 sweeps: they pay off
@@ -58,7 +60,7 @@ struct Layout {
   // device
   int32_t* sptr = nullptr;   // [nslices+1]
   int32_t* rev = nullptr;    // [epad]
-  int16_t* rev16 = nullptr;  // [epad] rev[p] - p when every real slot's reverse lies within
+  int16_t* rev16 = nullptr;  // [epad] rev[p] - p when every slot's reverse lies within
                              // int16 range (grid matrices); padding slots hold 0 (self)
   int32_t* col = nullptr;    // [epad]
   double* val = nullptr;     // [epad] A_ji at slot (j,i)
@@ -69,12 +71,16 @@ struct Layout {
   int32_t* diag_src = nullptr;  // [n]
   int32_t* csr_row = nullptr;   // [nnz] row of each stored entry (adjoint scatter)
   int32_t* csr_col = nullptr;   // [nnz]
-  uint8_t* colour = nullptr;    // [n] or null
   int32_t ncolours = 0;         // colour classes (1 + the largest colour), 0 without colours
-  // With a colouring, each slice stores its rows colour-sorted (colour 0 first, ascending
-  // rows within a colour), so a red or black half-sweep reads one contiguous part of every
-  // 64-slot run. perm[t] = row held by lane t & 63 of slice t >> 6 (null: identity).
-  int32_t* perm = nullptr;      // [nslices * 64] or null
+  // Lanes: thread t of a row kernel serves lane t & 63 of slice t >> 6. Without colours lane
+  // t holds row t (nlanes = n). With a colouring the lanes are colour-major: the rows of
+  // colour 0 in ascending order, padded to whole slices, then those of colour 1, ..., so a
+  // colour pass is one launch over the full slices of lanes [cstart[c], cstart[c+1]).
+  // perm[t] = row held by lane t, -1 for a padding lane (null: identity).
+  int32_t nlanes = 0;
+  std::vector<int32_t> cstart;        // [ncolours + 1] first lane of each colour (host)
+  std::vector<int32_t> cslot;         // [ncolours + 1] first slot of each colour (host)
+  int32_t* perm = nullptr;            // [nlanes] or null
   std::vector<int32_t> lane_of_row;   // host copy of the inverse (empty: identity)
 };
 
@@ -113,6 +119,10 @@ struct gabp_ctx {
   // fault injection (environment GABP_FAULT_INJECT=nan@sweep:k, read at set-up): before the
   // first check block that starts at or after sweep k, the incoming mean messages are
   // overwritten with NaN; -1 when off or already done
+  // message buffers that are logically zero (reset) but not cleared: the next sweep of
+  // that precision treats them as zero and writes every slot
+  bool fresh64 = false;
+  bool fresh32 = false;
   int32_t inject_nan_at = -1;
   // GABP_FAULT_INJECT=poison-outputs: every ping-pong sweep first fills its output message
   // buffers with NaN, so a slot the sweep does not write shows up in the next read-off
@@ -147,7 +157,10 @@ struct SweepArgs {
   double* lam_out;
   double* msg_out;
   double* x;                // null: no read-off written
-  int colour;               // -1 flood, 0/1 only rows of that colour (in place)
+  int colour;               // -1 all lanes, else only the lanes of that colour (in place)
+  // >= 0: first sweep after a message reset; incoming slot p counts only if rev(p) < fresh
+  // (the slots of the colours already updated in this sweep), else its message is zero
+  int fresh = -1;
 };
 hipError_t launch_joint_sweep(const SweepArgs& a, hipStream_t s);
 
@@ -160,6 +173,7 @@ struct MeanArgs64 {
   double* msg_out;
   double* x;
   int colour;
+  int fresh = -1;
 };
 hipError_t launch_mean_sweep64(const MeanArgs64& a, hipStream_t s);
 
@@ -172,6 +186,7 @@ struct MeanArgs32 {
   float* msg_out;
   float* x;
   int colour;
+  int fresh = -1;
 };
 hipError_t launch_mean_sweep32(const MeanArgs32& a, hipStream_t s);
 
@@ -185,9 +200,12 @@ hipError_t launch_lambda_finalize(const Layout* L, const double* coef, const dou
 
 // r = b - A_eff x_eff, x_eff = x (+ scale[0] * dx if dx); writes r (if r) and block
 // partials; then reduces them into red[0..2].
+// norms == false: r only (per-block partials are still written, the reduction into red is
+// skipped), for callers that do not read the norms
 hipError_t launch_residual(const Layout* L, const double* coef_row, const double* b,
                            const double* x, const float* dx, const double* scale, double* r,
-                           double* partials, int32_t nred, double* red, hipStream_t s);
+                           double* partials, int32_t nred, double* red, hipStream_t s,
+                           bool norms = true);
 
 hipError_t launch_copy_probe(const void* src, void* dst, int64_t bytes, hipStream_t s);
 // out[0] = max of partials[2q], out[1] = max of partials[2q+1] over q < nblk

@@ -20,8 +20,8 @@ namespace {
 
 inline int nblocks(int64_t n, int b = kBlock) { return static_cast<int>((n + b - 1) / b); }
 
-// Thread t serves lane t & 63 of slice t >> 6; that lane holds row perm[t] when the context
-// stores colour-sorted slices (red rows first), else row t.
+// Thread t serves lane t & 63 of slice t >> 6; that lane holds row perm[t] (-1: a padding
+// lane, no row) when the context stores colour-major lanes, else row t.
 __device__ __forceinline__ int row_of(const int32_t* __restrict__ perm, int t) {
   return perm ? perm[t] : t;
 }
@@ -60,7 +60,8 @@ __device__ __forceinline__ double wave_max(double v) {
 // ---------------------------------------------------------------------------------------
 // Joint flood sweep (Algorithm 1, FP64): read off x_j, then send Lt_ji and m_ji.
 // KMAX > 0: row held in registers; KMAX == 0: two passes over memory for wide rows.
-// colour >= 0: only rows of that colour work, in place (red-black schedule).
+// Lanes [t0, t1): all of them (flood) or one colour class of a coloured layout, which the
+// class updates in place (red-black / 4-colour schedule).
 // ---------------------------------------------------------------------------------------
 // Reverse slot of p: rev[p] (int32) or p + rev16[p] (int16 delta; padding slots point at
 // themselves and write zeros there).
@@ -71,18 +72,22 @@ __device__ __forceinline__ int rev_of(const int32_t* __restrict__ rev,
   else return ld_s<NT>(rev + p);
 }
 
-template <int KMAX, bool WX, bool NT, bool R16>
+// FIRST: the sweep right after a message reset. The incoming buffers are not read (nor
+// cleared beforehand): an incoming slot counts as written only if its sender's slot rev(p)
+// lies below `fresh` (the colour classes already updated in this sweep; 0 for a flood
+// sweep), every other incoming message is zero.
+template <int KMAX, bool WX, bool NT, bool R16, bool FIRST>
 __global__ __launch_bounds__(kBlock) void k_joint(
-    int n, const int32_t* __restrict__ sptr, const int32_t* __restrict__ rev,
+    int t1, const int32_t* __restrict__ sptr, const int32_t* __restrict__ rev,
     const int16_t* __restrict__ rev16,
     const double* __restrict__ coef, const double* __restrict__ diag,
     const double* __restrict__ b, const double* lam_in, const double* msg_in,
-    double* lam_out, double* msg_out, double* __restrict__ x,
-    const uint8_t* __restrict__ colour, int c, const int32_t* __restrict__ perm) {
-  const int t = blockIdx.x * kBlock + threadIdx.x;
-  if (t >= n) return;
+    double* lam_out, double* msg_out, double* __restrict__ x, int t0, int fresh,
+    const int32_t* __restrict__ perm) {
+  const int t = t0 + static_cast<int>(blockIdx.x) * kBlock + static_cast<int>(threadIdx.x);
+  if (t >= t1) return;
   const int j = row_of(perm, t);
-  if (c >= 0 && colour[j] != c) return;
+  if (j < 0) return;
   int w;
   const int p0 = row_base(sptr, t, &w);
   double S = diag[j];
@@ -94,10 +99,16 @@ __global__ __launch_bounds__(kBlock) void k_joint(
     for (int k = 0; k < KMAX; ++k) {
       if (k < w) {
         const int p = p0 + 64 * k;
-        l[k] = ld_s<NT>(lam_in + p);
-        m[k] = ld_s<NT>(msg_in + p);
         a[k] = ld_s<NT>(coef + p);
         r[k] = rev_of<NT, R16>(rev, rev16, p);
+        if constexpr (FIRST) {
+          const bool v = r[k] < fresh;
+          l[k] = v ? ld_s<NT>(lam_in + p) : 0.0;
+          m[k] = v ? ld_s<NT>(msg_in + p) : 0.0;
+        } else {
+          l[k] = ld_s<NT>(lam_in + p);
+          m[k] = ld_s<NT>(msg_in + p);
+        }
       }
     }
 #pragma unroll
@@ -117,15 +128,19 @@ __global__ __launch_bounds__(kBlock) void k_joint(
       }
     }
   } else {
+    auto in = [&](const double* buf, int p) -> double {
+      if constexpr (FIRST) return rev_of<false, R16>(rev, rev16, p) < fresh ? buf[p] : 0.0;
+      else return buf[p];
+    };
     for (int k = 0; k < w; ++k) {
       const int p = p0 + 64 * k;
-      S = fma(lam_in[p], coef[p], S);
-      M += msg_in[p];
+      S = fma(in(lam_in, p), coef[p], S);
+      M += in(msg_in, p);
     }
     if (WX) x[j] = M / S;
     for (int k = 0; k < w; ++k) {
       const int p = p0 + 64 * k;
-      const double l = lam_in[p], a = coef[p], m = msg_in[p];
+      const double l = in(lam_in, p), a = coef[p], m = in(msg_in, p);
       const int r = rev_of<false, R16>(rev, rev16, p);
       const double L = -a / (S - l * a);
       lam_out[r] = L;
@@ -151,17 +166,17 @@ struct ReadOff<float> {
   }
 };
 
-template <typename T, int KMAX, bool WX, bool NT, bool R16>
+template <typename T, int KMAX, bool WX, bool NT, bool R16, bool FIRST>
 __global__ __launch_bounds__(kBlock) void k_mean(
-    int n, const int32_t* __restrict__ sptr, const int32_t* __restrict__ rev,
+    int t1, const int32_t* __restrict__ sptr, const int32_t* __restrict__ rev,
     const int16_t* __restrict__ rev16,
     const T* __restrict__ lamout, const T* __restrict__ Sx, const T* __restrict__ b,
-    const T* msg_in, T* msg_out, T* __restrict__ x, const uint8_t* __restrict__ colour,
-    int c, const int32_t* __restrict__ perm) {
-  const int t = blockIdx.x * kBlock + threadIdx.x;
-  if (t >= n) return;
+    const T* msg_in, T* msg_out, T* __restrict__ x, int t0, int fresh,
+    const int32_t* __restrict__ perm) {
+  const int t = t0 + static_cast<int>(blockIdx.x) * kBlock + static_cast<int>(threadIdx.x);
+  if (t >= t1) return;
   const int j = row_of(perm, t);
-  if (c >= 0 && colour[j] != c) return;
+  if (j < 0) return;
   int w;
   const int p0 = row_base(sptr, t, &w);
   T M = b[j];
@@ -172,9 +187,10 @@ __global__ __launch_bounds__(kBlock) void k_mean(
     for (int k = 0; k < KMAX; ++k) {
       if (k < w) {
         const int p = p0 + 64 * k;
-        m[k] = ld_s<NT>(msg_in + p);
         lo[k] = ld_s<NT>(lamout + p);
         r[k] = rev_of<NT, R16>(rev, rev16, p);
+        if constexpr (FIRST) m[k] = r[k] < fresh ? ld_s<NT>(msg_in + p) : T(0);
+        else m[k] = ld_s<NT>(msg_in + p);
       }
     }
 #pragma unroll
@@ -185,11 +201,15 @@ __global__ __launch_bounds__(kBlock) void k_mean(
     for (int k = 0; k < KMAX; ++k)
       if (k < w) st_s<NT>(lo[k] * (M - m[k]), msg_out + r[k]);
   } else {
-    for (int k = 0; k < w; ++k) M += msg_in[p0 + 64 * k];
+    auto in = [&](int p) -> T {
+      if constexpr (FIRST) return rev_of<false, R16>(rev, rev16, p) < fresh ? msg_in[p] : T(0);
+      else return msg_in[p];
+    };
+    for (int k = 0; k < w; ++k) M += in(p0 + 64 * k);
     if (WX) x[j] = ReadOff<T>::f(M, Sx, j);
     for (int k = 0; k < w; ++k) {
       const int p = p0 + 64 * k;
-      msg_out[rev_of<false, R16>(rev, rev16, p)] = lamout[p] * (M - msg_in[p]);
+      msg_out[rev_of<false, R16>(rev, rev16, p)] = lamout[p] * (M - in(p));
     }
   }
 }
@@ -207,8 +227,8 @@ __global__ __launch_bounds__(kBlock) void k_lambda(
   __shared__ double sh[2][kBlock / 64];
   const int t = blockIdx.x * kBlock + threadIdx.x;
   double dm = 0.0, lm = 0.0;
-  if (t < n) {
-    const int j = row_of(perm, t);
+  const int j = t < n ? row_of(perm, t) : -1;   // n: lanes
+  if (j >= 0) {
     int w;
     const int p0 = row_base(sptr, t, &w);
     double S = diag[j];
@@ -312,8 +332,9 @@ __global__ __launch_bounds__(kBlock) void k_lambda_fin(
     const double* __restrict__ lamout, double* __restrict__ Sout, float* __restrict__ lamout32,
     float* __restrict__ invS32, const int32_t* __restrict__ perm) {
   const int t = blockIdx.x * kBlock + threadIdx.x;
-  if (t >= n) return;
+  if (t >= n) return;   // n: lanes
   const int j = row_of(perm, t);
+  if (j < 0) return;
   int w;
   const int p0 = row_base(sptr, t, &w);
   double S = diag[j];
@@ -340,8 +361,8 @@ __global__ __launch_bounds__(kRedBlock) void k_residual(
   __shared__ double sh[3][kRedBlock / 64];
   const int t = blockIdx.x * kRedBlock + threadIdx.x;
   double rr = 0.0, ra = 0.0, bb = 0.0;
-  if (t < n) {
-    const int j = row_of(perm, t);
+  const int j = t < n ? row_of(perm, t) : -1;   // n: lanes
+  if (j >= 0) {
     int w;
     const int p0 = row_base(sptr, t, &w);
     const double sc = XADD ? scale[0] : 0.0;
@@ -577,9 +598,9 @@ __global__ __launch_bounds__(kBlock) void k_rbgs(int n, int side, int c,
                                                  const double* __restrict__ b, double* x,
                                                  const int32_t* __restrict__ perm) {
   const int t = blockIdx.x * kBlock + threadIdx.x;
-  if (t >= n) return;
+  if (t >= n) return;   // n: lanes
   const int j = row_of(perm, t);
-  if (((j % side) + (j / side)) % 2 != c) return;
+  if (j < 0 || ((j % side) + (j / side)) % 2 != c) return;
   int w;
   const int p0 = row_base(sptr, t, &w);
   double s = 0.0;
@@ -624,53 +645,67 @@ int grid_for(int64_t n) {
 #define GABP_DISPATCH_R16(RV, ...)                     \
   if (RV) { constexpr bool R16B = true; __VA_ARGS__; } \
   else { constexpr bool R16B = false; __VA_ARGS__; }
+#define GABP_DISPATCH_FIRST(FV, ...)                    \
+  if (FV) { constexpr bool FB = true; __VA_ARGS__; }  \
+  else { constexpr bool FB = false; __VA_ARGS__; }
+
+// lanes of a sweep: all, or those of colour class c
+inline void lane_range(const Layout& L, int c, int* t0, int* t1) {
+  *t0 = c >= 0 ? L.cstart[c] : 0;
+  *t1 = c >= 0 ? L.cstart[c + 1] : L.nlanes;
+}
 
 hipError_t launch_joint_sweep(const SweepArgs& a, hipStream_t s) {
   const Layout& L = *a.L;
-  const int g = nblocks(L.n);
+  int t0, t1;
+  lane_range(L, a.colour, &t0, &t1);
+  if (t1 <= t0) return hipSuccess;
+  const int g = nblocks(t1 - t0);
 #define JOINT_ARGS                                                                      \
-  L.n, L.sptr, L.rev, L.rev16, a.coef, L.diag, a.b, a.lam_in, a.msg_in, a.lam_out,       \
-      a.msg_out, a.x, L.colour, a.colour, L.perm
-  GABP_DISPATCH_NT(L.stream_hints, GABP_DISPATCH_R16(L.rev16 != nullptr, {
+  t1, L.sptr, L.rev, L.rev16, a.coef, L.diag, a.b, a.lam_in, a.msg_in, a.lam_out,        \
+      a.msg_out, a.x, t0, a.fresh, L.perm
+  GABP_DISPATCH_FIRST(a.fresh >= 0, GABP_DISPATCH_NT(L.stream_hints, GABP_DISPATCH_R16(L.rev16 != nullptr, {
     if (a.x) {
       GABP_DISPATCH_WIDTH(L.max_width,
-                          (k_joint<4, true, NTB, R16B><<<g, kBlock, 0, s>>>(JOINT_ARGS)),
-                          (k_joint<8, true, NTB, R16B><<<g, kBlock, 0, s>>>(JOINT_ARGS)),
-                          (k_joint<16, true, NTB, R16B><<<g, kBlock, 0, s>>>(JOINT_ARGS)),
-                          (k_joint<0, true, NTB, R16B><<<g, kBlock, 0, s>>>(JOINT_ARGS)));
+                          (k_joint<4, true, NTB, R16B, FB><<<g, kBlock, 0, s>>>(JOINT_ARGS)),
+                          (k_joint<8, true, NTB, R16B, FB><<<g, kBlock, 0, s>>>(JOINT_ARGS)),
+                          (k_joint<16, true, NTB, R16B, FB><<<g, kBlock, 0, s>>>(JOINT_ARGS)),
+                          (k_joint<0, true, NTB, R16B, FB><<<g, kBlock, 0, s>>>(JOINT_ARGS)));
     } else {
       GABP_DISPATCH_WIDTH(L.max_width,
-                          (k_joint<4, false, NTB, R16B><<<g, kBlock, 0, s>>>(JOINT_ARGS)),
-                          (k_joint<8, false, NTB, R16B><<<g, kBlock, 0, s>>>(JOINT_ARGS)),
-                          (k_joint<16, false, NTB, R16B><<<g, kBlock, 0, s>>>(JOINT_ARGS)),
-                          (k_joint<0, false, NTB, R16B><<<g, kBlock, 0, s>>>(JOINT_ARGS)));
+                          (k_joint<4, false, NTB, R16B, FB><<<g, kBlock, 0, s>>>(JOINT_ARGS)),
+                          (k_joint<8, false, NTB, R16B, FB><<<g, kBlock, 0, s>>>(JOINT_ARGS)),
+                          (k_joint<16, false, NTB, R16B, FB><<<g, kBlock, 0, s>>>(JOINT_ARGS)),
+                          (k_joint<0, false, NTB, R16B, FB><<<g, kBlock, 0, s>>>(JOINT_ARGS)));
     }
-  }))
+  })))
 #undef JOINT_ARGS
   return hipGetLastError();
 }
 
 template <typename T, typename A>
 hipError_t mean_dispatch(const Layout& L, const A& a, const T* Sx, bool nt, hipStream_t s) {
-  const int g = nblocks(L.n);
+  int t0, t1;
+  lane_range(L, a.colour, &t0, &t1);
+  if (t1 <= t0) return hipSuccess;
+  const int g = nblocks(t1 - t0);
 #define MEAN_ARGS \
-  L.n, L.sptr, L.rev, L.rev16, a.lamout, Sx, a.b, a.msg_in, a.msg_out, a.x, L.colour, a.colour, \
-      L.perm
-  GABP_DISPATCH_NT(nt, GABP_DISPATCH_R16(L.rev16 != nullptr, {
+  t1, L.sptr, L.rev, L.rev16, a.lamout, Sx, a.b, a.msg_in, a.msg_out, a.x, t0, a.fresh, L.perm
+  GABP_DISPATCH_FIRST(a.fresh >= 0, GABP_DISPATCH_NT(nt, GABP_DISPATCH_R16(L.rev16 != nullptr, {
     if (a.x) {
       GABP_DISPATCH_WIDTH(L.max_width,
-                          (k_mean<T, 4, true, NTB, R16B><<<g, kBlock, 0, s>>>(MEAN_ARGS)),
-                          (k_mean<T, 8, true, NTB, R16B><<<g, kBlock, 0, s>>>(MEAN_ARGS)),
-                          (k_mean<T, 16, true, NTB, R16B><<<g, kBlock, 0, s>>>(MEAN_ARGS)),
-                          (k_mean<T, 0, true, NTB, R16B><<<g, kBlock, 0, s>>>(MEAN_ARGS)));
+                          (k_mean<T, 4, true, NTB, R16B, FB><<<g, kBlock, 0, s>>>(MEAN_ARGS)),
+                          (k_mean<T, 8, true, NTB, R16B, FB><<<g, kBlock, 0, s>>>(MEAN_ARGS)),
+                          (k_mean<T, 16, true, NTB, R16B, FB><<<g, kBlock, 0, s>>>(MEAN_ARGS)),
+                          (k_mean<T, 0, true, NTB, R16B, FB><<<g, kBlock, 0, s>>>(MEAN_ARGS)));
     } else {
       GABP_DISPATCH_WIDTH(L.max_width,
-                          (k_mean<T, 4, false, NTB, R16B><<<g, kBlock, 0, s>>>(MEAN_ARGS)),
-                          (k_mean<T, 8, false, NTB, R16B><<<g, kBlock, 0, s>>>(MEAN_ARGS)),
-                          (k_mean<T, 16, false, NTB, R16B><<<g, kBlock, 0, s>>>(MEAN_ARGS)),
-                          (k_mean<T, 0, false, NTB, R16B><<<g, kBlock, 0, s>>>(MEAN_ARGS)));
+                          (k_mean<T, 4, false, NTB, R16B, FB><<<g, kBlock, 0, s>>>(MEAN_ARGS)),
+                          (k_mean<T, 8, false, NTB, R16B, FB><<<g, kBlock, 0, s>>>(MEAN_ARGS)),
+                          (k_mean<T, 16, false, NTB, R16B, FB><<<g, kBlock, 0, s>>>(MEAN_ARGS)),
+                          (k_mean<T, 0, false, NTB, R16B, FB><<<g, kBlock, 0, s>>>(MEAN_ARGS)));
     }
-  }))
+  })))
 #undef MEAN_ARGS
   return hipGetLastError();
 }
@@ -687,13 +722,13 @@ hipError_t launch_lambda_sweep(const Layout* Lp, const double* coef, const doubl
                                double* lam_out, double* lamout, double* partials, double* out,
                                hipStream_t s) {
   const Layout& L = *Lp;
-  const int g = nblocks(L.n);
+  const int g = nblocks(L.nlanes);
   GABP_DISPATCH_WIDTH(
       L.max_width,
-      (k_lambda<4><<<g, kBlock, 0, s>>>(L.n, L.sptr, L.rev, coef, L.diag, lam_in, lam_out, lamout, partials, L.perm)),
-      (k_lambda<8><<<g, kBlock, 0, s>>>(L.n, L.sptr, L.rev, coef, L.diag, lam_in, lam_out, lamout, partials, L.perm)),
-      (k_lambda<16><<<g, kBlock, 0, s>>>(L.n, L.sptr, L.rev, coef, L.diag, lam_in, lam_out, lamout, partials, L.perm)),
-      (k_lambda<0><<<g, kBlock, 0, s>>>(L.n, L.sptr, L.rev, coef, L.diag, lam_in, lam_out, lamout, partials, L.perm)));
+      (k_lambda<4><<<g, kBlock, 0, s>>>(L.nlanes, L.sptr, L.rev, coef, L.diag, lam_in, lam_out, lamout, partials, L.perm)),
+      (k_lambda<8><<<g, kBlock, 0, s>>>(L.nlanes, L.sptr, L.rev, coef, L.diag, lam_in, lam_out, lamout, partials, L.perm)),
+      (k_lambda<16><<<g, kBlock, 0, s>>>(L.nlanes, L.sptr, L.rev, coef, L.diag, lam_in, lam_out, lamout, partials, L.perm)),
+      (k_lambda<0><<<g, kBlock, 0, s>>>(L.nlanes, L.sptr, L.rev, coef, L.diag, lam_in, lam_out, lamout, partials, L.perm)));
   k_lambda_reduce<<<1, 1024, 0, s>>>(g, partials, out);
   return hipGetLastError();
 }
@@ -706,7 +741,7 @@ hipError_t launch_max_pairs(int nblk, const double* partials, double* out, hipSt
 hipError_t launch_lambda_finalize(const Layout* Lp, const double* coef, const double* lam_in,
                                   Precomp* P, hipStream_t s) {
   const Layout& L = *Lp;
-  k_lambda_fin<0><<<nblocks(L.n), kBlock, 0, s>>>(L.n, L.sptr, coef, L.diag, lam_in,
+  k_lambda_fin<0><<<nblocks(L.nlanes), kBlock, 0, s>>>(L.nlanes, L.sptr, coef, L.diag, lam_in,
                                                   P->lamout, P->S, P->lamout32, P->invS32,
                                                   L.perm);
   return hipGetLastError();
@@ -714,9 +749,10 @@ hipError_t launch_lambda_finalize(const Layout* Lp, const double* coef, const do
 
 hipError_t launch_residual(const Layout* Lp, const double* coef_row, const double* b,
                            const double* x, const float* dx, const double* scale, double* r,
-                           double* partials, int32_t nred, double* red, hipStream_t s) {
+                           double* partials, int32_t nred, double* red, hipStream_t s,
+                           bool norms) {
   const Layout& L = *Lp;
-#define RES_ARGS(DX, SC) L.n, L.sptr, L.col, coef_row, L.diag, b, x, DX, SC, r, partials, L.perm
+#define RES_ARGS(DX, SC) L.nlanes, L.sptr, L.col, coef_row, L.diag, b, x, DX, SC, r, partials, L.perm
   if (dx) {
     GABP_DISPATCH_WIDTH(L.max_width,
                         (k_residual<4, true><<<nred, kRedBlock, 0, s>>>(RES_ARGS(dx, scale))),
@@ -731,7 +767,7 @@ hipError_t launch_residual(const Layout* Lp, const double* coef_row, const doubl
                         (k_residual<0, false><<<nred, kRedBlock, 0, s>>>(RES_ARGS(nullptr, nullptr))));
   }
 #undef RES_ARGS
-  k_finalize_norms<<<1, kFinBlock, 0, s>>>(nred, partials, red);
+  if (norms) k_finalize_norms<<<1, kFinBlock, 0, s>>>(nred, partials, red);
   return hipGetLastError();
 }
 
@@ -819,8 +855,8 @@ hipError_t launch_prolong_add(int nc, const double* ec, double* xf, hipStream_t 
 hipError_t launch_rbgs(const Layout* Lp, int side, int colour, const double* b, double* x,
                        hipStream_t s) {
   const Layout& L = *Lp;
-  k_rbgs<0><<<nblocks(L.n), kBlock, 0, s>>>(L.n, side, colour, L.sptr, L.col, L.val, L.diag, b, x,
-                                            L.perm);
+  k_rbgs<0><<<nblocks(L.nlanes), kBlock, 0, s>>>(L.nlanes, side, colour, L.sptr, L.col, L.val,
+                                                 L.diag, b, x, L.perm);
   return hipGetLastError();
 }
 hipError_t launch_dense_matvec(int n, const double* inv, const double* b, double* x,

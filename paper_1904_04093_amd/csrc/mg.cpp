@@ -87,11 +87,11 @@ int dense_of(gabp_ctx* c, std::vector<double>& A, hipStream_t s) {
   A.assign(static_cast<size_t>(n) * n, 0.0);
   for (int j = 0; j < n; ++j) {
     A[static_cast<size_t>(j) * n + j] = diag[j];
-    const int sl = j / kSlice;
+    const int t = L.lane_of_row.empty() ? j : L.lane_of_row[j];
+    const int sl = t / kSlice;
     const int w = (sptr[sl + 1] - sptr[sl]) / kSlice;
     for (int k = 0; k < w; ++k) {
-      const int lane = L.lane_of_row.empty() ? (j % kSlice) : L.lane_of_row[j];
-      const int p = sptr[sl] + k * kSlice + lane;
+      const int p = sptr[sl] + k * kSlice + t % kSlice;
       if (val[p] != 0.0) A[static_cast<size_t>(j) * n + col[p]] += val[p];
     }
   }
@@ -116,7 +116,7 @@ int vcycle(mg_ctx* m, int l, const double* b, double* x, hipStream_t s) {
   gabp_ctx* c = m->lv[l];
   if ((st = smooth(m, l, b, x, m->nu1, s)) != GABP_OK) return st;
   GABP_HIP(launch_residual(&c->L, c->L.val, b, x, nullptr, nullptr, m->r[l], c->partials,
-                           c->nred, c->red, s));
+                           c->nred, c->red, s, false));
   GABP_HIP(launch_restrict_fw(m->side[l + 1], m->r[l], m->b[l + 1], s));
   GABP_HIP(launch_fill64(m->x[l + 1], m->lv[l + 1]->L.n, 0.0, s));
   if ((st = vcycle(m, l + 1, m->b[l + 1], m->x[l + 1], s)) != GABP_OK) return st;
@@ -124,19 +124,24 @@ int vcycle(mg_ctx* m, int l, const double* b, double* x, hipStream_t s) {
   return smooth(m, l, b, x, m->nu2, s);
 }
 
+// host-side message state of every level (ping-pong parities, reset flags)
 std::vector<int> parities(const mg_ctx* m) {
   std::vector<int> p;
   for (const gabp_ctx* c : m->lv) {
     p.push_back(c->parity);
     p.push_back(c->parity32);
+    p.push_back(c->fresh64);
+    p.push_back(c->fresh32);
   }
   return p;
 }
 
 void set_parities(mg_ctx* m, const std::vector<int>& p) {
   for (size_t l = 0; l < m->lv.size(); ++l) {
-    m->lv[l]->parity = p[2 * l];
-    m->lv[l]->parity32 = p[2 * l + 1];
+    m->lv[l]->parity = p[4 * l];
+    m->lv[l]->parity32 = p[4 * l + 1];
+    m->lv[l]->fresh64 = p[4 * l + 2] != 0;
+    m->lv[l]->fresh32 = p[4 * l + 3] != 0;
   }
 }
 

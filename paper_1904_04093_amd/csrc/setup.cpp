@@ -147,49 +147,62 @@ int gabp_setup(gabp_ctx** out, int32_t n, int64_t nnz, const int32_t* rowptr,
     max_w = std::max(max_w, w);
   }
   const int64_t slots = uptr[n];
-  // --- slices of 64 rows, column-major inside a slice
-  const int32_t nslices = (n + kSlice - 1) / kSlice;
-  std::vector<int64_t> sptr64(nslices + 1, 0);
-  for (int32_t s = 0; s < nslices; ++s) {
-    int64_t w = 0;
-    for (int32_t j = s * kSlice; j < std::min(n, (s + 1) * kSlice); ++j)
-      w = std::max<int64_t>(w, uptr[j + 1] - uptr[j]);
-    sptr64[s + 1] = sptr64[s] + w * kSlice;
-  }
-  const int64_t epad = sptr64[nslices];
-  if (epad + 1 >= std::numeric_limits<int32_t>::max())
-    return fail(GABP_ENOTSUPP, "more than 2^31-1 padded message slots");
-  // lane of every row: identity, or colour-sorted within each slice when colours are given
-  std::vector<int32_t> lane_of_row, row_of_lane;
+  // --- lanes: row j at lane j, or (with colours) colour-major: the rows of each colour in
+  // ascending order, each colour padded to whole slices; lanes without a row hold -1
+  std::vector<int32_t> lane_of_row, row_of_lane, cstart;
   int ncolours = 0;
+  int64_t nlanes = n;
   if (colour) {
     for (int32_t j = 0; j < n; ++j) {
       if (colour[j] >= kMaxColours)
         return fail(GABP_EINVAL, "colour must be below " + std::to_string(kMaxColours));
       ncolours = std::max(ncolours, colour[j] + 1);
     }
+    std::vector<int64_t> cnt(ncolours, 0), next(ncolours);
+    for (int32_t j = 0; j < n; ++j) ++cnt[colour[j]];
+    int64_t acc = 0;
+    for (int c = 0; c < ncolours; ++c) {
+      next[c] = acc;
+      acc += (cnt[c] + kSlice - 1) / kSlice * kSlice;
+    }
+    if (acc >= std::numeric_limits<int32_t>::max() - kBlock)
+      return fail(GABP_ENOTSUPP, "too many rows for a coloured layout");
+    cstart.assign(ncolours + 1, static_cast<int32_t>(acc));
+    for (int c = 0; c < ncolours; ++c) cstart[c] = static_cast<int32_t>(next[c]);
+    nlanes = acc;
     lane_of_row.resize(n);
-    row_of_lane.resize(static_cast<size_t>(nslices) * kSlice);
-    for (int32_t s = 0; s < nslices; ++s) {
-      int32_t lane = 0;
-      const int32_t r0 = s * kSlice, r1 = std::min(n, r0 + kSlice);
-      for (int c = 0; c < ncolours; ++c)
-        for (int32_t j = r0; j < r1; ++j)
-          if (colour[j] == c) {
-            lane_of_row[j] = lane;
-            row_of_lane[r0 + lane] = j;
-            ++lane;
-          }
-      for (; lane < kSlice; ++lane) row_of_lane[r0 + lane] = r0 + lane;   // rows >= n
+    row_of_lane.assign(static_cast<size_t>(nlanes), -1);
+    for (int32_t j = 0; j < n; ++j) {
+      const int64_t t = next[colour[j]]++;
+      lane_of_row[j] = static_cast<int32_t>(t);
+      row_of_lane[t] = j;
     }
   }
-  auto lane = [&](int32_t j) -> int64_t {
-    return lane_of_row.empty() ? (j % kSlice) : lane_of_row[j];
+  auto row_at = [&](int64_t t) -> int32_t {
+    return colour ? row_of_lane[t] : (t < n ? static_cast<int32_t>(t) : -1);
   };
-  auto pos = [&](int32_t j, int64_t k) -> int64_t {
-    return sptr64[j / kSlice] + k * kSlice + lane(j);
+  // --- slices of 64 lanes, column-major inside a slice
+  const int32_t nslices = static_cast<int32_t>((nlanes + kSlice - 1) / kSlice);
+  std::vector<int64_t> sptr64(nslices + 1, 0);
+  for (int32_t s = 0; s < nslices; ++s) {
+    int64_t w = 0;
+    for (int64_t t = static_cast<int64_t>(s) * kSlice; t < std::min<int64_t>(nlanes, (s + 1) * int64_t(kSlice)); ++t) {
+      const int32_t j = row_at(t);
+      if (j >= 0) w = std::max<int64_t>(w, uptr[j + 1] - uptr[j]);
+    }
+    sptr64[s + 1] = sptr64[s] + w * kSlice;
+  }
+  const int64_t epad = sptr64[nslices];
+  if (epad + 1 >= std::numeric_limits<int32_t>::max())
+    return fail(GABP_ENOTSUPP, "more than 2^31-1 padded message slots");
+  auto pos = [&](int32_t j, int64_t k) -> int64_t {   // slot k of row j
+    const int64_t t = lane_of_row.empty() ? j : lane_of_row[j];
+    return sptr64[t / kSlice] + k * kSlice + t % kSlice;
   };
-  std::vector<int32_t> h_rev(epad, static_cast<int32_t>(epad)), h_col(epad, 0);
+  // padding slots are their own reverse: every sweep writes a zero message there, so each
+  // slot a sweep reads was written by the sweep before (or the reset)
+  std::vector<int32_t> h_rev(epad), h_col(epad, 0);
+  for (int64_t p = 0; p < epad; ++p) h_rev[p] = static_cast<int32_t>(p);
   std::vector<int32_t> h_vsrc(epad, -1), h_asrc(epad, -1);
   std::vector<double> h_val(epad, 0.0), h_aT(epad, 0.0), h_diag(n);
   for (int32_t s = 0; s < nslices; ++s) {   // padding slots: own row as column (coef 0)
@@ -229,15 +242,13 @@ int gabp_setup(gabp_ctx** out, int32_t n, int64_t nnz, const int32_t* rowptr,
   std::vector<int16_t> h_rev16;
   {
     bool fits = true;
-    for (int64_t p = 0; p < epad && fits; ++p)
-      if (h_rev[p] != epad) {
-        const int64_t d = static_cast<int64_t>(h_rev[p]) - p;
-        fits = d >= -32767 && d <= 32767;
-      }
+    for (int64_t p = 0; p < epad && fits; ++p) {
+      const int64_t d = static_cast<int64_t>(h_rev[p]) - p;
+      fits = d >= -32767 && d <= 32767;
+    }
     if (fits) {
       h_rev16.resize(epad);
-      for (int64_t p = 0; p < epad; ++p)
-        h_rev16[p] = h_rev[p] == epad ? int16_t(0) : static_cast<int16_t>(h_rev[p] - p);
+      for (int64_t p = 0; p < epad; ++p) h_rev16[p] = static_cast<int16_t>(h_rev[p] - p);
     }
   }
   std::vector<int32_t> h_sptr(nslices + 1);
@@ -258,6 +269,7 @@ int gabp_setup(gabp_ctx** out, int32_t n, int64_t nnz, const int32_t* rowptr,
   L.slots = slots;
   L.epad = epad;
   L.nslices = nslices;
+  L.nlanes = static_cast<int32_t>(nlanes);
   L.max_width = max_w;
   // footprint of one FP64 joint sweep (44 B per slot, 16 B per row) and one FP32 mean
   // sweep (16 B per slot, 4 B per row) against the 256 MiB last-level cache
@@ -285,11 +297,13 @@ int gabp_setup(gabp_ctx** out, int32_t n, int64_t nnz, const int32_t* rowptr,
   UP(L.csr_row, h_row);
   UP(L.csr_col, h_ccol);
   if (colour) {
-    std::vector<uint8_t> hc(colour, colour + n);
-    UP(L.colour, hc);
     UP(L.perm, row_of_lane);
     L.lane_of_row = lane_of_row;
     L.ncolours = ncolours;
+    L.cstart = cstart;
+    L.cslot.resize(cstart.size());
+    for (size_t q = 0; q < cstart.size(); ++q)
+      L.cslot[q] = static_cast<int32_t>(sptr64[cstart[q] / kSlice]);
   }
   for (int q = 0; q < 2; ++q) {
     AL(c->lam[q], epad + 1);
@@ -300,7 +314,7 @@ int gabp_setup(gabp_ctx** out, int32_t n, int64_t nnz, const int32_t* rowptr,
   AL(c->e, n);
   AL(c->r32, n);
   AL(c->d32, n);
-  c->nred = (n + kRedBlock - 1) / kRedBlock;
+  c->nred = static_cast<int32_t>((nlanes + kRedBlock - 1) / kRedBlock);
   AL(c->partials, 3 * (int64_t)c->nred);
   AL(c->red, 8);
   AL(c->lmax, 2);
@@ -350,7 +364,7 @@ void gabp_destroy(gabp_ctx* c) {
   };
   Layout& L = c->L;
   F(L.sptr); F(L.rev); F(L.rev16); F(L.col); F(L.val); F(L.aT); F(L.diag); F(L.val_src); F(L.aT_src);
-  F(L.diag_src); F(L.csr_row); F(L.csr_col); F(L.colour); F(L.perm);
+  F(L.diag_src); F(L.csr_row); F(L.csr_col); F(L.perm);
   for (int q = 0; q < 2; ++q) {
     F(c->lam[q]); F(c->msg[q]); F(c->msg32[q]);
     F(c->pre[q].lamout); F(c->pre[q].S); F(c->pre[q].lamout32); F(c->pre[q].invS32);

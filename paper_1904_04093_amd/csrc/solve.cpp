@@ -41,9 +41,9 @@ inline const double* sweep_coef(const gabp_ctx* c, int T) { return T ? c->L.val 
 inline const double* row_coef(const gabp_ctx* c, int T) { return T ? c->L.aT : c->L.val; }
 
 int residual(gabp_ctx* c, int T, const double* b, const double* x, const float* dx,
-             const double* scale, double* r, hipStream_t s) {
+             const double* scale, double* r, hipStream_t s, bool norms = true) {
   GABP_HIP(launch_residual(&c->L, row_coef(c, T), b, x, dx, scale, r, c->partials, c->nred,
-                           c->red, s));
+                           c->red, s, norms));
   return GABP_OK;
 }
 
@@ -82,9 +82,8 @@ int ensure_pre(gabp_ctx* c, int T, hipStream_t s) {
   GABP_HIP(launch_lambda_finalize(&L, coef, c->lam[par], &P, s));
   P.sweeps = done;
   P.valid = true;
-  c->parity = 0;   // the joint-mode message buffers were used as scratch
-  GABP_HIP(launch_fill64(c->lam[0], L.epad + 1, 0.0, s));
-  GABP_HIP(launch_fill64(c->msg[0], L.epad + 1, 0.0, s));
+  c->parity = 0;   // the joint-mode message buffers were used as scratch: logically zero now
+  c->fresh64 = true;
   return GABP_OK;
 }
 
@@ -104,7 +103,7 @@ int ensure_msg32(gabp_ctx* c, hipStream_t s) {
   return GABP_OK;
 }
 
-// (the slot past the padded slots is the zero message of one-way edges: never poisoned)
+// (the slot one past the padded slots holds no message and is left alone)
 constexpr double kPoison = std::numeric_limits<double>::quiet_NaN();
 
 // One FP64 sweep of the configured mode and schedule on right-hand side b (coloured
@@ -113,8 +112,10 @@ constexpr double kPoison = std::numeric_limits<double>::quiet_NaN();
 int sweep64(gabp_ctx* c, int T, const double* b, double* x, hipStream_t s) {
   if (c->lines) return line_sweep64(c, T, b, x, s);
   const bool rb = c->opt.schedule == GABP_SCHED_REDBLACK;
+  const int fresh = c->fresh64 ? 0 : -1;   // first sweep after a reset
+  c->fresh64 = false;
   if (c->opt.mode == GABP_MODE_JOINT) {
-    SweepArgs a{&c->L, sweep_coef(c, T), b, nullptr, nullptr, nullptr, nullptr, x, -1};
+    SweepArgs a{&c->L, sweep_coef(c, T), b, nullptr, nullptr, nullptr, nullptr, x, -1, fresh};
     if (!rb) {
       a.lam_in = c->lam[c->parity];
       a.msg_in = c->msg[c->parity];
@@ -131,12 +132,13 @@ int sweep64(gabp_ctx* c, int T, const double* b, double* x, hipStream_t s) {
       a.msg_in = a.msg_out = c->msg[c->parity];
       for (int col = 0; col < c->L.ncolours; ++col) {
         a.colour = col;
+        if (fresh >= 0) a.fresh = c->L.cslot[col];
         GABP_HIP(launch_joint_sweep(a, s));
       }
     }
   } else {
     const Precomp& P = c->pre[T];
-    MeanArgs64 a{&c->L, P.lamout, P.S, b, nullptr, nullptr, x, -1};
+    MeanArgs64 a{&c->L, P.lamout, P.S, b, nullptr, nullptr, x, -1, fresh};
     if (!rb) {
       a.msg_in = c->msg[c->parity];
       a.msg_out = c->msg[c->parity ^ 1];
@@ -147,6 +149,7 @@ int sweep64(gabp_ctx* c, int T, const double* b, double* x, hipStream_t s) {
       a.msg_in = a.msg_out = c->msg[c->parity];
       for (int col = 0; col < c->L.ncolours; ++col) {
         a.colour = col;
+        if (fresh >= 0) a.fresh = c->L.cslot[col];
         GABP_HIP(launch_mean_sweep64(a, s));
       }
     }
@@ -157,7 +160,9 @@ int sweep64(gabp_ctx* c, int T, const double* b, double* x, hipStream_t s) {
 int sweep32(gabp_ctx* c, int T, const float* b, float* x, hipStream_t s) {
   if (c->lines) return line_sweep32(c, T, b, x, s);
   const Precomp& P = c->pre[T];
-  MeanArgs32 a{&c->L, P.lamout32, P.invS32, b, nullptr, nullptr, x, -1};
+  const int fresh = c->fresh32 ? 0 : -1;   // first sweep after a reset
+  c->fresh32 = false;
+  MeanArgs32 a{&c->L, P.lamout32, P.invS32, b, nullptr, nullptr, x, -1, fresh};
   if (c->opt.schedule != GABP_SCHED_REDBLACK) {
     a.msg_in = c->msg32[c->parity32];
     a.msg_out = c->msg32[c->parity32 ^ 1];
@@ -169,24 +174,25 @@ int sweep32(gabp_ctx* c, int T, const float* b, float* x, hipStream_t s) {
     a.msg_in = a.msg_out = c->msg32[c->parity32];
     for (int col = 0; col < c->L.ncolours; ++col) {
       a.colour = col;
+      if (fresh >= 0) a.fresh = c->L.cslot[col];
       GABP_HIP(launch_mean_sweep32(a, s));
     }
   }
   return GABP_OK;
 }
 
+// Point schedules: no clearing; the next sweep reads the buffers as zero (fresh flags).
 int reset_messages64(gabp_ctx* c, hipStream_t s) {
   c->parity = 0;
   if (c->lines) return line_reset64(c, s);
-  GABP_HIP(launch_fill64(c->msg[0], c->L.epad + 1, 0.0, s));
-  if (c->opt.mode == GABP_MODE_JOINT) GABP_HIP(launch_fill64(c->lam[0], c->L.epad + 1, 0.0, s));
+  c->fresh64 = true;
   return GABP_OK;
 }
 
 int reset_messages32(gabp_ctx* c, hipStream_t s) {
   c->parity32 = 0;
   if (c->lines) return line_reset32(c, s);
-  GABP_HIP(launch_fill32(c->msg32[0], c->L.epad + 1, 0.0f, s));
+  c->fresh32 = true;
   return GABP_OK;
 }
 
@@ -230,8 +236,16 @@ static int maybe_inject(gabp_ctx* c, int done, bool f32, hipStream_t s) {
     }
     return GABP_OK;
   }
-  if (f32) GABP_HIP(launch_fill32(c->msg32[c->parity32], c->L.epad + 1, static_cast<float>(nan), s));
-  else GABP_HIP(launch_fill64(c->msg[c->parity], c->L.epad + 1, nan, s));
+  // a logically zero (reset) state is made explicit first, so the next sweep reads the NaN
+  if (f32) {
+    c->fresh32 = false;
+    GABP_HIP(launch_fill32(c->msg32[c->parity32], c->L.epad + 1, static_cast<float>(nan), s));
+    return GABP_OK;
+  }
+  if (c->fresh64 && c->opt.mode == GABP_MODE_JOINT)
+    GABP_HIP(launch_fill64(c->lam[c->parity], c->L.epad + 1, 0.0, s));
+  c->fresh64 = false;
+  GABP_HIP(launch_fill64(c->msg[c->parity], c->L.epad + 1, nan, s));
   return GABP_OK;
 }
 
@@ -254,10 +268,12 @@ int solve64(gabp_ctx* c, int T, const double* b, double* x, double tol, int max_
     const int k = std::min(c->opt.check_every, max_sweeps - done);
     if ((st = maybe_inject(c, done, false, s)) != GABP_OK) return st;
     const int start = c->parity;
+    const bool fresh = c->fresh64;
     // one check block: k sweeps (read-off on the last), residual, norms to the host
-    st = run_block(c, *c->graphs, s, GraphKey{1, b, x, nullptr, start, k, T, 0.0},
+    st = run_block(c, *c->graphs, s, GraphKey{1, b, x, nullptr, start + 2 * fresh, k, T, 0.0},
                    [&](hipStream_t ss) -> int {
                      c->parity = start;
+                     c->fresh64 = fresh;
                      for (int i = 0; i < k; ++i) {
                        const int e = sweep64(c, T, b, i == k - 1 ? x : nullptr, ss);
                        if (e != GABP_OK) return e;
@@ -270,6 +286,7 @@ int solve64(gabp_ctx* c, int T, const double* b, double* x, double tol, int max_
                    });
     if (st != GABP_OK) return st;
     c->parity = rb ? start : start ^ (k & 1);
+    c->fresh64 = false;
     done += k;
     GABP_HIP(hipStreamSynchronize(s));
     host_norms(c, &nm);
@@ -336,11 +353,13 @@ int solve_ir(gabp_ctx* c, int T, const double* b, double* x, double tol, int max
       const int k = std::min({c->opt.check_every, max_sweeps - total, c->opt.ir_max_inner - inner});
       if ((st = maybe_inject(c, total, true, s)) != GABP_OK) return st;
       const int start = c->parity32;
+      const bool fresh = c->fresh32;
       double* rt = buf[itry];
       // one inner block: k FP32 sweeps, FP64 residual of x + s d, norms to the host
-      st = run_block(c, *c->graphs, s, GraphKey{2, b, x, rt, start, k, T, 0.0},
+      st = run_block(c, *c->graphs, s, GraphKey{2, b, x, rt, start + 2 * fresh, k, T, 0.0},
                      [&](hipStream_t ss) -> int {
                        c->parity32 = start;
+                       c->fresh32 = fresh;
                        for (int i = 0; i < k; ++i) {
                          const int e = sweep32(c, T, c->r32, i == k - 1 ? c->d32 : nullptr, ss);
                          if (e != GABP_OK) return e;
@@ -353,6 +372,7 @@ int solve_ir(gabp_ctx* c, int T, const double* b, double* x, double tol, int max
                      });
       if (st != GABP_OK) return st;
       c->parity32 = rb ? start : start ^ (k & 1);
+      c->fresh32 = false;
       inner += k;
       total += k;
       Norms nt;
@@ -482,7 +502,7 @@ int gabp_smooth(gabp_ctx* c, const double* b, double* x, int32_t mu, hipStream_t
   int st;
   const int64_t n = c->L.n;
   const bool warm = c->opt.warm == GABP_WARM_ALL;
-  if ((st = residual(c, 0, b, x, nullptr, nullptr, c->r, s)) != GABP_OK) return st;
+  if ((st = residual(c, 0, b, x, nullptr, nullptr, c->r, s, false)) != GABP_OK) return st;
   if (c->opt.precision == GABP_F32_IR) {
     if ((st = ensure_pre(c, 0, s)) != GABP_OK) return st;
     const bool fresh = !has_msg32(c);
@@ -617,16 +637,27 @@ int gabp_get_state(gabp_ctx* c, void* dst, size_t* bytes, hipStream_t s) {
     p += nb;
     return GABP_OK;
   };
+  auto zeros = [&](size_t nb) {   // a reset state: the buffers are logically zero
+    std::memset(p, 0, nb);
+    p += nb;
+  };
   int st;
-  if ((st = get(c->lam[c->parity], E * sizeof(double))) || (st = get(c->msg[c->parity], E * sizeof(double))))
+  if (c->fresh64) {
+    zeros(2 * E * sizeof(double));
+  } else if ((st = get(c->lam[c->parity], E * sizeof(double))) ||
+             (st = get(c->msg[c->parity], E * sizeof(double)))) {
     return st;
+  }
   for (int T = 0; T < 2; ++T)
     if (c->pre[T].valid) {
       if ((st = get(c->pre[T].lamout, E * sizeof(double))) || (st = get(c->pre[T].S, N * sizeof(double))) ||
           (st = get(c->pre[T].lamout32, E * sizeof(float))) || (st = get(c->pre[T].invS32, N * sizeof(float))))
         return st;
     }
-  if (c->msg32[0] && (st = get(c->msg32[c->parity32], E * sizeof(float)))) return st;
+  if (c->msg32[0]) {
+    if (c->fresh32) zeros(E * sizeof(float));
+    else if ((st = get(c->msg32[c->parity32], E * sizeof(float)))) return st;
+  }
   GABP_HIP(hipStreamSynchronize(s));
   *bytes = need;
   return GABP_OK;
@@ -655,6 +686,7 @@ int gabp_set_state(gabp_ctx* c, const void* src, size_t bytes, hipStream_t s) {
   };
   int st;
   c->parity = 0;
+  c->fresh64 = false;
   if ((st = put(c->lam[0], E * sizeof(double))) || (st = put(c->msg[0], E * sizeof(double)))) return st;
   for (int T = 0; T < 2; ++T) {
     if (!h.pre_valid[T]) {
@@ -677,6 +709,7 @@ int gabp_set_state(gabp_ctx* c, const void* src, size_t bytes, hipStream_t s) {
   if (h.has32) {
     if ((st = ensure_msg32(c, s)) != GABP_OK) return st;
     c->parity32 = 0;
+    c->fresh32 = false;
     if ((st = put(c->msg32[0], E * sizeof(float)))) return st;
   }
   GABP_HIP(hipStreamSynchronize(s));

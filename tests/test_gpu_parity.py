@@ -402,17 +402,24 @@ def test_every_output_slot_is_written(B, monkeypatch, kw):
     assert np.array_equal(xg.cpu().numpy(), xw.cpu().numpy())
 
 
-@pytest.mark.parametrize("name", ["walk200", "tree150", "upwind9", "n1"])
+@pytest.mark.parametrize("name", ["walk200", "tree150", "upwind9", "n1", "sparse20k"])
 @pytest.mark.parametrize("mode", ["joint", "precomp"])
 def test_every_output_slot_is_written_ragged(B, monkeypatch, name, mode):
-    """The same check on ragged, one-way and tiny graphs (padding lanes, missing reverses)."""
-    a, b, _ = CASES[name]
+    """The same check on ragged, one-way and tiny graphs (padding slots of short rows,
+    missing reverses), and on long-range couplings that need the 4-byte reverse index."""
+    if name == "sparse20k":
+        a = W.random_sparse_dominant(20000, 3, W.rng(300, 9))
+        b = W.rng(300, 10).uniform(-1, 1, a.n)
+    else:
+        a, b, _ = CASES[name]
     bt = _cuda(b)
     kw = dict(mode=mode, tol_lambda=0.0, max_lambda_sweeps=40)
     clean = B.Solver.from_csr(a, **kw)
     monkeypatch.setenv("GABP_FAULT_INJECT", "poison-outputs")
     poisoned = B.Solver.from_csr(a, **kw)
     monkeypatch.delenv("GABP_FAULT_INJECT")
+    if name == "sparse20k":
+        assert clean.layout_info()["rev_bytes"] == 4
     for k in (1, 2, 7):
         want = clean.sweeps(bt, k).cpu().numpy()
         got = poisoned.sweeps(bt, k).cpu().numpy()
