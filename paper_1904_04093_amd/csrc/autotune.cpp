@@ -148,6 +148,8 @@ int autotune_lines(gabp_ctx* c, int32_t* check_every_out, int32_t* hints_out, hi
     t.hints = 0;
     t.check_every = ce;
     cache_store(key, t);
+    c->fresh64 = true;   // the timing sweeps leave the messages in use: logically zero again
+    c->fresh32 = true;
   }
   c->opt.check_every = t.check_every;
   c->graphs->clear();

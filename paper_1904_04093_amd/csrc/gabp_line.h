@@ -139,6 +139,9 @@ int line_reset64(gabp_ctx* c, hipStream_t s);
 int line_ensure32(gabp_ctx* c, hipStream_t s);   // FP32 message buffers (zeroed)
 bool line_has32(const gabp_ctx* c);
 int line_reset32(gabp_ctx* c, hipStream_t s);
+// write out the zeros a reset only marked (no-op unless c->fresh64 / c->fresh32)
+int line_zero_incoming64(gabp_ctx* c, hipStream_t s);
+int line_zero_incoming32(gabp_ctx* c, hipStream_t s);
 int line_rhs64(gabp_ctx* c, const double* b, hipStream_t s);
 int line_rhs32(gabp_ctx* c, const float* b, hipStream_t s);
 int line_sweep64(gabp_ctx* c, int T, const double* b, double* x, hipStream_t s);

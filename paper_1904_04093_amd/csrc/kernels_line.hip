@@ -260,8 +260,11 @@ __global__ __launch_bounds__(kLT, 2) void k_line_joint(LineArgs a0, LineArgs a1,
     double gd[NPL], gc[NPL], gl[NPL], gh[NPL];
 #pragma unroll
     for (int j = 0; j < NPL; ++j) {
-      gd[j] = ld_stripe(A.diag + base, j, len) + ld_stripe(A.lam_in + base, j, len);
-      gc[j] = ld_stripe(A.b + base, j, len) + ld_stripe(A.m_in + base, j, len);
+      // null incoming arrays: the other orientation's messages are zero (first update
+      // after a reset)
+      gd[j] = ld_stripe(A.diag + base, j, len) +
+              (A.lam_in ? ld_stripe(A.lam_in + base, j, len) : 0.0);
+      gc[j] = ld_stripe(A.b + base, j, len) + (A.m_in ? ld_stripe(A.m_in + base, j, len) : 0.0);
       gl[j] = ld_stripe(A.lo + base, j, len);
       gh[j] = ld_stripe(A.hi + base, j, len);
     }
@@ -459,7 +462,7 @@ __global__ __launch_bounds__(kLT, 3) void k_line_mean(LineMeanArgs<T> a0, LineMe
     for (int j = 0; j < NPL; ++j) {
       ga[j] = ld_stripe(A.alpha + base, j, len);
       gb[j] = ld_stripe(A.beta + base, j, len);
-      gc[j] = ld_stripe(A.b + base, j, len) + ld_stripe(A.m_in + base, j, len);
+      gc[j] = ld_stripe(A.b + base, j, len) + (A.m_in ? ld_stripe(A.m_in + base, j, len) : T(0));
     }
     stage_regs<NPL>(sh, ga, len);
     stage_take<NPL>(sh, t0, len, T(0), al);
@@ -546,8 +549,9 @@ __global__ void k_line_readoff64(int64_t n, const double* __restrict__ b,
                                  double* __restrict__ x) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
   if (i >= n) return;
-  const double M = b[i] + m_r[i] + m_c[i];
-  x[i] = invS ? M * invS[i] : M / (diag[i] + lam_r[i] + lam_c[i]);
+  // null row messages: zero (first flood update after a reset)
+  const double M = b[i] + (m_r ? m_r[i] : 0.0) + m_c[i];
+  x[i] = invS ? M * invS[i] : M / (diag[i] + (lam_r ? lam_r[i] : 0.0) + lam_c[i]);
 }
 
 __global__ void k_line_readoff32(int64_t n, const float* __restrict__ b, const float* __restrict__ m_r,
@@ -555,7 +559,7 @@ __global__ void k_line_readoff32(int64_t n, const float* __restrict__ b, const f
                                  float* __restrict__ x) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
   if (i >= n) return;
-  x[i] = (b[i] + m_r[i] + m_c[i]) * invS[i];
+  x[i] = (b[i] + (m_r ? m_r[i] : 0.0f) + m_c[i]) * invS[i];
 }
 
 __global__ void k_gather_values(int64_t n, const int32_t* __restrict__ src,

@@ -75,12 +75,15 @@ void joint_args(const LineLayout& G, int T, const double* b_row, const double* b
 
 // Read-off of the column update just made (before the column messages move to the row
 // layout): x = (b + m_row + m_col) / (A_ii + Lambda_row + Lambda_col) in the column layout
-// with the row messages that update used (flood: previous sweep; alt: this sweep), then
-// transposed into x (row layout). invS: frozen 1/Sigma* in the column layout, or null.
-int readoff_col64(const LineLayout& G, const double* invS, double* x, hipStream_t s) {
+// with the row messages that update used (flood: previous sweep, zero when rows_zero; alt:
+// this sweep), then transposed into x (row layout). invS: frozen 1/Sigma* in the column
+// layout, or null.
+int readoff_col64(const LineLayout& G, const double* invS, double* x, hipStream_t s,
+                  bool rows_zero = false) {
   const LineSide& R = G.side[0];
   const LineSide& C = G.side[1];
-  GABP_HIP(launch_line_readoff64(G.n, G.bcol, C.diag, R.lam_x, R.m_x, C.lam_own, C.m_own, invS,
+  GABP_HIP(launch_line_readoff64(G.n, G.bcol, C.diag, rows_zero ? nullptr : R.lam_x,
+                                 rows_zero ? nullptr : R.m_x, C.lam_own, C.m_own, invS,
                                  G.xcol, s));
   TransposeJob<double> j{G.xcol, x, G.nx, G.ny};
   GABP_HIP(launch_transpose64(&j, 1, s));
@@ -88,12 +91,14 @@ int readoff_col64(const LineLayout& G, const double* invS, double* x, hipStream_
 }
 
 // one joint update of every line (flood: both orientations from the previous messages;
-// alt: rows, then columns from the new row messages); x != null: the read-off
-int joint_update(const LineLayout& G, LineArgs a[2], double* x, hipStream_t s) {
+// alt: rows, then columns from the new row messages); x != null: the read-off. first: the
+// update right after a reset (the incoming arrays of a are null where the messages are zero)
+int joint_update(const LineLayout& G, LineArgs a[2], double* x, hipStream_t s,
+                 bool first = false) {
   int st;
   if (!G.alt) {
     GABP_HIP(launch_line_joint(a, 2, s));
-    if (x && (st = readoff_col64(G, nullptr, x, s)) != GABP_OK) return st;
+    if (x && (st = readoff_col64(G, nullptr, x, s, first)) != GABP_OK) return st;
     if ((st = transpose_side(G, 0, true, s)) != GABP_OK) return st;
     return transpose_side(G, 1, true, s);
   }
@@ -222,12 +227,21 @@ int line_update_values(gabp_ctx* c, const double* val, hipStream_t s) {
   return GABP_OK;
 }
 
-// Zero messages: only the incoming copies a sweep reads before anything writes them -- the
-// column messages in the row layout, and (flood) the row messages in the column layout; the
-// rows-then-columns schedule rewrites the latter before the columns read them, and every
-// outgoing array is written by its own update before anything reads it. With precomputed
-// Lambda only the mean messages restart.
+// Zero messages. Only the incoming copies a sweep reads before anything writes them are
+// zero -- the column messages in the row layout, and (flood) the row messages in the column
+// layout; the rows-then-columns schedule rewrites the latter before the columns read them,
+// and every outgoing array is written by its own update before anything reads it. With
+// precomputed Lambda only the mean messages restart. A reset only marks them (c->fresh64):
+// the next sweep passes null for them; line_zero_incoming64 writes the zeros out when
+// the arrays themselves are needed (checkpoints, fault injection).
 int line_reset64(gabp_ctx* c, hipStream_t s) {
+  (void)s;
+  c->fresh64 = true;
+  return GABP_OK;
+}
+
+int line_zero_incoming64(gabp_ctx* c, hipStream_t s) {
+  if (!c->fresh64) return GABP_OK;
   const LineLayout& G = *c->lines;
   const bool joint = c->opt.mode == GABP_MODE_JOINT;
   for (int o = 1; o >= (G.alt ? 1 : 0); --o) {   // columns' messages (row layout), then rows'
@@ -235,6 +249,7 @@ int line_reset64(gabp_ctx* c, hipStream_t s) {
     GABP_HIP(launch_fill64(S.m_x, G.n, 0.0, s));
     if (joint) GABP_HIP(launch_fill64(S.lam_x, G.n, 0.0, s));
   }
+  c->fresh64 = false;
   return GABP_OK;
 }
 
@@ -252,8 +267,17 @@ int line_ensure32(gabp_ctx* c, hipStream_t s) {
 bool line_has32(const gabp_ctx* c) { return c->lines->side[0].m32_own != nullptr; }
 
 int line_reset32(gabp_ctx* c, hipStream_t s) {   // as line_reset64
+  (void)s;
+  c->fresh32 = true;
+  return GABP_OK;
+}
+
+int line_zero_incoming32(gabp_ctx* c, hipStream_t s) {
+  if (!c->fresh32) return GABP_OK;
   const LineLayout& G = *c->lines;
-  for (int o = 1; o >= (G.alt ? 1 : 0); --o) GABP_HIP(launch_fill32(G.side[o].m32_x, G.n, 0.0f, s));
+  if (G.side[0].m32_x)
+    for (int o = 1; o >= (G.alt ? 1 : 0); --o) GABP_HIP(launch_fill32(G.side[o].m32_x, G.n, 0.0f, s));
+  c->fresh32 = false;
   return GABP_OK;
 }
 
@@ -294,17 +318,23 @@ int line_sweep64(gabp_ctx* c, int T, const double* b, double* x, hipStream_t s) 
   const LineSide& C = G.side[1];
   int st;
   if ((st = poison_own(c, false, s)) != GABP_OK) return st;
+  // first sweep after a reset: the columns' messages (and for flood the rows') are zero
+  const bool first = c->fresh64;
+  c->fresh64 = false;
+  const bool rows_zero = first && !G.alt;
   if (c->opt.mode != GABP_MODE_PRECOMP) {
     LineArgs a[2];
     joint_args(G, T, b, G.bcol, a);
-    return joint_update(G, a, x, s);
+    if (first) a[0].lam_in = a[0].m_in = nullptr;
+    if (rows_zero) a[1].lam_in = a[1].m_in = nullptr;
+    return joint_update(G, a, x, s, first);
   }
   LineMeanArgs<double> m[2] = {
-      {R.nlines, R.len, R.alpha[T], R.beta[T], b, C.m_x, R.m_own},
-      {C.nlines, C.len, C.alpha[T], C.beta[T], G.bcol, R.m_x, C.m_own}};
+      {R.nlines, R.len, R.alpha[T], R.beta[T], b, first ? nullptr : C.m_x, R.m_own},
+      {C.nlines, C.len, C.alpha[T], C.beta[T], G.bcol, rows_zero ? nullptr : R.m_x, C.m_own}};
   if (!G.alt) {
     GABP_HIP(launch_line_mean64(m, 2, s));
-    if (x && (st = readoff_col64(G, G.invS[T], x, s)) != GABP_OK) return st;
+    if (x && (st = readoff_col64(G, G.invS[T], x, s, rows_zero)) != GABP_OK) return st;
     if ((st = transpose_side(G, 0, false, s)) != GABP_OK) return st;
     return transpose_side(G, 1, false, s);
   }
@@ -322,15 +352,20 @@ int line_sweep32(gabp_ctx* c, int T, const float* b, float* x, hipStream_t s) {
   const LineSide& C = G.side[1];
   int st;
   if ((st = poison_own(c, true, s)) != GABP_OK) return st;
+  const bool first = c->fresh32;   // as line_sweep64
+  c->fresh32 = false;
+  const bool rows_zero = first && !G.alt;
   auto readoff = [&]() -> int {
-    GABP_HIP(launch_line_readoff32(G.n, G.bcol32, R.m32_x, C.m32_own, G.invS32[T], G.xcol32, s));
+    GABP_HIP(launch_line_readoff32(G.n, G.bcol32, rows_zero ? nullptr : R.m32_x, C.m32_own,
+                                   G.invS32[T], G.xcol32, s));
     TransposeJob<float> j{G.xcol32, x, G.nx, G.ny};
     GABP_HIP(launch_transpose32(&j, 1, s));
     return GABP_OK;
   };
   LineMeanArgs<float> m[2] = {
-      {R.nlines, R.len, R.alpha32[T], R.beta32[T], b, C.m32_x, R.m32_own},
-      {C.nlines, C.len, C.alpha32[T], C.beta32[T], G.bcol32, R.m32_x, C.m32_own}};
+      {R.nlines, R.len, R.alpha32[T], R.beta32[T], b, first ? nullptr : C.m32_x, R.m32_own},
+      {C.nlines, C.len, C.alpha32[T], C.beta32[T], G.bcol32, rows_zero ? nullptr : R.m32_x,
+       C.m32_own}};
   if (!G.alt) {
     GABP_HIP(launch_line_mean32(m, 2, s));
     if (x && (st = readoff()) != GABP_OK) return st;

@@ -230,6 +230,8 @@ static int maybe_inject(gabp_ctx* c, int done, bool f32, hipStream_t s) {
   c->inject_nan_at = -1;
   const double nan = std::numeric_limits<double>::quiet_NaN();
   if (c->lines) {
+    int st;
+    if ((st = f32 ? line_zero_incoming32(c, s) : line_zero_incoming64(c, s)) != GABP_OK) return st;
     for (const auto& S : c->lines->side) {
       if (f32) GABP_HIP(launch_fill32(S.m32_x, c->lines->n, static_cast<float>(nan), s));
       else GABP_HIP(launch_fill64(S.m_x, c->lines->n, nan, s));
@@ -569,6 +571,9 @@ int line_get_state(gabp_ctx* c, void* dst, size_t* bytes, hipStream_t s) {
   const bool has32 = line_has32(c);
   std::vector<StateArray> arr;
   int st;
+  if (dst && ((st = line_zero_incoming64(c, s)) != GABP_OK ||
+              (st = line_zero_incoming32(c, s)) != GABP_OK))
+    return st;
   if ((st = line_state_arrays(c, has32, pre, false, &arr)) != GABP_OK) return st;
   size_t need = sizeof(StateHeader);
   for (const auto& a : arr) need += a.bytes;
@@ -608,6 +613,8 @@ int line_set_state(gabp_ctx* c, const StateHeader& h, const char* p, size_t byte
     c->pre[T].valid = pre[T];
     c->pre[T].sweeps = pre[T] ? h.pre_sweeps[T] : 0;
   }
+  c->fresh64 = false;
+  c->fresh32 = false;
   GABP_HIP(hipStreamSynchronize(s));
   return GABP_OK;
 }
