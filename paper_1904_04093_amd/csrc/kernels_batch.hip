@@ -54,6 +54,7 @@ __global__ __launch_bounds__(kB) void k_mean_b(
   VecR<T, R> m[KMAX];
   T lo[KMAX];
   int rv[KMAX];
+  // every load of the row first, the sums after: no wait between the slots' loads
 #pragma unroll
   for (int k = 0; k < KMAX; ++k) {
     if (k < w) {
@@ -61,10 +62,14 @@ __global__ __launch_bounds__(kB) void k_mean_b(
       m[k] = ldv<T, R>(msg_in + (int64_t)p * R);
       lo[k] = lamout[p];
       rv[k] = rev[p];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k)
+    if (k < w) {
 #pragma unroll
       for (int q = 0; q < R; ++q) M.v[q] += m[k].v[q];
     }
-  }
   if (WX) {
     // a converged (system, rhs) pair keeps the read-off it converged with
 #pragma unroll
@@ -104,6 +109,7 @@ __global__ __launch_bounds__(kB) void k_joint_b(
   VecR<double, R> m[KMAX];
   double l[KMAX], a[KMAX];
   int rv[KMAX];
+  // every load of the row first, the sums after: no wait between the slots' loads
 #pragma unroll
   for (int k = 0; k < KMAX; ++k) {
     if (k < w) {
@@ -112,11 +118,15 @@ __global__ __launch_bounds__(kB) void k_joint_b(
       l[k] = lam_in[p];
       a[k] = coef[p];
       rv[k] = rev[p];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k)
+    if (k < w) {
       S = fma(l[k], a[k], S);
 #pragma unroll
       for (int q = 0; q < R; ++q) M.v[q] += m[k].v[q];
     }
-  }
   if (WX) {
 #pragma unroll
     for (int q = 0; q < R; ++q)

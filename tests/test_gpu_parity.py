@@ -298,6 +298,32 @@ def test_checkpoint_resume_is_bitwise(B):
     assert np.array_equal(x12, x1)   # 7 + 5 sweeps from zero, same bits
 
 
+@pytest.mark.parametrize("kw", [dict(mode="joint"),
+                                dict(mode="joint", schedule="redblack"),
+                                dict(mode="precomp", precision="f32_ir", tol_lambda=1e-10),
+                                dict(mode="joint", schedule="lines_alt", grid=(32, 32)),
+                                dict(mode="joint", schedule="lines", grid=(32, 32))])
+def test_reset_state_is_zero_messages_everywhere(B, kw):
+    """A reset marks the messages zero without clearing them; every reader agrees: the next
+    sweeps (reset or not), a checkpoint taken in that state, and a context restored from it."""
+    a, b, _ = CASES["upwind32"]
+    if kw.get("schedule") == "redblack":
+        kw = dict(kw, colour=W.grid_colouring(32))
+    bt = _cuda(b)
+    ref = B.Solver.from_csr(a, **kw)
+    want = ref.sweeps(bt, 3).cpu().numpy()               # 3 sweeps from zero messages
+    s = B.Solver.from_csr(a, **kw)
+    s.sweeps(bt, 5)                                      # some non-zero message state
+    s.autotune()                                         # leaves the messages reset
+    blob = s.get_state()
+    r = B.Solver.from_csr(a, **kw)
+    r.sweeps(bt, 2)
+    r.set_state(blob)
+    assert np.array_equal(r.sweeps(bt, 3, reset=False).cpu().numpy(), want)
+    assert np.array_equal(s.sweeps(bt, 3, reset=False).cpu().numpy(), want)
+    assert np.array_equal(s.sweeps(bt, 3).cpu().numpy(), want)
+
+
 def test_repeat_runs_are_bitwise_identical(B):
     a, b, _ = CASES["field45"]
     s = B.Solver.from_csr(a, check_every=4)
@@ -479,6 +505,52 @@ def test_full_size_sampled_parity(B):
     # property at full size: the residual of the 5-sweep read-off is finite and below that of x = 0
     r, (n2, _, bn) = s.residual(bt, torch.as_tensor(x).cuda())
     assert np.isfinite(n2) and n2 < bn
+
+
+def _ball_problem(a, b, j, radius):
+    """The sub-system on the radius-`radius` graph ball around j (CSR, rhs, nodes, j's index)."""
+    nodes = _ball(a, j, radius)
+    rows = []
+    for u in nodes:
+        lo, hi = a.rowptr[u], a.rowptr[u + 1]
+        keep = np.isin(a.col[lo:hi], nodes)
+        rows.append((np.searchsorted(nodes, a.col[lo:hi][keep]), a.val[lo:hi][keep]))
+    rp = np.zeros(len(nodes) + 1, dtype=np.int32)
+    rp[1:] = np.cumsum([len(c) for c, _ in rows])
+    sub_a = W.CSR(len(nodes), rp, np.concatenate([c for c, _ in rows]).astype(np.int32),
+                  np.concatenate([v for _, v in rows]))
+    return sub_a, b[nodes], nodes, int(np.searchsorted(nodes, j))
+
+
+@pytest.mark.parametrize("op", ["upwind5_redblack", "grid9_colour4"])
+def test_full_size_coloured_sampled_parity(B, op):
+    """Coloured schedules at 2048 x 2048 in the launch configuration the coloured-sweep
+    benchmark times (colour-major lanes, 4-byte reverse index): sampled read-offs after s
+    sweeps equal the coloured oracle on the graph ball of radius K s + 2 around each sample
+    (within one sweep a message can cross at most K edges, one per colour class)."""
+    n = 2048
+    if op == "upwind5_redblack":
+        a, b = W.precision_at_scale(n)
+        colour = W.grid_colouring(n)
+    else:
+        a = W.random_grid_9pt(n, n, W.rng(6, 0))
+        b = W.rng(6, 1).uniform(-1, 1, a.n)
+        colour = W.grid_colouring4(n)
+    K = int(colour.max()) + 1
+    s = B.Solver.from_csr(a, colour=colour, schedule="redblack")
+    assert s.layout_info()["rev_bytes"] == 4
+    bt = _cuda(b)
+    samples = W.rng(306, K).choice(a.n, 6, replace=False)
+    samples[0], samples[1] = 0, a.n - 1
+    for sweeps in (1, 3):
+        x = s.sweeps(bt, sweeps).cpu().numpy()
+        for j in samples:
+            sub_a, sub_b, nodes, sj = _ball_problem(a, b, j, K * sweeps + 2)
+            g = G.Graph.from_csr(sub_a)
+            Lt, m = np.zeros(g.E), np.zeros(g.E)
+            for _ in range(sweeps):
+                xo, Lt, m = G.sweep_coloured(g, sub_b, Lt, m, colour[nodes])
+            assert abs(x[j] - xo[sj]) <= TOL * max(abs(xo[sj]), 1e-300) + 1e-300, (op, j, sweeps)
 
 
 def test_f32_mean_sweeps_track_fp64_oracle(B):
