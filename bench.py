@@ -729,7 +729,27 @@ def suite_batch(log):
                               "min_sweeps": min(i.sweeps for i in infos),
                               "loop_worst_rel_res2": worst}
     log(f"[suite] batch reduced: {out['reduced_to_1e-8']}")
+    out["cpu_baseline"] = cpu_baseline_batch(systems, rhs_l, t_batch, log)
     return out
+
+
+def cpu_baseline_batch(systems, rhs_l, t_batch, log):
+    """The oracle's FP32-message refinement (numpy, one thread) on the smallest system of the
+    reduced batch, one right-hand side, against the batch's time per (system, rhs) pair."""
+    from oracle import gabp as G
+    k = int(np.argmin([x.n for x in systems]))
+    g = G.Graph.from_csr(systems[k])
+    t0 = time.perf_counter()
+    Lt, S, _ = G.lambda_phase(g, 1e-7, 10000)
+    x, info = G.ir_solve(g, rhs_l[k][0], 1e-8,
+                         (Lt.astype(np.float32), (1.0 / S).astype(np.float32)), check_every=256)
+    dt = time.perf_counter() - t0
+    per_pair_gpu = t_batch / (len(systems) * len(rhs_l[0]))
+    rec = {"unknowns": g.n, "sweeps": info.sweeps, "seconds": dt, "cores": 1, "kind": "oracle",
+           "gpu_batch_seconds_per_pair": per_pair_gpu, "ratio": dt / per_pair_gpu,
+           "sample": "one (system, rhs) pair, the smallest system of the reduced batch"}
+    log(f"[suite] batch cpu baseline (oracle): {rec}")
+    return rec
 
 
 def suite_mg(log, J=12):
@@ -777,8 +797,30 @@ def suite_mg(log, J=12):
                               "setup_s": setup}
             log(f"[suite] mg {name} {sm_name}: {entry[sm_name]}")
             del mg, solvers
+        if JJ <= 6:
+            entry["cpu_baseline"] = cpu_baseline_mg(levels, b, log)
         out[name] = entry
     return out
+
+
+def cpu_baseline_mg(levels, b, log):
+    """The oracle's V(2,2) cycles (numpy, one thread) on the same hierarchy, to rel.res 1e-8
+    (cap 60): cycle counts to compare with the GPU's and seconds per cycle."""
+    from oracle import mg as MG
+    rec = {}
+    for name, kw in (("rbgs_2_2", dict(smoother="rbgs")),
+                     ("redblack_gabp_f64_joint_2_2",
+                      dict(smoother="gabp", gabp_mode="joint", schedule="redblack")),
+                     ("lines_alt_gabp_f64_joint_2_2",
+                      dict(smoother="gabp", gabp_mode="joint", schedule="lines_alt"))):
+        t0 = time.perf_counter()
+        h = MG.Hierarchy(levels, nu1=2, nu2=2, **kw)
+        _, hist = h.solve(b, 1e-8, 60)
+        dt = time.perf_counter() - t0
+        rec[name] = {"cycles": len(hist), "rel_res2": hist[-1], "seconds": dt,
+                     "ms_per_cycle": 1e3 * dt / max(len(hist), 1), "cores": 1, "kind": "oracle"}
+        log(f"[suite] mg cpu baseline (oracle) {name}: {rec[name]}")
+    return rec
 
 
 def suite_adjoint(log, n_full=1024, n_small=128, batch=8):
@@ -826,7 +868,47 @@ def suite_adjoint(log, n_full=1024, n_small=128, batch=8):
         out[f"gradients_{n}x{n}_batch{batch}"] = {"seconds": dt, "per_theta_s": dt / batch,
                                                  "loss_mean": float(np.mean(losses))}
         log(f"[suite] adjoint {n}: {out[f'gradients_{n}x{n}_batch{batch}']}")
+    out["cpu_baseline"] = cpu_baseline_adjoint(log)
     return out
+
+
+def cpu_baseline_adjoint(log, n=64):
+    """One theta-gradient on an n x n grid: the oracle (FP64 flood GaBP forward and
+    transposed solves to 1e-8 and the scatter, numpy, one thread) against the HIP path
+    (FP32 messages, FP64 refinement, autograd) on the same problem."""
+    import torch
+    from oracle import adjoint as OA
+    from oracle import gabp as G
+    from paper_1904_04093_amd import autograd as AG
+    from paper_1904_04093_amd import gabp
+    from paper_1904_04093_amd import workloads as W
+    th = W.theta_problem(n, 0)
+    b = W.rng(5, 101).uniform(-1, 1, n * n)
+    xt = W.rng(5, 100).uniform(-1, 1, n * n)
+    a = W.theta_operator(n, th)
+    t0 = time.perf_counter()
+    res = OA.gabp_adjoint(G.Graph.from_csr(a), b, xt, 1e-8, 2_000_000, check_every=16)
+    t_cpu = time.perf_counter() - t0
+    field = AG.ThetaField(n)
+    solver = gabp.Solver.from_csr(field.pattern, mode="precomp", precision="f32_ir",
+                                  tol_lambda=1e-7)
+    bt, xtt = torch.as_tensor(b).cuda(), torch.as_tensor(xt).cuda()
+
+    def grad_once():
+        tt = torch.tensor(th, device="cuda", requires_grad=True)
+        x = AG.gabp_solve(field.values(tt), bt, solver, tol=1e-8)
+        (0.5 * ((x - xtt) ** 2).sum()).backward()
+    grad_once()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    grad_once()
+    torch.cuda.synchronize()
+    t_gpu = time.perf_counter() - t0
+    rec = {"grid": f"{n}x{n}", "cpu_seconds": t_cpu, "gpu_seconds": t_gpu, "cores": 1,
+           "kind": "oracle", "cpu_sweeps": [res["info"][0].sweeps, res["info"][1].sweeps],
+           "sample": "one theta-gradient (forward + transposed solve to 1e-8, scatter)"}
+    log(f"[suite] adjoint cpu baseline (oracle): {rec}")
+    return rec
 
 
 if __name__ == "__main__":
