@@ -156,6 +156,55 @@ def test_four_colour_sweeps_on_a_nine_point_grid_match_oracle(B, mode, n):
         assert _rel_inf(x, xo) <= TOL, (mode, n, sweeps)
 
 
+def _greedy_colouring(a, skip=None):
+    """Greedy proper colouring of the symmetrised pattern (smallest free colour, row order);
+    `skip`: a colour value left unused (an empty class)."""
+    nb = [set() for _ in range(a.n)]
+    for i in range(a.n):
+        for c in a.col[a.rowptr[i]:a.rowptr[i + 1]]:
+            if c != i:
+                nb[i].add(int(c))
+                nb[int(c)].add(i)
+    col = np.full(a.n, -1)
+    for j in range(a.n):
+        used = {col[k] for k in nb[j] if col[k] >= 0}
+        c = 0
+        while c in used or c == skip:
+            c += 1
+        col[j] = c
+    return col.astype(np.uint8)
+
+
+@pytest.mark.parametrize("case", ["walk200_8colours", "sparse3000_5colours_one_empty"])
+@pytest.mark.parametrize("mode", ["joint", "precomp"])
+def test_many_colour_classes_match_oracle(B, case, mode):
+    """Coloured sweeps with up to 8 uneven colour classes (padding lanes after every class,
+    and an empty class) against the coloured oracle."""
+    if case.startswith("walk200"):
+        a, b, _ = CASES["walk200"]
+        colour = _greedy_colouring(a)
+    else:
+        a = W.random_sparse_dominant(3000, 2, W.rng(307, 0))
+        b = W.rng(307, 1).uniform(-1, 1, a.n)
+        colour = _greedy_colouring(a, skip=2)
+    assert colour.max() < 8
+    kw = dict(mode=mode, schedule="redblack")
+    lam = None
+    g = G.Graph.from_csr(a)
+    if mode == "precomp":
+        kw.update(tol_lambda=0.0, max_lambda_sweeps=40)
+        Lt, S, _ = G.lambda_phase(g, 0.0, 40)
+        lam = (Lt, S)
+    s = B.Solver.from_csr(a, colour=colour, **kw)
+    bt = _cuda(b)
+    for sweeps in (1, 2, 5):
+        x = s.sweeps(bt, sweeps).cpu().numpy()
+        Lt0, m = np.zeros(g.E), np.zeros(g.E)
+        for _ in range(sweeps):
+            xo, Lt0, m = G.sweep_coloured(g, b, Lt0, m, colour, lambda_fixed=lam)
+        assert _rel_inf(x, xo) < TOL, (case, mode, sweeps)
+
+
 def test_four_colour_sweeps_on_the_mixed_derivative_problem(B):
     a, b, _ = W.sec5_problem("mixed_derivative", 31, eps=0.01)
     colour = G.grid_colour4(31)
