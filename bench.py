@@ -98,8 +98,8 @@ def main():
                     help="also measure the multigrid, batching and adjoint configurations")
     ap.add_argument("--suite-only", action="store_true")
     ap.add_argument("--suite-part", default="all",
-                    choices=["all", "small", "batch", "mg", "adjoint", "lines", "sec5",
-                             "colours"],
+                    choices=["all", "small", "batch", "batch_full", "mg", "adjoint", "lines",
+                             "sec5", "colours"],
                     help="with --suite-only: run one part of the suite")
     ap.add_argument("--line-sweeps", type=int, default=50,
                     help="timed sweeps per variant in the line-sweep part")
@@ -404,6 +404,7 @@ def suite(log, part="all", line_sweeps=50):
     res = {}
     if part != "all":
         fn = {"small": lambda: suite_small(log), "batch": lambda: suite_batch(log),
+              "batch_full": lambda: suite_batch(log, full_only=True),
               "mg": lambda: suite_mg(log), "adjoint": lambda: suite_adjoint(log),
               "lines": lambda: suite_lines(log, sweeps=line_sweeps),
               "sec5": lambda: suite_sec5(log), "colours": lambda: suite_colours(log)}[part]
@@ -659,7 +660,7 @@ def cpu_baseline_lines(log, n=256, sweeps=3):
     return rec
 
 
-def suite_batch(log):
+def suite_batch(log, full_only=False):
     import torch
     from paper_1904_04093_amd import gabp
     from paper_1904_04093_amd import workloads as W
@@ -691,6 +692,8 @@ def suite_batch(log):
                          "generate_s": gen, "setup_s": setup}
     log(f"[suite] batch full shape: {out['full_shape']}")
     del bs, X, Bt
+    if full_only:   # the full shape alone (for a kernel profile of the batched sweep)
+        return out
     # reduced batch to rel.res 1e-8: 64 systems, sides 48..96, 4 rhs; batched vs loop
     fam = W.batch_family(nsys=64, nrhs=4, side_lo=48, side_hi=96, seed=3)
     systems = [x for x, _ in fam]

@@ -29,6 +29,58 @@ __device__ __forceinline__ void stv(T* p, const VecR<T, R>& v) {
   *reinterpret_cast<VecR<T, R>*>(p) = v;
 }
 
+// Per-slot streams with or without non-temporal hints (NT: the sweep's footprint exceeds
+// the last-level cache, so a line read or written once should not displace reused data).
+template <bool NT, typename T>
+__device__ __forceinline__ T ld_s(const T* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p); else return *p;
+}
+template <bool NT, typename T>
+__device__ __forceinline__ void st_s(T v, T* p) {
+  if constexpr (NT) __builtin_nontemporal_store(v, p); else *p = v;
+}
+template <bool NT, typename T, int R>
+__device__ __forceinline__ VecR<T, R> ldv_s(const T* p) {
+  if constexpr (NT && R > 1) {
+    typedef T V __attribute__((ext_vector_type(R)));
+    const V v = __builtin_nontemporal_load(reinterpret_cast<const V*>(p));
+    VecR<T, R> o;
+#pragma unroll
+    for (int q = 0; q < R; ++q) o.v[q] = v[q];
+    return o;
+  } else if constexpr (NT) {
+    VecR<T, R> o;
+    o.v[0] = __builtin_nontemporal_load(p);
+    return o;
+  } else {
+    return ldv<T, R>(p);
+  }
+}
+template <bool NT, typename T, int R>
+__device__ __forceinline__ void stv_s(T* p, const VecR<T, R>& o) {
+  if constexpr (NT && R > 1) {
+    typedef T V __attribute__((ext_vector_type(R)));
+    V v;
+#pragma unroll
+    for (int q = 0; q < R; ++q) v[q] = o.v[q];
+    __builtin_nontemporal_store(v, reinterpret_cast<V*>(p));
+  } else if constexpr (NT) {
+    __builtin_nontemporal_store(o.v[0], p);
+  } else {
+    stv<T, R>(p, o);
+  }
+}
+
+// XCD-aware block order. Consecutive workgroups are dispatched round-robin over the 8 XCDs,
+// each with its own L2; block i takes the logical block that makes every XCD cover one
+// contiguous range of rows (a bijection on [0, G)), so that gathers of neighbouring rows a
+// grid side away hit in the L2 of the XCD that loaded them.
+__device__ __forceinline__ int xcd_block(int i, int G) {
+  constexpr int kXcd = 8;
+  const int x = i % kXcd, k = i / kXcd, q = G / kXcd, r = G % kXcd;
+  return x * q + min(x, r) + k;
+}
+
 __device__ __forceinline__ int base_of(const int32_t* __restrict__ sptr, int j, int* w) {
   const int s = j >> 6;
   const int a = sptr[s];
@@ -37,7 +89,7 @@ __device__ __forceinline__ int base_of(const int32_t* __restrict__ sptr, int j, 
 }
 
 // ---- mean-only sweep for R right-hand sides with a shared Lt* ---------------------------
-template <typename T, int R, int KMAX, bool WX>
+template <typename T, int R, int KMAX, bool WX, bool NT>
 __global__ __launch_bounds__(kB) void k_mean_b(
     int n, const int32_t* __restrict__ sptr, const int32_t* __restrict__ rev,
     const int32_t* __restrict__ slice_sys, const int32_t* __restrict__ sys_on,
@@ -59,9 +111,9 @@ __global__ __launch_bounds__(kB) void k_mean_b(
   for (int k = 0; k < KMAX; ++k) {
     if (k < w) {
       const int p = p0 + 64 * k;
-      m[k] = ldv<T, R>(msg_in + (int64_t)p * R);
-      lo[k] = lamout[p];
-      rv[k] = rev[p];
+      m[k] = ldv_s<NT, T, R>(msg_in + (int64_t)p * R);
+      lo[k] = ld_s<NT>(lamout + p);
+      rv[k] = ld_s<NT>(rev + p);
     }
   }
 #pragma unroll
@@ -85,13 +137,13 @@ __global__ __launch_bounds__(kB) void k_mean_b(
       VecR<T, R> o;
 #pragma unroll
       for (int q = 0; q < R; ++q) o.v[q] = lo[k] * (M.v[q] - m[k].v[q]);
-      stv<T, R>(msg_out + (int64_t)rv[k] * R, o);
+      stv_s<NT, T, R>(msg_out + (int64_t)rv[k] * R, o);
     }
   }
 }
 
 // ---- joint FP64 sweep for R right-hand sides (Lt updated once per slot) ---------------
-template <int R, int KMAX, bool WX>
+template <int R, int KMAX, bool WX, bool NT>
 __global__ __launch_bounds__(kB) void k_joint_b(
     int n, const int32_t* __restrict__ sptr, const int32_t* __restrict__ rev,
     const int32_t* __restrict__ slice_sys, const int32_t* __restrict__ sys_on,
@@ -114,10 +166,10 @@ __global__ __launch_bounds__(kB) void k_joint_b(
   for (int k = 0; k < KMAX; ++k) {
     if (k < w) {
       const int p = p0 + 64 * k;
-      m[k] = ldv<double, R>(msg_in + (int64_t)p * R);
-      l[k] = lam_in[p];
-      a[k] = coef[p];
-      rv[k] = rev[p];
+      m[k] = ldv_s<NT, double, R>(msg_in + (int64_t)p * R);
+      l[k] = ld_s<NT>(lam_in + p);
+      a[k] = ld_s<NT>(coef + p);
+      rv[k] = ld_s<NT>(rev + p);
     }
   }
 #pragma unroll
@@ -136,11 +188,11 @@ __global__ __launch_bounds__(kB) void k_joint_b(
   for (int k = 0; k < KMAX; ++k) {
     if (k < w) {
       const double L = -a[k] / (S - l[k] * a[k]);
-      lam_out[rv[k]] = L;
+      st_s<NT>(L, lam_out + rv[k]);
       VecR<double, R> o;
 #pragma unroll
       for (int q = 0; q < R; ++q) o.v[q] = L * (M.v[q] - m[k].v[q]);
-      stv<double, R>(msg_out + (int64_t)rv[k] * R, o);
+      stv_s<NT, double, R>(msg_out + (int64_t)rv[k] * R, o);
     }
   }
 }
@@ -154,7 +206,7 @@ __global__ __launch_bounds__(kB) void k_residual_b(
     const double* __restrict__ val, const double* __restrict__ diag,
     const double* __restrict__ b, const double* __restrict__ x, const float* __restrict__ dx,
     const double* __restrict__ scale, double* __restrict__ r, double* __restrict__ partials) {
-  const int j = blockIdx.x * kB + threadIdx.x;
+  const int j = xcd_block(blockIdx.x, gridDim.x) * kB + threadIdx.x;
   // The internal row count n is a multiple of 64 (systems are slice-aligned), so this test
   // retires whole wavefronts: the grid rounds up to 256 threads, and the extra wavefronts
   // must not read slice_sys past its last slice.
@@ -490,6 +542,15 @@ __global__ void k_unpack(int n_int, const int32_t* __restrict__ slice_sys,
 
 inline int nb(int64_t n, int b = kB) { return static_cast<int>((n + b - 1) / b); }
 
+// Whether a batched sweep streams its per-slot arrays with non-temporal hints: its bytes
+// per sweep (per slot and per row, for R right-hand sides) against the 256 MiB last-level
+// cache, with the single-system sweeps' thresholds (1x for FP64, 2x for FP32).
+inline bool stream_hints(const Layout& L, double per_slot, double per_row, double factor) {
+  constexpr double kLLC = 256.0 * 1024 * 1024;
+  return per_slot * static_cast<double>(L.epad) + per_row * static_cast<double>(L.n) >
+         factor * kLLC;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------------------
@@ -500,6 +561,10 @@ inline int nb(int64_t n, int b = kB) { return static_cast<int>((n + b - 1) / b);
     case 4: { constexpr int RR = 4; __VA_ARGS__; break; } \
     default: return hipErrorInvalidValue;                \
   }
+
+#define GABP_B_NT_DISPATCH(NTV, ...)                 \
+  if (NTV) { constexpr bool NN = true; __VA_ARGS__; }   \
+  else { constexpr bool NN = false; __VA_ARGS__; }
 
 #define GABP_K_DISPATCH(W, ...)                                 \
   if ((W) <= 4) { constexpr int KK = 4; __VA_ARGS__; }          \
@@ -512,10 +577,11 @@ hipError_t batch_mean32(const gabp_ctx* c, const Batch* B, const float* msg_in, 
   const Layout& L = c->L;
   const Precomp& P = c->pre[0];
   const int g = nb(L.n);
-  GABP_R_DISPATCH(B->R, GABP_K_DISPATCH(L.max_width, {
-    if (x) k_mean_b<float, RR, KK, true><<<g, kB, 0, s>>>(L.n, L.sptr, L.rev, B->slice_sys, B->sys_on, B->flags, P.lamout32, P.invS32, B->r32, msg_in, msg_out, x);
-    else k_mean_b<float, RR, KK, false><<<g, kB, 0, s>>>(L.n, L.sptr, L.rev, B->slice_sys, B->sys_on, B->flags, P.lamout32, P.invS32, B->r32, msg_in, msg_out, x);
-  }));
+  const bool nt = stream_hints(L, 8.0 + 8.0 * B->R, 4.0 * B->R, 2.0);
+  GABP_R_DISPATCH(B->R, GABP_K_DISPATCH(L.max_width, GABP_B_NT_DISPATCH(nt, {
+    if (x) k_mean_b<float, RR, KK, true, NN><<<g, kB, 0, s>>>(L.n, L.sptr, L.rev, B->slice_sys, B->sys_on, B->flags, P.lamout32, P.invS32, B->r32, msg_in, msg_out, x);
+    else k_mean_b<float, RR, KK, false, NN><<<g, kB, 0, s>>>(L.n, L.sptr, L.rev, B->slice_sys, B->sys_on, B->flags, P.lamout32, P.invS32, B->r32, msg_in, msg_out, x);
+  })));
   return hipGetLastError();
 }
 
@@ -524,10 +590,11 @@ hipError_t batch_mean64(const gabp_ctx* c, const Batch* B, const double* msg_in,
   const Layout& L = c->L;
   const Precomp& P = c->pre[0];
   const int g = nb(L.n);
-  GABP_R_DISPATCH(B->R, GABP_K_DISPATCH(L.max_width, {
-    if (x) k_mean_b<double, RR, KK, true><<<g, kB, 0, s>>>(L.n, L.sptr, L.rev, B->slice_sys, B->sys_on, B->flags, P.lamout, P.S, B->b, msg_in, msg_out, x);
-    else k_mean_b<double, RR, KK, false><<<g, kB, 0, s>>>(L.n, L.sptr, L.rev, B->slice_sys, B->sys_on, B->flags, P.lamout, P.S, B->b, msg_in, msg_out, x);
-  }));
+  const bool nt = stream_hints(L, 12.0 + 16.0 * B->R, 8.0 * B->R, 1.0);
+  GABP_R_DISPATCH(B->R, GABP_K_DISPATCH(L.max_width, GABP_B_NT_DISPATCH(nt, {
+    if (x) k_mean_b<double, RR, KK, true, NN><<<g, kB, 0, s>>>(L.n, L.sptr, L.rev, B->slice_sys, B->sys_on, B->flags, P.lamout, P.S, B->b, msg_in, msg_out, x);
+    else k_mean_b<double, RR, KK, false, NN><<<g, kB, 0, s>>>(L.n, L.sptr, L.rev, B->slice_sys, B->sys_on, B->flags, P.lamout, P.S, B->b, msg_in, msg_out, x);
+  })));
   return hipGetLastError();
 }
 
@@ -536,10 +603,11 @@ hipError_t batch_joint64(const gabp_ctx* c, const Batch* B, const double* lam_in
                          hipStream_t s) {
   const Layout& L = c->L;
   const int g = nb(L.n);
-  GABP_R_DISPATCH(B->R, GABP_K_DISPATCH(L.max_width, {
-    if (x) k_joint_b<RR, KK, true><<<g, kB, 0, s>>>(L.n, L.sptr, L.rev, B->slice_sys, B->sys_on, B->flags, L.aT, L.diag, B->b, lam_in, msg_in, lam_out, msg_out, x);
-    else k_joint_b<RR, KK, false><<<g, kB, 0, s>>>(L.n, L.sptr, L.rev, B->slice_sys, B->sys_on, B->flags, L.aT, L.diag, B->b, lam_in, msg_in, lam_out, msg_out, x);
-  }));
+  const bool nt = stream_hints(L, 28.0 + 16.0 * B->R, 8.0 + 8.0 * B->R, 1.0);
+  GABP_R_DISPATCH(B->R, GABP_K_DISPATCH(L.max_width, GABP_B_NT_DISPATCH(nt, {
+    if (x) k_joint_b<RR, KK, true, NN><<<g, kB, 0, s>>>(L.n, L.sptr, L.rev, B->slice_sys, B->sys_on, B->flags, L.aT, L.diag, B->b, lam_in, msg_in, lam_out, msg_out, x);
+    else k_joint_b<RR, KK, false, NN><<<g, kB, 0, s>>>(L.n, L.sptr, L.rev, B->slice_sys, B->sys_on, B->flags, L.aT, L.diag, B->b, lam_in, msg_in, lam_out, msg_out, x);
+  })));
   return hipGetLastError();
 }
 
