@@ -14,6 +14,7 @@
 #include <cmath>
 
 #include "gabp_internal.h"
+#include "xcd.h"
 
 namespace gabp {
 namespace {
@@ -359,7 +360,8 @@ __global__ __launch_bounds__(kRedBlock) void k_residual(
     const double* __restrict__ scale, double* __restrict__ r, double* __restrict__ partials,
     const int32_t* __restrict__ perm) {
   __shared__ double sh[3][kRedBlock / 64];
-  const int t = blockIdx.x * kRedBlock + threadIdx.x;
+  const int blk = xcd_block(blockIdx.x, gridDim.x);   // row range and partials slot
+  const int t = blk * kRedBlock + threadIdx.x;
   double rr = 0.0, ra = 0.0, bb = 0.0;
   const int j = t < n ? row_of(perm, t) : -1;   // n: lanes
   if (j >= 0) {
@@ -421,9 +423,9 @@ __global__ __launch_bounds__(kRedBlock) void k_residual(
       s1 = fmax(s1, sh[1][q]);
       s2 += sh[2][q];
     }
-    partials[3 * blockIdx.x + 0] = s0;
-    partials[3 * blockIdx.x + 1] = s1;
-    partials[3 * blockIdx.x + 2] = s2;
+    partials[3 * blk + 0] = s0;
+    partials[3 * blk + 1] = s1;
+    partials[3 * blk + 2] = s2;
   }
 }
 

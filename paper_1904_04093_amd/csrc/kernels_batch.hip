@@ -9,6 +9,7 @@
 #include <cmath>
 
 #include "gabp_batch.h"
+#include "xcd.h"
 
 namespace gabp {
 namespace {
@@ -69,16 +70,6 @@ __device__ __forceinline__ void stv_s(T* p, const VecR<T, R>& o) {
   } else {
     stv<T, R>(p, o);
   }
-}
-
-// XCD-aware block order. Consecutive workgroups are dispatched round-robin over the 8 XCDs,
-// each with its own L2; block i takes the logical block that makes every XCD cover one
-// contiguous range of rows (a bijection on [0, G)), so that gathers of neighbouring rows a
-// grid side away hit in the L2 of the XCD that loaded them.
-__device__ __forceinline__ int xcd_block(int i, int G) {
-  constexpr int kXcd = 8;
-  const int x = i % kXcd, k = i / kXcd, q = G / kXcd, r = G % kXcd;
-  return x * q + min(x, r) + k;
 }
 
 __device__ __forceinline__ int base_of(const int32_t* __restrict__ sptr, int j, int* w) {
