@@ -81,6 +81,7 @@ struct Layout {
   std::vector<int32_t> cstart;        // [ncolours + 1] first lane of each colour (host)
   std::vector<int32_t> cslot;         // [ncolours + 1] first slot of each colour (host)
   int32_t* perm = nullptr;            // [nlanes] or null
+  int32_t* lane_of_row_d = nullptr;   // [n] lane of each row, the inverse of perm, or null
   std::vector<int32_t> lane_of_row;   // host copy of the inverse (empty: identity)
 };
 

@@ -350,7 +350,9 @@ __global__ __launch_bounds__(kBlock) void k_lambda_fin(
 
 // ---------------------------------------------------------------------------------------
 // Residual r = b - A x (coef_row = val) or b - A^T x (coef_row = aT), optionally at
-// x + scale * dx, with per-block partial norms.
+// x + scale * dx, with per-block partial norms. Threads take rows in row order, also for a
+// colour-major layout (a row's slots found through its lane), so that b, x, diag and r are
+// read and written in whole runs and a row's neighbours are gathered near its own x.
 // ---------------------------------------------------------------------------------------
 template <int KMAX, bool XADD>
 __global__ __launch_bounds__(kRedBlock) void k_residual(
@@ -358,15 +360,15 @@ __global__ __launch_bounds__(kRedBlock) void k_residual(
     const double* __restrict__ coef_row, const double* __restrict__ diag,
     const double* __restrict__ b, const double* __restrict__ x, const float* __restrict__ dx,
     const double* __restrict__ scale, double* __restrict__ r, double* __restrict__ partials,
-    const int32_t* __restrict__ perm) {
+    const int32_t* __restrict__ lane_of_row) {
   __shared__ double sh[3][kRedBlock / 64];
   const int blk = xcd_block(blockIdx.x, gridDim.x);   // row range and partials slot
   const int t = blk * kRedBlock + threadIdx.x;
   double rr = 0.0, ra = 0.0, bb = 0.0;
-  const int j = t < n ? row_of(perm, t) : -1;   // n: lanes
+  const int j = t < n ? t : -1;   // n: rows
   if (j >= 0) {
     int w;
-    const int p0 = row_base(sptr, t, &w);
+    const int p0 = row_base(sptr, lane_of_row ? lane_of_row[j] : j, &w);
     const double sc = XADD ? scale[0] : 0.0;
     double xj = x[j];
     if (XADD) xj = fma(sc, static_cast<double>(dx[j]), xj);
@@ -754,7 +756,7 @@ hipError_t launch_residual(const Layout* Lp, const double* coef_row, const doubl
                            double* partials, int32_t nred, double* red, hipStream_t s,
                            bool norms) {
   const Layout& L = *Lp;
-#define RES_ARGS(DX, SC) L.nlanes, L.sptr, L.col, coef_row, L.diag, b, x, DX, SC, r, partials, L.perm
+#define RES_ARGS(DX, SC) L.n, L.sptr, L.col, coef_row, L.diag, b, x, DX, SC, r, partials, L.lane_of_row_d
   if (dx) {
     GABP_DISPATCH_WIDTH(L.max_width,
                         (k_residual<4, true><<<nred, kRedBlock, 0, s>>>(RES_ARGS(dx, scale))),

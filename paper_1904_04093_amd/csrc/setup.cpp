@@ -298,6 +298,7 @@ int gabp_setup(gabp_ctx** out, int32_t n, int64_t nnz, const int32_t* rowptr,
   UP(L.csr_col, h_ccol);
   if (colour) {
     UP(L.perm, row_of_lane);
+    UP(L.lane_of_row_d, lane_of_row);
     L.lane_of_row = lane_of_row;
     L.ncolours = ncolours;
     L.cstart = cstart;
@@ -364,7 +365,7 @@ void gabp_destroy(gabp_ctx* c) {
   };
   Layout& L = c->L;
   F(L.sptr); F(L.rev); F(L.rev16); F(L.col); F(L.val); F(L.aT); F(L.diag); F(L.val_src); F(L.aT_src);
-  F(L.diag_src); F(L.csr_row); F(L.csr_col); F(L.perm);
+  F(L.diag_src); F(L.csr_row); F(L.csr_col); F(L.perm); F(L.lane_of_row_d);
   for (int q = 0; q < 2; ++q) {
     F(c->lam[q]); F(c->msg[q]); F(c->msg32[q]);
     F(c->pre[q].lamout); F(c->pre[q].S); F(c->pre[q].lamout32); F(c->pre[q].invS32);
