@@ -72,6 +72,15 @@ __device__ __forceinline__ void stv_s(T* p, const VecR<T, R>& o) {
   }
 }
 
+// Reverse slot of p: rev[p] (int32) or p + rev16[p] (2-byte delta, when every reverse slot
+// lies within int16 range of its slot, as on grids).
+template <bool NT, bool R16>
+__device__ __forceinline__ int rev_at(const int32_t* __restrict__ rev,
+                                      const int16_t* __restrict__ rev16, int p) {
+  if constexpr (R16) return p + static_cast<int>(ld_s<NT>(rev16 + p));
+  else return ld_s<NT>(rev + p);
+}
+
 __device__ __forceinline__ int base_of(const int32_t* __restrict__ sptr, int j, int* w) {
   const int s = j >> 6;
   const int a = sptr[s];
@@ -80,9 +89,10 @@ __device__ __forceinline__ int base_of(const int32_t* __restrict__ sptr, int j, 
 }
 
 // ---- mean-only sweep for R right-hand sides with a shared Lt* ---------------------------
-template <typename T, int R, int KMAX, bool WX, bool NT>
+template <typename T, int R, int KMAX, bool WX, bool NT, bool R16>
 __global__ __launch_bounds__(kB) void k_mean_b(
     int n, const int32_t* __restrict__ sptr, const int32_t* __restrict__ rev,
+    const int16_t* __restrict__ rev16,
     const int32_t* __restrict__ slice_sys, const int32_t* __restrict__ sys_on,
     const uint32_t* __restrict__ pair_flags, const T* __restrict__ lamout,
     const T* __restrict__ Sx, const T* __restrict__ b, const T* msg_in, T* msg_out,
@@ -104,7 +114,7 @@ __global__ __launch_bounds__(kB) void k_mean_b(
       const int p = p0 + 64 * k;
       m[k] = ldv_s<NT, T, R>(msg_in + (int64_t)p * R);
       lo[k] = ld_s<NT>(lamout + p);
-      rv[k] = ld_s<NT>(rev + p);
+      rv[k] = rev_at<NT, R16>(rev, rev16, p);
     }
   }
 #pragma unroll
@@ -134,9 +144,10 @@ __global__ __launch_bounds__(kB) void k_mean_b(
 }
 
 // ---- joint FP64 sweep for R right-hand sides (Lt updated once per slot) ---------------
-template <int R, int KMAX, bool WX, bool NT>
+template <int R, int KMAX, bool WX, bool NT, bool R16>
 __global__ __launch_bounds__(kB) void k_joint_b(
     int n, const int32_t* __restrict__ sptr, const int32_t* __restrict__ rev,
+    const int16_t* __restrict__ rev16,
     const int32_t* __restrict__ slice_sys, const int32_t* __restrict__ sys_on,
     const uint32_t* __restrict__ pair_flags, const double* __restrict__ coef,
     const double* __restrict__ diag, const double* __restrict__ b, const double* lam_in,
@@ -160,7 +171,7 @@ __global__ __launch_bounds__(kB) void k_joint_b(
       m[k] = ldv_s<NT, double, R>(msg_in + (int64_t)p * R);
       l[k] = ld_s<NT>(lam_in + p);
       a[k] = ld_s<NT>(coef + p);
-      rv[k] = ld_s<NT>(rev + p);
+      rv[k] = rev_at<NT, R16>(rev, rev16, p);
     }
   }
 #pragma unroll
@@ -557,6 +568,10 @@ inline bool stream_hints(const Layout& L, double per_slot, double per_row, doubl
   if (NTV) { constexpr bool NN = true; __VA_ARGS__; }   \
   else { constexpr bool NN = false; __VA_ARGS__; }
 
+#define GABP_B_R16_DISPATCH(R16V, ...)                 \
+  if (R16V) { constexpr bool RV = true; __VA_ARGS__; }   \
+  else { constexpr bool RV = false; __VA_ARGS__; }
+
 #define GABP_K_DISPATCH(W, ...)                                 \
   if ((W) <= 4) { constexpr int KK = 4; __VA_ARGS__; }          \
   else if ((W) <= 8) { constexpr int KK = 8; __VA_ARGS__; }     \
@@ -569,10 +584,10 @@ hipError_t batch_mean32(const gabp_ctx* c, const Batch* B, const float* msg_in, 
   const Precomp& P = c->pre[0];
   const int g = nb(L.n);
   const bool nt = stream_hints(L, 8.0 + 8.0 * B->R, 4.0 * B->R, 2.0);
-  GABP_R_DISPATCH(B->R, GABP_K_DISPATCH(L.max_width, GABP_B_NT_DISPATCH(nt, {
-    if (x) k_mean_b<float, RR, KK, true, NN><<<g, kB, 0, s>>>(L.n, L.sptr, L.rev, B->slice_sys, B->sys_on, B->flags, P.lamout32, P.invS32, B->r32, msg_in, msg_out, x);
-    else k_mean_b<float, RR, KK, false, NN><<<g, kB, 0, s>>>(L.n, L.sptr, L.rev, B->slice_sys, B->sys_on, B->flags, P.lamout32, P.invS32, B->r32, msg_in, msg_out, x);
-  })));
+  GABP_R_DISPATCH(B->R, GABP_K_DISPATCH(L.max_width, GABP_B_NT_DISPATCH(nt, GABP_B_R16_DISPATCH(L.rev16 != nullptr, {
+    if (x) k_mean_b<float, RR, KK, true, NN, RV><<<g, kB, 0, s>>>(L.n, L.sptr, L.rev, L.rev16, B->slice_sys, B->sys_on, B->flags, P.lamout32, P.invS32, B->r32, msg_in, msg_out, x);
+    else k_mean_b<float, RR, KK, false, NN, RV><<<g, kB, 0, s>>>(L.n, L.sptr, L.rev, L.rev16, B->slice_sys, B->sys_on, B->flags, P.lamout32, P.invS32, B->r32, msg_in, msg_out, x);
+  }))));
   return hipGetLastError();
 }
 
@@ -582,10 +597,10 @@ hipError_t batch_mean64(const gabp_ctx* c, const Batch* B, const double* msg_in,
   const Precomp& P = c->pre[0];
   const int g = nb(L.n);
   const bool nt = stream_hints(L, 12.0 + 16.0 * B->R, 8.0 * B->R, 1.0);
-  GABP_R_DISPATCH(B->R, GABP_K_DISPATCH(L.max_width, GABP_B_NT_DISPATCH(nt, {
-    if (x) k_mean_b<double, RR, KK, true, NN><<<g, kB, 0, s>>>(L.n, L.sptr, L.rev, B->slice_sys, B->sys_on, B->flags, P.lamout, P.S, B->b, msg_in, msg_out, x);
-    else k_mean_b<double, RR, KK, false, NN><<<g, kB, 0, s>>>(L.n, L.sptr, L.rev, B->slice_sys, B->sys_on, B->flags, P.lamout, P.S, B->b, msg_in, msg_out, x);
-  })));
+  GABP_R_DISPATCH(B->R, GABP_K_DISPATCH(L.max_width, GABP_B_NT_DISPATCH(nt, GABP_B_R16_DISPATCH(L.rev16 != nullptr, {
+    if (x) k_mean_b<double, RR, KK, true, NN, RV><<<g, kB, 0, s>>>(L.n, L.sptr, L.rev, L.rev16, B->slice_sys, B->sys_on, B->flags, P.lamout, P.S, B->b, msg_in, msg_out, x);
+    else k_mean_b<double, RR, KK, false, NN, RV><<<g, kB, 0, s>>>(L.n, L.sptr, L.rev, L.rev16, B->slice_sys, B->sys_on, B->flags, P.lamout, P.S, B->b, msg_in, msg_out, x);
+  }))));
   return hipGetLastError();
 }
 
@@ -595,10 +610,10 @@ hipError_t batch_joint64(const gabp_ctx* c, const Batch* B, const double* lam_in
   const Layout& L = c->L;
   const int g = nb(L.n);
   const bool nt = stream_hints(L, 28.0 + 16.0 * B->R, 8.0 + 8.0 * B->R, 1.0);
-  GABP_R_DISPATCH(B->R, GABP_K_DISPATCH(L.max_width, GABP_B_NT_DISPATCH(nt, {
-    if (x) k_joint_b<RR, KK, true, NN><<<g, kB, 0, s>>>(L.n, L.sptr, L.rev, B->slice_sys, B->sys_on, B->flags, L.aT, L.diag, B->b, lam_in, msg_in, lam_out, msg_out, x);
-    else k_joint_b<RR, KK, false, NN><<<g, kB, 0, s>>>(L.n, L.sptr, L.rev, B->slice_sys, B->sys_on, B->flags, L.aT, L.diag, B->b, lam_in, msg_in, lam_out, msg_out, x);
-  })));
+  GABP_R_DISPATCH(B->R, GABP_K_DISPATCH(L.max_width, GABP_B_NT_DISPATCH(nt, GABP_B_R16_DISPATCH(L.rev16 != nullptr, {
+    if (x) k_joint_b<RR, KK, true, NN, RV><<<g, kB, 0, s>>>(L.n, L.sptr, L.rev, L.rev16, B->slice_sys, B->sys_on, B->flags, L.aT, L.diag, B->b, lam_in, msg_in, lam_out, msg_out, x);
+    else k_joint_b<RR, KK, false, NN, RV><<<g, kB, 0, s>>>(L.n, L.sptr, L.rev, L.rev16, B->slice_sys, B->sys_on, B->flags, L.aT, L.diag, B->b, lam_in, msg_in, lam_out, msg_out, x);
+  }))));
   return hipGetLastError();
 }
 
