@@ -200,8 +200,9 @@ int gabp_set_state(gabp_ctx* ctx, const void* src, size_t bytes, hipStream_t str
  * single-system solve check block that starts at or after sweep k begins with every
  * incoming mean message set to NaN (once), so the check reports GABP_ENUMERIC; with
  * poison-outputs every ping-pong sweep (flood and line schedules) first fills the message
- * arrays it writes with NaN, so results equal the unpoisoned ones only if every slot that
- * is read was written; gabp_setup returns GABP_EINVAL for any other value of the variable. */
+ * arrays it writes with NaN, and every message reset fills the arrays the next sweep reads
+ * (not cleared, read as zero) with NaN, so results equal the unpoisoned ones only if every
+ * slot that is read was written; gabp_setup returns GABP_EINVAL for any other value of the variable. */
 int gabp_residual_history(const gabp_ctx* ctx, double* out, int32_t cap, int32_t* count);
 
 /* Sizes of the internal layout (host outputs, any may be NULL): number of rows, stored

@@ -34,7 +34,8 @@ struct GraphCache;
 struct LineLayout;
 constexpr int kSlice = 64;      // rows per slice = wavefront size on CDNA
 constexpr int kBlock = 256;     // threads per block for row kernels (4 slices)
-constexpr int kRedBlock = 256;  // threads per block for reductions
+constexpr int kRedBlock = 256;
+constexpr int kRevSelf16 = -32768;   // classed rev16: the slot is its own reverse  // threads per block for reductions
 constexpr int kMaxColours = 8;  // colour classes of the coloured schedule
 
 struct Precomp {
@@ -60,6 +61,10 @@ struct Layout {
   // device
   int32_t* sptr = nullptr;   // [nslices+1]
   int32_t* rev = nullptr;    // [epad]
+  // rev16 in a two-class colour-major layout (rev16_classed): rev[p] - p - (first slot of
+  // the other class - first slot of p's class), or kRevSelf16 for a padding slot (its own
+  // reverse); a flood launch over such a layout reads rev instead
+  bool rev16_classed = false;
   int16_t* rev16 = nullptr;  // [epad] rev[p] - p when every slot's reverse lies within
                              // int16 range (grid matrices); padding slots hold 0 (self)
   int32_t* col = nullptr;    // [epad]

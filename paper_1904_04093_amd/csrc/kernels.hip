@@ -64,13 +64,19 @@ __device__ __forceinline__ double wave_max(double v) {
 // Lanes [t0, t1): all of them (flood) or one colour class of a coloured layout, which the
 // class updates in place (red-black / 4-colour schedule).
 // ---------------------------------------------------------------------------------------
-// Reverse slot of p: rev[p] (int32) or p + rev16[p] (int16 delta; padding slots point at
-// themselves and write zeros there).
+// Reverse slot of p: rev[p] (int32) or from the int16 delta rev16[p]: p + rev16[p] +
+// rshift, where rshift is 0 for a flood layout and, for one colour class of a two-class
+// layout, the distance from its first slot to the other class's; kRevSelf16 marks a padding
+// slot of such a layout (its own reverse). Padding slots write zeros at themselves.
 template <bool NT, bool R16>
 __device__ __forceinline__ int rev_of(const int32_t* __restrict__ rev,
-                                      const int16_t* __restrict__ rev16, int p) {
-  if constexpr (R16) return p + static_cast<int>(ld_s<NT>(rev16 + p));
-  else return ld_s<NT>(rev + p);
+                                      const int16_t* __restrict__ rev16, int p, int rshift) {
+  if constexpr (R16) {
+    const int d = static_cast<int>(ld_s<NT>(rev16 + p));
+    return d == kRevSelf16 ? p : p + d + rshift;
+  } else {
+    return ld_s<NT>(rev + p);
+  }
 }
 
 // FIRST: the sweep right after a message reset. The incoming buffers are not read (nor
@@ -84,7 +90,7 @@ __global__ __launch_bounds__(kBlock) void k_joint(
     const double* __restrict__ coef, const double* __restrict__ diag,
     const double* __restrict__ b, const double* lam_in, const double* msg_in,
     double* lam_out, double* msg_out, double* __restrict__ x, int t0, int fresh,
-    const int32_t* __restrict__ perm) {
+    const int32_t* __restrict__ perm, int rshift) {
   const int t = t0 + static_cast<int>(blockIdx.x) * kBlock + static_cast<int>(threadIdx.x);
   if (t >= t1) return;
   const int j = row_of(perm, t);
@@ -101,7 +107,7 @@ __global__ __launch_bounds__(kBlock) void k_joint(
       if (k < w) {
         const int p = p0 + 64 * k;
         a[k] = ld_s<NT>(coef + p);
-        r[k] = rev_of<NT, R16>(rev, rev16, p);
+        r[k] = rev_of<NT, R16>(rev, rev16, p, rshift);
         if constexpr (FIRST) {
           const bool v = r[k] < fresh;
           l[k] = v ? ld_s<NT>(lam_in + p) : 0.0;
@@ -130,7 +136,7 @@ __global__ __launch_bounds__(kBlock) void k_joint(
     }
   } else {
     auto in = [&](const double* buf, int p) -> double {
-      if constexpr (FIRST) return rev_of<false, R16>(rev, rev16, p) < fresh ? buf[p] : 0.0;
+      if constexpr (FIRST) return rev_of<false, R16>(rev, rev16, p, rshift) < fresh ? buf[p] : 0.0;
       else return buf[p];
     };
     for (int k = 0; k < w; ++k) {
@@ -142,7 +148,7 @@ __global__ __launch_bounds__(kBlock) void k_joint(
     for (int k = 0; k < w; ++k) {
       const int p = p0 + 64 * k;
       const double l = in(lam_in, p), a = coef[p], m = in(msg_in, p);
-      const int r = rev_of<false, R16>(rev, rev16, p);
+      const int r = rev_of<false, R16>(rev, rev16, p, rshift);
       const double L = -a / (S - l * a);
       lam_out[r] = L;
       msg_out[r] = L * (M - m);
@@ -173,7 +179,7 @@ __global__ __launch_bounds__(kBlock) void k_mean(
     const int16_t* __restrict__ rev16,
     const T* __restrict__ lamout, const T* __restrict__ Sx, const T* __restrict__ b,
     const T* msg_in, T* msg_out, T* __restrict__ x, int t0, int fresh,
-    const int32_t* __restrict__ perm) {
+    const int32_t* __restrict__ perm, int rshift) {
   const int t = t0 + static_cast<int>(blockIdx.x) * kBlock + static_cast<int>(threadIdx.x);
   if (t >= t1) return;
   const int j = row_of(perm, t);
@@ -189,7 +195,7 @@ __global__ __launch_bounds__(kBlock) void k_mean(
       if (k < w) {
         const int p = p0 + 64 * k;
         lo[k] = ld_s<NT>(lamout + p);
-        r[k] = rev_of<NT, R16>(rev, rev16, p);
+        r[k] = rev_of<NT, R16>(rev, rev16, p, rshift);
         if constexpr (FIRST) m[k] = r[k] < fresh ? ld_s<NT>(msg_in + p) : T(0);
         else m[k] = ld_s<NT>(msg_in + p);
       }
@@ -203,14 +209,14 @@ __global__ __launch_bounds__(kBlock) void k_mean(
       if (k < w) st_s<NT>(lo[k] * (M - m[k]), msg_out + r[k]);
   } else {
     auto in = [&](int p) -> T {
-      if constexpr (FIRST) return rev_of<false, R16>(rev, rev16, p) < fresh ? msg_in[p] : T(0);
+      if constexpr (FIRST) return rev_of<false, R16>(rev, rev16, p, rshift) < fresh ? msg_in[p] : T(0);
       else return msg_in[p];
     };
     for (int k = 0; k < w; ++k) M += in(p0 + 64 * k);
     if (WX) x[j] = ReadOff<T>::f(M, Sx, j);
     for (int k = 0; k < w; ++k) {
       const int p = p0 + 64 * k;
-      msg_out[rev_of<false, R16>(rev, rev16, p)] = lamout[p] * (M - in(p));
+      msg_out[rev_of<false, R16>(rev, rev16, p, rshift)] = lamout[p] * (M - in(p));
     }
   }
 }
@@ -653,6 +659,17 @@ int grid_for(int64_t n) {
   if (FV) { constexpr bool FB = true; __VA_ARGS__; }  \
   else { constexpr bool FB = false; __VA_ARGS__; }
 
+// Whether a sweep over colour class c (-1: all lanes) reads the int16 reverse deltas, and
+// the shift they are taken from: a flood sweep over a classed layout reads rev instead.
+inline bool use_rev16(const Layout& L, int c, int* rshift) {
+  *rshift = 0;
+  if (!L.rev16) return false;
+  if (!L.rev16_classed) return true;
+  if (c < 0 || L.cslot.size() != 3) return false;
+  *rshift = L.cslot[1 - c] - L.cslot[c];
+  return true;
+}
+
 // lanes of a sweep: all, or those of colour class c
 inline void lane_range(const Layout& L, int c, int* t0, int* t1) {
   *t0 = c >= 0 ? L.cstart[c] : 0;
@@ -667,8 +684,10 @@ hipError_t launch_joint_sweep(const SweepArgs& a, hipStream_t s) {
   const int g = nblocks(t1 - t0);
 #define JOINT_ARGS                                                                      \
   t1, L.sptr, L.rev, L.rev16, a.coef, L.diag, a.b, a.lam_in, a.msg_in, a.lam_out,        \
-      a.msg_out, a.x, t0, a.fresh, L.perm
-  GABP_DISPATCH_FIRST(a.fresh >= 0, GABP_DISPATCH_NT(L.stream_hints, GABP_DISPATCH_R16(L.rev16 != nullptr, {
+      a.msg_out, a.x, t0, a.fresh, L.perm, rshift
+  int rshift;
+  const bool r16 = use_rev16(L, a.colour, &rshift);
+  GABP_DISPATCH_FIRST(a.fresh >= 0, GABP_DISPATCH_NT(L.stream_hints, GABP_DISPATCH_R16(r16, {
     if (a.x) {
       GABP_DISPATCH_WIDTH(L.max_width,
                           (k_joint<4, true, NTB, R16B, FB><<<g, kBlock, 0, s>>>(JOINT_ARGS)),
@@ -694,8 +713,11 @@ hipError_t mean_dispatch(const Layout& L, const A& a, const T* Sx, bool nt, hipS
   if (t1 <= t0) return hipSuccess;
   const int g = nblocks(t1 - t0);
 #define MEAN_ARGS \
-  t1, L.sptr, L.rev, L.rev16, a.lamout, Sx, a.b, a.msg_in, a.msg_out, a.x, t0, a.fresh, L.perm
-  GABP_DISPATCH_FIRST(a.fresh >= 0, GABP_DISPATCH_NT(nt, GABP_DISPATCH_R16(L.rev16 != nullptr, {
+  t1, L.sptr, L.rev, L.rev16, a.lamout, Sx, a.b, a.msg_in, a.msg_out, a.x, t0, a.fresh, L.perm, \
+      rshift
+  int rshift;
+  const bool r16 = use_rev16(L, a.colour, &rshift);
+  GABP_DISPATCH_FIRST(a.fresh >= 0, GABP_DISPATCH_NT(nt, GABP_DISPATCH_R16(r16, {
     if (a.x) {
       GABP_DISPATCH_WIDTH(L.max_width,
                           (k_mean<T, 4, true, NTB, R16B, FB><<<g, kBlock, 0, s>>>(MEAN_ARGS)),

@@ -584,7 +584,7 @@ hipError_t batch_mean32(const gabp_ctx* c, const Batch* B, const float* msg_in, 
   const Precomp& P = c->pre[0];
   const int g = nb(L.n);
   const bool nt = stream_hints(L, 8.0 + 8.0 * B->R, 4.0 * B->R, 2.0);
-  GABP_R_DISPATCH(B->R, GABP_K_DISPATCH(L.max_width, GABP_B_NT_DISPATCH(nt, GABP_B_R16_DISPATCH(L.rev16 != nullptr, {
+  GABP_R_DISPATCH(B->R, GABP_K_DISPATCH(L.max_width, GABP_B_NT_DISPATCH(nt, GABP_B_R16_DISPATCH(L.rev16 != nullptr && !L.rev16_classed, {
     if (x) k_mean_b<float, RR, KK, true, NN, RV><<<g, kB, 0, s>>>(L.n, L.sptr, L.rev, L.rev16, B->slice_sys, B->sys_on, B->flags, P.lamout32, P.invS32, B->r32, msg_in, msg_out, x);
     else k_mean_b<float, RR, KK, false, NN, RV><<<g, kB, 0, s>>>(L.n, L.sptr, L.rev, L.rev16, B->slice_sys, B->sys_on, B->flags, P.lamout32, P.invS32, B->r32, msg_in, msg_out, x);
   }))));
@@ -597,7 +597,7 @@ hipError_t batch_mean64(const gabp_ctx* c, const Batch* B, const double* msg_in,
   const Precomp& P = c->pre[0];
   const int g = nb(L.n);
   const bool nt = stream_hints(L, 12.0 + 16.0 * B->R, 8.0 * B->R, 1.0);
-  GABP_R_DISPATCH(B->R, GABP_K_DISPATCH(L.max_width, GABP_B_NT_DISPATCH(nt, GABP_B_R16_DISPATCH(L.rev16 != nullptr, {
+  GABP_R_DISPATCH(B->R, GABP_K_DISPATCH(L.max_width, GABP_B_NT_DISPATCH(nt, GABP_B_R16_DISPATCH(L.rev16 != nullptr && !L.rev16_classed, {
     if (x) k_mean_b<double, RR, KK, true, NN, RV><<<g, kB, 0, s>>>(L.n, L.sptr, L.rev, L.rev16, B->slice_sys, B->sys_on, B->flags, P.lamout, P.S, B->b, msg_in, msg_out, x);
     else k_mean_b<double, RR, KK, false, NN, RV><<<g, kB, 0, s>>>(L.n, L.sptr, L.rev, L.rev16, B->slice_sys, B->sys_on, B->flags, P.lamout, P.S, B->b, msg_in, msg_out, x);
   }))));
@@ -610,7 +610,7 @@ hipError_t batch_joint64(const gabp_ctx* c, const Batch* B, const double* lam_in
   const Layout& L = c->L;
   const int g = nb(L.n);
   const bool nt = stream_hints(L, 28.0 + 16.0 * B->R, 8.0 + 8.0 * B->R, 1.0);
-  GABP_R_DISPATCH(B->R, GABP_K_DISPATCH(L.max_width, GABP_B_NT_DISPATCH(nt, GABP_B_R16_DISPATCH(L.rev16 != nullptr, {
+  GABP_R_DISPATCH(B->R, GABP_K_DISPATCH(L.max_width, GABP_B_NT_DISPATCH(nt, GABP_B_R16_DISPATCH(L.rev16 != nullptr && !L.rev16_classed, {
     if (x) k_joint_b<RR, KK, true, NN, RV><<<g, kB, 0, s>>>(L.n, L.sptr, L.rev, L.rev16, B->slice_sys, B->sys_on, B->flags, L.aT, L.diag, B->b, lam_in, msg_in, lam_out, msg_out, x);
     else k_joint_b<RR, KK, false, NN, RV><<<g, kB, 0, s>>>(L.n, L.sptr, L.rev, L.rev16, B->slice_sys, B->sys_on, B->flags, L.aT, L.diag, B->b, lam_in, msg_in, lam_out, msg_out, x);
   }))));

@@ -240,6 +240,7 @@ int gabp_setup(gabp_ctx** out, int32_t n, int64_t nnz, const int32_t* rowptr,
   }
   // int16 reverse deltas when every real slot's reverse is within +-32767 positions
   std::vector<int16_t> h_rev16;
+  bool rev16_classed = false;
   {
     bool fits = true;
     for (int64_t p = 0; p < epad && fits; ++p) {
@@ -249,6 +250,26 @@ int gabp_setup(gabp_ctx** out, int32_t n, int64_t nnz, const int32_t* rowptr,
     if (fits) {
       h_rev16.resize(epad);
       for (int64_t p = 0; p < epad; ++p) h_rev16[p] = static_cast<int16_t>(h_rev[p] - p);
+    } else if (colour && ncolours == 2) {
+      // two colour classes: a real slot's reverse lies in the other class at about the same
+      // relative position, so the delta is taken from the other class's first slot
+      const int64_t cs1 = sptr64[cstart[1] / kSlice];
+      bool ok = true;
+      std::vector<int16_t> d16(epad);
+      for (int64_t p = 0; p < epad && ok; ++p) {
+        if (h_rev[p] == p) {
+          d16[p] = static_cast<int16_t>(kRevSelf16);
+          continue;
+        }
+        const int64_t shift = p < cs1 ? cs1 : -cs1;
+        const int64_t d = static_cast<int64_t>(h_rev[p]) - p - shift;
+        ok = d >= -32767 && d <= 32767;
+        d16[p] = static_cast<int16_t>(d);
+      }
+      if (ok) {
+        h_rev16.swap(d16);
+        rev16_classed = true;
+      }
     }
   }
   std::vector<int32_t> h_sptr(nslices + 1);
@@ -287,6 +308,7 @@ int gabp_setup(gabp_ctx** out, int32_t n, int64_t nnz, const int32_t* rowptr,
   UP(L.sptr, h_sptr);
   UP(L.rev, h_rev);
   if (!h_rev16.empty()) UP(L.rev16, h_rev16);
+  L.rev16_classed = rev16_classed;
   UP(L.col, h_col);
   UP(L.val, h_val);
   UP(L.aT, h_aT);

@@ -182,10 +182,16 @@ int sweep32(gabp_ctx* c, int T, const float* b, float* x, hipStream_t s) {
 }
 
 // Point schedules: no clearing; the next sweep reads the buffers as zero (fresh flags).
+// With poison-outputs the buffers the next sweep reads from are filled with NaN instead, so
+// a first sweep (flood, or a colour class in place) that read a stale slot would show it.
 int reset_messages64(gabp_ctx* c, hipStream_t s) {
   c->parity = 0;
   if (c->lines) return line_reset64(c, s);
   c->fresh64 = true;
+  if (c->poison_outputs) {
+    if (c->opt.mode == GABP_MODE_JOINT) GABP_HIP(launch_fill64(c->lam[0], c->L.epad, kPoison, s));
+    GABP_HIP(launch_fill64(c->msg[0], c->L.epad, kPoison, s));
+  }
   return GABP_OK;
 }
 
@@ -193,6 +199,8 @@ int reset_messages32(gabp_ctx* c, hipStream_t s) {
   c->parity32 = 0;
   if (c->lines) return line_reset32(c, s);
   c->fresh32 = true;
+  if (c->poison_outputs && c->msg32[0])
+    GABP_HIP(launch_fill32(c->msg32[0], c->L.epad, static_cast<float>(kPoison), s));
   return GABP_OK;
 }
 

@@ -114,6 +114,46 @@ def test_redblack_sweeps_match_oracle(B, mode):
         assert _rel_inf(x, xo) <= TOL, (mode, sweeps)
 
 
+@pytest.mark.parametrize("mode", ["joint", "precomp"])
+def test_redblack_class_relative_reverse_deltas(B, monkeypatch, mode):
+    """Two colour classes on a 191 x 193 grid (36,863 rows, one-way and sign-flipped
+    couplings): a slot and its reverse lie in different classes, tens of thousands of slots
+    apart, so the 2-byte reverse deltas are taken from the other class's first slot, with a
+    marker for padding slots (their own reverse). Sweeps match the oracle, and with every
+    output buffer poisoned first the results are the same bits (every slot read was
+    written)."""
+    nx, ny = 191, 193
+    a = W.random_grid_5pt(nx, ny, W.rng(320, 0), one_way=0.15, flip=0.2)
+    b = W.rng(320, 1).uniform(-1, 1, a.n)
+    idx = np.arange(a.n)
+    colour = ((idx % nx + idx // nx) % 2).astype(np.uint8)
+    kw = dict(mode=mode, schedule="redblack")
+    if mode == "precomp":
+        kw.update(tol_lambda=0.0, max_lambda_sweeps=30)
+    s = B.Solver.from_csr(a, colour=colour, **kw)
+    assert s.layout_info()["rev_bytes"] == 2
+    g = G.Graph.from_csr(a)
+    lam = None
+    if mode == "precomp":
+        Lt, S, _ = G.lambda_phase(g, 0.0, 30)
+        lam = (Lt, S)
+    bt = _cuda(b)
+    for sweeps in (1, 2, 5):
+        x = s.sweeps(bt, sweeps).cpu().numpy()
+        Lt0 = np.zeros(g.E) if lam is None else lam[0]
+        m = np.zeros(g.E)
+        for _ in range(sweeps):
+            xo, Lt0, m = G.sweep_coloured(g, b, Lt0, m, colour, lambda_fixed=lam)
+        assert _rel_inf(x, xo) <= TOL, (mode, sweeps)
+    monkeypatch.setenv("GABP_FAULT_INJECT", "poison-outputs")
+    poisoned = B.Solver.from_csr(a, colour=colour, **kw)
+    monkeypatch.delenv("GABP_FAULT_INJECT")
+    for tr in (False, True):
+        want = s.sweeps(bt, 6, transposed=tr).cpu().numpy()
+        got = poisoned.sweeps(bt, 6, transposed=tr).cpu().numpy()
+        assert np.all(np.isfinite(got)) and np.array_equal(got, want), tr
+
+
 def test_redblack_rejects_improper_colouring(B):
     a, _ = W.small_upwind(8)
     with pytest.raises(B.GaBPError) as e:
@@ -574,7 +614,8 @@ def _ball_problem(a, b, j, radius):
 @pytest.mark.parametrize("op", ["upwind5_redblack", "grid9_colour4"])
 def test_full_size_coloured_sampled_parity(B, op):
     """Coloured schedules at 2048 x 2048 in the launch configuration the coloured-sweep
-    benchmark times (colour-major lanes, 4-byte reverse index): sampled read-offs after s
+    benchmark times (colour-major lanes, 2-byte class-relative reverse deltas for red-black,
+    4-byte reverse index for four colours): sampled read-offs after s
     sweeps equal the coloured oracle on the graph ball of radius K s + 2 around each sample
     (within one sweep a message can cross at most K edges, one per colour class)."""
     n = 2048
@@ -587,7 +628,8 @@ def test_full_size_coloured_sampled_parity(B, op):
         colour = W.grid_colouring4(n)
     K = int(colour.max()) + 1
     s = B.Solver.from_csr(a, colour=colour, schedule="redblack")
-    assert s.layout_info()["rev_bytes"] == 4
+    # two classes: 2-byte deltas from the other class's first slot; four: 4-byte indices
+    assert s.layout_info()["rev_bytes"] == (2 if K == 2 else 4)
     bt = _cuda(b)
     samples = W.rng(306, K).choice(a.n, 6, replace=False)
     samples[0], samples[1] = 0, a.n - 1
