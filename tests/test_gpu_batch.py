@@ -82,3 +82,44 @@ def test_batch_rejects_coupled_systems(B):
                                 a.col.ctypes.data_as(ctypes.c_void_p),
                                 a.val.ctypes.data_as(ctypes.c_void_p), 1, ctypes.byref(o), None)
     assert st == B.EINVAL
+
+
+@pytest.fixture(scope="module")
+def full_family():
+    return _family(512, 48, 384, 4, seed=3)
+
+
+@pytest.mark.parametrize("mode", ["joint", "precomp"])
+def test_batch_full_shape_sampled_parity(B, full_family, mode):
+    """The full batching shape (512 systems, sides 48..384, 28.2M unknowns, 4 right-hand
+    sides) in one context, with the kernel variants the batched benchmark runs at that size
+    (non-temporal streams, 2-byte reverse deltas): after 5 sweeps (FP64, joint or with 30
+    precomputed Lt sweeps) the smallest, the largest and one random system match the oracle
+    for every right-hand side."""
+    from oracle import gabp as G
+    systems, rhs = full_family
+    k, klam = 5, 30
+    kw = dict(mode=mode, check_every=k)
+    if mode == "precomp":
+        kw.update(precision="f64", tol_lambda=0.0, max_lambda_sweeps=klam)
+    bs = B.BatchSolver(systems, nrhs=4, **kw)
+    X, infos = bs.solve(_stack(rhs, 4), 1e-30, k)
+    X = X.cpu().numpy()
+    off = bs.offsets
+    sizes = np.array([a.n for a in systems])
+    picks = {int(np.argmin(sizes)), int(np.argmax(sizes)),
+             int(W.rng(330, 0).integers(0, len(systems)))}
+    for s in sorted(picks):
+        g = G.Graph.from_csr(systems[s])
+        lam = G.lambda_phase(g, 0.0, klam)[:2] if mode == "precomp" else None
+        for q in range(4):
+            assert infos[s * 4 + q].sweeps == k, (s, q, infos[s * 4 + q])
+            b = rhs[s][q]
+            if lam is None:
+                xo, _, _ = G.run(g, b, k)
+            else:
+                m = np.zeros(g.E)
+                for _ in range(k):
+                    xo, m = G.msweep(g, b, lam[0], lam[1], m)
+            xb = X[q, off[s]:off[s + 1]]
+            assert np.abs(xb - xo).max() <= 1e-12 * np.abs(xo).max(), (mode, s, q)

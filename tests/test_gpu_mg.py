@@ -115,3 +115,35 @@ def test_recorded_vcycles_match_eager(B, warm):
     assert np.array_equal(outs[0][0], outs[1][0])
     assert np.array_equal(outs[0][1], outs[1][1])
     assert outs[0][2] == outs[1][2]
+
+
+@pytest.mark.parametrize("kw,tol", [
+    (dict(mode="joint", schedule="redblack"), 1e-11),
+    (dict(mode="precomp", precision="f32_ir", schedule="redblack", tol_lambda=1e-7), 1e-4)])
+def test_full_size_vcycles_are_linear_and_scale_invariant(B, kw, tol):
+    """The 4095 x 4095 multigrid configuration (11 levels, kx/ky = 100, cell Peclet 4) with
+    red-black GaBP smoothers. Lt does not depend on b and every other step of a V-cycle
+    (smoother mean messages from zero, residual, restriction, prolongation, coarse solve)
+    is linear in (b, x), so two V-cycles from x = 0 are linear in b: doubling b doubles x
+    exactly (power-of-two scaling is exact through every step, including the FP32 messages'
+    norm scaling), and V(b1 + b2) = V(b1) + V(b2) to rounding (FP64 messages) or to FP32
+    message rounding."""
+    levels = W.mg_hierarchy(12, coarsest=3, kx=1.0, ky=0.01, peclet=4.0)
+    assert levels[0].n == 4095 * 4095
+    mg = _gpu_mg(B, levels, "gabp", 2, 2, **kw)
+    n = levels[0].n
+    r = W.rng(331, 0)
+    b1, b2 = r.uniform(-1, 1, n), r.uniform(-1, 1, n)
+
+    def two_cycles(b):
+        x = torch.zeros(n, dtype=torch.float64, device="cuda")
+        bt = torch.as_tensor(b).cuda()
+        for _ in range(2):
+            mg.vcycle(bt, x)
+        return x.cpu().numpy()
+
+    x1, x2, x12, xd = two_cycles(b1), two_cycles(b2), two_cycles(b1 + b2), two_cycles(2.0 * b1)
+    assert np.all(np.isfinite(x1))
+    assert np.array_equal(xd, 2.0 * x1)
+    err = np.abs(x12 - (x1 + x2)).max() / np.abs(x1 + x2).max()
+    assert err <= tol, err
