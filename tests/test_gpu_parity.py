@@ -631,6 +631,30 @@ def _ball_problem(a, b, j, radius):
     return sub_a, b[nodes], nodes, int(np.searchsorted(nodes, j))
 
 
+def test_full_size_f32_sampled_parity(B):
+    """The FP32 refinement inner kernel at 2048 x 2048 in its launch configuration: after
+    K = 20 Lt sweeps and s FP32 mean sweeps, a read-off depends only on the graph ball of
+    radius K + s + 1 around its node, so sampled read-offs are compared with the FP64
+    oracle on that ball, to FP32 rounding."""
+    a, b = W.precision_at_scale(2048)
+    K = 20
+    s = B.Solver.from_csr(a, mode="precomp", precision="f32_ir", tol_lambda=0.0,
+                          max_lambda_sweeps=K)
+    bt = _cuda(b)
+    samples = W.rng(307, 2).choice(a.n, 6, replace=False)
+    samples[0], samples[1] = 0, a.n - 1
+    for sweeps in (1, 5):
+        x = s.sweeps(bt, sweeps).cpu().numpy()
+        for j in samples:
+            sub_a, sub_b, nodes, sj = _ball_problem(a, b, j, K + sweeps + 1)
+            g = G.Graph.from_csr(sub_a)
+            Lt, S, _ = G.lambda_phase(g, 0.0, K)
+            m = np.zeros(g.E)
+            for _ in range(sweeps):
+                xo, m = G.msweep(g, sub_b, Lt, S, m)
+            assert abs(x[j] - xo[sj]) <= 2e-6 * (1 + sweeps) * np.abs(xo).max(), (j, sweeps)
+
+
 @pytest.mark.parametrize("op", ["upwind5_redblack", "grid9_colour4"])
 def test_full_size_coloured_sampled_parity(B, op):
     """Coloured schedules at 2048 x 2048 in the launch configuration the coloured-sweep
