@@ -485,7 +485,7 @@ def suite_small(log):
     # small plain case: 32 x 32 upwind operator, FP64 joint GaBP to rel.res 1e-10
     a, b = W.small_upwind(32)
     s = gabp.Solver.from_csr(a, mode="joint")
-    s.autotune()
+    ce = s.autotune()["check_every"]
     bt = torch.as_tensor(b).cuda()
     x = torch.zeros(a.n, dtype=torch.float64, device="cuda")
     for _ in range(3):      # recordings of the check blocks, clocks up
@@ -501,6 +501,15 @@ def suite_small(log):
     out = {"seconds": float(np.median(times)), "sweeps": info.sweeps,
            "rel_res2": info.rel_res2,
            "x_rel_err_vs_dense": float(np.abs(x.cpu().numpy() - xs).max() / np.abs(xs).max())}
+    # CPU baseline: the oracle's whole solve with the same check interval (measured, not
+    # extrapolated: it converges in about a second)
+    from oracle import gabp as G
+    g = G.Graph.from_csr(a)
+    t0 = time.perf_counter()
+    _, oinfo, _, _ = G.solve(g, b, 1e-10, 10000, check_every=ce)
+    out["cpu_baseline"] = {"seconds": time.perf_counter() - t0, "sweeps": oinfo.sweeps,
+                           "cores": 1, "kind": "oracle",
+                           "sample": "the whole solve, same check interval"}
     log(f"[suite] small: {out}")
     return out
 
