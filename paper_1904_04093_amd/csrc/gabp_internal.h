@@ -144,6 +144,8 @@ int hip_fail(hipError_t e, const char* what);
 // CSR check of gabp_validate_csr (host only, validate.cpp)
 int validate(int32_t n, int64_t nnz, const int32_t* rowptr, const int32_t* col,
              const double* val, const int32_t* rev);
+// Algorithm 3 (gabp_smooth); r_ready: c->r already holds b - A x for this x (solve.cpp)
+int smooth_from(gabp_ctx* c, const double* b, double* x, int mu, bool r_ready, hipStream_t s);
 #define GABP_HIP(call)                                           \
   do {                                                           \
     hipError_t _e = (call);                                      \

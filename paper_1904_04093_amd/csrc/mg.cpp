@@ -22,6 +22,7 @@ using namespace gabp;
 struct MgGraph {
   const double* b = nullptr;
   const double* x = nullptr;
+  bool reuse = false;   // the finest pre-smoothing takes the previous check's residual
   std::vector<int> before, after;
   hipGraphExec_t exec = nullptr;
 };
@@ -98,23 +99,24 @@ int dense_of(gabp_ctx* c, std::vector<double>& A, hipStream_t s) {
   return GABP_OK;
 }
 
-int smooth(mg_ctx* m, int l, const double* b, double* x, int nu, hipStream_t s) {
+int smooth(mg_ctx* m, int l, const double* b, double* x, int nu, hipStream_t s,
+           bool r_ready = false) {
   if (nu <= 0) return GABP_OK;
   gabp_ctx* c = m->lv[l];
-  if (m->smoother == 0) return gabp_smooth(c, b, x, nu, s);
+  if (m->smoother == 0) return smooth_from(c, b, x, nu, r_ready, s);
   for (int it = 0; it < nu; ++it)
     for (int col = 0; col < 2; ++col) GABP_HIP(launch_rbgs(&c->L, m->side[l], col, b, x, s));
   return GABP_OK;
 }
 
-int vcycle(mg_ctx* m, int l, const double* b, double* x, hipStream_t s) {
+int vcycle(mg_ctx* m, int l, const double* b, double* x, hipStream_t s, bool r_ready = false) {
   int st;
   if (l == m->levels - 1) {
     GABP_HIP(launch_dense_matvec(m->nc, m->inv, b, x, s));
     return GABP_OK;
   }
   gabp_ctx* c = m->lv[l];
-  if ((st = smooth(m, l, b, x, m->nu1, s)) != GABP_OK) return st;
+  if ((st = smooth(m, l, b, x, m->nu1, s, r_ready)) != GABP_OK) return st;
   GABP_HIP(launch_residual(&c->L, c->L.val, b, x, nullptr, nullptr, m->r[l], c->partials,
                            c->nred, c->red, s, false));
   GABP_HIP(launch_restrict_fw(m->side[l + 1], m->r[l], m->b[l + 1], s));
@@ -145,12 +147,14 @@ void set_parities(mg_ctx* m, const std::vector<int>& p) {
   }
 }
 
-// one V-cycle followed by the finest residual's norms copied to the host (no wait)
-int enqueue_cycle(mg_ctx* m, const double* b, double* x, hipStream_t s) {
-  int st = vcycle(m, 0, b, x, s);
+// One V-cycle followed by the finest residual's norms copied to the host (no wait). The
+// check's residual b - A x is kept in the finest smoother's residual buffer: a solve's next
+// cycle (reuse) starts its pre-smoothing from it instead of forming it again.
+int enqueue_cycle(mg_ctx* m, const double* b, double* x, bool reuse, hipStream_t s) {
+  int st = vcycle(m, 0, b, x, s, reuse && m->smoother == 0);
   if (st != GABP_OK) return st;
   gabp_ctx* c = m->lv[0];
-  GABP_HIP(launch_residual(&c->L, c->L.val, b, x, nullptr, nullptr, nullptr, c->partials,
+  GABP_HIP(launch_residual(&c->L, c->L.val, b, x, nullptr, nullptr, c->r, c->partials,
                            c->nred, c->red, s));
   GABP_HIP(hipMemcpyAsync(c->host_red, c->red, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
   return GABP_OK;
@@ -158,15 +162,15 @@ int enqueue_cycle(mg_ctx* m, const double* b, double* x, hipStream_t s) {
 
 // Run one cycle; from the second cycle on (every Lt phase done, every buffer allocated) the
 // cycle is recorded once per starting state and replayed. Returns the relative residual.
-int run_cycle(mg_ctx* m, const double* b, double* x, double* rel, hipStream_t s) {
+int run_cycle(mg_ctx* m, const double* b, double* x, bool reuse, double* rel, hipStream_t s) {
   int st;
   if (!m->use_graphs || m->cycles_run == 0) {
-    if ((st = enqueue_cycle(m, b, x, s)) != GABP_OK) return st;
+    if ((st = enqueue_cycle(m, b, x, reuse, s)) != GABP_OK) return st;
   } else {
     const std::vector<int> before = parities(m);
     MgGraph* g = nullptr;
     for (auto& e : m->graphs)
-      if (e.b == b && e.x == x && e.before == before) g = &e;
+      if (e.b == b && e.x == x && e.reuse == reuse && e.before == before) g = &e;
     if (!g) {
       if (m->graphs.size() >= 4) {
         (void)hipGraphExecDestroy(m->graphs.front().exec);
@@ -175,7 +179,7 @@ int run_cycle(mg_ctx* m, const double* b, double* x, double* rel, hipStream_t s)
       if (!m->capture_stream)
         GABP_HIP(hipStreamCreateWithFlags(&m->capture_stream, hipStreamNonBlocking));
       GABP_HIP(hipStreamBeginCapture(m->capture_stream, hipStreamCaptureModeThreadLocal));
-      st = enqueue_cycle(m, b, x, m->capture_stream);
+      st = enqueue_cycle(m, b, x, reuse, m->capture_stream);
       hipGraph_t graph = nullptr;
       const hipError_t e = hipStreamEndCapture(m->capture_stream, &graph);
       if (st != GABP_OK) {
@@ -187,6 +191,7 @@ int run_cycle(mg_ctx* m, const double* b, double* x, double* rel, hipStream_t s)
       MgGraph ng;
       ng.b = b;
       ng.x = x;
+      ng.reuse = reuse;
       ng.before = before;
       ng.after = parities(m);
       const hipError_t e2 = hipGraphInstantiate(&ng.exec, graph, nullptr, nullptr, 0);
@@ -266,7 +271,7 @@ int mg_setup(mg_ctx** out, int32_t levels, gabp_ctx* const* level_ctx, const int
 int mg_vcycle(mg_ctx* m, const double* b, double* x, double* rel_res_out, hipStream_t s) {
   if (!m || !b || !x) return fail(GABP_EINVAL, "NULL argument");
   double rel = 0.0;
-  const int st = run_cycle(m, b, x, &rel, s);
+  const int st = run_cycle(m, b, x, false, &rel, s);   // x may have changed since
   if (st != GABP_OK) return st;
   if (rel_res_out) *rel_res_out = rel;
   return GABP_OK;
@@ -280,7 +285,8 @@ int mg_solve(mg_ctx* m, const double* b, double* x, double tol, int32_t max_cycl
   double rel = 1.0;
   int k = 0, st;
   while (k < max_cycles) {
-    if ((st = run_cycle(m, b, x, &rel, s)) != GABP_OK) return st;
+    // from the second cycle on, x is the one the previous check's residual was formed for
+    if ((st = run_cycle(m, b, x, k > 0, &rel, s)) != GABP_OK) return st;
     ++k;
     if (!std::isfinite(rel)) {
       if (cycles_out) *cycles_out = k;

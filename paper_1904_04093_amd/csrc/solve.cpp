@@ -509,10 +509,21 @@ int gabp_sweeps(gabp_ctx* c, const double* b, double* x, int32_t sweeps, int32_t
 int gabp_smooth(gabp_ctx* c, const double* b, double* x, int32_t mu, hipStream_t s) {
   if (!c || !b || !x) return fail(GABP_EINVAL, "NULL argument");
   if (mu < 1) return fail(GABP_EINVAL, "mu must be >= 1");
+  return gabp::smooth_from(c, b, x, mu, false, s);
+}
+
+}  // extern "C"
+
+namespace gabp {
+
+// Algorithm 3 with the residual either computed here or already in c->r (r_ready: the
+// caller has just formed b - A x for this x into c->r with the same residual kernel).
+int smooth_from(gabp_ctx* c, const double* b, double* x, int mu, bool r_ready, hipStream_t s) {
   int st;
   const int64_t n = c->L.n;
   const bool warm = c->opt.warm == GABP_WARM_ALL;
-  if ((st = residual(c, 0, b, x, nullptr, nullptr, c->r, s, false)) != GABP_OK) return st;
+  if (!r_ready && (st = residual(c, 0, b, x, nullptr, nullptr, c->r, s, false)) != GABP_OK)
+    return st;
   if (c->opt.precision == GABP_F32_IR) {
     if ((st = ensure_pre(c, 0, s)) != GABP_OK) return st;
     const bool fresh = !has_msg32(c);
@@ -533,6 +544,10 @@ int gabp_smooth(gabp_ctx* c, const double* b, double* x, int32_t mu, hipStream_t
   GABP_HIP(launch_axpy64(x, c->e, n, s));
   return GABP_OK;
 }
+
+}  // namespace gabp
+
+extern "C" {
 
 int gabp_residual(gabp_ctx* c, const double* b, const double* x, double* r,
                   int32_t transposed, double* norms, hipStream_t s) {

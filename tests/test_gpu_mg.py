@@ -147,3 +147,46 @@ def test_full_size_vcycles_are_linear_and_scale_invariant(B, kw, tol):
     assert np.array_equal(xd, 2.0 * x1)
     err = np.abs(x12 - (x1 + x2)).max() / np.abs(x1 + x2).max()
     assert err <= tol, err
+
+
+@pytest.mark.parametrize("kw", [
+    dict(mode="joint", schedule="redblack"),
+    dict(mode="precomp", precision="f32_ir", schedule="redblack", tol_lambda=1e-7),
+    dict(mode="joint", schedule="lines_alt", lines=True),
+    dict(mode="precomp", precision="f32_ir", schedule="lines_alt", tol_lambda=1e-7, lines=True)])
+def test_solve_equals_a_loop_of_single_cycles(B, kw):
+    """mg_solve starts each cycle after the first from the residual its previous check
+    formed (the finest pre-smoothing does not form it again); mg_vcycle always forms it.
+    Both give the same x bit for bit after every cycle and stop after the same cycle."""
+    kw = dict(kw)
+    lines = kw.pop("lines", False)
+    # Poisson, where every one of these smoothers converges (frozen-Lt FP32 red-black
+    # GaBP diverges on the anisotropic convection problem)
+    levels = W.mg_hierarchy(7, coarsest=3, kx=1.0, ky=1.0, peclet=0.0)
+    sides = [int(round(np.sqrt(a.n))) for a in levels]
+
+    def build():
+        solvers = [B.Solver.from_csr(a, colour=None if lines else W.grid_colouring(sd),
+                                     grid=(sd, sd) if lines else None, **kw)
+                   for a, sd in zip(levels, sides)]
+        return B.Multigrid(solvers, sides, smoother="gabp", nu1=2, nu2=2)
+
+    b = torch.as_tensor(W.rng(332, 0).uniform(-1, 1, levels[0].n)).cuda()
+    tol, cap = 1e-8, 60
+    xs, info = build().solve(b, tol, cap)
+    mg = build()
+    x = torch.zeros_like(b)
+    cycles = 0
+    for cycles in range(1, cap + 1):
+        rel = mg.vcycle(b, x)
+        if not np.isfinite(rel) or rel <= tol:
+            break
+    assert info["status"] == B.OK and info["cycles"] == cycles
+    assert np.array_equal(xs.cpu().numpy(), x.cpu().numpy())
+    for k in (1, 3):   # also when the solve stops at the cap
+        xk, ik = build().solve(b, 0.0, k)
+        m2 = build()
+        y = torch.zeros_like(b)
+        for _ in range(k):
+            m2.vcycle(b, y)
+        assert ik["cycles"] == k and np.array_equal(xk.cpu().numpy(), y.cpu().numpy()), k
