@@ -275,7 +275,10 @@ int mg_vcycle(mg_ctx* m, const double* b, double* x, double* rel_res_out, hipStr
 
 /* x = 0, then V-cycles until ||b - A_0 x||_2 / ||b||_2 <= tol or max_cycles. Returns
  * GABP_OK, GABP_MAXSWEEPS (cycle cap) or GABP_ENUMERIC (divergence to non-finite values).
- * cycles_out / rel_res_out: host, may be NULL. */
+ * cycles_out / rel_res_out: host, may be NULL. Each cycle after the first starts its
+ * finest GaBP pre-smoothing from the residual the previous cycle's check formed (x has not
+ * changed in between), so the iterates equal those of repeated mg_vcycle calls bit for bit;
+ * the finest context's residual buffer holds that residual between cycles. */
 int mg_solve(mg_ctx* m, const double* b, double* x, double tol, int32_t max_cycles,
              int32_t* cycles_out, double* rel_res_out, hipStream_t stream);
 
