@@ -55,6 +55,14 @@ extern "C" {
 #define GABP_MODE_PRECOMP 1  /* Lt iterated alone to convergence first, then frozen and
                                 shared by every right-hand side and smoother call
                                 (Sec. 2.3 remark on decoupling; Sec. 4.2)                    */
+#define GABP_MODE_PRECOMP_SEQ 2 /* the Lt of the first sweeps after a message reset, one set
+                                per sweep, computed once from zero messages and kept: the
+                                precision messages every smoother call needs (Sec. 4.2;
+                                they do not depend on the residual), so gabp_smooth and
+                                gabp_sweeps give the iterates of JOINT at the cost of mean-
+                                only sweeps. Point schedules only (ENOTSUPP at set-up for
+                                line schedules and batches); gabp_solve and
+                                gabp_solve_transposed return ENOTSUPP                      */
 #define GABP_F64 0           /* all message arithmetic in FP64                              */
 #define GABP_F32_IR 1        /* FP32 mean messages (precomputed Lt rounded to FP32) inside
                                 FP64 iterative refinement: r = b - A x and x += d are the
@@ -70,8 +78,6 @@ extern "C" {
                                 from the previous messages; needs grid_nx, grid_ny          */
 #define GABP_SCHED_LINES_ALT 3 /* line GaBP with all rows updated first, then all columns from
                                 the new row messages (one chain of the flood iteration)     */
-#define GABP_WARM_RESET_M 0  /* smoother: mean messages restart from zero every call        */
-#define GABP_WARM_ALL 1      /* smoother: mean messages carry over between calls            */
 
 typedef struct {
   int32_t mode;              /* GABP_MODE_*                      default GABP_MODE_JOINT   */
@@ -80,7 +86,6 @@ typedef struct {
   double tol_lambda;         /* Lt converged when max|dLt| <= tol_lambda * max|Lt|
                                 (0: run exactly max_lambda_sweeps)  default 1e-14          */
   int32_t max_lambda_sweeps; /* cap on the Lt phase               default 100000           */
-  int32_t warm;              /* GABP_WARM_*                       default RESET_M          */
   double ir_inner_tol;       /* IR: inner solve ends when ||r_new|| <= ir_inner_tol*||r||
                                                                   default 1e-4             */
   int32_t ir_max_inner;      /* IR: cap on inner sweeps per outer step  default 1000000   */
@@ -118,7 +123,11 @@ int gabp_validate_csr(int32_t n, int64_t nnz, const int32_t* rowptr, const int32
                       const double* val, const int32_t* rev);
 
 /* Build a solver context for A (Sec. 2.3: graph of A plus reverse-edge pairing). rowptr,
- * col, val, rev: HOST pointers as in gabp_validate_csr (rev NULL: built here). The matrix
+ * col, val, rev: HOST pointers as in gabp_validate_csr (rev NULL: built here). The CSR is
+ * read on the host on purpose: the symmetrised pattern, the reverse index and the slice
+ * layout are built there once, so a device-resident CSR is copied to the host by the
+ * caller first (later value changes go through gabp_update_values, which takes device
+ * values). The matrix
  * is copied into context-owned device memory in slice-of-64-rows, column-major order over
  * the symmetrised pattern; the caller may free its arrays on return. opt NULL = defaults.
  * `colour` (host, may be NULL): one byte per row, the row's colour class 0..7 (red-black:
@@ -164,7 +173,8 @@ int gabp_precompute_lambda(gabp_ctx* ctx, int32_t transposed, int32_t* sweeps_ou
                            hipStream_t stream);
 
 /* Algorithm 3 (error-correction smoother): r = b - A x; mu sweeps on A e = r with the
- * context's mode/schedule/precision and warm policy; x += e^mu (the mu-th read-off).
+ * context's mode/schedule/precision, messages restarted from zero (Algorithm 3 applies
+ * Algorithm 1 to the error equation); x += e^mu (the mu-th read-off).
  * b: DEVICE const, x: DEVICE in/out, n doubles. */
 int gabp_smooth(gabp_ctx* ctx, const double* b, double* x, int32_t mu, hipStream_t stream);
 
@@ -191,6 +201,15 @@ int gabp_adjoint_scatter(gabp_ctx* ctx, const double* lambda, const double* x, d
  * of another layout or schedule family, or a truncated one). */
 int gabp_get_state(gabp_ctx* ctx, void* dst, size_t* bytes, hipStream_t stream);
 int gabp_set_state(gabp_ctx* ctx, const void* src, size_t bytes, hipStream_t stream);
+
+/* Message state in the matrix's own order, for parity checks of the messages of
+ * eq. nonsymmetric_GaBP_rules: for every stored off-diagonal entry e = (i, j) of the setup
+ * CSR, lam[e] = Lt_ji and msg[e] = m_ji, the messages j -> i that row i receives now (after
+ * the sweeps since the last reset; zero right after a reset). Diagonal entries get 0.
+ * PRECOMP: lam is the frozen Lt*; PRECOMP_SEQ: the Lt of the last sweep done; F32_IR
+ * precision: msg is the FP32 mean-message state widened. lam, msg: DEVICE, nnz doubles each
+ * (either may be NULL). Line schedules and batches: ENOTSUPP. */
+int gabp_get_messages(gabp_ctx* ctx, double* lam, double* msg, hipStream_t stream);
 
 /* Residual history of the context's last gabp_solve / gabp_solve_transposed: the
  * ||b - A x||_2 / ||b||_2 read at every check (FP32 refinement: of every trial x + s d),
@@ -229,6 +248,8 @@ int gabp_autotune(gabp_ctx* ctx, int32_t* check_every_out, int32_t* hints_out,
 /* ---- batches of independent systems ------------------------------------------------- */
 /* Build one context for nsys independent systems given as a block-diagonal CSR matrix
  * (HOST arrays, n rows in total; system s owns rows sys_row_off[s] .. sys_row_off[s+1]-1
+ * (int32 row offsets, nsys + 1 of them; a system's entries are found through rowptr, so no
+ * separate entry offsets are taken)
  * and no entry may couple two systems), each with nrhs right-hand sides (1, 2 or 4).
  * Every system is laid out from a 64-row slice boundary so that a wavefront never mixes
  * two systems. The precision messages Lt* (b-independent, Sec. 2.3) are computed once per
@@ -254,11 +275,13 @@ int gabp_solve_batched(gabp_ctx* ctx, const double* B, double* X, double tol,
 /* ---- geometric multigrid (Sec. 4: GaBP as a multigrid smoother) ---------------------- */
 /* Build a V-cycle over `levels` contexts, finest first (level_ctx[l] owns the operator of
  * level l: a rediscretisation on a vertex-centred side[l] x side[l] interior grid, rows x
- * fastest, with side[l] = 2 side[l+1] + 1; the coarsest side must be <= 63). Transfers:
+ * fastest, with side[l] = 2 side[l+1] + 1; the coarsest side must be <= 63). Grids are
+ * square, so one side per level is taken (not separate x and y sizes). Transfers:
  * full-weighting restriction and bilinear interpolation. The coarsest system is solved
  * directly (its inverse is formed once here, by Gauss-Jordan with partial pivoting).
  * smoother 0: GaBP as the error-correction smoother of Algorithm 3, run by each level's
- * context with its own mode, schedule, precision and warm policy; smoother 1: red-black
+ * context with its own mode, schedule and precision, messages restarted from zero at every
+ * call (GABP_MODE_PRECOMP_SEQ keeps the per-sweep Lt between calls); smoother 1: red-black
  * Gauss-Seidel (colour (ix + iy) mod 2, red first). nu1 / nu2: pre- / post-smoothing
  * steps (GaBP: sweeps per smoother call; RB-GS: red+black sweeps). The contexts are
  * borrowed and must outlive the multigrid context; their message state is used by the

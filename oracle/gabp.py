@@ -239,16 +239,15 @@ def solve_precomp(g: Graph, b, tol, max_sweeps, check_every=1, tol_lambda=1e-14,
 # Algorithm 3: GaBP as an error-correction smoother
 # ----------------------------------------------------------------------------------------
 
-def smooth(g: Graph, b, x, mu, lam=None, m_state=None):
-    """x_new = x + e^mu, where e^mu is the mu-th read-off of GaBP on A e = b - A x.
+def smooth(g: Graph, b, x, mu, lam=None):
+    """x_new = x + e^mu, where e^mu is the mu-th read-off of GaBP on A e = b - A x from zero
+    messages (Algorithm 3).
 
-    ``lam=None``: joint sweeps from zero messages (Algorithm 1 on the error equation).
-    ``lam=(Lt*, S*)``: mean-only sweeps with precomputed Lambda~. ``m_state``: start the
-    mean messages from these (warm start) instead of zero; the final messages are returned.
-    Returns (x_new, m_after).
+    ``lam=None``: joint sweeps (Algorithm 1 on the error equation). ``lam=(Lt*, S*)``:
+    mean-only sweeps with the converged precision messages frozen.
     """
     r = g.residual(b, x)
-    m = np.zeros(g.E) if m_state is None else m_state.copy()
+    m = np.zeros(g.E)
     if lam is None:
         Lt = np.zeros(g.E)
         for _ in range(mu):
@@ -257,24 +256,83 @@ def smooth(g: Graph, b, x, mu, lam=None, m_state=None):
         Lt_star, S_star = lam
         for _ in range(mu):
             e, m = msweep(g, r, Lt_star, S_star, m)
-    return x + e, m
+    return x + e
+
+
+def lambda_sequence(g: Graph, depth, colour=None):
+    """Precision messages of the first ``depth`` sweeps from zero messages.
+
+    They do not depend on the right-hand side (Sec. 2.3 remark after Algorithm 1), so a
+    smoother that restarts from zero messages at every call needs exactly these, and they
+    can be computed once and reused by every call (Sec. 4.2, precomputing the required
+    messages). Returns ``[(Lt_s, S_s) for s = 1..depth]``: ``S_s`` = the node precisions
+    the read-off of sweep s divides by, ``Lt_s`` = the precision messages sent in sweep s.
+    ``colour``: the coloured schedule (classes in turn, in place); None: flood.
+    """
+    seq = []
+    Lt = np.zeros(g.E)
+    colour = None if colour is None else np.asarray(colour)
+    for _ in range(depth):
+        if colour is None:
+            S, _ = node_totals(g, np.zeros(g.n), Lt, np.zeros(g.E))
+            with np.errstate(divide="ignore", invalid="ignore"):
+                Lt = -g.a_ij / (S[g.src] - _gather(Lt, g.rev) * g.a_ij)
+            seq.append((Lt, S))
+            continue
+        S_rec = np.zeros(g.n)
+        Lt = Lt.copy()
+        for c in range(int(colour.max()) + 1 if len(colour) else 0):
+            S, _ = node_totals(g, np.zeros(g.n), Lt, np.zeros(g.E))
+            sel = colour == c
+            S_rec[sel] = S[sel]
+            with np.errstate(divide="ignore", invalid="ignore"):
+                L_new = -g.a_ij / (S[g.src] - _gather(Lt, g.rev) * g.a_ij)
+            Lt = np.where(colour[g.src] == c, L_new, Lt)
+        seq.append((Lt.copy(), S_rec))
+    return seq
+
+
+def smooth_seq(g: Graph, b, x, mu, seq, colour=None):
+    """Algorithm 3 with mean-only sweeps that take the precision messages of sweep s from
+    ``seq = lambda_sequence(g, >= mu, colour)``: the same iterates as the joint smoother
+    from zero messages, without recomputing the precision messages."""
+    assert len(seq) >= mu
+    r = g.residual(b, x)
+    m = np.zeros(g.E)
+    colour = None if colour is None else np.asarray(colour)
+    e = np.zeros(g.n)
+    for s in range(mu):
+        Lt_s, S_s = seq[s]
+        if colour is None:
+            M = r + np.bincount(g.dst, weights=m, minlength=g.n)
+            e = M / S_s
+            m = Lt_s * (M[g.src] - _gather(m, g.rev))
+            continue
+        for c in range(int(colour.max()) + 1 if len(colour) else 0):
+            M = r + np.bincount(g.dst, weights=m, minlength=g.n)
+            sel = colour == c
+            e[sel] = M[sel] / S_s[sel]
+            m_new = Lt_s * (M[g.src] - _gather(m, g.rev))
+            m = np.where(colour[g.src] == c, m_new, m)
+    return x + e
 
 
 # ----------------------------------------------------------------------------------------
 # FP32 messages inside FP64 iterative refinement
 # ----------------------------------------------------------------------------------------
 
-def ir_solve(g: Graph, b, tol, lam32, check_every=16, inner_tol=1e-4, max_sweeps=10**6,
-             patience=8):
-    """Iterative refinement with FP32 mean-only GaBP as the inner solver.
+def ir_solve(g: Graph, b, tol, lam32, check_every=16, inner_tol=1e-4, max_inner=10**5,
+             max_sweeps=10**6):
+    """Classical iterative refinement (not in the paper) around FP32 mean-only GaBP.
 
-    Outer loop in FP64: r = b - A x; stop at ||r||_2/||b||_2 <= tol. Inner: mean-only sweeps
-    on A d = r / s (s = ||r||_inf) in FP32 with FP32 Lt*, 1/S*, from zero messages; every
-    ``check_every`` sweeps the FP64 residual of x + s d is formed and the best trial kept;
-    the inner solve ends when the best trial reached inner_tol * ||r|| or tol * ||b||, or
-    after ``patience`` checks without a new best once one was found. Then x += s d_best.
-    ``lam32 = (Lt*, 1/S*)`` as float32 arrays. Parity unpinned as a bitwise reference (the
-    FP32 rounding order is free); only its converged result is compared.
+    Outer loop in FP64: x = 0; r = b - A x; stop when ||r||_2 / ||b||_2 <= tol. Each outer
+    step scales the residual by s = ||r||_inf and solves A d = r / s approximately with
+    mean-only sweeps (Sec. 2.3 decoupling) in FP32 from zero messages, using the FP32
+    precision messages and reciprocal node precisions ``lam32 = (Lt*, 1/S*)``; the inner
+    solve stops when the FP64 residual of the correction equation satisfies
+    ||r/s - A d||_2 <= inner_tol ||r/s||_2 (checked every ``check_every`` sweeps) or after
+    ``max_inner`` sweeps; then x += s d. Returns MAXSWEEPS when ``max_sweeps`` inner sweeps
+    are spent or an outer step does not reduce ||r||_2.
     """
     Lt32, invS32 = lam32
     f32 = np.float32
@@ -282,38 +340,35 @@ def ir_solve(g: Graph, b, tol, lam32, check_every=16, inner_tol=1e-4, max_sweeps
     bnorm = float(np.linalg.norm(b)) or 1.0
     info = Info(status=MAXSWEEPS)
     r = g.residual(b, x)
+    prev = np.inf
     while True:
         rn = float(np.linalg.norm(r))
         info.rel_res2, info.res_inf = rn / bnorm, float(np.abs(r).max())
         if info.rel_res2 <= tol:
             info.status = OK
             return x, info
-        if info.sweeps >= max_sweeps:
+        if info.sweeps >= max_sweeps or not rn < prev:
             return x, info
+        prev = rn
         s = float(np.abs(r).max())
-        r32 = (r / s).astype(f32)
+        rs = r / s
+        r32 = rs.astype(f32)
         m = np.zeros(g.E, dtype=f32)
-        best, d_best, r_best, since = rn, None, None, 0
+        inner = 0
         while True:
             for _ in range(check_every):
                 M = r32 + np.bincount(g.dst, weights=m, minlength=g.n).astype(f32)
                 d = M * invS32
                 back = np.where(g.rev >= 0, m[np.maximum(g.rev, 0)], f32(0))
                 m = (Lt32 * (M[g.src] - back)).astype(f32)
-                info.sweeps += 1
-            rt = b - g.matvec(x + s * d.astype(np.float64))
-            nt = float(np.linalg.norm(rt))
-            if nt < best:
-                best, d_best, r_best, since = nt, d.copy(), rt, 0
-            else:
-                since += 1
-            if (best <= inner_tol * rn or best / bnorm <= tol or
-                    (d_best is not None and since >= patience) or info.sweeps >= max_sweeps):
+            inner += check_every
+            info.sweeps += check_every
+            res = np.linalg.norm(rs - g.matvec(d.astype(np.float64)))
+            if (res <= inner_tol * np.linalg.norm(rs) or inner >= max_inner or
+                    info.sweeps >= max_sweeps):
                 break
-        if d_best is None:
-            return x, info
-        x = x + s * d_best.astype(np.float64)
-        r = r_best
+        x = x + s * d.astype(np.float64)
+        r = g.residual(b, x)
         info.outer_iters += 1
 
 
@@ -372,15 +427,13 @@ def grid_colour4(nx, ny=None):
     return ((ix % 2) + 2 * (iy % 2)).astype(np.uint8)
 
 
-def smooth_coloured(g: Graph, b, x, mu, colour, lam=None, m_state=None, Lt_state=None):
-    """Algorithm 3 with red-black sweeps: e^mu = the read-offs of the mu-th red-black sweep.
-
-    ``lam = (Lt*, S*)``: mean-only with precomputed Lambda~; otherwise joint from
-    ``Lt_state`` (zero if None). ``m_state``: warm mean messages. Returns (x_new, Lt, m).
-    """
+def smooth_coloured(g: Graph, b, x, mu, colour, lam=None):
+    """Algorithm 3 with coloured sweeps from zero messages: e^mu = the read-offs of the
+    mu-th coloured sweep. ``lam = (Lt*, S*)``: mean-only with the converged precision
+    messages frozen; otherwise joint. Returns x + e^mu."""
     r = g.residual(b, x)
-    m = np.zeros(g.E) if m_state is None else m_state.copy()
-    Lt = (np.zeros(g.E) if Lt_state is None else Lt_state.copy()) if lam is None else lam[0]
+    m = np.zeros(g.E)
+    Lt = np.zeros(g.E) if lam is None else lam[0]
     for _ in range(mu):
         e, Lt, m = sweep_coloured(g, r, Lt, m, colour, lambda_fixed=lam)
-    return x + e, Lt, m
+    return x + e

@@ -58,26 +58,30 @@ def rbgs(g: _g.Graph, b, x, n, sweeps):
 
 
 class Hierarchy:
-    """Per-level oracle state: graphs, grid sides, precomputed Lambda~ and warm messages.
+    """Per-level oracle state: graphs, grid sides and precomputed precision messages.
 
-    smoother: "rbgs" (red-black Gauss-Seidel) or "gabp" (Algorithm 3) with
-    gabp_mode "joint" | "precomp", schedule "flood" | "redblack" | "colour4" | "lines" |
-    "lines_alt" and
-    warm "reset" | "all" (mean messages -- and, for point GaBP in joint mode, precision
-    messages -- carried between calls). "lines" is the two-layer region iteration on the
-    grid's rows and columns (Algorithm 2 with the partition of Fig. two_layers_network, line
-    GaBP) in the flood schedule; "lines_alt" updates all rows, then all columns.
+    smoother: "rbgs" (red-black Gauss-Seidel) or "gabp" (Algorithm 3, messages restarted
+    from zero at every call) with gabp_mode "joint" (precision messages recomputed every
+    sweep), "precomp" (the converged precision messages frozen) or "seq" (the precision
+    messages of the smoother's own sweeps precomputed once: the same iterates as "joint"),
+    and schedule "flood" | "redblack" | "colour4" | "lines" | "lines_alt". "lines" is the
+    two-layer region iteration on the grid's rows and columns (Algorithm 2 with the
+    partition of Fig. two_layers_network, line GaBP) in the flood schedule; "lines_alt"
+    updates all rows, then all columns.
     """
 
     def __init__(self, csrs, smoother="gabp", nu1=2, nu2=2, gabp_mode="precomp",
-                 warm="reset", tol_lambda=1e-14, max_lambda_sweeps=10000, schedule="flood"):
+                 tol_lambda=1e-14, max_lambda_sweeps=10000, schedule="flood"):
         self.graphs = [_g.Graph.from_csr(a) for a in csrs]
         self.sides = [int(round(np.sqrt(a.n))) for a in csrs]
         self.smoother, self.nu1, self.nu2 = smoother, nu1, nu2
-        self.gabp_mode, self.warm, self.schedule = gabp_mode, warm, schedule
+        self.gabp_mode, self.schedule = gabp_mode, schedule
         self.lam = [None] * len(csrs)
+        self.seq = [None] * len(csrs)
         self.rgs = None
         if smoother == "gabp" and schedule in ("lines", "lines_alt"):
+            if gabp_mode == "seq":
+                raise ValueError("per-sweep precision messages are built for point schedules")
             self.rgs = [_rg.RegionGraph(a, _rg.grid_lines(s, s))
                         for a, s in zip(csrs[:-1], self.sides[:-1])]
             self.groups = [None if schedule == "lines" else _rg.line_groups(s, s)
@@ -91,9 +95,17 @@ class Hierarchy:
             for l, g in enumerate(self.graphs[:-1]):
                 Lt, S, _ = _g.lambda_phase(g, tol_lambda, max_lambda_sweeps)
                 self.lam[l] = (Lt, S)
-        self.m_state = [None] * len(csrs)
-        self.Lt_state = [None] * len(csrs)
+        elif smoother == "gabp" and gabp_mode == "seq":
+            for l, g in enumerate(self.graphs[:-1]):
+                self.seq[l] = _g.lambda_sequence(g, max(nu1, nu2, 1), self._colour(l))
         self.coarse = np.linalg.inv(self.graphs[-1].dense())
+
+    def _colour(self, l):
+        if self.schedule == "redblack":
+            return _g.grid_colour(self.sides[l])
+        if self.schedule == "colour4":
+            return _g.grid_colour4(self.sides[l])
+        return None
 
     def _smooth(self, l, b, x, nu):
         g = self.graphs[l]
@@ -101,38 +113,14 @@ class Hierarchy:
             return x
         if self.smoother == "rbgs":
             return rbgs(g, b, x, self.sides[l], nu)
-        warm = self.warm == "all"
-        m0 = self.m_state[l] if warm else None
         if self.schedule in ("lines", "lines_alt"):
-            rg, grp = self.rgs[l], self.groups[l]
-            if warm and self.lam[l] is None:     # joint: the precision messages carry over too
-                L0 = self.Lt_state[l] if self.Lt_state[l] is not None else rg.zeros()
-                x, m, lam = _rg.smooth(rg, b, x, nu, m_state=m0, groups=grp, lam_state=L0)
-                self.Lt_state[l] = lam
-            else:
-                x, m = _rg.smooth(rg, b, x, nu, precomp=self.lam[l], m_state=m0, groups=grp)
-            if warm:
-                self.m_state[l] = m
-            return x
-        if self.schedule in ("redblack", "colour4"):
-            L0 = self.Lt_state[l] if warm else None
-            col = (_g.grid_colour if self.schedule == "redblack" else _g.grid_colour4)(self.sides[l])
-            x, Lt, m = _g.smooth_coloured(g, b, x, nu, col, lam=self.lam[l], m_state=m0,
-                                          Lt_state=L0)
-        elif self.lam[l] is None and warm:
-            r = g.residual(b, x)
-            Lt = np.zeros(g.E) if self.Lt_state[l] is None else self.Lt_state[l]
-            m = np.zeros(g.E) if m0 is None else m0
-            for _ in range(nu):
-                e, Lt, m, _, _ = _g.sweep(g, r, Lt, m)
-            x = x + e
-        else:
-            x, m = _g.smooth(g, b, x, nu, lam=self.lam[l], m_state=m0)
-            Lt = None
-        if warm:
-            self.m_state[l] = m
-            self.Lt_state[l] = Lt if self.lam[l] is None else None
-        return x
+            return _rg.smooth(self.rgs[l], b, x, nu, precomp=self.lam[l], groups=self.groups[l])
+        col = self._colour(l)
+        if self.seq[l] is not None:
+            return _g.smooth_seq(g, b, x, nu, self.seq[l], col)
+        if col is not None:
+            return _g.smooth_coloured(g, b, x, nu, col, lam=self.lam[l])
+        return _g.smooth(g, b, x, nu, lam=self.lam[l])
 
     def vcycle(self, b, x, l=0):
         """One V(nu1, nu2) cycle on level l; returns the new iterate."""

@@ -222,20 +222,14 @@ def solve(rg, b, tol, max_sweeps, check_every=1, precomp=None, groups=None):
     return x, MAXSWEEPS, max_sweeps, rel
 
 
-def smooth(rg, b, x, mu, precomp=None, m_state=None, groups=None, lam_state=None):
+def smooth(rg, b, x, mu, precomp=None, groups=None):
     """Algorithm 3 with the region iteration: x + (mu-th read-off of the sweeps on
-    A e = b - A x, from zero messages unless ``m_state`` (and, without ``precomp``,
-    ``lam_state``) carry the previous call's). Returns (x, m) or, with ``lam_state`` given,
-    (x, m, lam)."""
+    A e = b - A x from zero messages). ``precomp = (lam*, inverses)`` freezes the converged
+    precision messages."""
     r = rg.residual(b, x)
-    if precomp is not None:
-        lam = precomp[0]
-    else:
-        lam = rg.zeros() if lam_state is None else [v.copy() for v in lam_state]
-    m = rg.zeros() if m_state is None else [v.copy() for v in m_state]
+    lam = rg.zeros() if precomp is None else precomp[0]
+    m = rg.zeros()
     e = None
     for _ in range(mu):
         e, _, lam, m = sweep(rg, r, lam, m, lam_fixed=precomp, groups=groups)
-    if lam_state is not None:
-        return np.asarray(x, float) + e, m, lam
-    return np.asarray(x, float) + e, m
+    return np.asarray(x, float) + e

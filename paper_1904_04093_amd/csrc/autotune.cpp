@@ -171,8 +171,17 @@ int gabp_autotune(gabp_ctx* c, int32_t* check_every_out, int32_t* hints_out, hip
   bool& hints = f32 ? c->L.stream_hints32 : c->L.stream_hints;
   if (!cache_lookup(key, &t)) {
     int st;
-    if (f32 || c->opt.mode == GABP_MODE_PRECOMP)
+    const bool seq = c->opt.mode == GABP_MODE_PRECOMP_SEQ;
+    if (seq) {
+      if ((st = ensure_seq(c, 1, s)) != GABP_OK) return st;
+    } else if (f32 || c->opt.mode == GABP_MODE_PRECOMP) {
       if ((st = precompute(c, 0, s)) != GABP_OK) return st;
+    }
+    // the mean-only sweeps are timed with the converged Lt, or with the first sweep's Lt
+    const double* lam64 = seq ? c->seq.lamout[0] : c->pre[0].lamout;
+    const double* S64 = seq ? c->seq.S[0] : c->pre[0].S;
+    const float* lam32 = seq ? c->seq.lamout32[0] : c->pre[0].lamout32;
+    const float* invS32 = seq ? c->seq.invS32[0] : c->pre[0].invS32;
     const int64_t n = c->L.n;
     const int64_t R = c->batch ? c->batch->R : 1;
     // zero right-hand side and messages: timing only (nothing denormal, nothing non-finite)
@@ -205,16 +214,15 @@ int gabp_autotune(gabp_ctx* c, int32_t* check_every_out, int32_t* hints_out, hip
           GABP_HIP(batch_joint64(c, B, c->lam[par], B->msg64[par], c->lam[par ^ 1], B->msg64[par ^ 1], nullptr, s));
         else GABP_HIP(batch_mean64(c, B, B->msg64[par], B->msg64[par ^ 1], nullptr, s));
       } else if (f32) {
-        MeanArgs32 a{&c->L, c->pre[0].lamout32, c->pre[0].invS32, zero32, c->msg32[par],
-                     c->msg32[par ^ 1], nullptr, -1};
+        MeanArgs32 a{&c->L, lam32, invS32, zero32, c->msg32[par], c->msg32[par ^ 1], nullptr,
+                     -1};
         GABP_HIP(launch_mean_sweep32(a, s));
       } else if (c->opt.mode == GABP_MODE_JOINT) {
         SweepArgs a{&c->L, c->L.aT, zero64, c->lam[par], c->msg[par], c->lam[par ^ 1],
                     c->msg[par ^ 1], nullptr, -1};
         GABP_HIP(launch_joint_sweep(a, s));
       } else {
-        MeanArgs64 a{&c->L, c->pre[0].lamout, c->pre[0].S, zero64, c->msg[par], c->msg[par ^ 1],
-                     nullptr, -1};
+        MeanArgs64 a{&c->L, lam64, S64, zero64, c->msg[par], c->msg[par ^ 1], nullptr, -1};
         GABP_HIP(launch_mean_sweep64(a, s));
       }
       par ^= 1;

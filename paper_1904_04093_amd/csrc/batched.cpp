@@ -191,6 +191,8 @@ int gabp_setup_batched(gabp_ctx** out, int32_t nsys, const int32_t* sys_row_off,
   if (nrhs != 1 && nrhs != 2 && nrhs != 4) return fail(GABP_EINVAL, "nrhs must be 1, 2 or 4");
   if (opt && (opt->schedule == GABP_SCHED_LINES || opt->schedule == GABP_SCHED_LINES_ALT))
     return fail(GABP_ENOTSUPP, "batched solves use point schedules only");
+  if (opt && opt->mode == GABP_MODE_PRECOMP_SEQ)
+    return fail(GABP_ENOTSUPP, "batched solves take the joint or the converged precomputed Lt");
   // the whole CSR first, so that the block-diagonal scan below reads only inside col
   if (const int st = validate(n, nnz, rowptr, col, val, nullptr); st != GABP_OK) return st;
   if (sys_row_off[0] != 0 || sys_row_off[nsys] != n) return fail(GABP_EINVAL, "sys_row_off must run from 0 to n");

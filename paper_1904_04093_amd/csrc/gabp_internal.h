@@ -34,8 +34,8 @@ struct GraphCache;
 struct LineLayout;
 constexpr int kSlice = 64;      // rows per slice = wavefront size on CDNA
 constexpr int kBlock = 256;     // threads per block for row kernels (4 slices)
-constexpr int kRedBlock = 256;
-constexpr int kRevSelf16 = -32768;   // classed rev16: the slot is its own reverse  // threads per block for reductions
+constexpr int kRedBlock = 256;      // threads per block for reductions
+constexpr int kRevSelf16 = -32768;  // classed rev16: the slot is its own reverse
 constexpr int kMaxColours = 8;  // colour classes of the coloured schedule
 
 struct Precomp {
@@ -45,6 +45,18 @@ struct Precomp {
   double* S = nullptr;         // [n] Sigma*_j
   float* lamout32 = nullptr;   // [epad] FP32 copy of lamout
   float* invS32 = nullptr;     // [n] FP32 of 1/Sigma* (computed in FP64, rounded once)
+};
+
+// Precision messages of the first sweeps after a message reset (mode GABP_MODE_PRECOMP_SEQ).
+// They do not depend on the right-hand side, so a smoother that restarts from zero messages
+// needs exactly these at every call; entry s - 1 holds what sweep s uses.
+struct SeqPrecomp {
+  bool valid = false;            // the stored entries belong to the current values of A
+  int depth = 0;                 // entries computed
+  std::vector<double*> lamout;   // [epad + 1] Lt sent in sweep s, at the sender's slot (j,i)
+  std::vector<double*> S;        // [n] Sigma_j of sweep s's read-off
+  std::vector<float*> lamout32;  // FP32 copies (rounded once from FP64)
+  std::vector<float*> invS32;    // FP32 of 1 / Sigma_j (computed in FP64)
 };
 
 struct Layout {
@@ -88,6 +100,7 @@ struct Layout {
   int32_t* perm = nullptr;            // [nlanes] or null
   int32_t* lane_of_row_d = nullptr;   // [n] lane of each row, the inverse of perm, or null
   std::vector<int32_t> lane_of_row;   // host copy of the inverse (empty: identity)
+  uint64_t hash = 0;                  // of the slot and lane layout (checkpoint check)
 };
 
 }  // namespace gabp
@@ -103,6 +116,9 @@ struct gabp_ctx {
   int parity = 0;
   int parity32 = 0;
   gabp::Precomp pre[2];       // [0] A, [1] A^T
+  gabp::SeqPrecomp seq;       // per-sweep Lt of A (mode GABP_MODE_PRECOMP_SEQ)
+  int seq_pos64 = 0;          // sweeps since the last message reset, FP64 / FP32 messages
+  int seq_pos32 = 0;
   // work vectors
   double* r = nullptr;        // [n]
   double* r2 = nullptr;       // [n]
@@ -154,6 +170,9 @@ int smooth_from(gabp_ctx* c, const double* b, double* x, int mu, bool r_ready, h
 
 // Lt phase of the context (T = 1: for A^T), computed once and cached (solve.cpp)
 int precompute(gabp_ctx* c, int T, hipStream_t s);
+// per-sweep Lt of the first `depth` sweeps after a reset (mode PRECOMP_SEQ, solve.cpp)
+int ensure_seq(gabp_ctx* c, int depth, hipStream_t s);
+void free_seq(gabp_ctx* c);
 
 // ---- kernel launchers (kernels.hip) ----
 struct SweepArgs {
@@ -205,6 +224,12 @@ hipError_t launch_lambda_sweep(const Layout* L, const double* coef, const double
                                hipStream_t s);
 hipError_t launch_lambda_finalize(const Layout* L, const double* coef, const double* lam_in,
                                   Precomp* P, hipStream_t s);
+// One Lt-only sweep over the lanes of colour class `colour` (-1: all, flood), in place when
+// lam_in == lam_out: Sigma_j -> S[j], invS32[j]; every Lt_ji sent -> lam_out[rev p] and, at
+// the sender's slot p, lamout[p] and lamout32[p]
+hipError_t launch_lambda_step(const Layout* L, const double* coef, const double* lam_in,
+                              double* lam_out, double* lamout, float* lamout32, double* S,
+                              float* invS32, int colour, hipStream_t s);
 
 // r = b - A_eff x_eff, x_eff = x (+ scale[0] * dx if dx); writes r (if r) and block
 // partials; then reduces them into red[0..2].
@@ -230,6 +255,11 @@ hipError_t launch_axpy32(double* x, const float* d, const double* scale, int64_t
 hipError_t launch_axpy64(double* x, const double* d, int64_t n, hipStream_t s);
 hipError_t launch_update_values(const Layout* L, const double* csr_val, int* flag,
                                 hipStream_t s);
+// CSR-order copy of the message state (see gabp_get_messages); lam_outgoing: lam is a
+// sender-slot array (precomputed Lt), read at the reverse slot
+hipError_t launch_gather_messages(const Layout* L, const double* lam, bool lam_outgoing,
+                                  const double* msg, const float* msg32, double* out_lam,
+                                  double* out_msg, hipStream_t s);
 hipError_t launch_entry_grad(const Layout* L, const double* lam, const double* x, double* G,
                              hipStream_t s);
 hipError_t launch_param_reduce(int32_t nparam, const int32_t* jptr, const int32_t* jnnz,

@@ -354,6 +354,39 @@ __global__ __launch_bounds__(kBlock) void k_lambda_fin(
   invS32[j] = static_cast<float>(1.0 / S);
 }
 
+// One Lt-only sweep that keeps what it computes: the node precisions of this sweep's
+// read-off and the messages it sends, at the sender's slot (per-sweep precompute). Lanes
+// [t0, t1): all (flood, lam_in != lam_out) or one colour class (in place). Runs once per
+// matrix, so it is the plain two-pass form.
+__global__ __launch_bounds__(kBlock) void k_lambda_step(
+    int t1, const int32_t* __restrict__ sptr, const int32_t* __restrict__ rev,
+    const double* __restrict__ coef, const double* __restrict__ diag, const double* lam_in,
+    double* lam_out, double* __restrict__ lamout, float* __restrict__ lamout32,
+    double* __restrict__ Sout, float* __restrict__ invS32, int t0,
+    const int32_t* __restrict__ perm) {
+  const int t = t0 + static_cast<int>(blockIdx.x) * kBlock + static_cast<int>(threadIdx.x);
+  if (t >= t1) return;
+  const int j = row_of(perm, t);
+  if (j < 0) return;
+  int w;
+  const int p0 = row_base(sptr, t, &w);
+  double S = diag[j];
+  for (int k = 0; k < w; ++k) {
+    const int p = p0 + 64 * k;
+    S = fma(lam_in[p], coef[p], S);
+  }
+  Sout[j] = S;
+  invS32[j] = static_cast<float>(1.0 / S);
+  for (int k = 0; k < w; ++k) {
+    const int p = p0 + 64 * k;
+    const double l = lam_in[p], a = coef[p];
+    const double L = -a / (S - l * a);
+    lamout[p] = L;
+    lamout32[p] = static_cast<float>(L);
+    lam_out[rev[p]] = L;
+  }
+}
+
 // ---------------------------------------------------------------------------------------
 // Residual r = b - A x (coef_row = val) or b - A^T x (coef_row = aT), optionally at
 // x + scale * dx, with per-block partial norms. Threads take rows in row order, also for a
@@ -530,6 +563,23 @@ __global__ void k_update_diag(int n, const int32_t* __restrict__ dsrc,
   const double d = csr[dsrc[j]];
   diag[j] = d;
   if (!(d != 0.0) || !isfinite(d)) atomicOr(bad, 1);
+}
+
+// Message state in setup CSR order: slot p = (j,i) holds the message i -> j, which belongs
+// to CSR entry (j,i) = val_src[p]. lam_outgoing: lam holds the sender-slot copy of the
+// precomputed Lt (the value at p is the one j sends), so the incoming one is lam[rev p].
+__global__ void k_gather_messages(int64_t epad, const int32_t* __restrict__ vsrc,
+                                  const int32_t* __restrict__ rev, const double* __restrict__ lam,
+                                  int lam_outgoing, const double* __restrict__ msg,
+                                  const float* __restrict__ msg32, double* __restrict__ out_lam,
+                                  double* __restrict__ out_msg) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < epad;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t e = vsrc[p];
+    if (e < 0) continue;
+    if (out_lam) out_lam[e] = lam ? (lam_outgoing ? lam[rev[p]] : lam[p]) : 0.0;
+    if (out_msg) out_msg[e] = msg ? msg[p] : (msg32 ? static_cast<double>(msg32[p]) : 0.0);
+  }
 }
 
 __global__ void k_entry_grad(int64_t nnz, const int32_t* __restrict__ row,
@@ -773,6 +823,19 @@ hipError_t launch_lambda_finalize(const Layout* Lp, const double* coef, const do
   return hipGetLastError();
 }
 
+hipError_t launch_lambda_step(const Layout* Lp, const double* coef, const double* lam_in,
+                              double* lam_out, double* lamout, float* lamout32, double* S,
+                              float* invS32, int colour, hipStream_t s) {
+  const Layout& L = *Lp;
+  int t0, t1;
+  lane_range(L, colour, &t0, &t1);
+  if (t1 <= t0) return hipSuccess;
+  k_lambda_step<<<nblocks(t1 - t0), kBlock, 0, s>>>(t1, L.sptr, L.rev, coef, L.diag, lam_in,
+                                                    lam_out, lamout, lamout32, S, invS32, t0,
+                                                    L.perm);
+  return hipGetLastError();
+}
+
 hipError_t launch_residual(const Layout* Lp, const double* coef_row, const double* b,
                            const double* x, const float* dx, const double* scale, double* r,
                            double* partials, int32_t nred, double* red, hipStream_t s,
@@ -850,6 +913,19 @@ hipError_t launch_update_values(const Layout* Lp, const double* csr, int* bad, h
   k_update_slots<<<grid_for(L.epad), 256, 0, s>>>(L.epad, L.val_src, L.aT_src, csr, L.val,
                                                   L.aT);
   k_update_diag<<<nblocks(L.n), 256, 0, s>>>(L.n, L.diag_src, csr, L.diag, bad);
+  return hipGetLastError();
+}
+hipError_t launch_gather_messages(const Layout* Lp, const double* lam, bool lam_outgoing,
+                                  const double* msg, const float* msg32, double* out_lam,
+                                  double* out_msg, hipStream_t s) {
+  const Layout& L = *Lp;
+  hipError_t e;
+  if (out_lam && (e = launch_fill64(out_lam, L.nnz, 0.0, s)) != hipSuccess) return e;
+  if (out_msg && (e = launch_fill64(out_msg, L.nnz, 0.0, s)) != hipSuccess) return e;
+  if (L.epad <= 0) return hipSuccess;
+  k_gather_messages<<<grid_for(L.epad), 256, 0, s>>>(L.epad, L.val_src, L.rev, lam,
+                                                     lam_outgoing ? 1 : 0, msg, msg32, out_lam,
+                                                     out_msg);
   return hipGetLastError();
 }
 hipError_t launch_entry_grad(const Layout* Lp, const double* lam, const double* x, double* G,

@@ -58,7 +58,6 @@ void gabp_default_options(gabp_options* o) {
   o->check_every = 16;
   o->tol_lambda = 1e-14;
   o->max_lambda_sweeps = 100000;
-  o->warm = GABP_WARM_RESET_M;
   o->ir_inner_tol = 1e-4;
   o->ir_max_inner = 1000000;
   o->schedule = GABP_SCHED_FLOOD;
@@ -79,14 +78,17 @@ int gabp_setup(gabp_ctx** out, int32_t n, int64_t nnz, const int32_t* rowptr,
   gabp_default_options(&o);
   if (opt) o = *opt;
   if (o.check_every < 1 || o.max_lambda_sweeps < 0 || o.tol_lambda < 0 ||
-      (o.mode != GABP_MODE_JOINT && o.mode != GABP_MODE_PRECOMP) ||
+      (o.mode < GABP_MODE_JOINT || o.mode > GABP_MODE_PRECOMP_SEQ) ||
       (o.precision != GABP_F64 && o.precision != GABP_F32_IR) ||
       (o.schedule < GABP_SCHED_FLOOD || o.schedule > GABP_SCHED_LINES_ALT) ||
-      (o.warm != GABP_WARM_RESET_M && o.warm != GABP_WARM_ALL) || o.ir_max_inner < 1 ||
+      o.ir_max_inner < 1 ||
       !(o.ir_inner_tol > 0.0))
     return fail(GABP_EINVAL, "invalid options");
   if (o.schedule == GABP_SCHED_REDBLACK && !colour)
     return fail(GABP_EINVAL, "red-black schedule needs node colours");
+  if (o.mode == GABP_MODE_PRECOMP_SEQ &&
+      (o.schedule == GABP_SCHED_LINES || o.schedule == GABP_SCHED_LINES_ALT))
+    return fail(GABP_ENOTSUPP, "per-sweep precision messages are built for point schedules");
   int32_t inject_at = -1;
   bool poison = false;
   if (const char* fi = std::getenv("GABP_FAULT_INJECT")) {
@@ -328,6 +330,19 @@ int gabp_setup(gabp_ctx** out, int32_t n, int64_t nnz, const int32_t* rowptr,
     for (size_t q = 0; q < cstart.size(); ++q)
       L.cslot[q] = static_cast<int32_t>(sptr64[cstart[q] / kSlice]);
   }
+  {   // FNV-1a over the slot and lane layout: two contexts share message positions iff equal
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&h](int64_t v) {
+      for (int q = 0; q < 8; ++q) {
+        h ^= static_cast<uint64_t>(v >> (8 * q)) & 0xffu;
+        h *= 1099511628211ull;
+      }
+    };
+    mix(n); mix(epad); mix(nlanes); mix(ncolours);
+    for (int32_t q = 0; q <= nslices; ++q) mix(sptr64[q]);
+    for (int32_t t : lane_of_row) mix(t);
+    L.hash = h;
+  }
   for (int q = 0; q < 2; ++q) {
     AL(c->lam[q], epad + 1);
     AL(c->msg[q], epad + 1);
@@ -376,6 +391,7 @@ int gabp_update_values(gabp_ctx* c, const double* val, hipStream_t stream) {
   // recorded blocks read the coefficient and precomputed-Lt buffers in place, so they stay
   // valid; only the precomputed Lt must be recomputed for the new values
   c->pre[0].valid = c->pre[1].valid = false;
+  c->seq.valid = false;
   if (hbad) return fail(GABP_EZERODIAG, "zero or non-finite diagonal in updated values");
   return GABP_OK;
 }
@@ -392,6 +408,7 @@ void gabp_destroy(gabp_ctx* c) {
     F(c->lam[q]); F(c->msg[q]); F(c->msg32[q]);
     F(c->pre[q].lamout); F(c->pre[q].S); F(c->pre[q].lamout32); F(c->pre[q].invS32);
   }
+  free_seq(c);
   F(c->r); F(c->r2); F(c->e); F(c->bsol); F(c->xsol); F(c->r32); F(c->d32); F(c->dbest32); F(c->partials); F(c->red); F(c->lmax);
   if (c->host_red) (void)hipHostFree(c->host_red);
   if (c->batch) {

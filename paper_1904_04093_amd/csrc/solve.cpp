@@ -16,7 +16,63 @@
 
 using namespace gabp;
 
+namespace gabp {
+
+void free_seq(gabp_ctx* c) {
+  SeqPrecomp& Q = c->seq;
+  for (double* p : Q.lamout) (void)hipFree(p);
+  for (double* p : Q.S) (void)hipFree(p);
+  for (float* p : Q.lamout32) (void)hipFree(p);
+  for (float* p : Q.invS32) (void)hipFree(p);
+  Q = SeqPrecomp{};
+}
+
+// Lt-only sweeps from zero messages in the context's schedule, keeping what each sweep
+// computes. Entries already allocated keep their addresses (recorded graphs read them in
+// place); the joint-mode Lt buffers, unused in this mode, hold the running Lt state.
+int ensure_seq(gabp_ctx* c, int depth, hipStream_t s) {
+  SeqPrecomp& Q = c->seq;
+  if (Q.valid && Q.depth >= depth) return GABP_OK;
+  depth = std::max(depth, Q.depth);
+  const Layout& L = c->L;
+  const int64_t E = L.epad + 1;
+  while (static_cast<int>(Q.lamout.size()) < depth) {
+    double* d = nullptr;
+    float* f = nullptr;
+    GABP_HIP(hipMalloc(reinterpret_cast<void**>(&d), E * sizeof(double)));
+    Q.lamout.push_back(d);
+    GABP_HIP(hipMalloc(reinterpret_cast<void**>(&d), L.n * sizeof(double)));
+    Q.S.push_back(d);
+    GABP_HIP(hipMalloc(reinterpret_cast<void**>(&f), E * sizeof(float)));
+    Q.lamout32.push_back(f);
+    GABP_HIP(hipMalloc(reinterpret_cast<void**>(&f), L.n * sizeof(float)));
+    Q.invS32.push_back(f);
+  }
+  GABP_HIP(launch_fill64(c->lam[0], E, 0.0, s));
+  GABP_HIP(launch_fill64(c->lam[1], E, 0.0, s));
+  const bool coloured = c->opt.schedule == GABP_SCHED_REDBLACK;
+  int par = 0;
+  for (int k = 0; k < depth; ++k) {
+    if (coloured) {
+      for (int col = 0; col < L.ncolours; ++col)
+        GABP_HIP(launch_lambda_step(&L, L.aT, c->lam[0], c->lam[0], Q.lamout[k], Q.lamout32[k],
+                                    Q.S[k], Q.invS32[k], col, s));
+    } else {
+      GABP_HIP(launch_lambda_step(&L, L.aT, c->lam[par], c->lam[par ^ 1], Q.lamout[k],
+                                  Q.lamout32[k], Q.S[k], Q.invS32[k], -1, s));
+      par ^= 1;
+    }
+  }
+  Q.depth = depth;
+  Q.valid = true;
+  return GABP_OK;
+}
+
+}  // namespace gabp
+
 namespace {
+
+inline bool seq_mode(const gabp_ctx* c) { return c->opt.mode == GABP_MODE_PRECOMP_SEQ; }
 
 struct Norms {
   double r2, rinf, b2;
@@ -137,8 +193,16 @@ int sweep64(gabp_ctx* c, int T, const double* b, double* x, hipStream_t s) {
       }
     }
   } else {
-    const Precomp& P = c->pre[T];
-    MeanArgs64 a{&c->L, P.lamout, P.S, b, nullptr, nullptr, x, -1, fresh};
+    const double* lo = c->pre[T].lamout;
+    const double* Sx = c->pre[T].S;
+    if (seq_mode(c)) {   // sweep seq_pos64 + 1 after the reset
+      if (T != 0 || c->seq_pos64 >= c->seq.depth)
+        return fail(GABP_EINVAL, "per-sweep precision messages missing for this sweep");
+      lo = c->seq.lamout[c->seq_pos64];
+      Sx = c->seq.S[c->seq_pos64];
+      ++c->seq_pos64;
+    }
+    MeanArgs64 a{&c->L, lo, Sx, b, nullptr, nullptr, x, -1, fresh};
     if (!rb) {
       a.msg_in = c->msg[c->parity];
       a.msg_out = c->msg[c->parity ^ 1];
@@ -159,10 +223,18 @@ int sweep64(gabp_ctx* c, int T, const double* b, double* x, hipStream_t s) {
 
 int sweep32(gabp_ctx* c, int T, const float* b, float* x, hipStream_t s) {
   if (c->lines) return line_sweep32(c, T, b, x, s);
-  const Precomp& P = c->pre[T];
+  const float* lo = c->pre[T].lamout32;
+  const float* iS = c->pre[T].invS32;
+  if (seq_mode(c)) {
+    if (T != 0 || c->seq_pos32 >= c->seq.depth)
+      return fail(GABP_EINVAL, "per-sweep precision messages missing for this sweep");
+    lo = c->seq.lamout32[c->seq_pos32];
+    iS = c->seq.invS32[c->seq_pos32];
+    ++c->seq_pos32;
+  }
   const int fresh = c->fresh32 ? 0 : -1;   // first sweep after a reset
   c->fresh32 = false;
-  MeanArgs32 a{&c->L, P.lamout32, P.invS32, b, nullptr, nullptr, x, -1, fresh};
+  MeanArgs32 a{&c->L, lo, iS, b, nullptr, nullptr, x, -1, fresh};
   if (c->opt.schedule != GABP_SCHED_REDBLACK) {
     a.msg_in = c->msg32[c->parity32];
     a.msg_out = c->msg32[c->parity32 ^ 1];
@@ -186,6 +258,7 @@ int sweep32(gabp_ctx* c, int T, const float* b, float* x, hipStream_t s) {
 // a first sweep (flood, or a colour class in place) that read a stale slot would show it.
 int reset_messages64(gabp_ctx* c, hipStream_t s) {
   c->parity = 0;
+  c->seq_pos64 = 0;
   if (c->lines) return line_reset64(c, s);
   c->fresh64 = true;
   if (c->poison_outputs) {
@@ -197,6 +270,7 @@ int reset_messages64(gabp_ctx* c, hipStream_t s) {
 
 int reset_messages32(gabp_ctx* c, hipStream_t s) {
   c->parity32 = 0;
+  c->seq_pos32 = 0;
   if (c->lines) return line_reset32(c, s);
   c->fresh32 = true;
   if (c->poison_outputs && c->msg32[0])
@@ -349,7 +423,10 @@ int solve_ir(gabp_ctx* c, int T, const double* b, double* x, double tol, int max
       return GABP_OK;
     }
     if (total >= max_sweeps) break;
-    GABP_HIP(launch_copy64(scale, c->red + 3, 1, s));   // s = ||r||_inf
+    // s = ||r||_inf of the accepted residual (the device copy of max|r| belongs to the
+    // last trial, which need not be the one kept); host_red[7] is read by no check
+    c->host_red[7] = nm.rinf;
+    GABP_HIP(hipMemcpyAsync(scale, c->host_red + 7, sizeof(double), hipMemcpyHostToDevice, s));
     GABP_HIP(launch_cast_scaled(c->r32, buf[ir], scale, n, s));
     if ((st = prep_rhs32(c, c->r32, s)) != GABP_OK) return st;
     if ((st = reset_messages32(c, s)) != GABP_OK) return st;
@@ -433,6 +510,9 @@ int solve_any(gabp_ctx* c, int T, const double* b, double* x, double tol, int32_
               gabp_info* info, hipStream_t s) {
   if (!c || !b || !x) return fail(GABP_EINVAL, "NULL argument");
   if (max_sweeps < 1 || !(tol >= 0.0)) return fail(GABP_EINVAL, "max_sweeps < 1 or tol < 0");
+  if (seq_mode(c))
+    return fail(GABP_ENOTSUPP, "solves need the precision messages of every sweep: use the "
+                               "joint or the converged precomputed mode");
   GABP_HIP(hipSetDevice(c->device));
   const int64_t n = c->L.n;
   if (!c->bsol) {
@@ -484,10 +564,17 @@ int gabp_sweeps(gabp_ctx* c, const double* b, double* x, int32_t sweeps, int32_t
   if (sweeps < 1) return fail(GABP_EINVAL, "sweeps must be >= 1");
   const int T = transposed ? 1 : 0;
   int st;
+  if (seq_mode(c) && T != 0)
+    return fail(GABP_ENOTSUPP, "per-sweep precision messages are kept for A only");
   if (c->opt.precision == GABP_F32_IR) {
     // FP32 mean-only sweeps on fp32(b) with the FP32 copy of the precomputed Lt
-    if ((st = ensure_pre(c, T, s)) != GABP_OK) return st;
     const bool fresh = !has_msg32(c);
+    if (seq_mode(c)) {
+      st = ensure_seq(c, (reset || fresh ? 0 : c->seq_pos32) + sweeps, s);
+    } else {
+      st = ensure_pre(c, T, s);
+    }
+    if (st != GABP_OK) return st;
     if ((st = ensure_msg32(c, s)) != GABP_OK) return st;
     GABP_HIP(launch_cast_scaled(c->r32, b, nullptr, c->L.n, s));
     if ((st = prep_rhs32(c, c->r32, s)) != GABP_OK) return st;
@@ -499,6 +586,8 @@ int gabp_sweeps(gabp_ctx* c, const double* b, double* x, int32_t sweeps, int32_t
     return GABP_OK;
   }
   if (c->opt.mode == GABP_MODE_PRECOMP && (st = ensure_pre(c, T, s)) != GABP_OK) return st;
+  if (seq_mode(c) && (st = ensure_seq(c, (reset ? 0 : c->seq_pos64) + sweeps, s)) != GABP_OK)
+    return st;
   if (reset && (st = reset_messages64(c, s)) != GABP_OK) return st;
   if ((st = prep_rhs64(c, b, s)) != GABP_OK) return st;
   for (int i = 0; i < sweeps; ++i)
@@ -521,23 +610,22 @@ namespace gabp {
 int smooth_from(gabp_ctx* c, const double* b, double* x, int mu, bool r_ready, hipStream_t s) {
   int st;
   const int64_t n = c->L.n;
-  const bool warm = c->opt.warm == GABP_WARM_ALL;
   if (!r_ready && (st = residual(c, 0, b, x, nullptr, nullptr, c->r, s, false)) != GABP_OK)
     return st;
+  if (seq_mode(c) && (st = ensure_seq(c, mu, s)) != GABP_OK) return st;
   if (c->opt.precision == GABP_F32_IR) {
-    if ((st = ensure_pre(c, 0, s)) != GABP_OK) return st;
-    const bool fresh = !has_msg32(c);
+    if (!seq_mode(c) && (st = ensure_pre(c, 0, s)) != GABP_OK) return st;
     if ((st = ensure_msg32(c, s)) != GABP_OK) return st;
     GABP_HIP(launch_cast_scaled(c->r32, c->r, nullptr, n, s));
     if ((st = prep_rhs32(c, c->r32, s)) != GABP_OK) return st;
-    if ((!warm || fresh) && (st = reset_messages32(c, s)) != GABP_OK) return st;
+    if ((st = reset_messages32(c, s)) != GABP_OK) return st;
     for (int i = 0; i < mu; ++i)
       if ((st = sweep32(c, 0, c->r32, i == mu - 1 ? c->d32 : nullptr, s)) != GABP_OK) return st;
     GABP_HIP(launch_axpy32(x, c->d32, nullptr, n, s));
     return GABP_OK;
   }
   if (c->opt.mode == GABP_MODE_PRECOMP && (st = ensure_pre(c, 0, s)) != GABP_OK) return st;
-  if (!warm && (st = reset_messages64(c, s)) != GABP_OK) return st;
+  if ((st = reset_messages64(c, s)) != GABP_OK) return st;
   if ((st = prep_rhs64(c, c->r, s)) != GABP_OK) return st;
   for (int i = 0; i < mu; ++i)
     if ((st = sweep64(c, 0, c->r, i == mu - 1 ? c->e : nullptr, s)) != GABP_OK) return st;
@@ -579,14 +667,37 @@ int gabp_adjoint_scatter(gabp_ctx* c, const double* lam, const double* x, double
 
 // ---- checkpoints ----------------------------------------------------------------------
 namespace {
+// The header names what the message positions depend on (layout, schedule, mode,
+// precision), so a blob only loads into a context that lays its messages out the same way.
 struct StateHeader {
   uint64_t magic;
   int64_t n, epad;
   int32_t pre_valid[2], pre_sweeps[2];
   int32_t has32, pad;
+  uint64_t layout_hash;
+  int32_t schedule, mode, precision, seq_pos64, seq_pos32, pad2;
 };
-constexpr uint64_t kMagic = 0x6761627073743031ull;      // "gabpst01"
-constexpr uint64_t kLineMagic = 0x676162706c6e3031ull;  // "gabpln01"
+constexpr uint64_t kMagic = 0x6761627073743032ull;      // "gabpst02"
+constexpr uint64_t kLineMagic = 0x676162706c6e3032ull;  // "gabpln02"
+
+StateHeader make_header(const gabp_ctx* c, uint64_t magic, bool pre0, bool pre1, bool has32) {
+  StateHeader h{};
+  h.magic = magic;
+  h.n = c->L.n;
+  h.epad = c->L.epad;
+  h.pre_valid[0] = pre0;
+  h.pre_valid[1] = pre1;
+  h.pre_sweeps[0] = c->pre[0].sweeps;
+  h.pre_sweeps[1] = c->pre[1].sweeps;
+  h.has32 = has32;
+  h.layout_hash = c->L.hash;
+  h.schedule = c->opt.schedule;
+  h.mode = c->opt.mode;
+  h.precision = c->opt.precision;
+  h.seq_pos64 = c->seq_pos64;
+  h.seq_pos32 = c->seq_pos32;
+  return h;
+}
 
 // Line schedules: the header, then the arrays listed by line_state_arrays.
 int line_get_state(gabp_ctx* c, void* dst, size_t* bytes, hipStream_t s) {
@@ -605,8 +716,7 @@ int line_get_state(gabp_ctx* c, void* dst, size_t* bytes, hipStream_t s) {
     return GABP_OK;
   }
   if (*bytes < need) return fail(GABP_EINVAL, "state buffer too small");
-  StateHeader h{kLineMagic, c->L.n, c->L.epad, {pre[0], pre[1]},
-                {c->pre[0].sweeps, c->pre[1].sweeps}, has32, 0};
+  const StateHeader h = make_header(c, kLineMagic, pre[0], pre[1], has32);
   char* p = static_cast<char*>(dst);
   std::memcpy(p, &h, sizeof(h));
   p += sizeof(h);
@@ -657,8 +767,8 @@ int gabp_get_state(gabp_ctx* c, void* dst, size_t* bytes, hipStream_t s) {
     return GABP_OK;
   }
   if (*bytes < need) return fail(GABP_EINVAL, "state buffer too small");
-  StateHeader h{kMagic, L.n, L.epad, {c->pre[0].valid, c->pre[1].valid},
-                {c->pre[0].sweeps, c->pre[1].sweeps}, c->msg32[0] != nullptr, 0};
+  const StateHeader h = make_header(c, kMagic, c->pre[0].valid, c->pre[1].valid,
+                                    c->msg32[0] != nullptr);
   char* p = static_cast<char*>(dst);
   std::memcpy(p, &h, sizeof(h));
   p += sizeof(h);
@@ -698,8 +808,12 @@ int gabp_set_state(gabp_ctx* c, const void* src, size_t bytes, hipStream_t s) {
   StateHeader h;
   std::memcpy(&h, src, sizeof(h));
   const Layout& L = c->L;
-  if (h.magic != (c->lines ? kLineMagic : kMagic) || h.n != L.n || h.epad != L.epad)
-    return fail(GABP_EINVAL, "state was taken from a different layout or schedule");
+  if (h.magic != (c->lines ? kLineMagic : kMagic) || h.n != L.n || h.epad != L.epad ||
+      h.layout_hash != L.hash || h.schedule != c->opt.schedule || h.mode != c->opt.mode ||
+      h.precision != c->opt.precision)
+    return fail(GABP_EINVAL, "state was taken from a different layout, schedule or mode");
+  c->seq_pos64 = h.seq_pos64;
+  c->seq_pos32 = h.seq_pos32;
   if (c->lines)
     return line_set_state(c, h, static_cast<const char*>(src) + sizeof(h), bytes, s);
   const size_t E = static_cast<size_t>(L.epad + 1), N = static_cast<size_t>(L.n);
@@ -743,6 +857,39 @@ int gabp_set_state(gabp_ctx* c, const void* src, size_t bytes, hipStream_t s) {
     if ((st = put(c->msg32[0], E * sizeof(float)))) return st;
   }
   GABP_HIP(hipStreamSynchronize(s));
+  return GABP_OK;
+}
+
+int gabp_get_messages(gabp_ctx* c, double* lam, double* msg, hipStream_t s) {
+  if (!c) return fail(GABP_EINVAL, "NULL context");
+  if (c->lines) return fail(GABP_ENOTSUPP, "line schedules keep line messages, not edge messages");
+  if (c->batch) return fail(GABP_ENOTSUPP, "batched contexts keep one message set per rhs");
+  const double* L = nullptr;
+  bool outgoing = false;
+  const bool f32 = c->opt.precision == GABP_F32_IR;
+  if (c->opt.mode == GABP_MODE_JOINT && !f32) {
+    if (!c->fresh64) L = c->lam[c->parity];
+  } else if (seq_mode(c)) {
+    const int k = f32 ? c->seq_pos32 : c->seq_pos64;   // the Lt of sweep k is in use
+    if (k > 0) {
+      if (!c->seq.valid || k > c->seq.depth)
+        return fail(GABP_EINVAL, "per-sweep precision messages not computed");
+      L = c->seq.lamout[k - 1];
+      outgoing = true;
+    }
+  } else {
+    if (!c->pre[0].valid) return fail(GABP_EINVAL, "precision messages not computed yet");
+    L = c->pre[0].lamout;
+    outgoing = true;
+  }
+  const double* M = nullptr;
+  const float* M32 = nullptr;
+  if (f32) {
+    if (c->msg32[0] && !c->fresh32) M32 = c->msg32[c->parity32];
+  } else if (!c->fresh64) {
+    M = c->msg[c->parity];
+  }
+  GABP_HIP(launch_gather_messages(&c->L, L, outgoing, M, M32, lam, msg, s));
   return GABP_OK;
 }
 

@@ -19,10 +19,9 @@ LIB_PATH = os.path.join(_HERE, "libgabp.so")
 
 OK, MAXSWEEPS = 0, 1
 EINVAL, ENOMEM, EZERODIAG, ENUMERIC, EDEVICE, ENOTSUPP = -1, -2, -3, -4, -5, -6
-MODES = {"joint": 0, "precomp": 1}
+MODES = {"joint": 0, "precomp": 1, "seq": 2}
 PRECISIONS = {"f64": 0, "f32_ir": 1}
 SCHEDULES = {"flood": 0, "redblack": 1, "lines": 2, "lines_alt": 3}
-WARM = {"reset": 0, "all": 1}
 
 
 class GaBPError(RuntimeError):
@@ -34,7 +33,7 @@ class GaBPError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("tol_lambda", ctypes.c_double),
-                ("max_lambda_sweeps", ctypes.c_int32), ("warm", ctypes.c_int32),
+                ("max_lambda_sweeps", ctypes.c_int32),
                 ("ir_inner_tol", ctypes.c_double), ("ir_max_inner", ctypes.c_int32),
                 ("schedule", ctypes.c_int32), ("use_graphs", ctypes.c_int32),
                 ("grid_nx", ctypes.c_int32), ("grid_ny", ctypes.c_int32)]
@@ -75,6 +74,7 @@ _SIGS = {
     "gabp_get_state": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_size_t), _P]),
     "gabp_set_state": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P]),
     "gabp_residual_history": (ctypes.c_int, [_P, _P, _I32, _PI32]),
+    "gabp_get_messages": (ctypes.c_int, [_P, _P, _P, _P]),
     "gabp_layout_info": (ctypes.c_int, [_P, _PI32, _PI64, _PI64, _PI64, _PI32]),
     "gabp_copy_probe": (ctypes.c_int, [_P, _P, _I64, _P]),
     "gabp_autotune": (ctypes.c_int, [_P, _PI32, _PI32, _P]),
@@ -177,7 +177,7 @@ class Solver:
 
     def __init__(self, n, rowptr, col, val, rev=None, colour=None, *, mode="joint",
                  precision="f64", check_every=16, tol_lambda=1e-14,
-                 max_lambda_sweeps=100000, warm="reset", ir_inner_tol=1e-4,
+                 max_lambda_sweeps=100000, ir_inner_tol=1e-4,
                  ir_max_inner=1000000, schedule="flood", use_graphs=True, grid=None):
         lib = load()
         self._lib = lib
@@ -185,7 +185,7 @@ class Solver:
         lib.gabp_default_options(ctypes.byref(o))
         o.mode, o.precision = MODES[mode], PRECISIONS[precision]
         o.check_every, o.tol_lambda = int(check_every), float(tol_lambda)
-        o.max_lambda_sweeps, o.warm = int(max_lambda_sweeps), WARM[warm]
+        o.max_lambda_sweeps = int(max_lambda_sweeps)
         o.ir_inner_tol, o.ir_max_inner = float(ir_inner_tol), int(ir_max_inner)
         o.schedule = SCHEDULES[schedule]
         o.use_graphs = int(bool(use_graphs))
@@ -297,6 +297,16 @@ class Solver:
         buf = ctypes.create_string_buffer(blob, len(blob))
         _check(self._lib.gabp_set_state(self._h, buf, len(blob), _stream()))
 
+    def messages(self):
+        """(Lt, m) of the current message state in setup CSR order (device tensors of nnz
+        doubles; see gabp_get_messages)."""
+        import torch
+        lam = torch.empty(self.nnz, dtype=torch.float64, device="cuda")
+        msg = torch.empty(self.nnz, dtype=torch.float64, device="cuda")
+        _check(self._lib.gabp_get_messages(self._h, _dev(lam, self.nnz), _dev(msg, self.nnz),
+                                           _stream()))
+        return lam, msg
+
     def residual_history(self):
         """||r||_2 / ||b||_2 at every check of the last solve (numpy array)."""
         import numpy as np
@@ -328,13 +338,13 @@ class Solver:
 
 
 def _options(mode="joint", precision="f64", check_every=16, tol_lambda=1e-14,
-             max_lambda_sweeps=100000, warm="reset", ir_inner_tol=1e-4, ir_max_inner=1000000,
+             max_lambda_sweeps=100000, ir_inner_tol=1e-4, ir_max_inner=1000000,
              schedule="flood", use_graphs=True):
     o = Options()
     load().gabp_default_options(ctypes.byref(o))
     o.mode, o.precision = MODES[mode], PRECISIONS[precision]
     o.check_every, o.tol_lambda = int(check_every), float(tol_lambda)
-    o.max_lambda_sweeps, o.warm = int(max_lambda_sweeps), WARM[warm]
+    o.max_lambda_sweeps = int(max_lambda_sweeps)
     o.ir_inner_tol, o.ir_max_inner = float(ir_inner_tol), int(ir_max_inner)
     o.schedule = SCHEDULES[schedule]
     o.use_graphs = int(bool(use_graphs))

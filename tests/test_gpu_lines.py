@@ -149,24 +149,22 @@ def test_line_smoother_matches_oracle(B, kw):
         pc = (lam, invs)
     s = B.Solver.from_csr(a, schedule="lines_alt", grid=(nx, ny), **kw)
     for mu in (1, 2, 4):
-        want, _ = RG.smooth(rg, b, x0, mu, precomp=pc, groups=grp)
+        want = RG.smooth(rg, b, x0, mu, precomp=pc, groups=grp)
         xt = _cuda(x0)
         s.smooth(_cuda(b), xt, mu)
         assert _rel_inf(xt.cpu().numpy(), want) < TOL, mu
 
 
-@pytest.mark.parametrize("warm", ["reset", "all"])
 @pytest.mark.parametrize("mode", ["precomp", "joint"])
-def test_line_smoothed_v_cycles_match_oracle(B, mode, warm):
+def test_line_smoothed_v_cycles_match_oracle(B, mode):
     J = 5
     csrs = W.mg_hierarchy(J, kx=1.0, ky=0.2, peclet=1.0)
     sides = [int(round(np.sqrt(c.n))) for c in csrs]
     b = W.rng(503, 0).uniform(-1, 1, csrs[0].n)
     oracle = MG.Hierarchy(csrs, smoother="gabp", nu1=2, nu2=2, gabp_mode=mode,
-                          schedule="lines_alt", tol_lambda=0.0, max_lambda_sweeps=40,
-                          warm=warm)
+                          schedule="lines_alt", tol_lambda=0.0, max_lambda_sweeps=40)
     solvers = [B.Solver.from_csr(c, schedule="lines_alt", grid=(n, n), mode=mode,
-                                 tol_lambda=0.0, max_lambda_sweeps=40, warm=warm)
+                                 tol_lambda=0.0, max_lambda_sweeps=40)
                for c, n in zip(csrs, sides)]
     mg = B.Multigrid(solvers, sides, smoother="gabp", nu1=2, nu2=2)
     x = np.zeros(csrs[0].n)

@@ -304,41 +304,142 @@ def test_transposed_solve(B):
     assert _rel_inf(lam.cpu().numpy(), ls) <= 1e-10
 
 
-@pytest.mark.parametrize("mode,warm", [("joint", "reset"), ("precomp", "reset"),
-                                       ("joint", "all"), ("precomp", "all")])
-def test_smoother_matches_oracle(B, mode, warm):
-    a, b = W.small_upwind(20)
+@pytest.mark.parametrize("mode", ["joint", "precomp", "seq"])
+@pytest.mark.parametrize("schedule", ["flood", "redblack"])
+def test_smoother_matches_oracle(B, mode, schedule):
+    """Algorithm 3 from zero messages; with the per-sweep precomputed precision messages
+    (seq) the oracle's joint smoother is the reference (the two are the same iterates)."""
+    n = 20
+    a, b = W.small_upwind(n)
     g = G.Graph.from_csr(a)
-    kw = dict(mode=mode, warm=warm)
+    col = G.grid_colour(n) if schedule == "redblack" else None
+    kw = dict(mode=mode, schedule=schedule)
     lam = None
     if mode == "precomp":
         kw.update(tol_lambda=0.0, max_lambda_sweeps=25)
         Lt, S, _ = G.lambda_phase(g, 0.0, 25)
         lam = (Lt, S)
-    s = B.Solver.from_csr(a, **kw)
+    s = B.Solver.from_csr(a, colour=col, **kw)
     x0 = W.rng(301, 0).uniform(-1, 1, a.n)
     xg = _cuda(x0)
     bt = _cuda(b)
     xo = x0.copy()
-    m_state = None
-    Lt_state = None
-    for mu in (1, 2, 3, 2):
+    for mu in (1, 2, 3, 2, 5):
         s.smooth(bt, xg, mu)
-        if mode == "joint" and warm == "all":
-            # joint smoother carrying both message kinds between calls
-            r = g.residual(b, xo)
-            Lt_c = np.zeros(g.E) if Lt_state is None else Lt_state
-            m_c = np.zeros(g.E) if m_state is None else m_state
-            for _ in range(mu):
-                e, Lt_c, m_c, _, _ = G.sweep(g, r, Lt_c, m_c)
-            xo = xo + e
-            Lt_state, m_state = Lt_c, m_c
-        else:
-            xo, m_new = G.smooth(g, b, xo, mu, lam=lam,
-                                 m_state=m_state if warm == "all" else None)
-            if warm == "all":
-                m_state = m_new
-        assert _rel_inf(xg.cpu().numpy(), xo) <= TOL, (mode, warm, mu)
+        xo = G.smooth(g, b, xo, mu, lam=lam) if col is None else \
+            G.smooth_coloured(g, b, xo, mu, col, lam=lam)
+        assert _rel_inf(xg.cpu().numpy(), xo) <= TOL, (mode, schedule, mu)
+
+
+@pytest.mark.parametrize("schedule", ["flood", "redblack"])
+def test_seq_fp32_smoother_is_the_joint_smoother_to_fp32_rounding(B, schedule):
+    """FP32 mean messages with the per-sweep precision messages rounded once to FP32: the
+    joint FP64 smoother's iterates to FP32 rounding (a few ulps per sweep)."""
+    n = 24
+    a, b = W.small_upwind(n)
+    g = G.Graph.from_csr(a)
+    col = G.grid_colour(n) if schedule == "redblack" else None
+    s = B.Solver.from_csr(a, colour=col, mode="seq", precision="f32_ir", schedule=schedule)
+    x0 = W.rng(302, 0).uniform(-1, 1, a.n)
+    for mu in (1, 2, 4):
+        xg = _cuda(x0)
+        s.smooth(_cuda(b), xg, mu)
+        xo = G.smooth(g, b, x0, mu) if col is None else G.smooth_coloured(g, b, x0, mu, col)
+        # the correction e^mu carries the FP32 error, relative to its own size
+        err = np.abs(xg.cpu().numpy() - xo).max() / np.abs(xo - x0).max()
+        assert err <= 2e-6 * (1 + mu), (schedule, mu, err)
+
+
+@pytest.mark.parametrize("name", ["upwind32", "walk200", "tree150", "upwind9"])
+def test_seq_sweeps_match_joint_oracle(B, name):
+    """gabp_sweeps in the per-sweep precomputed mode, from a reset and continued without
+    one (the stored sequence grows on demand), against the oracle's joint iteration."""
+    a, b, _ = CASES[name]
+    s = B.Solver.from_csr(a, mode="seq")
+    g = G.Graph.from_csr(a)
+    bt = _cuda(b)
+    for sweeps in (1, 2, 3, 10):
+        x = s.sweeps(bt, sweeps).cpu().numpy()
+        xo, _, _ = G.run(g, b, sweeps)
+        assert _rel_inf(x, xo) <= TOL, (name, sweeps)
+    x = s.sweeps(bt, 4, reset=False).cpu().numpy()      # sweeps 11..14
+    xo, _, _ = G.run(g, b, 14)
+    assert _rel_inf(x, xo) <= TOL, name
+
+
+def test_seq_mode_rejects_solves(B):
+    a, b = W.small_upwind(8)
+    s = B.Solver.from_csr(a, mode="seq")
+    with pytest.raises(B.GaBPError) as e:
+        s.solve(_cuda(b), 1e-8, 100)
+    assert e.value.status == B.ENOTSUPP
+    with pytest.raises(B.GaBPError) as e:
+        B.Solver.from_csr(a, mode="seq", schedule="lines", grid=(8, 8))
+    assert e.value.status == B.ENOTSUPP
+
+
+def _oracle_edges(a):
+    """CSR positions of the oracle's edges (off-diagonal entries with A_ij != 0), in the
+    oracle's edge order."""
+    rows = a.row_of_nnz()
+    return np.nonzero((rows != a.col) & (a.val != 0.0))[0]
+
+
+def _rel_msgs(got, want):
+    return float(np.abs(got - want).max() / max(np.abs(want).max(), 1e-300))
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_joint_messages_match_oracle(B, name):
+    """The messages themselves (Lt_ji, m_ji of eq. nonsymmetric_GaBP_rules), not only the
+    read-offs, after 1, 2, 3 and 10 sweeps."""
+    a, b, _ = CASES[name]
+    s = B.Solver.from_csr(a)
+    g = G.Graph.from_csr(a)
+    idx = _oracle_edges(a)
+    assert len(idx) == g.E
+    bt = _cuda(b)
+    for sweeps in (1, 2, 3, 10):
+        s.sweeps(bt, sweeps)
+        lam, msg = (t.cpu().numpy() for t in s.messages())
+        _, Lt, m = G.run(g, b, sweeps)
+        if g.E:
+            assert _rel_msgs(lam[idx], Lt) <= TOL, (name, sweeps)
+            assert _rel_msgs(msg[idx], m) <= TOL, (name, sweeps)
+        rest = np.setdiff1d(np.arange(a.nnz), idx)
+        assert np.all(lam[rest] == 0.0) and np.all(msg[rest] == 0.0)
+
+
+@pytest.mark.parametrize("mode", ["precomp", "seq"])
+@pytest.mark.parametrize("schedule", ["flood", "redblack"])
+def test_precomputed_messages_match_oracle(B, mode, schedule):
+    n = 24
+    a, b = W.small_upwind(n)
+    g = G.Graph.from_csr(a)
+    col = G.grid_colour(n) if schedule == "redblack" else None
+    kw = dict(mode=mode, schedule=schedule)
+    if mode == "precomp":
+        kw.update(tol_lambda=0.0, max_lambda_sweeps=30)
+    s = B.Solver.from_csr(a, colour=col, **kw)
+    idx = _oracle_edges(a)
+    lamfix = None
+    if mode == "precomp":
+        Lt, S, _ = G.lambda_phase(g, 0.0, 30)
+        lamfix = (Lt, S)
+    bt = _cuda(b)
+    for sweeps in (1, 2, 5):
+        s.sweeps(bt, sweeps)
+        lam, msg = (t.cpu().numpy() for t in s.messages())
+        L0, m = (np.zeros(g.E) if lamfix is None else lamfix[0]), np.zeros(g.E)
+        for _ in range(sweeps):
+            if col is not None:
+                _, L0, m = G.sweep_coloured(g, b, L0, m, col, lambda_fixed=lamfix)
+            elif lamfix is None:
+                _, L0, m, _, _ = G.sweep(g, b, L0, m)
+            else:
+                _, m = G.msweep(g, b, lamfix[0], lamfix[1], m)
+        assert _rel_msgs(lam[idx], L0) <= TOL, (mode, schedule, sweeps)
+        assert _rel_msgs(msg[idx], m) <= TOL, (mode, schedule, sweeps)
 
 
 def test_residual_and_norms(B):

@@ -215,7 +215,7 @@ def test_smoother_one_sweep_is_jacobi():
     a, b = W.small_upwind(16)
     g = _graph(a)
     x0 = W.rng(108, 0).uniform(-1, 1, a.n)
-    x1, _ = G.smooth(g, b, x0, 1)
+    x1 = G.smooth(g, b, x0, 1)
     A = _dense(a)
     assert np.allclose(x1, x0 + (b - A @ x0) / np.diag(A), rtol=1e-14, atol=1e-15)
 
@@ -242,6 +242,56 @@ def test_interior_lambda_closed_form():
     assert x1[c] == pytest.approx(3 * b[c] / 8, rel=1e-13)
     nb = b[c - 1] + b[c + 1] + b[c - n] + b[c + n]
     assert x2[c] == pytest.approx((3 * b[c] + nb) / 8, rel=1e-12)
+
+
+def test_sequence_interior_closed_form():
+    """Per-sweep precision messages from zero (flood): on the Laplacian interior the
+    messages of sweeps 1..4 are 1/4, 4/13, 13/40, 40/121 and the read-off precisions are
+    4, 3, 36/13, 27/10 (Sigma_s = 4 - 4 Lt_{s-1}); red-black: a red interior node reads
+    off with Sigma = 4 and sends 1/4, a black one with 4 - 4/4 = 3 in the same sweep."""
+    n = 64
+    a = W.laplacian_5pt(n)
+    g = _graph(a)
+    c = 32 * n + 32
+    into_c = np.nonzero(g.dst == c)[0]
+    seq = G.lambda_sequence(g, 4)
+    for (Lt_s, S_s), lt, sg in zip(seq, (1 / 4, 4 / 13, 13 / 40, 40 / 121),
+                                   (4.0, 3.0, 36 / 13, 27 / 10)):
+        assert np.allclose(Lt_s[into_c], lt, rtol=1e-15)
+        assert S_s[c] == pytest.approx(sg, rel=1e-15)
+    col = G.grid_colour(n)
+    (Lt1, S1), = G.lambda_sequence(g, 1, col)
+    red, black = (c if col[c] == 0 else c + 1), (c if col[c] == 1 else c + 1)
+    assert S1[red] == 4.0 and S1[black] == 3.0
+    from_red = np.nonzero(g.src == red)[0]
+    assert np.allclose(Lt1[from_red], 0.25, rtol=1e-15)
+
+
+@pytest.mark.parametrize("schedule", ["flood", "redblack", "colour4"])
+def test_sequence_smoother_equals_joint_smoother(schedule):
+    """Algorithm 3 restarts from zero messages, so the precision messages of its sweeps do
+    not depend on the residual: mean-only sweeps with the per-sweep precomputed messages
+    reproduce the joint smoother exactly (same operations, same order)."""
+    if schedule == "colour4":
+        a = W.random_grid_9pt(13, 11, W.rng(121, 0))
+        col = G.grid_colour4(13, 11)
+    else:
+        a, _ = W.small_upwind(16)
+        col = G.grid_colour(16) if schedule == "redblack" else None
+    g = _graph(a)
+    r = W.rng(121, 1)
+    b, x0 = r.uniform(-1, 1, a.n), r.uniform(-1, 1, a.n)
+    seq = G.lambda_sequence(g, 5, col)
+    for mu in (1, 2, 3, 5):
+        want = G.smooth(g, b, x0, mu) if col is None else G.smooth_coloured(g, b, x0, mu, col)
+        got = G.smooth_seq(g, b, x0, mu, seq, col)
+        assert np.array_equal(got, want), (schedule, mu)
+    # planted mistake: the converged (frozen) precision messages instead of the sequence
+    Lt_s, S_s, _ = G.lambda_phase(g, 1e-14, 2000)
+    frozen = G.smooth(g, b, x0, 3, lam=(Lt_s, S_s)) if col is None else \
+        G.smooth_coloured(g, b, x0, 3, col, lam=(Lt_s, S_s))
+    want = G.smooth(g, b, x0, 3) if col is None else G.smooth_coloured(g, b, x0, 3, col)
+    assert _relerr(frozen, want) > 1e-6
 
 
 # --------------------------------------------------------------------------------------
@@ -319,12 +369,49 @@ def test_precomp_reaches_dense_solution():
 
 
 def test_ir_fp32_messages_reaches_fp64_accuracy():
+    """Refinement's fixed point is A^-1 b however inexact the FP32 inner solves are: the
+    converged x equals the dense solution far below FP32 resolution."""
     a, b = W.small_upwind(32)
     g = _graph(a)
     Lt, S, _ = G.lambda_phase(g, 1e-7, 1000)
     x, info = G.ir_solve(g, b, 1e-12, (Lt.astype(np.float32), (1.0 / S).astype(np.float32)))
     assert info.status == G.OK
+    assert info.outer_iters >= 2          # one FP32 inner solve alone cannot get there
     assert _relerr(x, np.linalg.solve(_dense(a), b)) < 1e-9
+
+
+def test_ir_on_a_tree_needs_one_exact_inner_solve_per_step():
+    """On a tridiagonal matrix GaBP is exact after diameter updates (tree exactness, Sec.
+    2.3), so each inner solve of n + 1 sweeps is exact up to FP32 rounding: every outer step
+    must cut the residual by about the FP32 unit roundoff times the condition number."""
+    a = W.random_tridiagonal(24, W.rng(120, 0))
+    g = _graph(a)
+    b = W.rng(120, 1).uniform(-1, 1, a.n)
+    Lt, S, _ = G.lambda_phase(g, 0.0, a.n)
+    lam32 = (Lt.astype(np.float32), (1.0 / S).astype(np.float32))
+    x, info = G.ir_solve(g, b, 1e-14, lam32, check_every=a.n + 1, inner_tol=0.0,
+                         max_inner=a.n + 1)
+    A = _dense(a)
+    assert info.status == G.OK
+    assert info.outer_iters <= 4
+    assert _relerr(x, np.linalg.solve(A, b)) < 1e-13
+
+
+def test_ir_planted_mistake_fails():
+    """A wrong sign in the outer residual (b + A x) breaks convergence to the dense
+    solution: the pin above sees it."""
+    a, b = W.small_upwind(16)
+    g = _graph(a)
+    Lt, S, _ = G.lambda_phase(g, 1e-7, 1000)
+    lam32 = (Lt.astype(np.float32), (1.0 / S).astype(np.float32))
+    xs = np.linalg.solve(_dense(a), b)
+
+    class WrongSign(G.Graph):
+        def residual(self, bb, xx):        # planted: refinement sees b + A x
+            return bb + self.matvec(xx)
+    bad = WrongSign.from_csr(a)
+    x, info = G.ir_solve(bad, b, 1e-12, lam32, max_sweeps=20000)
+    assert not (info.status == G.OK and _relerr(x, xs) < 1e-9)
 
 
 # --------------------------------------------------------------------------------------

@@ -3,8 +3,9 @@
 restriction, bilinear prolongation, rediscretised coarse operators, coarse solve, smoother
 schedule and sweep counting, stopping rule -- so an exact match pins all of them at once.
 
-Where the paper's count is not reproduced the test states our count (soft: the paper does
-not give its discretisation; the readings are listed in the design notes)."""
+Where the paper's count is not reproduced nothing is pinned: those entries are checked only
+for the paper's qualitative claim (the GaBP smoother converges, within a factor of two of
+the printed count), and the one where even that fails is an expected failure."""
 import numpy as np
 import pytest
 
@@ -32,14 +33,17 @@ SMOOTHER = {"redblack_gabp": dict(smoother="gabp", gabp_mode="joint", schedule="
             "line_gabp": dict(smoother="gabp", gabp_mode="joint", schedule="lines_alt"),
             "colour4_gabp": dict(smoother="gabp", gabp_mode="joint", schedule="colour4"),
             "redblack_gs": dict(smoother="rbgs")}
-# our counts where they differ from the printed ones (None: diverges)
-NOT_REPRODUCED = {("mixed_derivative", "eps=0.01", "colour4_gabp"): 29,
-                  ("mixed_derivative", "eps=-0.01", "colour4_gabp"): 35,
-                  ("boundary_layers", "eps=0.02", "line_gabp"): 6,
-                  ("boundary_layers", "eps=0.01", "redblack_gabp"): None,
-                  ("inner_layers", "eps=0.01", "redblack_gabp"): 8,
-                  ("stretched", "p=20,eta=0.5,eps=8e-8", "redblack_gabp"): 24,
-                  ("stretched", "p=20,eta=0.5,eps=8e-8", "line_gabp"): 24}
+# printed counts this discretisation does not reproduce (the paper's own discretisation is
+# unstated): not pins
+NOT_REPRODUCED = {("mixed_derivative", "eps=0.01", "colour4_gabp"),
+                  ("mixed_derivative", "eps=-0.01", "colour4_gabp"),
+                  ("boundary_layers", "eps=0.02", "line_gabp"),
+                  ("boundary_layers", "eps=0.01", "redblack_gabp"),
+                  ("inner_layers", "eps=0.01", "redblack_gabp"),
+                  ("stretched", "p=20,eta=0.5,eps=8e-8", "redblack_gabp"),
+                  ("stretched", "p=20,eta=0.5,eps=8e-8", "line_gabp")}
+# printed convergence that this discretisation does not even reproduce qualitatively
+DIVERGES_HERE = {("boundary_layers", "eps=0.01", "redblack_gabp")}
 
 
 def _cycles(levels, b, nu, cap=100, **kw):
@@ -56,12 +60,43 @@ def _cycles(levels, b, nu, cap=100, **kw):
     return None
 
 
-@pytest.mark.parametrize("key", sorted(PRINTED))
-def test_sec5_cycle_counts(key):
+def _run(key):
     prob, _, smoother = key
     kw, nu, printed = PRINTED[key]
     levels, b = W.sec5_hierarchy(prob, 6, 1, **kw)
     nu = (2, 2) if nu == ["any"] else (int(nu[0]), int(nu[1]))
-    ours = _cycles(levels, b, nu, **SMOOTHER[smoother])
-    want = NOT_REPRODUCED.get(key, printed)
-    assert ours == want, (key, printed, ours)
+    return printed, _cycles(levels, b, nu, **SMOOTHER[smoother])
+
+
+@pytest.mark.parametrize("key", sorted(k for k in PRINTED if k not in NOT_REPRODUCED))
+def test_sec5_cycle_counts(key):
+    printed, ours = _run(key)
+    assert ours == printed, (key, printed, ours)
+
+
+@pytest.mark.parametrize("key", sorted(NOT_REPRODUCED - DIVERGES_HERE))
+def test_sec5_unreproduced_counts_converge(key):
+    printed, ours = _run(key)
+    assert ours is not None and printed / 2 <= ours <= 2 * printed, (key, printed, ours)
+
+
+@pytest.mark.xfail(strict=True, reason="the paper prints 3 cycles; red-black GaBP (5,0) "
+                   "diverges on this discretisation of the eps = 0.01 boundary layer")
+@pytest.mark.parametrize("key", sorted(DIVERGES_HERE))
+def test_sec5_printed_convergence_not_reproduced(key):
+    printed, ours = _run(key)
+    assert ours is not None, (key, printed, ours)
+
+
+def test_sec5_sequence_smoother_counts_equal_joint():
+    """Precomputing the precision messages of the smoother's own sweeps (Sec. 4.2) leaves
+    the V-cycle iterates unchanged: the stretched-grid red-black count stays at the printed
+    18, where freezing the converged precision messages changes it."""
+    key = ("stretched", "p=20,eta=0.5,eps=1e-6", "redblack_gabp")
+    kw, nu, printed = PRINTED[key]
+    levels, b = W.sec5_hierarchy("stretched", 6, 1, **kw)
+    nu = (int(nu[0]), int(nu[1]))
+    seq = _cycles(levels, b, nu, smoother="gabp", gabp_mode="seq", schedule="redblack")
+    frozen = _cycles(levels, b, nu, smoother="gabp", gabp_mode="precomp", schedule="redblack")
+    assert seq == printed == 18
+    assert frozen != printed
