@@ -15,11 +15,14 @@ Also reported on the same JSON line:
     average launch time from HIP events on the launch stream;
   * FP32 mean-only sweep rate (the inner kernel of FP32-message iterative refinement) and
     FP64 mean-only sweep rate with precomputed Lt;
-  * time to relative residual 1e-8, plain FP64 GaBP vs FP32 messages + FP64 refinement, on a
-    smaller grid of the same family (the 2048 grid needs ~6M sweeps per solve);
+  * time to relative residual 1e-8 on the same 2048 x 2048 operator through gabp_solve:
+    by default FP32 messages + FP64 refinement with a manufactured solution (b := A x*), so
+    the error of x is reported too; the FP64 variants and the workload's own b with
+    --ttr-only --ttr-variants ... --ttr-rhs uniform (each takes minutes);
   * the CPU oracle timed on a bounded sample of sweeps on this host (a baseline only).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--ttr-grid 512]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-ttr]
+       python bench.py --ttr-only --ttr-variants fp64_joint,fp64_precomp,fp32_ir
 """
 from __future__ import annotations
 
@@ -88,8 +91,13 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--grid", type=int, default=2048)
-    ap.add_argument("--ttr-grid", type=int, default=512)
     ap.add_argument("--no-ttr", action="store_true")
+    ap.add_argument("--ttr-variants", default="fp32_ir",
+                    help="comma list of fp64_joint, fp64_precomp, fp32_ir (time to rel.res)")
+    ap.add_argument("--ttr-rhs", default="manufactured", choices=["manufactured", "uniform"])
+    ap.add_argument("--ttr-tol", type=float, default=1e-8)
+    ap.add_argument("--ttr-only", action="store_true",
+                    help="only the time-to-residual legs on the --grid workload")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sweeps", type=int, default=60)
     ap.add_argument("--profile", action="store_true",
@@ -98,20 +106,20 @@ def main():
                     help="also measure the multigrid, batching and adjoint configurations")
     ap.add_argument("--suite-only", action="store_true")
     ap.add_argument("--suite-part", default="all",
-                    choices=["all", "small", "batch", "batch_full", "mg", "adjoint", "lines",
-                             "sec5", "colours"],
+                    choices=["all", "small", "batch", "batch_full", "mg", "adjoint",
+                             "adjoint_full", "lines", "sec5", "colours"],
                     help="with --suite-only: run one part of the suite")
     ap.add_argument("--line-sweeps", type=int, default=50,
                     help="timed sweeps per variant in the line-sweep part")
-    ap.add_argument("--ttr-full", default=None,
-                    help="only time to rel.res 1e-8 on the --grid workload, driven in chunks "
-                         "with progress lines: comma list of fp64_joint, fp64_precomp, fp32_ir")
     args = ap.parse_args()
-    if args.ttr_full:
+    ttr_variants = tuple(v for v in args.ttr_variants.split(",") if v)
+    if any(v not in TTR_VARIANTS for v in ttr_variants):
+        ap.error(f"--ttr-variants: choose from {sorted(TTR_VARIANTS)}")
+    if args.ttr_only:
         import torch  # noqa: F401
         lg = lambda *a: print(*a, file=sys.stderr, flush=True)
-        print(json.dumps([ttr_chunked(args.grid, v, lg) for v in args.ttr_full.split(",")]),
-              flush=True)
+        print(json.dumps(time_to_residual(args.grid, lg, ttr_variants, args.ttr_rhs,
+                                          args.ttr_tol)), flush=True)
         return
     if args.suite_only:
         import torch  # noqa: F401
@@ -183,10 +191,16 @@ def main():
     achieved = ab / t_sw / 1e9
     log(f"[bench] joint sweep {t_sw*1e6:.1f} us, {achieved:.0f} GB/s algorithmic")
 
-    # residual kernel and its norm reduction, without the host readback (for the record)
-    res_only = lambda k: [sj.residual(bt, x, want_r=False, want_norms=False) for _ in range(k)]
-    res_only(2)
-    t_res = _events_time(res_only, 20) / 20
+    # residual kernel and its norm reduction, without the host readback: 20 calls recorded
+    # in a graph and replayed, so that host launch gaps between the calls are not timed
+    sj.residual(bt, x, want_r=False, want_norms=False)
+    torch.cuda.synchronize()
+    res_graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(res_graph):
+        for _ in range(20):
+            sj.residual(bt, x, want_r=False, want_norms=False)
+    res_graph.replay()
+    t_res = _events_time(lambda k: [res_graph.replay() for _ in range(k)], 5) / 100
 
     # FP32 mean-only sweep and FP64 mean-only sweep with precomputed Lt
     s32 = gabp.Solver.from_csr(a, mode="precomp", precision="f32_ir", check_every=CE,
@@ -249,7 +263,8 @@ def main():
     del s32, sp
 
     if not args.no_ttr:
-        out["time_to_rel_res"] = time_to_residual(args.ttr_grid, log)
+        out["time_to_rel_res"] = time_to_residual(n, log, ttr_variants, args.ttr_rhs,
+                                                  args.ttr_tol, ab=(a, b))
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(a, b, args.cpu_sweeps, log)
@@ -258,122 +273,55 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def time_to_residual(n, log):
-    """Plain FP64 joint GaBP vs FP32 messages + FP64 refinement to rel.res 1e-8."""
+TTR_VARIANTS = {"fp64_joint": dict(mode="joint"),
+                "fp64_precomp": dict(mode="precomp", tol_lambda=1e-12),
+                "fp32_ir": dict(mode="precomp", precision="f32_ir", tol_lambda=1e-7)}
+
+
+def time_to_residual(n, log, variants=("fp32_ir",), rhs="manufactured", tol=1e-8, ab=None):
+    """Time to ||b - A x||_2 / ||b||_2 <= tol on the n x n workload, each variant one
+    gabp_solve call (Lt phase included in the time; autotuning before it is not).
+
+    rhs "manufactured": b := A x* with a smooth manufactured x* (the workload's operator,
+    x* a 16-mode random field), so the error of x is reported; rhs "uniform": the
+    workload's own b ~ U(-1,1) (no reference solution at this size, no x error)."""
     import torch
     from paper_1904_04093_amd import gabp
     from paper_1904_04093_amd import workloads as W
-    a, b = W.precision_at_scale(n)
+    a, b = W.precision_at_scale(n) if ab is None else ab
+    xstar = None
+    if rhs == "manufactured":
+        xstar, b = W.manufactured_solution(a, n)
     bt = torch.as_tensor(b).cuda()
-    res = {"grid": n, "unknowns": a.n, "tol": 1e-8}
-    try:
-        import scipy.sparse as sp
-        import scipy.sparse.linalg as spl
-        A = sp.csr_matrix((a.val, a.col, a.rowptr), shape=(a.n, a.n))
-        xs = spl.spsolve(A.tocsc(), b)
-        ref = "scipy sparse LU (FP64)"
-    except Exception:  # pragma: no cover
-        xs, ref = None, None
-    for name, kw in (("fp64_joint", dict(mode="joint")),
-                     ("fp64_precomp", dict(mode="precomp", tol_lambda=1e-12)),
-                     ("fp32_ir", dict(mode="precomp", precision="f32_ir", tol_lambda=1e-7))):
-        s = gabp.Solver.from_csr(a, **kw)
+    res = {"grid": n, "unknowns": a.n, "tol": tol, "rhs": rhs,
+           "entry_point": "gabp_solve (one call per variant)"}
+    for name in variants:
+        kw = TTR_VARIANTS[name]
+        s = gabp.Solver.from_csr(a, progress_s=30.0, **kw)
         tuned = s.autotune()             # hints and check interval by measurement
         torch.cuda.synchronize()
+        log(f"[ttr] {name} {n}x{n} rhs={rhs} tol={tol:g}: solving ({tuned})")
         t0 = time.perf_counter()
         lsw = s.precompute_lambda() if kw["mode"] == "precomp" else 0   # timed: Lt phase
-        x, info = s.solve(bt, 1e-8, 5_000_000)
+        x, info = s.solve(bt, tol, 2_000_000_000)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         entry = {"seconds": dt, "sweeps": info.sweeps, "lambda_sweeps": lsw,
                  "outer_iters": info.outer_iters, "rel_res2": info.rel_res2,
-                 "status": info.status, "autotuned": tuned}
-        if xs is not None:
+                 "res_inf": info.res_inf, "status": info.status, "autotuned": tuned}
+        if xstar is not None:
             xe = x.cpu().numpy()
-            entry["x_rel_err_vs_" + "sparse_lu"] = float(np.linalg.norm(xe - xs) / np.linalg.norm(xs))
+            entry["x_rel_err"] = float(np.linalg.norm(xe - xstar) / np.linalg.norm(xstar))
+            entry["x_max_rel_err"] = float(np.abs(xe - xstar).max() / np.abs(xstar).max())
         res[name] = entry
-        log(f"[bench] ttr {name}: {dt:.2f}s {info}")
+        log(f"[ttr] {name}: {json.dumps(entry)}")
         del s
-    res["reference"] = ref
-    if res["fp64_joint"]["seconds"] > 0:
+    if "fp64_joint" in res and "fp32_ir" in res:
         res["speedup_fp32_ir_vs_fp64_joint"] = res["fp64_joint"]["seconds"] / res["fp32_ir"]["seconds"]
+    if "fp64_precomp" in res and "fp32_ir" in res:
+        res["speedup_fp32_ir_vs_fp64_precomp"] = (res["fp64_precomp"]["seconds"] /
+                                                  res["fp32_ir"]["seconds"])
     return res
-
-
-def ttr_chunked(n, variant, log, tol=1e-8, chunk=256, max_sweeps=30_000_000):
-    """Time to rel.res ``tol`` on the n x n workload, driven through the library's sweep and
-    residual entry points in chunks of ``chunk`` sweeps (the same checks a solve makes every
-    ``chunk`` sweeps), so that a run of many minutes reports its progress. fp32_ir mirrors
-    the library's refinement: FP32 mean-only sweeps on A d = r / ||r||_inf from zero
-    messages, the FP64 residual of x + s d after every chunk, best trial kept, inner solve
-    ended at 1e-4 of ||r||, at tol, or 8 checks without a new best once one was found."""
-    import torch
-    from paper_1904_04093_amd import gabp
-    from paper_1904_04093_amd import workloads as W
-    a, b = W.precision_at_scale(n)
-    bt = torch.as_tensor(b).cuda()
-    kw = {"fp64_joint": dict(mode="joint"),
-          "fp64_precomp": dict(mode="precomp", tol_lambda=1e-12),
-          "fp32_ir": dict(mode="precomp", precision="f32_ir", tol_lambda=1e-7)}[variant]
-    s = gabp.Solver.from_csr(a, **kw)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    lsw = s.precompute_lambda() if kw["mode"] == "precomp" else 0
-    total, outer, last = 0, 0, t0
-    _, (rn2, rinf, bn) = s.residual(bt, torch.zeros_like(bt), want_r=False)
-
-    def progress(rel):
-        nonlocal last
-        if time.perf_counter() - last > 20.0:
-            last = time.perf_counter()
-            log(f"[ttr] {variant} n={n}: {total} sweeps, rel.res {rel:.3e}, "
-                f"{last - t0:.0f} s")
-
-    if variant != "fp32_ir":
-        x = torch.zeros_like(bt)
-        rel = 1.0
-        while total < max_sweeps:
-            s.sweeps(bt, chunk, reset=(total == 0), x=x)
-            total += chunk
-            _, (r2, _, _) = s.residual(bt, x, want_r=False)
-            rel = r2 / bn
-            if rel <= tol or not np.isfinite(rel):
-                break
-            progress(rel)
-    else:
-        x = torch.zeros_like(bt)
-        r, (rn2, rinf, _) = s.residual(bt, x)
-        rel = rn2 / bn
-        while rel > tol and total < max_sweeps:
-            scale = rinf
-            rs = r / scale
-            d = torch.zeros_like(bt)
-            best, dbest, since, first = rn2, None, 0, True
-            while total < max_sweeps:
-                s.sweeps(rs, chunk, reset=first, x=d)
-                first = False
-                total += chunk
-                _, (t2, _, _) = s.residual(bt, x + scale * d, want_r=False)
-                if t2 < best:
-                    best, dbest, since = t2, d.clone(), 0
-                else:
-                    since += 1
-                progress(t2 / bn)
-                if best <= 1e-4 * rn2 or best / bn <= tol or (dbest is not None and since >= 8):
-                    break
-            if dbest is None:
-                break
-            x = x + scale * dbest
-            outer += 1
-            r, (rn2, rinf, _) = s.residual(bt, x)
-            rel = rn2 / bn
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    out = {"variant": variant, "grid": n, "unknowns": a.n, "tol": tol, "seconds": dt,
-           "sweeps": total, "lambda_sweeps": lsw, "outer_iters": outer, "rel_res2": rel,
-           "check_every": chunk, "converged": bool(rel <= tol)}
-    log(f"[ttr] {out}")
-    return out
 
 
 def cpu_baseline(a, b, sweeps, log):
@@ -393,7 +341,17 @@ def cpu_baseline(a, b, sweeps, log):
     return {"value": rate, "unit": "edge-msg updates/s", "cores": 1, "kind": "oracle",
             "sample": f"{sweeps} FP64 joint flood sweeps of the full {int(np.sqrt(a.n))}^2 grid "
                       f"(numpy, single-threaded; graph build {t_build:.1f}s excluded)",
-            "host_cpus": os.cpu_count()}
+            "host_cpus": os.cpu_count(), "cpu_model": _cpu_model()}
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def suite(log, part="all", line_sweeps=50):
@@ -406,6 +364,7 @@ def suite(log, part="all", line_sweeps=50):
         fn = {"small": lambda: suite_small(log), "batch": lambda: suite_batch(log),
               "batch_full": lambda: suite_batch(log, full_only=True),
               "mg": lambda: suite_mg(log), "adjoint": lambda: suite_adjoint(log),
+              "adjoint_full": lambda: suite_adjoint_full(log),
               "lines": lambda: suite_lines(log, sweeps=line_sweeps),
               "sec5": lambda: suite_sec5(log), "colours": lambda: suite_colours(log)}[part]
         res[part] = fn()
@@ -786,12 +745,16 @@ def suite_mg(log, J=12):
         entry = {"grid": f"{sides[0]}x{sides[0]}", "levels": len(levels), "generate_s": gen}
         for sm_name, smoother, kwg in (
                 ("rbgs_2_2", "rbgs", {}),
-                ("redblack_gabp_f32_warm_lambda_2_2", "gabp",
-                 dict(mode="precomp", precision="f32_ir", schedule="redblack", tol_lambda=1e-7)),
+                ("redblack_gabp_f32_seq_lambda_2_2", "gabp",
+                 dict(mode="seq", precision="f32_ir", schedule="redblack")),
+                ("redblack_gabp_f64_seq_lambda_2_2", "gabp", dict(mode="seq", schedule="redblack")),
                 ("redblack_gabp_f64_joint_2_2", "gabp", dict(mode="joint", schedule="redblack")),
-                ("flood_gabp_f32_warm_lambda_2_2", "gabp",
+                ("redblack_gabp_f32_frozen_lambda_2_2", "gabp",
+                 dict(mode="precomp", precision="f32_ir", schedule="redblack", tol_lambda=1e-7)),
+                ("flood_gabp_f32_seq_lambda_2_2", "gabp", dict(mode="seq", precision="f32_ir")),
+                ("flood_gabp_f32_frozen_lambda_2_2", "gabp",
                  dict(mode="precomp", precision="f32_ir", tol_lambda=1e-7)),
-                ("lines_alt_gabp_f32_warm_lambda_2_2", "gabp",
+                ("lines_alt_gabp_f32_frozen_lambda_2_2", "gabp",
                  dict(mode="precomp", precision="f32_ir", schedule="lines_alt", tol_lambda=1e-7)),
                 ("lines_alt_gabp_f64_joint_2_2", "gabp", dict(mode="joint", schedule="lines_alt"))):
             t0 = time.perf_counter()
@@ -828,6 +791,8 @@ def cpu_baseline_mg(levels, b, log):
     for name, kw in (("rbgs_2_2", dict(smoother="rbgs")),
                      ("redblack_gabp_f64_joint_2_2",
                       dict(smoother="gabp", gabp_mode="joint", schedule="redblack")),
+                     ("redblack_gabp_f64_seq_lambda_2_2",
+                      dict(smoother="gabp", gabp_mode="seq", schedule="redblack")),
                      ("lines_alt_gabp_f64_joint_2_2",
                       dict(smoother="gabp", gabp_mode="joint", schedule="lines_alt"))):
         t0 = time.perf_counter()
@@ -887,6 +852,53 @@ def suite_adjoint(log, n_full=1024, n_small=128, batch=8):
         log(f"[suite] adjoint {n}: {out[f'gradients_{n}x{n}_batch{batch}']}")
     out["cpu_baseline"] = cpu_baseline_adjoint(log)
     return out
+
+
+def suite_adjoint_full(log, n=1024, batch=8, tol=1e-8):
+    """The differentiation configuration at its full size: 8 theta fields on the 1024 x 1024
+    grid, L = 0.5 ||x(theta) - x_target||^2, FP32 messages inside FP64 refinement to rel.res
+    1e-8 for the forward and the transposed (adjoint) solve, gradient reduced onto theta;
+    timed per theta end to end (operator assembly, both solves with their Lt phases, the
+    scatter and the chain rule)."""
+    import torch
+    from paper_1904_04093_amd import autograd as AG
+    from paper_1904_04093_amd import gabp
+    from paper_1904_04093_amd import workloads as W
+    field = AG.ThetaField(n)
+    solver = gabp.Solver.from_csr(field.pattern, mode="precomp", precision="f32_ir",
+                                  tol_lambda=1e-7, progress_s=30.0)
+    tuned = solver.autotune()
+    b = torch.as_tensor(W.rng(5, 101).uniform(-1, 1, n * n)).cuda()
+    xt = torch.as_tensor(W.rng(5, 100).uniform(-1, 1, n * n)).cuda()
+    per = []
+    t_all = time.perf_counter()
+    for t in range(batch):
+        th = torch.tensor(W.theta_problem(n, t), device="cuda", requires_grad=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x = AG.gabp_solve(field.values(th), b, solver, tol=tol, max_sweeps=2_000_000_000)
+        loss = 0.5 * ((x - xt) ** 2).sum()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        fi, bi = solver.last_forward_info, solver.last_backward_info
+        rec = {"theta": t, "loss": float(loss), "grad_norm": float(th.grad.norm()),
+               "forward": {"seconds": t1 - t0, "sweeps": fi.sweeps, "outer": fi.outer_iters,
+                           "rel_res2": fi.rel_res2, "status": fi.status},
+               "adjoint": {"seconds": t2 - t1, "sweeps": bi.sweeps, "outer": bi.outer_iters,
+                           "rel_res2": bi.rel_res2, "status": bi.status},
+               "seconds": t2 - t0}
+        per.append(rec)
+        log(f"[suite] adjoint {n}x{n} theta {t}: {json.dumps(rec)}")
+    total = time.perf_counter() - t_all
+    e = field.pattern.nnz - field.pattern.n
+    sweeps = sum(r["forward"]["sweeps"] + r["adjoint"]["sweeps"] for r in per)
+    return {"grid": f"{n}x{n}", "batch": batch, "tol": tol, "autotuned": tuned,
+            "seconds": total, "per_theta_s": total / batch, "per_theta": per,
+            "fp32_edge_updates_per_s": e * sweeps / total,
+            "cpu_baseline": cpu_baseline_adjoint(log)}
 
 
 def cpu_baseline_adjoint(log, n=64):

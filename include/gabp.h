@@ -96,6 +96,9 @@ typedef struct {
                                 couple a node only with its horizontal and vertical
                                 neighbours (5-point pattern); lines of at most 4096 nodes
                                                                   default 0, 0             */
+  double progress_s;         /* > 0: gabp_solve / gabp_solve_transposed print one line to
+                                stderr (sweeps done, relative residual, seconds) at the
+                                first check after every progress_s seconds     default 0 */
 } gabp_options;
 
 typedef struct {

@@ -4,8 +4,9 @@ Forward: solve A(v) x = b with the context's mode and precision (FP32 messages i
 refinement for the training use case). Backward: solve A^T lambda = dL/dx with the same
 GaBP on the transposed graph (A_ij and A_ji exchanged in every message rule), then
 dL/dA_e = -lambda_row(e) x_col(e) for every stored entry (HIP scatter kernel) and
-dL/db = lambda. Only x is saved between the passes: the forward messages are not stored,
-the backward recomputes its own (including its own precomputed Lt for A^T).
+dL/db = lambda. Only x and the matrix values are saved between the passes: the forward
+messages are not stored, the backward recomputes its own (including its own precomputed Lt
+for A^T).
 
 ``ThetaField`` is an example coefficient model: per-node log-diffusion theta on an upwind
 convection-diffusion grid (face coefficient exp((theta_a + theta_b)/2), boundary faces
@@ -22,24 +23,35 @@ from . import workloads as W
 
 
 class GaBPSolve(torch.autograd.Function):
-    """x = A(values)^{-1} b with the sparsity pattern and options of ``solver``."""
+    """x = A(values)^{-1} b with the sparsity pattern and options of ``solver``.
+
+    The solver holds one matrix at a time. The forward saves its (detached) values and the
+    solver's value version; when another forward on the same solver has replaced the
+    values before this backward runs (several solves summed into one loss), the backward
+    uploads its own values again before the transposed solve."""
 
     @staticmethod
     def forward(ctx, values, b, solver, tol, max_sweeps):
-        solver.update_values(values.detach().contiguous())
+        v = values.detach().contiguous()
+        solver.update_values(v)
         x, info = solver.solve(b.detach().contiguous(), tol, max_sweeps)
+        solver.last_forward_info = info
         if info.status != B.OK:
             raise B.GaBPError(info.status, f"forward solve did not converge: {info}")
         ctx.solver, ctx.tol, ctx.max_sweeps = solver, tol, max_sweeps
-        ctx.info_forward = info
-        ctx.save_for_backward(x)
+        ctx.version = solver.values_version
+        ctx.save_for_backward(x, v)
         return x
 
     @staticmethod
     def backward(ctx, gx):
-        (x,) = ctx.saved_tensors
+        x, v = ctx.saved_tensors
         s = ctx.solver
+        if s.values_version != ctx.version:
+            s.update_values(v)
+            ctx.version = s.values_version
         lam, info = s.solve_transposed(gx.contiguous(), ctx.tol, ctx.max_sweeps)
+        s.last_backward_info = info
         if info.status != B.OK:
             raise B.GaBPError(info.status, f"adjoint solve did not converge: {info}")
         G, _ = s.adjoint_scatter(lam, x)

@@ -64,6 +64,7 @@ void gabp_default_options(gabp_options* o) {
   o->use_graphs = 1;
   o->grid_nx = 0;
   o->grid_ny = 0;
+  o->progress_s = 0.0;
 }
 
 
@@ -81,7 +82,7 @@ int gabp_setup(gabp_ctx** out, int32_t n, int64_t nnz, const int32_t* rowptr,
       (o.mode < GABP_MODE_JOINT || o.mode > GABP_MODE_PRECOMP_SEQ) ||
       (o.precision != GABP_F64 && o.precision != GABP_F32_IR) ||
       (o.schedule < GABP_SCHED_FLOOD || o.schedule > GABP_SCHED_LINES_ALT) ||
-      o.ir_max_inner < 1 ||
+      o.ir_max_inner < 1 || !(o.progress_s >= 0.0) ||
       !(o.ir_inner_tol > 0.0))
     return fail(GABP_EINVAL, "invalid options");
   if (o.schedule == GABP_SCHED_REDBLACK && !colour)

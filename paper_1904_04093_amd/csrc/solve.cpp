@@ -5,7 +5,9 @@
 // All device work is enqueued on the caller's stream. Convergence is read back every
 // `check_every` sweeps through one small pinned buffer; nothing else synchronises.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <limits>
 #include <vector>
@@ -73,6 +75,23 @@ int ensure_seq(gabp_ctx* c, int depth, hipStream_t s) {
 namespace {
 
 inline bool seq_mode(const gabp_ctx* c) { return c->opt.mode == GABP_MODE_PRECOMP_SEQ; }
+
+// Progress lines of long solves (opt.progress_s > 0), printed from the solve's own checks.
+struct Progress {
+  using Clock = std::chrono::steady_clock;
+  double every;
+  Clock::time_point t0, last;
+  explicit Progress(double e) : every(e), t0(Clock::now()), last(t0) {}
+  void check(int sweeps, int outer, double rel) {
+    if (every <= 0.0) return;
+    const auto now = Clock::now();
+    if (std::chrono::duration<double>(now - last).count() < every) return;
+    last = now;
+    std::fprintf(stderr, "[gabp] %d sweeps, %d refinement steps, rel.res %.3e, %.0f s\n",
+                 sweeps, outer, rel, std::chrono::duration<double>(now - t0).count());
+    std::fflush(stderr);
+  }
+};
 
 struct Norms {
   double r2, rinf, b2;
@@ -348,6 +367,7 @@ int solve64(gabp_ctx* c, int T, const double* b, double* x, double tol, int max_
   int done = 0;
   const bool rb = in_place(c);
   c->history.clear();
+  Progress prog(c->opt.progress_s);
   while (done < max_sweeps) {
     const int k = std::min(c->opt.check_every, max_sweeps - done);
     if ((st = maybe_inject(c, done, false, s)) != GABP_OK) return st;
@@ -376,6 +396,7 @@ int solve64(gabp_ctx* c, int T, const double* b, double* x, double tol, int max_
     host_norms(c, &nm);
     const double rel = nm.b2 > 0 ? nm.r2 / nm.b2 : nm.r2;
     c->history.push_back(rel);
+    prog.check(done, 0, rel);
     if (!std::isfinite(nm.r2) || !std::isfinite(nm.rinf)) {
       fill_info(info, GABP_ENUMERIC, done, lsw, 0, nm);
       return fail(GABP_ENUMERIC, "non-finite residual after sweep " + std::to_string(done));
@@ -415,6 +436,7 @@ int solve_ir(gabp_ctx* c, int T, const double* b, double* x, double tol, int max
   const double bn = nm.b2;
   int total = 0, outer = 0;
   c->history.clear();
+  Progress prog(c->opt.progress_s);
   double* scale = c->red + 4;   // device copy of s for this outer step
   while (true) {
     const double rel = bn > 0 ? nm.r2 / bn : nm.r2;
@@ -466,6 +488,7 @@ int solve_ir(gabp_ctx* c, int T, const double* b, double* x, double tol, int max
       GABP_HIP(hipStreamSynchronize(s));
       host_norms(c, &nt);
       c->history.push_back(bn > 0 ? nt.r2 / bn : nt.r2);
+      prog.check(total, outer, bn > 0 ? nt.r2 / bn : nt.r2);
       if (!std::isfinite(nt.r2)) {
         fill_info(info, GABP_ENUMERIC, total, lsw, outer, nt);
         return fail(GABP_ENUMERIC, "non-finite residual in iterative refinement");

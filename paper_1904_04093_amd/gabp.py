@@ -36,7 +36,8 @@ class Options(ctypes.Structure):
                 ("max_lambda_sweeps", ctypes.c_int32),
                 ("ir_inner_tol", ctypes.c_double), ("ir_max_inner", ctypes.c_int32),
                 ("schedule", ctypes.c_int32), ("use_graphs", ctypes.c_int32),
-                ("grid_nx", ctypes.c_int32), ("grid_ny", ctypes.c_int32)]
+                ("grid_nx", ctypes.c_int32), ("grid_ny", ctypes.c_int32),
+                ("progress_s", ctypes.c_double)]
 
 
 class Info(ctypes.Structure):
@@ -178,7 +179,8 @@ class Solver:
     def __init__(self, n, rowptr, col, val, rev=None, colour=None, *, mode="joint",
                  precision="f64", check_every=16, tol_lambda=1e-14,
                  max_lambda_sweeps=100000, ir_inner_tol=1e-4,
-                 ir_max_inner=1000000, schedule="flood", use_graphs=True, grid=None):
+                 ir_max_inner=1000000, schedule="flood", use_graphs=True, grid=None,
+                 progress_s=0.0):
         lib = load()
         self._lib = lib
         o = Options()
@@ -189,6 +191,7 @@ class Solver:
         o.ir_inner_tol, o.ir_max_inner = float(ir_inner_tol), int(ir_max_inner)
         o.schedule = SCHEDULES[schedule]
         o.use_graphs = int(bool(use_graphs))
+        o.progress_s = float(progress_s)
         if grid is not None:                  # (nx, ny) of the line schedules
             o.grid_nx, o.grid_ny = int(grid[0]), int(grid[1])
         self.options = o
@@ -283,8 +286,11 @@ class Solver:
                 None, None, None, None, _stream()))
         return G, dtheta
 
+    values_version = 0          # bumped by every update_values (autograd checks it)
+
     def update_values(self, val):
         _check(self._lib.gabp_update_values(self._h, _dev(val, self.nnz), _stream()))
+        self.values_version += 1
 
     def get_state(self) -> bytes:
         nb = ctypes.c_size_t(0)

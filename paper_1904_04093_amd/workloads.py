@@ -37,7 +37,7 @@ __all__ = [
     "rng", "CSR", "assemble_cd", "random_field", "eval_field",
     "small_upwind", "precision_at_scale", "batch_family", "anisotropic_mg",
     "mg_hierarchy", "theta_problem", "theta_jacobian",
-    "random_walk_summable", "random_tridiagonal", "random_tree", "laplacian_5pt",
+    "random_walk_summable", "random_tridiagonal", "manufactured_solution", "random_tree", "laplacian_5pt",
     "toy_5x5", "csr_from_dense", "csr_to_dense", "grid_colouring", "random_sparse_dominant",
 ]
 
@@ -229,6 +229,16 @@ def batch_family(nsys: int = 512, nrhs: int = 4, side_lo: int = 48, side_hi: int
         bb = rng(seed, 2, t).uniform(-1.0, 1.0, size=(nrhs, int(s) * int(s)))
         out.append((a, bb))
     return out
+
+
+def manufactured_solution(a: CSR, n: int, seed: int = 2):
+    """Smooth manufactured solution x* on the ``n x n`` grid of ``a`` (a 16-mode random field
+    like the coefficient field, stream [seed, 2]) and the right-hand side b := A x*, so that
+    the error of a computed x is known exactly."""
+    x, y, _ = _grid_xy(n)
+    xs = eval_field(random_field(rng(seed, 2)), x, y).reshape(-1)
+    rows = a.row_of_nnz()
+    return xs, np.bincount(rows, weights=a.val * xs[a.col], minlength=a.n)
 
 
 def anisotropic_mg(n: int, kx: float = 1.0, ky: float = 0.01, peclet: float = 4.0,

@@ -91,3 +91,29 @@ def test_entry_gradient_and_rhs_gradient(mods):
     assert np.allclose(bt.grad.cpu().numpy(), lam, rtol=1e-10, atol=1e-13)
     G = -lam[a.row_of_nnz()] * xs[a.col]
     assert np.allclose(vals.grad.cpu().numpy(), G, rtol=1e-9, atol=1e-13)
+
+
+def test_two_forwards_then_one_backward(mods):
+    """Two solves on one solver with different theta summed into one loss: each backward
+    must use its own matrix (the solver holds only the last one uploaded)."""
+    gabp, AG = mods
+    n = 16
+    b = W.rng(5, 101).uniform(-1, 1, n * n)
+    xt = W.rng(5, 100).uniform(-1, 1, n * n)
+    field = AG.ThetaField(n)
+    solver = gabp.Solver.from_csr(field.pattern, mode="precomp", precision="f32_ir",
+                                  check_every=16, tol_lambda=1e-12)
+    bt = torch.as_tensor(b, device="cuda")
+    xtt = torch.as_tensor(xt, device="cuda")
+    thetas = [W.theta_problem(n, t) for t in (0, 1)]
+    ths = [torch.tensor(t, dtype=torch.float64, device="cuda", requires_grad=True)
+           for t in thetas]
+    loss = sum(0.5 * ((AG.gabp_solve(field.values(th), bt, solver, tol=1e-13) - xtt) ** 2).sum()
+               for th in ths)
+    loss.backward()
+    for t, th in zip(thetas, ths):
+        a, jptr, jnnz, jw = W.theta_jacobian(n, t)
+        ref = AD.dense_reference(W.csr_to_dense(a), b, xt, a.row_of_nnz(), a.col,
+                                 jac=(jptr, jnnz, jw))
+        g = th.grad.cpu().numpy()
+        assert np.linalg.norm(g - ref["dtheta"]) <= 1e-8 * np.linalg.norm(ref["dtheta"])
