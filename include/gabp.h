@@ -186,6 +186,19 @@ int gabp_smooth(gabp_ctx* ctx, const double* b, double* x, int32_t mu, hipStream
 int gabp_residual(gabp_ctx* ctx, const double* b, const double* x, double* r,
                   int32_t transposed, double* norms, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): gabp_residual with the norms written
+ * to DEVICE memory and its per-block partial sums kept in a fixed 2 MiB device array that
+ * the library holds on each GPU until the process ends, so the call allocates nothing,
+ * never waits for the stream and can be captured. b, x, r: DEVICE as in gabp_residual
+ * (r may be NULL); norms (DEVICE, may be NULL): [||r||_2, ||r||_inf, ||b||_2], the same
+ * values gabp_residual returns (same kernels, same reduction order). Contexts of more than
+ * 22,369,280 rows (lanes) are rejected with GABP_EINVAL. Every call on one GPU shares that
+ * array: calls that overlap on one GPU (other streams or threads) race; calls in order on
+ * one stream do not. */
+int gabp_residual_noalloc(gabp_ctx* ctx, const double* b, const double* x, double* r,
+                          int32_t transposed, double* norms, hipStream_t stream);
+
 /* Adjoint scatter for L(x(A)) with A x = b: G_e = dL/dA_e = -lambda_row(e) x_col(e) for
  * every stored entry e in setup CSR order (lambda solves A^T lambda = dL/dx). lambda, x:
  * DEVICE n doubles; G: DEVICE nnz doubles (may be NULL). If jptr != NULL the entry

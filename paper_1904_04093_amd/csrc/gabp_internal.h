@@ -170,6 +170,9 @@ int smooth_from(gabp_ctx* c, const double* b, double* x, int mu, bool r_ready, h
 
 // Lt phase of the context (T = 1: for A^T), computed once and cached (solve.cpp)
 int precompute(gabp_ctx* c, int T, hipStream_t s);
+// device address of the allocation-free entry point's static array on device `dev`, which
+// must be current; looked up once per device (noalloc.hip). out may be NULL.
+int scratch_on(int dev, double** out);
 // per-sweep Lt of the first `depth` sweeps after a reset (mode PRECOMP_SEQ, solve.cpp)
 int ensure_seq(gabp_ctx* c, int depth, hipStream_t s);
 void free_seq(gabp_ctx* c);

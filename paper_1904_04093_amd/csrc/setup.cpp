@@ -308,6 +308,7 @@ int gabp_setup(gabp_ctx** out, int32_t n, int64_t nnz, const int32_t* rowptr,
   if ((st = upload(&(dst), src, stream)) != GABP_OK) return cleanup_fail(st)
 #define AL(dst, cnt) \
   if ((st = alloc(&(dst), cnt)) != GABP_OK) return cleanup_fail(st)
+  if ((st = scratch_on(c->device, nullptr)) != GABP_OK) return cleanup_fail(st);
   UP(L.sptr, h_sptr);
   UP(L.rev, h_rev);
   if (!h_rev16.empty()) UP(L.rev16, h_rev16);

@@ -71,6 +71,7 @@ _SIGS = {
     "gabp_precompute_lambda": (ctypes.c_int, [_P, _I32, _PI32, _P]),
     "gabp_smooth": (ctypes.c_int, [_P, _P, _P, _I32, _P]),
     "gabp_residual": (ctypes.c_int, [_P, _P, _P, _P, _I32, _P, _P]),
+    "gabp_residual_noalloc": (ctypes.c_int, [_P, _P, _P, _P, _I32, _P, _P]),
     "gabp_adjoint_scatter": (ctypes.c_int, [_P, _P, _P, _P, _I32, _P, _P, _P, _P, _P]),
     "gabp_get_state": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_size_t), _P]),
     "gabp_set_state": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P]),
@@ -265,6 +266,15 @@ class Solver:
                                        _dev(r, self.n) if want_r else None,
                                        int(bool(transposed)), norms, _stream()))
         return r, tuple(norms) if want_norms else None
+
+    def residual_noalloc(self, b, x, r=None, norms=None, transposed=False):
+        """gabp_residual_noalloc: r = b - A x and the norms into caller-owned device tensors
+        (r: n doubles, norms: 3 doubles; either may be None); nothing is read back."""
+        _check(self._lib.gabp_residual_noalloc(
+            self._h, _dev(b, self.n), _dev(x, self.n),
+            _dev(r, self.n) if r is not None else None, int(bool(transposed)),
+            _dev(norms, 3) if norms is not None else None, _stream()))
+        return r, norms
 
     def adjoint_scatter(self, lam, x, jac=None, want_G=True):
         import torch
