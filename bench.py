@@ -99,6 +99,9 @@ def main():
     ap.add_argument("--ttr-only", action="store_true",
                     help="only the time-to-residual legs on the --grid workload")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-tiles", action="store_true",
+                    help="plain one-sweep-per-launch flood kernels instead of the tiled "
+                         "two-sweep kernels")
     ap.add_argument("--cpu-sweeps", type=int, default=60)
     ap.add_argument("--profile", action="store_true",
                     help="short run for the profiler: few launches of each kernel")
@@ -106,8 +109,9 @@ def main():
                     help="also measure the multigrid, batching and adjoint configurations")
     ap.add_argument("--suite-only", action="store_true")
     ap.add_argument("--suite-part", default="all",
-                    choices=["all", "small", "batch", "batch_full", "mg", "adjoint",
-                             "adjoint_full", "lines", "sec5", "colours"],
+                    choices=["all", "small", "batch", "batch_full", "mg", "mg_profile",
+                             "sweeps_large",
+                             "adjoint", "adjoint_full", "lines", "sec5", "colours"],
                     help="with --suite-only: run one part of the suite")
     ap.add_argument("--line-sweeps", type=int, default=50,
                     help="timed sweeps per variant in the line-sweep part")
@@ -119,7 +123,7 @@ def main():
         import torch  # noqa: F401
         lg = lambda *a: print(*a, file=sys.stderr, flush=True)
         print(json.dumps(time_to_residual(args.grid, lg, ttr_variants, args.ttr_rhs,
-                                          args.ttr_tol)), flush=True)
+                                          args.ttr_tol, tiles=not args.no_tiles)), flush=True)
         return
     if args.suite_only:
         import torch  # noqa: F401
@@ -147,7 +151,9 @@ def main():
     edges = a.nnz - a.n
     CE = 16
     t0 = time.time()
-    sj = gabp.Solver.from_csr(a, mode="joint", check_every=CE)
+    tiles = not args.no_tiles
+    tkw = dict(tiles=True, grid=(n, n)) if tiles else {}
+    sj = gabp.Solver.from_csr(a, mode="joint", check_every=CE, **tkw)
     lay = sj.layout_info()
     log(f"[bench] setup {time.time()-t0:.1f}s layout {lay}")
     bt = torch.as_tensor(b).cuda()
@@ -181,15 +187,21 @@ def main():
     del src, dst
     log(f"[bench] copy probe: {copy_gbs:.0f} GB/s (read + write of 1 GiB)")
 
-    # dominant kernel: the joint FP64 sweep, back-to-back launches on the launch stream
+    # dominant kernel: the joint FP64 sweep kernel, back-to-back launches on the launch
+    # stream; tiled, one launch does two sweeps and moves the message state once, so its
+    # algorithmic bytes are one pass over the state (int32 reverse index)
     NS = 20 if args.profile else 200
     sweeps_only = lambda k: sj.sweeps(bt, k, reset=False, x=x)
     sweeps_only(20)
-    t_sw = _events_time(sweeps_only, NS) / NS
-    rb = lay["rev_bytes"]
+    t_all = _events_time(sweeps_only, NS)
+    per_launch = 2 if tiles else 1
+    t_launch = t_all / (NS // per_launch)
+    t_sw = t_all / NS
+    rb = 4 if tiles else lay["rev_bytes"]
     ab = sweep_bytes_joint64(lay["slots"], a.n, rb)
-    achieved = ab / t_sw / 1e9
-    log(f"[bench] joint sweep {t_sw*1e6:.1f} us, {achieved:.0f} GB/s algorithmic")
+    achieved = ab / t_launch / 1e9
+    log(f"[bench] joint sweep kernel {t_launch*1e6:.1f} us per launch ({per_launch} sweeps), "
+        f"{achieved:.0f} GB/s algorithmic")
 
     # residual kernel and its norm reduction, without the host readback: 20 calls recorded
     # in a graph and replayed, so that host launch gaps between the calls are not timed
@@ -204,9 +216,9 @@ def main():
 
     # FP32 mean-only sweep and FP64 mean-only sweep with precomputed Lt
     s32 = gabp.Solver.from_csr(a, mode="precomp", precision="f32_ir", check_every=CE,
-                               tol_lambda=1e-7)
+                               tol_lambda=1e-7, **tkw)
     lsw = s32.precompute_lambda()
-    sp = gabp.Solver.from_csr(a, mode="precomp", check_every=CE, tol_lambda=1e-12)
+    sp = gabp.Solver.from_csr(a, mode="precomp", check_every=CE, tol_lambda=1e-12, **tkw)
     lsw64 = sp.precompute_lambda()
     sp.sweeps(bt, 1, reset=True, x=x)
     t_m64 = _events_time(lambda k: sp.sweeps(bt, k, reset=False, x=x), NS) / NS
@@ -234,26 +246,33 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"upwind convection-diffusion {n}x{n}, variable k=exp(g), "
-                               "rotating v, FP64 joint flood GaBP, 16 sweeps + residual check per step",
+                               "rotating v, FP64 joint flood GaBP, 16 sweeps + residual check per step"
+                               + (" (two sweeps per launch over 16x64 tiles)" if tiles else ""),
                    "unknowns": a.n, "nnz": a.nnz, "directed_edges": edges,
-                   "sweeps_per_step": CE},
-        "roofline": {"bound": "hbm", "kernel": "k_joint (FP64 joint flood sweep)",
+                   "sweeps_per_step": CE, "tiles": tiles},
+        "roofline": {"bound": "hbm",
+                     "kernel": ("k_joint2 (two FP64 joint flood sweeps per launch, tiled)"
+                                if tiles else "k_joint (FP64 joint flood sweep)"),
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic("k_joint<4, false, true, true, false>"),
+                     "traffic": measured_traffic("k_joint2<0, true, false>" if tiles
+                                                 else "k_joint<4, false, true, true, false>"),
                      "frac_of_copy": achieved / copy_gbs,
-                     "algorithmic_bytes_per_launch": ab, "launch_us": t_sw * 1e6,
-                     "reverse_index_bytes": rb},
+                     "algorithmic_bytes_per_launch": ab, "launch_us": t_launch * 1e6,
+                     "sweeps_per_launch": per_launch, "reverse_index_bytes": rb},
         "wall_s_timed": t_wall,
         "kernels": {
             "joint_f64_sweep_us": t_sw * 1e6,
             "joint_f64_edge_updates_per_s": edges / t_sw,
             "mean_f64_sweep_us": t_m64 * 1e6,
             "mean_f64_edge_updates_per_s": edges / t_m64,
-            "mean_f64_GBs": sweep_bytes_mean64(lay["slots"], a.n, rb) / t_m64 / 1e9,
+            "mean_f64_GBs": sweep_bytes_mean64(lay["slots"], a.n, rb) / (per_launch * t_m64) / 1e9,
             "mean_f32_sweep_us": t_m32 * 1e6,
             "mean_f32_edge_updates_per_s": edges / t_m32,
-            "mean_f32_GBs": sweep_bytes_mean32(lay["slots"], a.n, rb) / t_m32 / 1e9,
+            "mean_f32_GBs": sweep_bytes_mean32(lay["slots"], a.n, rb) / (per_launch * t_m32) / 1e9,
+            "sweeps_per_launch": per_launch,
+            "GBs_note": "algorithmic bytes of one pass over the message state per launch "
+                        "(a launch does sweeps_per_launch sweeps)",
             "residual_us": t_res * 1e6,
             "residual_GBs": (12 * lay["slots"] + 32 * a.n) / t_res / 1e9,
             "copy_probe_GBs": copy_gbs,
@@ -264,7 +283,7 @@ def main():
 
     if not args.no_ttr:
         out["time_to_rel_res"] = time_to_residual(n, log, ttr_variants, args.ttr_rhs,
-                                                  args.ttr_tol, ab=(a, b))
+                                                  args.ttr_tol, ab=(a, b), tiles=tiles)
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(a, b, args.cpu_sweeps, log)
@@ -278,7 +297,8 @@ TTR_VARIANTS = {"fp64_joint": dict(mode="joint"),
                 "fp32_ir": dict(mode="precomp", precision="f32_ir", tol_lambda=1e-7)}
 
 
-def time_to_residual(n, log, variants=("fp32_ir",), rhs="manufactured", tol=1e-8, ab=None):
+def time_to_residual(n, log, variants=("fp32_ir",), rhs="manufactured", tol=1e-8, ab=None,
+                     tiles=True):
     """Time to ||b - A x||_2 / ||b||_2 <= tol on the n x n workload, each variant one
     gabp_solve call (Lt phase included in the time; autotuning before it is not).
 
@@ -293,11 +313,12 @@ def time_to_residual(n, log, variants=("fp32_ir",), rhs="manufactured", tol=1e-8
     if rhs == "manufactured":
         xstar, b = W.manufactured_solution(a, n)
     bt = torch.as_tensor(b).cuda()
-    res = {"grid": n, "unknowns": a.n, "tol": tol, "rhs": rhs,
+    res = {"grid": n, "unknowns": a.n, "tol": tol, "rhs": rhs, "tiles": tiles,
            "entry_point": "gabp_solve (one call per variant)"}
     for name in variants:
         kw = TTR_VARIANTS[name]
-        s = gabp.Solver.from_csr(a, progress_s=30.0, **kw)
+        s = gabp.Solver.from_csr(a, progress_s=30.0,
+                                 **(dict(tiles=True, grid=(n, n)) if tiles else {}), **kw)
         tuned = s.autotune()             # hints and check interval by measurement
         torch.cuda.synchronize()
         log(f"[ttr] {name} {n}x{n} rhs={rhs} tol={tol:g}: solving ({tuned})")
@@ -365,6 +386,8 @@ def suite(log, part="all", line_sweeps=50):
               "batch_full": lambda: suite_batch(log, full_only=True),
               "mg": lambda: suite_mg(log), "adjoint": lambda: suite_adjoint(log),
               "adjoint_full": lambda: suite_adjoint_full(log),
+              "mg_profile": lambda: suite_mg_profile(log),
+              "sweeps_large": lambda: suite_sweeps_large(log),
               "lines": lambda: suite_lines(log, sweeps=line_sweeps),
               "sec5": lambda: suite_sec5(log), "colours": lambda: suite_colours(log)}[part]
         res[part] = fn()
@@ -780,6 +803,90 @@ def suite_mg(log, J=12):
         if JJ <= 6:
             entry["cpu_baseline"] = cpu_baseline_mg(levels, b, log)
         out[name] = entry
+    return out
+
+
+def suite_sweeps_large(log, n=4095, sweeps=40):
+    """Sweep kernels on the 4095 x 4095 operator of the benchmark's family (16.8M rows,
+    67M directed slots): every message array is far larger than the 256 MB last-level
+    cache, so the rates are HBM rates. Plain (one sweep per launch) and tiled (two per
+    launch) joint FP64, frozen-Lt FP64 and FP32 mean-only sweeps."""
+    import torch
+    from paper_1904_04093_amd import gabp
+    from paper_1904_04093_amd import workloads as W
+    t0 = time.perf_counter()
+    a, b = W.precision_at_scale(n)
+    bt = torch.as_tensor(b).cuda()
+    out = {"grid": f"{n}x{n}", "unknowns": a.n, "generate_s": time.perf_counter() - t0}
+    src = torch.empty(2 ** 28, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    gabp.copy_probe(src, dst)
+    t_cp = _events_time(lambda k: [gabp.copy_probe(src, dst) for _ in range(k)], 4) / 4
+    out["copy_probe_GBps"] = 2 * src.numel() * 8 / t_cp / 1e9
+    del src, dst
+    for tiles in (False, True):
+        tkw = dict(tiles=True, grid=(n, n)) if tiles else {}
+        for name, kw, bytes_fn in (("joint_f64", dict(mode="joint"), sweep_bytes_joint64),
+                                   ("mean_f64", dict(mode="precomp", tol_lambda=1e-12),
+                                    sweep_bytes_mean64),
+                                   ("mean_f32", dict(mode="precomp", precision="f32_ir",
+                                                     tol_lambda=1e-7), sweep_bytes_mean32)):
+            s = gabp.Solver.from_csr(a, **kw, **tkw)
+            lay = s.layout_info()
+            if kw["mode"] == "precomp":
+                s.precompute_lambda()
+            x = torch.zeros(a.n, dtype=torch.float64, device="cuda")
+            s.sweeps(bt, 2, x=x)
+            torch.cuda.synchronize()
+            # FP32: differencing removes the cast of b and the widening of x per call
+            t1 = _events_time(lambda k: s.sweeps(bt, sweeps + 1, reset=False, x=x), 1)
+            t0_ = _events_time(lambda k: s.sweeps(bt, 1, reset=False, x=x), 1)
+            dt = (t1 - t0_) / sweeps
+            per = 2 if tiles else 1
+            rb = 4 if tiles else lay["rev_bytes"]
+            ab = bytes_fn(lay["slots"], a.n, rb)
+            rec = {"sweep_us": dt * 1e6, "launch_us": per * dt * 1e6, "sweeps_per_launch": per,
+                   "algorithmic_bytes_per_launch": ab,
+                   "GBps_per_launch": ab / (per * dt) / 1e9,
+                   "frac_of_hbm_peak": ab / (per * dt) / 1e9 / HBM_PEAK_GBS,
+                   "edge_updates_per_s": (a.nnz - a.n) / dt}
+            out[("tiled_" if tiles else "plain_") + name] = rec
+            log(f"[suite] sweeps {n}x{n} tiles={tiles} {name}: {rec}")
+            del s
+    return out
+
+
+MG_PROFILE_SMOOTHERS = (
+    ("redblack_gabp_f32_seq_lambda_2_2", "gabp",
+     dict(mode="seq", precision="f32_ir", schedule="redblack")),
+    ("redblack_gabp_f64_seq_lambda_2_2", "gabp", dict(mode="seq", schedule="redblack")),
+    ("redblack_gabp_f64_joint_2_2", "gabp", dict(mode="joint", schedule="redblack")),
+    ("rbgs_2_2", "rbgs", {}))
+
+
+def suite_mg_profile(log, J=12, cycles=4):
+    """A few V(2,2) cycles per smoother on the 4095 x 4095 anisotropic hierarchy, for a
+    kernel trace: one eager cycle (Lt phases, recording), then ``cycles`` replays of the
+    recorded cycle, each timed with HIP events on the caller's stream."""
+    import torch
+    from paper_1904_04093_amd import gabp
+    from paper_1904_04093_amd import workloads as W
+    levels = W.mg_hierarchy(J, coarsest=3, kx=1.0, ky=0.01, peclet=4.0)
+    sides = [int(round(np.sqrt(x.n))) for x in levels]
+    bt = torch.as_tensor(W.rng(4, 1).uniform(-1, 1, levels[0].n)).cuda()
+    out = {"grid": f"{sides[0]}x{sides[0]}", "levels": len(levels), "sides": sides}
+    for sm_name, smoother, kwg in MG_PROFILE_SMOOTHERS:
+        solvers = [gabp.Solver.from_csr(x, colour=W.grid_colouring(sd), **kwg)
+                   for x, sd in zip(levels, sides)]
+        mg = gabp.Multigrid(solvers, sides, smoother=smoother, nu1=2, nu2=2)
+        x = torch.zeros(levels[0].n, dtype=torch.float64, device="cuda")
+        mg.vcycle(bt, x)
+        mg.vcycle(bt, x)          # recorded here
+        torch.cuda.synchronize()
+        ts = [1e3 * _events_time(lambda k: mg.vcycle(bt, x), 1) for _ in range(cycles)]
+        out[sm_name] = {"ms_per_cycle": ts, "median_ms": float(np.median(ts))}
+        log(f"[suite] mg profile {sm_name}: {out[sm_name]}")
+        del mg, solvers
     return out
 
 

@@ -96,6 +96,16 @@ typedef struct {
                                 couple a node only with its horizontal and vertical
                                 neighbours (5-point pattern); lines of at most 4096 nodes
                                                                   default 0, 0             */
+  int32_t tiles;             /* 1: temporal blocking of the flood schedule -- the rows are
+                                laid out in tiles of 16 grid rows x 64 columns and one
+                                launch does two sweeps per tile, keeping the messages of
+                                the first in LDS (the tile's neighbour rows are swept once
+                                more to supply them); needs grid_nx, grid_ny (node (x, y) is
+                                row y * grid_nx + x), the flood schedule and rows of at most
+                                4 off-diagonal neighbours. Same iterates as 0.  default 0 */
+  int32_t block;             /* threads per workgroup of the single-system sweep kernels:
+                                64, 128 or 256 (gabp_autotune picks one by measurement)
+                                                                  default 256              */
   double progress_s;         /* > 0: gabp_solve / gabp_solve_transposed print one line to
                                 stderr (sweeps done, relative residual, seconds) at the
                                 first check after every progress_s seconds     default 0 */
@@ -248,18 +258,21 @@ int gabp_layout_info(const gabp_ctx* ctx, int32_t* n, int64_t* nnz, int64_t* slo
                      int64_t* padded_slots, int32_t* rev_bytes);
 
 /* Autotuner. Times the context's own sweep kernel (for its mode, precision and batch
- * shape) with and without non-temporal hints on the per-slot streams, keeps the faster,
- * then sets opt.check_every to the smallest power of two in [8, 256] for which one residual
- * check (kernel, reduction, readback, host wait) costs at most 2% of the sweeps between
- * checks. Results are cached per (architecture, sizes, mode) in memory and, when the
- * environment variable GABP_AUTOTUNE_CACHE names a file, in that JSON-lines file. Runs
- * sweeps on a zero right-hand side, so the context's message state is reset; computes the
- * precomputed Lt first when the mode needs it. Outputs (host, may be NULL): the chosen
- * check interval and hint setting (0/1). Because it changes check_every, later solves may
- * stop at a different (rounded-up) sweep count than untuned ones. Line schedules have no
- * hint variants: only the check interval is tuned (from one line sweep), hints_out is 0. */
+ * shape) with and without non-temporal hints on the per-slot streams and, for single
+ * systems, at workgroup sizes of 64, 128 and 256 threads (1, 2 or 4 slices of 64 rows per
+ * workgroup), keeps the fastest pair, then sets opt.check_every to the smallest power of
+ * two in [8, 256] for which one residual check (kernel, reduction, readback, host wait)
+ * costs at most 2% of the sweeps between checks. Results are cached per (architecture,
+ * sizes, mode) in memory and, when the environment variable GABP_AUTOTUNE_CACHE names a
+ * file, in that JSON-lines file. Runs sweeps on a zero right-hand side, so the context's
+ * message state is reset; computes the precomputed Lt first when the mode needs it.
+ * Outputs (host, may be NULL): the chosen check interval, hint setting (0/1) and workgroup
+ * size. Because it changes check_every, later solves may stop at a different (rounded-up)
+ * sweep count than untuned ones. Line schedules have no hint or workgroup variants: only
+ * the check interval is tuned (from one line sweep), hints_out is 0 and block_out 256;
+ * batches keep 256-thread workgroups. */
 int gabp_autotune(gabp_ctx* ctx, int32_t* check_every_out, int32_t* hints_out,
-                  hipStream_t stream);
+                  int32_t* block_out, hipStream_t stream);
 
 /* ---- batches of independent systems ------------------------------------------------- */
 /* Build one context for nsys independent systems given as a block-diagonal CSR matrix

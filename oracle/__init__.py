@@ -9,8 +9,9 @@ nothing from the product package.
 Modules
 -------
 gabp_loops  pure-Python loops over a dict of messages (small cases), Sec. 2.3 rules
-gabp        vectorized numpy form of the same iteration, plus Lambda-precompute,
-            the error-correction smoother (Alg. 3) and FP32-message iterative refinement
+gabp        vectorized numpy form of the same iteration, plus Lambda-precompute (converged,
+            and per sweep from zero messages), the error-correction smoother (Alg. 3) and
+            classical FP32-message iterative refinement
 mg          geometric V-cycle: full-weighting restriction, bilinear interpolation,
             dense coarse solve, red-black Gauss-Seidel comparison smoother (Sec. 4)
 adjoint     transposed solve and dL/dA_ij = -lambda_i x_j, dense-LU reference gradient

@@ -1,6 +1,7 @@
 // Autotuner: per context, measure and pick (1) whether the sweep kernels stream their
-// per-slot arrays with non-temporal hints and (2) the number of sweeps between residual
-// checks. Results are cached per (device, sizes, mode) in a JSON-lines file named by the
+// per-slot arrays with non-temporal hints, (2) the workgroup size of the single-system
+// sweep kernels (64, 128 or 256 threads: 1, 2 or 4 slices of 64 rows) and (3) the number of
+// sweeps between residual checks. Results are cached per (device, sizes, mode) in a JSON-lines file named by the
 // environment variable GABP_AUTOTUNE_CACHE (in memory only when it is unset).
 #include <algorithm>
 #include <cmath>
@@ -22,6 +23,7 @@ namespace {
 struct Tuned {
   int hints;
   int check_every;
+  int block;
 };
 
 std::mutex g_mu;
@@ -53,7 +55,7 @@ bool cache_lookup(const std::string& key, Tuned* t) {
   char line[1024];
   bool found = false;
   while (std::fgets(line, sizeof(line), f)) {
-    // {"key": "...", "stream_hints": H, "check_every": C}
+    // {"key": "...", "stream_hints": H, "check_every": C, "block": B}
     const char* k0 = std::strstr(line, "\"key\": \"");
     if (!k0) continue;
     k0 += 8;
@@ -65,8 +67,10 @@ bool cache_lookup(const std::string& key, Tuned* t) {
     if (!hp || !cp) continue;
     h = std::atoi(hp + 16);
     ce = std::atoi(cp + 15);
-    if (ce >= 1) {
-      *t = Tuned{h, ce};
+    const char* bp = std::strstr(k1, "\"block\": ");
+    const int blk = bp ? std::atoi(bp + 9) : kBlock;
+    if (ce >= 1 && (blk == 64 || blk == 128 || blk == 256)) {
+      *t = Tuned{h, ce, blk};
       found = true;
     }
   }
@@ -82,8 +86,8 @@ void cache_store(const std::string& key, const Tuned& t) {
   if (!path) return;
   FILE* f = std::fopen(path, "a");
   if (!f) return;
-  std::fprintf(f, "{\"key\": \"%s\", \"stream_hints\": %d, \"check_every\": %d}\n", key.c_str(),
-               t.hints, t.check_every);
+  std::fprintf(f, "{\"key\": \"%s\", \"stream_hints\": %d, \"check_every\": %d, \"block\": %d}\n",
+               key.c_str(), t.hints, t.check_every, t.block);
   std::fclose(f);
 }
 
@@ -146,6 +150,7 @@ int autotune_lines(gabp_ctx* c, int32_t* check_every_out, int32_t* hints_out, hi
     int ce = 8;
     while (ce < 256 && t_check > 0.02 * ce * t_sweep) ce *= 2;
     t.hints = 0;
+    t.block = kBlock;
     t.check_every = ce;
     cache_store(key, t);
     c->fresh64 = true;   // the timing sweeps leave the messages in use: logically zero again
@@ -162,8 +167,10 @@ int autotune_lines(gabp_ctx* c, int32_t* check_every_out, int32_t* hints_out, hi
 
 extern "C" {
 
-int gabp_autotune(gabp_ctx* c, int32_t* check_every_out, int32_t* hints_out, hipStream_t s) {
+int gabp_autotune(gabp_ctx* c, int32_t* check_every_out, int32_t* hints_out,
+                  int32_t* block_out, hipStream_t s) {
   if (!c) return fail(GABP_EINVAL, "NULL context");
+  if (block_out) *block_out = c->batch || c->lines ? kBlock : c->L.block;
   if (c->lines) return autotune_lines(c, check_every_out, hints_out, s);
   const std::string key = key_of(c);
   Tuned t{};
@@ -230,18 +237,28 @@ int gabp_autotune(gabp_ctx* c, int32_t* check_every_out, int32_t* hints_out, hip
     };
     const int reps = 20;
     double t_sweep = 0.0;
+    t.block = kBlock;
     if (c->batch) {   // batched sweeps stream without hints
       if ((st = time_it(s, reps, one_sweep, &t_sweep)) != GABP_OK) return st;
       t.hints = 0;
     } else {
-      double tt[2];
-      for (int h = 0; h < 2; ++h) {
-        hints = h != 0;
-        if ((st = time_it(s, reps, one_sweep, &tt[h])) != GABP_OK) return st;
-      }
-      t.hints = tt[1] < tt[0] ? 1 : 0;
-      t_sweep = std::min(tt[0], tt[1]);
+      // every (hints, workgroup size) pair; the fastest is kept
+      static const int kBlocks[3] = {64, 128, 256};
+      t_sweep = 0.0;
+      for (int h = 0; h < 2; ++h)
+        for (int bi = 0; bi < 3; ++bi) {
+          hints = h != 0;
+          c->L.block = kBlocks[bi];
+          double tt = 0.0;
+          if ((st = time_it(s, reps, one_sweep, &tt)) != GABP_OK) return st;
+          if (t_sweep == 0.0 || tt < t_sweep) {
+            t_sweep = tt;
+            t.hints = h;
+            t.block = kBlocks[bi];
+          }
+        }
       hints = t.hints != 0;
+      c->L.block = t.block;
     }
     // one residual check: residual kernel, reduction, readback and host wait
     double t_check = 0.0;
@@ -270,10 +287,12 @@ int gabp_autotune(gabp_ctx* c, int32_t* check_every_out, int32_t* hints_out, hip
     c->fresh32 = true;
   }
   hints = t.hints != 0;
+  if (!c->batch) c->L.block = t.block;
   c->opt.check_every = t.check_every;
   c->graphs->clear();
   if (check_every_out) *check_every_out = t.check_every;
   if (hints_out) *hints_out = t.hints;
+  if (block_out) *block_out = c->batch ? kBlock : c->L.block;
   return GABP_OK;
 }
 

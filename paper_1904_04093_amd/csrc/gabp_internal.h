@@ -37,6 +37,19 @@ constexpr int kBlock = 256;     // threads per block for row kernels (4 slices)
 constexpr int kRedBlock = 256;      // threads per block for reductions
 constexpr int kRevSelf16 = -32768;  // classed rev16: the slot is its own reverse
 constexpr int kMaxColours = 8;  // colour classes of the coloured schedule
+// Layout::row_slot packs a row's first slot (below 2^29) and its slice width (below 8)
+constexpr int kRowSlotShift = 29;
+constexpr unsigned kRowSlotMask = (1u << kRowSlotShift) - 1u;
+// Tiles of the two-sweep (temporally blocked) flood kernels: kTileSlices slices of 64 lanes
+// per tile, one thread per lane, plus kHaloThreads threads for the tile's halo rows (a
+// 5-point tile of 13 x 64 nodes has 154), in one workgroup of kTileThreads; rows of at most
+// kTileMaxWidth slots, so a tile's incoming messages fit in LDS (FP64 joint:
+// 2 x 8 B x 13 x 64 x 4 = 52 KiB)
+constexpr int kTileSlices = 13;
+constexpr int kTileLanes = kTileSlices * kSlice;
+constexpr int kHaloThreads = 192;
+constexpr int kTileThreads = kTileLanes + kHaloThreads;
+constexpr int kTileMaxWidth = 4;
 
 struct Precomp {
   bool valid = false;
@@ -70,6 +83,9 @@ struct Layout {
   // once a sweep's footprint exceeds the last-level cache and cost time below it
   bool stream_hints = false;
   bool stream_hints32 = false;
+  // threads per workgroup of the single-system sweep kernels: 64, 128 or 256 (1, 2 or 4
+  // slices), picked by the autotuner
+  int32_t block = kBlock;
   // device
   int32_t* sptr = nullptr;   // [nslices+1]
   int32_t* rev = nullptr;    // [epad]
@@ -100,7 +116,17 @@ struct Layout {
   int32_t* perm = nullptr;            // [nlanes] or null
   int32_t* lane_of_row_d = nullptr;   // [n] lane of each row, the inverse of perm, or null
   std::vector<int32_t> lane_of_row;   // host copy of the inverse (empty: identity)
+  // [n] for row-order kernels (the residual): first slot of row j | slice width << 29, or
+  // null when a slot index or width does not fit
+  int32_t* row_slot = nullptr;
   uint64_t hash = 0;                  // of the slot and lane layout (checkpoint check)
+  // tiled layout (opt.tiles): lanes tile-major, tile t = lanes [t, t + 1) * kTileLanes;
+  // halo of tile t = entries tile_halo[tile_hptr[t] .. tile_hptr[t + 1]) (rows outside the
+  // tile that send into it), each {first slot, slots, row, 0}
+  int32_t ntiles = 0;
+  int32_t tile_slots_max = 0;         // largest slot range of one tile
+  int32_t* tile_hptr = nullptr;       // [ntiles + 1]
+  int4* tile_halo = nullptr;
 };
 
 }  // namespace gabp
@@ -160,8 +186,10 @@ int hip_fail(hipError_t e, const char* what);
 // CSR check of gabp_validate_csr (host only, validate.cpp)
 int validate(int32_t n, int64_t nnz, const int32_t* rowptr, const int32_t* col,
              const double* val, const int32_t* rev);
-// Algorithm 3 (gabp_smooth); r_ready: c->r already holds b - A x for this x (solve.cpp)
-int smooth_from(gabp_ctx* c, const double* b, double* x, int mu, bool r_ready, hipStream_t s);
+// Algorithm 3 (gabp_smooth); r_ready: c->r already holds b - A x for this x; x_zero: x is
+// zero on entry and not read (solve.cpp)
+int smooth_from(gabp_ctx* c, const double* b, double* x, int mu, bool r_ready, bool x_zero,
+                hipStream_t s);
 #define GABP_HIP(call)                                           \
   do {                                                           \
     hipError_t _e = (call);                                      \
@@ -191,6 +219,8 @@ struct SweepArgs {
   // >= 0: first sweep after a message reset; incoming slot p counts only if rev(p) < fresh
   // (the slots of the colours already updated in this sweep), else its message is zero
   int fresh = -1;
+  double* xadd = nullptr;   // non-null: the read-off is added to xadd instead (x unused)
+  bool xset = false;        // with xadd: stored into xadd instead of added
 };
 hipError_t launch_joint_sweep(const SweepArgs& a, hipStream_t s);
 
@@ -204,6 +234,8 @@ struct MeanArgs64 {
   double* x;
   int colour;
   int fresh = -1;
+  double* xadd = nullptr;   // non-null: the read-off is added to xadd instead (x unused)
+  bool xset = false;        // with xadd: stored into xadd instead of added
 };
 hipError_t launch_mean_sweep64(const MeanArgs64& a, hipStream_t s);
 
@@ -217,8 +249,31 @@ struct MeanArgs32 {
   float* x;
   int colour;
   int fresh = -1;
+  double* xadd = nullptr;   // non-null: the FP32 read-off, widened, is added to xadd
+  bool xset = false;        // with xadd: stored into xadd instead of added
 };
 hipError_t launch_mean_sweep32(const MeanArgs32& a, hipStream_t s);
+
+// Two flood sweeps in one launch on a tiled layout (L.ntiles > 0): joint (SweepArgs with
+// colour -1) or mean-only with the Lt of the first sweep (lamA) and of the second (lamB,
+// with SxB its Sigma or 1/Sigma); read-off (x, xadd) of the second sweep.
+hipError_t launch_joint_pair(const SweepArgs& a, hipStream_t s);
+template <typename T>
+struct MeanPairArgs {
+  const Layout* L;
+  const T* lamA;
+  const T* lamB;
+  const T* SxB;
+  const T* b;
+  const T* msg_in;
+  T* msg_out;
+  T* x;
+  int fresh = -1;
+  double* xadd = nullptr;
+  bool xset = false;
+};
+hipError_t launch_mean_pair64(const MeanPairArgs<double>& a, hipStream_t s);
+hipError_t launch_mean_pair32(const MeanPairArgs<float>& a, hipStream_t s);
 
 // one Lt-only sweep; out[0] = max|dLt|, out[1] = max|Lt| over the sweep (device scalars);
 // partials needs 2 doubles per 256-row block
@@ -237,11 +292,11 @@ hipError_t launch_lambda_step(const Layout* L, const double* coef, const double*
 // r = b - A_eff x_eff, x_eff = x (+ scale[0] * dx if dx); writes r (if r) and block
 // partials; then reduces them into red[0..2].
 // norms == false: r only (per-block partials are still written, the reduction into red is
-// skipped), for callers that do not read the norms
+// skipped), for callers that do not read the norms; r32 (may be null): FP32 copy of r
 hipError_t launch_residual(const Layout* L, const double* coef_row, const double* b,
                            const double* x, const float* dx, const double* scale, double* r,
                            double* partials, int32_t nred, double* red, hipStream_t s,
-                           bool norms = true);
+                           bool norms = true, float* r32 = nullptr);
 
 hipError_t launch_copy_probe(const void* src, void* dst, int64_t bytes, hipStream_t s);
 // out[0] = max of partials[2q], out[1] = max of partials[2q+1] over q < nblk

@@ -83,15 +83,18 @@ __device__ __forceinline__ int rev_of(const int32_t* __restrict__ rev,
 // cleared beforehand): an incoming slot counts as written only if its sender's slot rev(p)
 // lies below `fresh` (the colour classes already updated in this sweep; 0 for a flood
 // sweep), every other incoming message is zero.
-template <int KMAX, bool WX, bool NT, bool R16, bool FIRST>
+// WX: 0 no read-off, 1 x_j = M_j / Sigma_j, 2 xadd_j += M_j / Sigma_j (the smoother's
+// error correction fused into its last sweep), 3 xadd_j = M_j / Sigma_j (a smoother
+// started from x = 0).
+template <int KMAX, int WX, bool NT, bool R16, bool FIRST>
 __global__ __launch_bounds__(kBlock) void k_joint(
     int t1, const int32_t* __restrict__ sptr, const int32_t* __restrict__ rev,
     const int16_t* __restrict__ rev16,
     const double* __restrict__ coef, const double* __restrict__ diag,
     const double* __restrict__ b, const double* lam_in, const double* msg_in,
     double* lam_out, double* msg_out, double* __restrict__ x, int t0, int fresh,
-    const int32_t* __restrict__ perm, int rshift) {
-  const int t = t0 + static_cast<int>(blockIdx.x) * kBlock + static_cast<int>(threadIdx.x);
+    const int32_t* __restrict__ perm, int rshift, double* __restrict__ xadd) {
+  const int t = t0 + static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x);
   if (t >= t1) return;
   const int j = row_of(perm, t);
   if (j < 0) return;
@@ -125,7 +128,9 @@ __global__ __launch_bounds__(kBlock) void k_joint(
         M += m[k];
       }
     }
-    if (WX) x[j] = M / S;
+    if constexpr (WX == 1) x[j] = M / S;
+    if constexpr (WX == 2) xadd[j] += M / S;
+    if constexpr (WX == 3) xadd[j] = M / S;
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) {
       if (k < w) {
@@ -144,7 +149,9 @@ __global__ __launch_bounds__(kBlock) void k_joint(
       S = fma(in(lam_in, p), coef[p], S);
       M += in(msg_in, p);
     }
-    if (WX) x[j] = M / S;
+    if constexpr (WX == 1) x[j] = M / S;
+    if constexpr (WX == 2) xadd[j] += M / S;
+    if constexpr (WX == 3) xadd[j] = M / S;
     for (int k = 0; k < w; ++k) {
       const int p = p0 + 64 * k;
       const double l = in(lam_in, p), a = coef[p], m = in(msg_in, p);
@@ -173,14 +180,14 @@ struct ReadOff<float> {
   }
 };
 
-template <typename T, int KMAX, bool WX, bool NT, bool R16, bool FIRST>
+template <typename T, int KMAX, int WX, bool NT, bool R16, bool FIRST>
 __global__ __launch_bounds__(kBlock) void k_mean(
     int t1, const int32_t* __restrict__ sptr, const int32_t* __restrict__ rev,
     const int16_t* __restrict__ rev16,
     const T* __restrict__ lamout, const T* __restrict__ Sx, const T* __restrict__ b,
     const T* msg_in, T* msg_out, T* __restrict__ x, int t0, int fresh,
-    const int32_t* __restrict__ perm, int rshift) {
-  const int t = t0 + static_cast<int>(blockIdx.x) * kBlock + static_cast<int>(threadIdx.x);
+    const int32_t* __restrict__ perm, int rshift, double* __restrict__ xadd) {
+  const int t = t0 + static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x);
   if (t >= t1) return;
   const int j = row_of(perm, t);
   if (j < 0) return;
@@ -203,7 +210,9 @@ __global__ __launch_bounds__(kBlock) void k_mean(
 #pragma unroll
     for (int k = 0; k < KMAX; ++k)
       if (k < w) M += m[k];
-    if (WX) x[j] = ReadOff<T>::f(M, Sx, j);
+    if constexpr (WX == 1) x[j] = ReadOff<T>::f(M, Sx, j);
+    if constexpr (WX == 2) xadd[j] += static_cast<double>(ReadOff<T>::f(M, Sx, j));
+    if constexpr (WX == 3) xadd[j] = static_cast<double>(ReadOff<T>::f(M, Sx, j));
 #pragma unroll
     for (int k = 0; k < KMAX; ++k)
       if (k < w) st_s<NT>(lo[k] * (M - m[k]), msg_out + r[k]);
@@ -213,12 +222,227 @@ __global__ __launch_bounds__(kBlock) void k_mean(
       else return msg_in[p];
     };
     for (int k = 0; k < w; ++k) M += in(p0 + 64 * k);
-    if (WX) x[j] = ReadOff<T>::f(M, Sx, j);
+    if constexpr (WX == 1) x[j] = ReadOff<T>::f(M, Sx, j);
+    if constexpr (WX == 2) xadd[j] += static_cast<double>(ReadOff<T>::f(M, Sx, j));
+    if constexpr (WX == 3) xadd[j] = static_cast<double>(ReadOff<T>::f(M, Sx, j));
     for (int k = 0; k < w; ++k) {
       const int p = p0 + 64 * k;
       msg_out[rev_of<false, R16>(rev, rev16, p, rshift)] = lamout[p] * (M - in(p));
     }
   }
+}
+
+// ---------------------------------------------------------------------------------------
+// Two flood sweeps in one pass (temporal blocking) over a tiled layout: one workgroup per
+// tile (kTileSlices slices of 64 lanes). The first kTileLanes threads own the tile's rows,
+// the last kHaloThreads its halo (the rows outside the tile that send into it, given by
+// {first slot, slots, row}). Sweep 1 runs for both; of the messages it sends, those into
+// the tile go to LDS and the rest are dropped (the tiles they belong to compute them for
+// themselves). Sweep 2 runs for the tile's rows from the LDS messages and writes its
+// messages to the output buffers like a plain sweep. Same operations in the same order as
+// two plain sweeps, so the results are the same bits; HBM traffic is about one sweep's plus
+// the halo's.
+// ---------------------------------------------------------------------------------------
+template <int WX, bool NT, bool FIRST>
+__global__ __launch_bounds__(kTileThreads) void k_joint2(
+    const int32_t* __restrict__ sptr, const int32_t* __restrict__ rev,
+    const int32_t* __restrict__ hptr, const int4* __restrict__ halo,
+    const double* __restrict__ coef, const double* __restrict__ diag,
+    const double* __restrict__ b, const double* lam_in, const double* msg_in,
+    double* lam_out, double* msg_out, double* __restrict__ x,
+    const int32_t* __restrict__ perm, double* __restrict__ xadd, int slots_max) {
+  extern __shared__ double lds[];
+  double* Ls = lds;
+  double* Ms = lds + slots_max;
+  const int tile = blockIdx.x;
+  const int ts0 = sptr[tile * kTileSlices];
+  const unsigned nts = static_cast<unsigned>(sptr[(tile + 1) * kTileSlices] - ts0);
+  const bool own = threadIdx.x < kTileLanes;
+  // own rows: coefficients, reverse slots, diagonal and b stay in registers for sweep 2
+  double a[kTileMaxWidth], l[kTileMaxWidth], m[kTileMaxWidth];
+  int r[kTileMaxWidth];
+  int w = 0, p0 = 0, j = -1;
+  double dj = 0.0, bj = 0.0;
+  if (own) {
+    const int tl = tile * kTileLanes + static_cast<int>(threadIdx.x);
+    j = perm[tl];
+    if (j >= 0) {
+      p0 = row_base(sptr, tl, &w);
+      dj = diag[j];
+      bj = b[j];
+#pragma unroll
+      for (int k = 0; k < kTileMaxWidth; ++k) {
+        if (k < w) {
+          const int p = p0 + 64 * k;
+          a[k] = ld_s<NT>(coef + p);
+          r[k] = ld_s<NT>(rev + p);
+          l[k] = FIRST ? 0.0 : ld_s<NT>(lam_in + p);
+          m[k] = FIRST ? 0.0 : ld_s<NT>(msg_in + p);
+        }
+      }
+    }
+  }
+  // sweep 1: own rows (every message into the tile) and halo rows (their messages into it)
+  auto send1 = [&](int wd, double S, double M) {
+#pragma unroll
+    for (int k = 0; k < kTileMaxWidth; ++k) {
+      const unsigned q = static_cast<unsigned>(r[k] - ts0);
+      if (k < wd && q < nts) {
+        const double L = -a[k] / (S - l[k] * a[k]);
+        Ls[q] = L;
+        Ms[q] = L * (M - m[k]);
+      }
+    }
+  };
+  if (own) {
+    if (j >= 0) {
+      double S = dj, M = bj;
+#pragma unroll
+      for (int k = 0; k < kTileMaxWidth; ++k) {
+        if (k < w) {
+          S = fma(l[k], a[k], S);
+          M += m[k];
+        }
+      }
+      send1(w, S, M);
+    }
+  } else {
+    const int h0 = hptr[tile], nh = hptr[tile + 1] - h0;
+    for (int e = threadIdx.x - kTileLanes; e < nh; e += kHaloThreads) {
+      const int4 h = halo[h0 + e];   // {first slot, slots, row, -}
+#pragma unroll
+      for (int k = 0; k < kTileMaxWidth; ++k) {
+        if (k < h.y) {
+          const int p = h.x + 64 * k;
+          a[k] = coef[p];
+          r[k] = rev[p];
+          l[k] = FIRST ? 0.0 : lam_in[p];
+          m[k] = FIRST ? 0.0 : msg_in[p];
+        }
+      }
+      double S = diag[h.z], M = b[h.z];
+#pragma unroll
+      for (int k = 0; k < kTileMaxWidth; ++k) {
+        if (k < h.y) {
+          S = fma(l[k], a[k], S);
+          M += m[k];
+        }
+      }
+      send1(h.y, S, M);
+    }
+  }
+  __syncthreads();
+  if (j < 0) return;
+  // sweep 2 of the own rows, from the LDS messages
+  double S = dj, M = bj;
+#pragma unroll
+  for (int k = 0; k < kTileMaxWidth; ++k) {
+    if (k < w) {
+      const int q = p0 + 64 * k - ts0;
+      l[k] = Ls[q];
+      m[k] = Ms[q];
+      S = fma(l[k], a[k], S);
+      M += m[k];
+    }
+  }
+  if constexpr (WX == 1) x[j] = M / S;
+  if constexpr (WX == 2) xadd[j] += M / S;
+  if constexpr (WX == 3) xadd[j] = M / S;
+#pragma unroll
+  for (int k = 0; k < kTileMaxWidth; ++k) {
+    if (k < w) {
+      const double L = -a[k] / (S - l[k] * a[k]);
+      st_s<NT>(L, lam_out + r[k]);
+      st_s<NT>(L * (M - m[k]), msg_out + r[k]);
+    }
+  }
+}
+
+// Mean-only form (frozen or per-sweep precomputed Lt): sweep 1 sends with lamA, sweep 2
+// reads off with SxB (Sigma, or 1/Sigma for FP32) and sends with lamB.
+template <typename T, int WX, bool NT, bool FIRST>
+__global__ __launch_bounds__(kTileThreads) void k_mean2(
+    const int32_t* __restrict__ sptr, const int32_t* __restrict__ rev,
+    const int32_t* __restrict__ hptr, const int4* __restrict__ halo,
+    const T* __restrict__ lamA, const T* __restrict__ lamB, const T* __restrict__ SxB,
+    const T* __restrict__ b, const T* msg_in, T* msg_out, T* __restrict__ x,
+    const int32_t* __restrict__ perm, double* __restrict__ xadd) {
+  extern __shared__ double lds_raw[];
+  T* Ms = reinterpret_cast<T*>(lds_raw);
+  const int tile = blockIdx.x;
+  const int ts0 = sptr[tile * kTileSlices];
+  const unsigned nts = static_cast<unsigned>(sptr[(tile + 1) * kTileSlices] - ts0);
+  const bool own = threadIdx.x < kTileLanes;
+  T lo[kTileMaxWidth], lb[kTileMaxWidth], m[kTileMaxWidth];
+  int r[kTileMaxWidth];
+  int w = 0, p0 = 0, j = -1;
+  T bj = T(0);
+  if (own) {
+    const int tl = tile * kTileLanes + static_cast<int>(threadIdx.x);
+    j = perm[tl];
+    if (j >= 0) {
+      p0 = row_base(sptr, tl, &w);
+      bj = b[j];
+#pragma unroll
+      for (int k = 0; k < kTileMaxWidth; ++k) {
+        if (k < w) {
+          const int p = p0 + 64 * k;
+          lo[k] = ld_s<NT>(lamA + p);
+          lb[k] = lamB == lamA ? lo[k] : ld_s<NT>(lamB + p);
+          r[k] = ld_s<NT>(rev + p);
+          m[k] = FIRST ? T(0) : ld_s<NT>(msg_in + p);
+        }
+      }
+      T M = bj;
+#pragma unroll
+      for (int k = 0; k < kTileMaxWidth; ++k)
+        if (k < w) M += m[k];
+#pragma unroll
+      for (int k = 0; k < kTileMaxWidth; ++k) {
+        const unsigned q = static_cast<unsigned>(r[k] - ts0);
+        if (k < w && q < nts) Ms[q] = lo[k] * (M - m[k]);
+      }
+    }
+  } else {
+    const int h0 = hptr[tile], nh = hptr[tile + 1] - h0;
+    for (int e = threadIdx.x - kTileLanes; e < nh; e += kHaloThreads) {
+      const int4 h = halo[h0 + e];
+#pragma unroll
+      for (int k = 0; k < kTileMaxWidth; ++k) {
+        if (k < h.y) {
+          const int p = h.x + 64 * k;
+          lo[k] = lamA[p];
+          r[k] = rev[p];
+          m[k] = FIRST ? T(0) : msg_in[p];
+        }
+      }
+      T M = b[h.z];
+#pragma unroll
+      for (int k = 0; k < kTileMaxWidth; ++k)
+        if (k < h.y) M += m[k];
+#pragma unroll
+      for (int k = 0; k < kTileMaxWidth; ++k) {
+        const unsigned q = static_cast<unsigned>(r[k] - ts0);
+        if (k < h.y && q < nts) Ms[q] = lo[k] * (M - m[k]);
+      }
+    }
+  }
+  __syncthreads();
+  if (j < 0) return;
+  T M = bj;
+#pragma unroll
+  for (int k = 0; k < kTileMaxWidth; ++k) {
+    if (k < w) {
+      m[k] = Ms[p0 + 64 * k - ts0];
+      M += m[k];
+    }
+  }
+  if constexpr (WX == 1) x[j] = ReadOff<T>::f(M, SxB, j);
+  if constexpr (WX == 2) xadd[j] += static_cast<double>(ReadOff<T>::f(M, SxB, j));
+  if constexpr (WX == 3) xadd[j] = static_cast<double>(ReadOff<T>::f(M, SxB, j));
+#pragma unroll
+  for (int k = 0; k < kTileMaxWidth; ++k)
+    if (k < w) st_s<NT>(lb[k] * (M - m[k]), msg_out + r[k]);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -399,15 +623,22 @@ __global__ __launch_bounds__(kRedBlock) void k_residual(
     const double* __restrict__ coef_row, const double* __restrict__ diag,
     const double* __restrict__ b, const double* __restrict__ x, const float* __restrict__ dx,
     const double* __restrict__ scale, double* __restrict__ r, double* __restrict__ partials,
-    const int32_t* __restrict__ lane_of_row) {
+    const int32_t* __restrict__ lane_of_row, float* __restrict__ r32,
+    const int32_t* __restrict__ row_slot) {
   __shared__ double sh[3][kRedBlock / 64];
   const int blk = xcd_block(blockIdx.x, gridDim.x);   // row range and partials slot
   const int t = blk * kRedBlock + threadIdx.x;
   double rr = 0.0, ra = 0.0, bb = 0.0;
   const int j = t < n ? t : -1;   // n: rows
   if (j >= 0) {
-    int w;
-    const int p0 = row_base(sptr, lane_of_row ? lane_of_row[j] : j, &w);
+    int w, p0;
+    if (row_slot) {   // first slot and slice width of row j, packed: one load, no sptr
+      const unsigned v = static_cast<unsigned>(row_slot[j]);
+      p0 = static_cast<int>(v & kRowSlotMask);
+      w = static_cast<int>(v >> kRowSlotShift);
+    } else {
+      p0 = row_base(sptr, lane_of_row ? lane_of_row[j] : j, &w);
+    }
     const double sc = XADD ? scale[0] : 0.0;
     double xj = x[j];
     if (XADD) xj = fma(sc, static_cast<double>(dx[j]), xj);
@@ -442,6 +673,7 @@ __global__ __launch_bounds__(kRedBlock) void k_residual(
       }
     }
     if (r) r[j] = acc;
+    if (r32) r32[j] = static_cast<float>(acc);
     rr = acc * acc;
     ra = fabs(acc);
     if (ra != ra) ra = INFINITY;
@@ -708,6 +940,11 @@ int grid_for(int64_t n) {
 #define GABP_DISPATCH_FIRST(FV, ...)                    \
   if (FV) { constexpr bool FB = true; __VA_ARGS__; }  \
   else { constexpr bool FB = false; __VA_ARGS__; }
+#define GABP_DISPATCH_WX(WV, ...)                                    \
+  if ((WV) == 3) { constexpr int WXB = 3; __VA_ARGS__; }             \
+  else if ((WV) == 2) { constexpr int WXB = 2; __VA_ARGS__; }        \
+  else if ((WV) == 1) { constexpr int WXB = 1; __VA_ARGS__; }        \
+  else { constexpr int WXB = 0; __VA_ARGS__; }
 
 // Whether a sweep over colour class c (-1: all lanes) reads the int16 reverse deltas, and
 // the shift they are taken from: a flood sweep over a classed layout reads rev instead.
@@ -731,27 +968,21 @@ hipError_t launch_joint_sweep(const SweepArgs& a, hipStream_t s) {
   int t0, t1;
   lane_range(L, a.colour, &t0, &t1);
   if (t1 <= t0) return hipSuccess;
-  const int g = nblocks(t1 - t0);
+  const int blk = L.block;
+  const int g = nblocks(t1 - t0, blk);
 #define JOINT_ARGS                                                                      \
   t1, L.sptr, L.rev, L.rev16, a.coef, L.diag, a.b, a.lam_in, a.msg_in, a.lam_out,        \
-      a.msg_out, a.x, t0, a.fresh, L.perm, rshift
+      a.msg_out, a.x, t0, a.fresh, L.perm, rshift, a.xadd
   int rshift;
   const bool r16 = use_rev16(L, a.colour, &rshift);
-  GABP_DISPATCH_FIRST(a.fresh >= 0, GABP_DISPATCH_NT(L.stream_hints, GABP_DISPATCH_R16(r16, {
-    if (a.x) {
+  GABP_DISPATCH_FIRST(a.fresh >= 0, GABP_DISPATCH_NT(L.stream_hints, GABP_DISPATCH_R16(r16,
+    GABP_DISPATCH_WX(a.xadd ? (a.xset ? 3 : 2) : (a.x ? 1 : 0), {
       GABP_DISPATCH_WIDTH(L.max_width,
-                          (k_joint<4, true, NTB, R16B, FB><<<g, kBlock, 0, s>>>(JOINT_ARGS)),
-                          (k_joint<8, true, NTB, R16B, FB><<<g, kBlock, 0, s>>>(JOINT_ARGS)),
-                          (k_joint<16, true, NTB, R16B, FB><<<g, kBlock, 0, s>>>(JOINT_ARGS)),
-                          (k_joint<0, true, NTB, R16B, FB><<<g, kBlock, 0, s>>>(JOINT_ARGS)));
-    } else {
-      GABP_DISPATCH_WIDTH(L.max_width,
-                          (k_joint<4, false, NTB, R16B, FB><<<g, kBlock, 0, s>>>(JOINT_ARGS)),
-                          (k_joint<8, false, NTB, R16B, FB><<<g, kBlock, 0, s>>>(JOINT_ARGS)),
-                          (k_joint<16, false, NTB, R16B, FB><<<g, kBlock, 0, s>>>(JOINT_ARGS)),
-                          (k_joint<0, false, NTB, R16B, FB><<<g, kBlock, 0, s>>>(JOINT_ARGS)));
-    }
-  })))
+                          (k_joint<4, WXB, NTB, R16B, FB><<<g, blk, 0, s>>>(JOINT_ARGS)),
+                          (k_joint<8, WXB, NTB, R16B, FB><<<g, blk, 0, s>>>(JOINT_ARGS)),
+                          (k_joint<16, WXB, NTB, R16B, FB><<<g, blk, 0, s>>>(JOINT_ARGS)),
+                          (k_joint<0, WXB, NTB, R16B, FB><<<g, blk, 0, s>>>(JOINT_ARGS)));
+    }))))
 #undef JOINT_ARGS
   return hipGetLastError();
 }
@@ -761,29 +992,62 @@ hipError_t mean_dispatch(const Layout& L, const A& a, const T* Sx, bool nt, hipS
   int t0, t1;
   lane_range(L, a.colour, &t0, &t1);
   if (t1 <= t0) return hipSuccess;
-  const int g = nblocks(t1 - t0);
+  const int blk = L.block;
+  const int g = nblocks(t1 - t0, blk);
 #define MEAN_ARGS \
   t1, L.sptr, L.rev, L.rev16, a.lamout, Sx, a.b, a.msg_in, a.msg_out, a.x, t0, a.fresh, L.perm, \
-      rshift
+      rshift, a.xadd
   int rshift;
   const bool r16 = use_rev16(L, a.colour, &rshift);
-  GABP_DISPATCH_FIRST(a.fresh >= 0, GABP_DISPATCH_NT(nt, GABP_DISPATCH_R16(r16, {
-    if (a.x) {
+  GABP_DISPATCH_FIRST(a.fresh >= 0, GABP_DISPATCH_NT(nt, GABP_DISPATCH_R16(r16,
+    GABP_DISPATCH_WX(a.xadd ? (a.xset ? 3 : 2) : (a.x ? 1 : 0), {
       GABP_DISPATCH_WIDTH(L.max_width,
-                          (k_mean<T, 4, true, NTB, R16B, FB><<<g, kBlock, 0, s>>>(MEAN_ARGS)),
-                          (k_mean<T, 8, true, NTB, R16B, FB><<<g, kBlock, 0, s>>>(MEAN_ARGS)),
-                          (k_mean<T, 16, true, NTB, R16B, FB><<<g, kBlock, 0, s>>>(MEAN_ARGS)),
-                          (k_mean<T, 0, true, NTB, R16B, FB><<<g, kBlock, 0, s>>>(MEAN_ARGS)));
-    } else {
-      GABP_DISPATCH_WIDTH(L.max_width,
-                          (k_mean<T, 4, false, NTB, R16B, FB><<<g, kBlock, 0, s>>>(MEAN_ARGS)),
-                          (k_mean<T, 8, false, NTB, R16B, FB><<<g, kBlock, 0, s>>>(MEAN_ARGS)),
-                          (k_mean<T, 16, false, NTB, R16B, FB><<<g, kBlock, 0, s>>>(MEAN_ARGS)),
-                          (k_mean<T, 0, false, NTB, R16B, FB><<<g, kBlock, 0, s>>>(MEAN_ARGS)));
-    }
-  })))
+                          (k_mean<T, 4, WXB, NTB, R16B, FB><<<g, blk, 0, s>>>(MEAN_ARGS)),
+                          (k_mean<T, 8, WXB, NTB, R16B, FB><<<g, blk, 0, s>>>(MEAN_ARGS)),
+                          (k_mean<T, 16, WXB, NTB, R16B, FB><<<g, blk, 0, s>>>(MEAN_ARGS)),
+                          (k_mean<T, 0, WXB, NTB, R16B, FB><<<g, blk, 0, s>>>(MEAN_ARGS)));
+    }))))
 #undef MEAN_ARGS
   return hipGetLastError();
+}
+
+hipError_t launch_joint_pair(const SweepArgs& a, hipStream_t s) {
+  const Layout& L = *a.L;
+  if (L.ntiles <= 0) return hipErrorInvalidValue;
+  const size_t lds = 2 * static_cast<size_t>(L.tile_slots_max) * sizeof(double);
+#define JOINT2_ARGS                                                                         \
+  L.sptr, L.rev, L.tile_hptr, L.tile_halo, a.coef, L.diag, a.b, a.lam_in, a.msg_in,          \
+      a.lam_out, a.msg_out, a.x, L.perm, a.xadd, L.tile_slots_max
+  GABP_DISPATCH_FIRST(a.fresh >= 0, GABP_DISPATCH_NT(L.stream_hints,
+    GABP_DISPATCH_WX(a.xadd ? (a.xset ? 3 : 2) : (a.x ? 1 : 0), {
+      k_joint2<WXB, NTB, FB><<<L.ntiles, kTileThreads, lds, s>>>(JOINT2_ARGS);
+    })))
+#undef JOINT2_ARGS
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t mean_pair_dispatch(const MeanPairArgs<T>& a, bool nt, hipStream_t s) {
+  const Layout& L = *a.L;
+  if (L.ntiles <= 0) return hipErrorInvalidValue;
+  const size_t lds = static_cast<size_t>(L.tile_slots_max) * sizeof(T);
+#define MEAN2_ARGS                                                                          \
+  L.sptr, L.rev, L.tile_hptr, L.tile_halo, a.lamA, a.lamB, a.SxB, a.b, a.msg_in, a.msg_out,  \
+      a.x, L.perm, a.xadd
+  GABP_DISPATCH_FIRST(a.fresh >= 0, GABP_DISPATCH_NT(nt,
+    GABP_DISPATCH_WX(a.xadd ? (a.xset ? 3 : 2) : (a.x ? 1 : 0), {
+      k_mean2<T, WXB, NTB, FB><<<L.ntiles, kTileThreads, lds, s>>>(MEAN2_ARGS);
+    })))
+#undef MEAN2_ARGS
+  return hipGetLastError();
+}
+
+hipError_t launch_mean_pair64(const MeanPairArgs<double>& a, hipStream_t s) {
+  return mean_pair_dispatch<double>(a, a.L->stream_hints, s);
+}
+
+hipError_t launch_mean_pair32(const MeanPairArgs<float>& a, hipStream_t s) {
+  return mean_pair_dispatch<float>(a, a.L->stream_hints32, s);
 }
 
 hipError_t launch_mean_sweep64(const MeanArgs64& a, hipStream_t s) {
@@ -839,9 +1103,10 @@ hipError_t launch_lambda_step(const Layout* Lp, const double* coef, const double
 hipError_t launch_residual(const Layout* Lp, const double* coef_row, const double* b,
                            const double* x, const float* dx, const double* scale, double* r,
                            double* partials, int32_t nred, double* red, hipStream_t s,
-                           bool norms) {
+                           bool norms, float* r32) {
   const Layout& L = *Lp;
-#define RES_ARGS(DX, SC) L.n, L.sptr, L.col, coef_row, L.diag, b, x, DX, SC, r, partials, L.lane_of_row_d
+#define RES_ARGS(DX, SC) \
+  L.n, L.sptr, L.col, coef_row, L.diag, b, x, DX, SC, r, partials, L.lane_of_row_d, r32, L.row_slot
   if (dx) {
     GABP_DISPATCH_WIDTH(L.max_width,
                         (k_residual<4, true><<<nred, kRedBlock, 0, s>>>(RES_ARGS(dx, scale))),

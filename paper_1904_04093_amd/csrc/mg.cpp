@@ -100,28 +100,32 @@ int dense_of(gabp_ctx* c, std::vector<double>& A, hipStream_t s) {
 }
 
 int smooth(mg_ctx* m, int l, const double* b, double* x, int nu, hipStream_t s,
-           bool r_ready = false) {
+           bool r_ready = false, bool x_zero = false) {
   if (nu <= 0) return GABP_OK;
   gabp_ctx* c = m->lv[l];
-  if (m->smoother == 0) return smooth_from(c, b, x, nu, r_ready, s);
+  if (m->smoother == 0) return smooth_from(c, b, x, nu, r_ready, x_zero, s);
   for (int it = 0; it < nu; ++it)
     for (int col = 0; col < 2; ++col) GABP_HIP(launch_rbgs(&c->L, m->side[l], col, b, x, s));
   return GABP_OK;
 }
 
-int vcycle(mg_ctx* m, int l, const double* b, double* x, hipStream_t s, bool r_ready = false) {
+// x_zero: the coarse levels' error equations start from x = 0; x is then not read (and
+// not cleared) unless the pre-smoother needs it (RB-GS, or no pre-smoothing)
+int vcycle(mg_ctx* m, int l, const double* b, double* x, hipStream_t s, bool r_ready = false,
+           bool x_zero = false) {
   int st;
   if (l == m->levels - 1) {
     GABP_HIP(launch_dense_matvec(m->nc, m->inv, b, x, s));
     return GABP_OK;
   }
   gabp_ctx* c = m->lv[l];
-  if ((st = smooth(m, l, b, x, m->nu1, s, r_ready)) != GABP_OK) return st;
+  const bool gabp_from_zero = x_zero && m->smoother == 0 && m->nu1 > 0;
+  if (x_zero && !gabp_from_zero) GABP_HIP(launch_fill64(x, c->L.n, 0.0, s));
+  if ((st = smooth(m, l, b, x, m->nu1, s, r_ready, gabp_from_zero)) != GABP_OK) return st;
   GABP_HIP(launch_residual(&c->L, c->L.val, b, x, nullptr, nullptr, m->r[l], c->partials,
                            c->nred, c->red, s, false));
   GABP_HIP(launch_restrict_fw(m->side[l + 1], m->r[l], m->b[l + 1], s));
-  GABP_HIP(launch_fill64(m->x[l + 1], m->lv[l + 1]->L.n, 0.0, s));
-  if ((st = vcycle(m, l + 1, m->b[l + 1], m->x[l + 1], s)) != GABP_OK) return st;
+  if ((st = vcycle(m, l + 1, m->b[l + 1], m->x[l + 1], s, false, true)) != GABP_OK) return st;
   GABP_HIP(launch_prolong_add(m->side[l + 1], m->x[l + 1], x, s));
   return smooth(m, l, b, x, m->nu2, s);
 }

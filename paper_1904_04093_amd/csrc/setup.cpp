@@ -64,6 +64,8 @@ void gabp_default_options(gabp_options* o) {
   o->use_graphs = 1;
   o->grid_nx = 0;
   o->grid_ny = 0;
+  o->block = kBlock;
+  o->tiles = 0;
   o->progress_s = 0.0;
 }
 
@@ -83,6 +85,7 @@ int gabp_setup(gabp_ctx** out, int32_t n, int64_t nnz, const int32_t* rowptr,
       (o.precision != GABP_F64 && o.precision != GABP_F32_IR) ||
       (o.schedule < GABP_SCHED_FLOOD || o.schedule > GABP_SCHED_LINES_ALT) ||
       o.ir_max_inner < 1 || !(o.progress_s >= 0.0) ||
+      (o.block != 64 && o.block != 128 && o.block != 256) || (o.tiles != 0 && o.tiles != 1) ||
       !(o.ir_inner_tol > 0.0))
     return fail(GABP_EINVAL, "invalid options");
   if (o.schedule == GABP_SCHED_REDBLACK && !colour)
@@ -181,8 +184,41 @@ int gabp_setup(gabp_ctx** out, int32_t n, int64_t nnz, const int32_t* rowptr,
       row_of_lane[t] = j;
     }
   }
+  // --- tiles (temporal blocking, flood schedule on a grid): lanes tile-major, each tile
+  // kTileSlices slices of 64 x-consecutive nodes of kTileSlices consecutive grid rows,
+  // padded with empty lanes past the grid's right and top edges
+  const bool tiled = o.tiles != 0;
+  int32_t tiles_x = 0, tiles_y = 0;
+  if (tiled) {
+    if (colour || o.schedule != GABP_SCHED_FLOOD)
+      return fail(GABP_EINVAL, "tiles need the flood schedule (no colouring)");
+    if (o.grid_nx < 1 || o.grid_ny < 1 || static_cast<int64_t>(o.grid_nx) * o.grid_ny != n)
+      return fail(GABP_EINVAL, "tiles need grid_nx * grid_ny == n");
+    if (max_w > kTileMaxWidth)
+      return fail(GABP_ENOTSUPP, "tiles need rows of at most " + std::to_string(kTileMaxWidth) +
+                                     " off-diagonal neighbours (5-point grids)");
+    tiles_x = (o.grid_nx + kSlice - 1) / kSlice;
+    tiles_y = (o.grid_ny + kTileSlices - 1) / kTileSlices;
+    nlanes = static_cast<int64_t>(tiles_x) * tiles_y * kTileSlices * kSlice;
+    if (nlanes >= std::numeric_limits<int32_t>::max() - kBlock)
+      return fail(GABP_ENOTSUPP, "too many rows for a tiled layout");
+    lane_of_row.assign(n, -1);
+    row_of_lane.assign(static_cast<size_t>(nlanes), -1);
+    for (int32_t ty = 0; ty < tiles_y; ++ty)
+      for (int32_t tx = 0; tx < tiles_x; ++tx)
+        for (int32_t r = 0; r < kTileSlices; ++r)
+          for (int32_t cx = 0; cx < kSlice; ++cx) {
+            const int64_t x = static_cast<int64_t>(tx) * kSlice + cx;
+            const int64_t y = static_cast<int64_t>(ty) * kTileSlices + r;
+            if (x >= o.grid_nx || y >= o.grid_ny) continue;
+            const int64_t t = ((static_cast<int64_t>(ty) * tiles_x + tx) * kTileSlices + r) * kSlice + cx;
+            const int32_t j = static_cast<int32_t>(y * o.grid_nx + x);
+            lane_of_row[j] = static_cast<int32_t>(t);
+            row_of_lane[t] = j;
+          }
+  }
   auto row_at = [&](int64_t t) -> int32_t {
-    return colour ? row_of_lane[t] : (t < n ? static_cast<int32_t>(t) : -1);
+    return !row_of_lane.empty() ? row_of_lane[t] : (t < n ? static_cast<int32_t>(t) : -1);
   };
   // --- slices of 64 lanes, column-major inside a slice
   const int32_t nslices = static_cast<int32_t>((nlanes + kSlice - 1) / kSlice);
@@ -295,6 +331,7 @@ int gabp_setup(gabp_ctx** out, int32_t n, int64_t nnz, const int32_t* rowptr,
   L.nslices = nslices;
   L.nlanes = static_cast<int32_t>(nlanes);
   L.max_width = max_w;
+  L.block = o.block;
   // footprint of one FP64 joint sweep (44 B per slot, 16 B per row) and one FP32 mean
   // sweep (16 B per slot, 4 B per row) against the 256 MiB last-level cache
   constexpr double kLLC = 256.0 * 1024 * 1024;
@@ -322,10 +359,67 @@ int gabp_setup(gabp_ctx** out, int32_t n, int64_t nnz, const int32_t* rowptr,
   UP(L.diag_src, diag_src);
   UP(L.csr_row, h_row);
   UP(L.csr_col, h_ccol);
-  if (colour) {
+  std::vector<int32_t> row_slot;
+  if (epad < (int64_t(1) << kRowSlotShift) && max_w < (1 << (32 - kRowSlotShift))) {
+    row_slot.resize(n);
+    for (int32_t j = 0; j < n; ++j) {
+      const int64_t t = lane_of_row.empty() ? j : lane_of_row[j];
+      const int64_t sl = t / kSlice;
+      const int64_t w = (sptr64[sl + 1] - sptr64[sl]) / kSlice;
+      row_slot[j] = static_cast<int32_t>((sptr64[sl] + t % kSlice) | (w << kRowSlotShift));
+    }
+    UP(L.row_slot, row_slot);
+  }
+  if (!row_of_lane.empty()) {
     UP(L.perm, row_of_lane);
     UP(L.lane_of_row_d, lane_of_row);
     L.lane_of_row = lane_of_row;
+  }
+  // (kept until the end of set-up: the uploads below are asynchronous)
+  std::vector<int32_t> hptr, hlane;
+  std::vector<int4> halo;
+  if (tiled) {
+    // halo of each tile: the rows outside it that send into it (neighbours of its rows in
+    // the symmetrised pattern), in ascending lane order, each as {first slot, slots, row}
+    const int32_t ntiles = tiles_x * tiles_y;
+    hptr.assign(ntiles + 1, 0);
+    std::vector<int32_t> mark(static_cast<size_t>(nlanes), -1);
+    int32_t slots_max = 0;
+    for (int32_t t = 0; t < ntiles; ++t) {
+      const int64_t l0 = static_cast<int64_t>(t) * kTileSlices * kSlice;
+      const int64_t l1 = l0 + kTileSlices * kSlice;
+      std::vector<int32_t> h;
+      for (int64_t ln = l0; ln < l1; ++ln) {
+        const int32_t j = row_of_lane[ln];
+        if (j < 0) continue;
+        for (int64_t u = uptr[j]; u < uptr[j + 1]; ++u) {
+          const int32_t li = lane_of_row[unbr[u]];
+          if ((li < l0 || li >= l1) && mark[li] != t) {
+            mark[li] = t;
+            h.push_back(li);
+          }
+        }
+      }
+      std::sort(h.begin(), h.end());
+      hlane.insert(hlane.end(), h.begin(), h.end());
+      hptr[t + 1] = static_cast<int32_t>(hlane.size());
+      slots_max = std::max<int32_t>(
+          slots_max, static_cast<int32_t>(sptr64[(t + 1) * kTileSlices] - sptr64[t * kTileSlices]));
+    }
+    UP(L.tile_hptr, hptr);
+    halo.assign(std::max<size_t>(hlane.size(), 1), int4{0, 0, 0, 0});
+    for (size_t q = 0; q < hlane.size(); ++q) {
+      const int64_t t = hlane[q];
+      const int64_t sl = t / kSlice;
+      halo[q] = int4{static_cast<int32_t>(sptr64[sl] + t % kSlice),
+                     static_cast<int32_t>((sptr64[sl + 1] - sptr64[sl]) / kSlice),
+                     row_of_lane[t], 0};
+    }
+    UP(L.tile_halo, halo);
+    L.ntiles = ntiles;
+    L.tile_slots_max = slots_max;
+  }
+  if (colour) {
     L.ncolours = ncolours;
     L.cstart = cstart;
     L.cslot.resize(cstart.size());
@@ -340,7 +434,7 @@ int gabp_setup(gabp_ctx** out, int32_t n, int64_t nnz, const int32_t* rowptr,
         h *= 1099511628211ull;
       }
     };
-    mix(n); mix(epad); mix(nlanes); mix(ncolours);
+    mix(n); mix(epad); mix(nlanes); mix(ncolours); mix(tiled ? 1 : 0);
     for (int32_t q = 0; q <= nslices; ++q) mix(sptr64[q]);
     for (int32_t t : lane_of_row) mix(t);
     L.hash = h;
@@ -406,6 +500,7 @@ void gabp_destroy(gabp_ctx* c) {
   Layout& L = c->L;
   F(L.sptr); F(L.rev); F(L.rev16); F(L.col); F(L.val); F(L.aT); F(L.diag); F(L.val_src); F(L.aT_src);
   F(L.diag_src); F(L.csr_row); F(L.csr_col); F(L.perm); F(L.lane_of_row_d);
+  F(L.tile_hptr); F(L.tile_halo); F(L.row_slot);
   for (int q = 0; q < 2; ++q) {
     F(c->lam[q]); F(c->msg[q]); F(c->msg32[q]);
     F(c->pre[q].lamout); F(c->pre[q].S); F(c->pre[q].lamout32); F(c->pre[q].invS32);

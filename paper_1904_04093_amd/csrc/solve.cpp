@@ -116,9 +116,10 @@ inline const double* sweep_coef(const gabp_ctx* c, int T) { return T ? c->L.val 
 inline const double* row_coef(const gabp_ctx* c, int T) { return T ? c->L.aT : c->L.val; }
 
 int residual(gabp_ctx* c, int T, const double* b, const double* x, const float* dx,
-             const double* scale, double* r, hipStream_t s, bool norms = true) {
+             const double* scale, double* r, hipStream_t s, bool norms = true,
+             float* r32 = nullptr) {
   GABP_HIP(launch_residual(&c->L, row_coef(c, T), b, x, dx, scale, r, c->partials, c->nred,
-                           c->red, s, norms));
+                           c->red, s, norms, r32));
   return GABP_OK;
 }
 
@@ -183,14 +184,24 @@ constexpr double kPoison = std::numeric_limits<double>::quiet_NaN();
 
 // One FP64 sweep of the configured mode and schedule on right-hand side b (coloured
 // schedule: the colour classes 0, 1, ... in turn, in place).
-// x != null: the read-off of this sweep is written there.
-int sweep64(gabp_ctx* c, int T, const double* b, double* x, hipStream_t s) {
-  if (c->lines) return line_sweep64(c, T, b, x, s);
+// x != null: the read-off of this sweep is written there; xadd != null instead: the
+// read-off is added to xadd (xset: stored into it).
+int sweep64(gabp_ctx* c, int T, const double* b, double* x, hipStream_t s,
+            double* xadd = nullptr, bool xset = false) {
+  if (c->lines) {
+    if (!xadd) return line_sweep64(c, T, b, x, s);
+    const int st = line_sweep64(c, T, b, c->e, s);
+    if (st != GABP_OK) return st;
+    GABP_HIP(xset ? launch_copy64(xadd, c->e, c->L.n, s) : launch_axpy64(xadd, c->e, c->L.n, s));
+    return GABP_OK;
+  }
   const bool rb = c->opt.schedule == GABP_SCHED_REDBLACK;
   const int fresh = c->fresh64 ? 0 : -1;   // first sweep after a reset
   c->fresh64 = false;
   if (c->opt.mode == GABP_MODE_JOINT) {
     SweepArgs a{&c->L, sweep_coef(c, T), b, nullptr, nullptr, nullptr, nullptr, x, -1, fresh};
+    a.xadd = xadd;
+    a.xset = xset;
     if (!rb) {
       a.lam_in = c->lam[c->parity];
       a.msg_in = c->msg[c->parity];
@@ -222,6 +233,8 @@ int sweep64(gabp_ctx* c, int T, const double* b, double* x, hipStream_t s) {
       ++c->seq_pos64;
     }
     MeanArgs64 a{&c->L, lo, Sx, b, nullptr, nullptr, x, -1, fresh};
+    a.xadd = xadd;
+    a.xset = xset;
     if (!rb) {
       a.msg_in = c->msg[c->parity];
       a.msg_out = c->msg[c->parity ^ 1];
@@ -240,8 +253,16 @@ int sweep64(gabp_ctx* c, int T, const double* b, double* x, hipStream_t s) {
   return GABP_OK;
 }
 
-int sweep32(gabp_ctx* c, int T, const float* b, float* x, hipStream_t s) {
-  if (c->lines) return line_sweep32(c, T, b, x, s);
+int sweep32(gabp_ctx* c, int T, const float* b, float* x, hipStream_t s,
+            double* xadd = nullptr, bool xset = false) {
+  if (c->lines) {
+    if (!xadd) return line_sweep32(c, T, b, x, s);
+    const int st = line_sweep32(c, T, b, c->d32, s);
+    if (st != GABP_OK) return st;
+    if (xset) GABP_HIP(launch_fill64(xadd, c->L.n, 0.0, s));
+    GABP_HIP(launch_axpy32(xadd, c->d32, nullptr, c->L.n, s));
+    return GABP_OK;
+  }
   const float* lo = c->pre[T].lamout32;
   const float* iS = c->pre[T].invS32;
   if (seq_mode(c)) {
@@ -254,6 +275,8 @@ int sweep32(gabp_ctx* c, int T, const float* b, float* x, hipStream_t s) {
   const int fresh = c->fresh32 ? 0 : -1;   // first sweep after a reset
   c->fresh32 = false;
   MeanArgs32 a{&c->L, lo, iS, b, nullptr, nullptr, x, -1, fresh};
+  a.xadd = xadd;
+  a.xset = xset;
   if (c->opt.schedule != GABP_SCHED_REDBLACK) {
     a.msg_in = c->msg32[c->parity32];
     a.msg_out = c->msg32[c->parity32 ^ 1];
@@ -268,6 +291,99 @@ int sweep32(gabp_ctx* c, int T, const float* b, float* x, hipStream_t s) {
       if (fresh >= 0) a.fresh = c->L.cslot[col];
       GABP_HIP(launch_mean_sweep32(a, s));
     }
+  }
+  return GABP_OK;
+}
+
+// Two FP64 sweeps in one launch on a tiled layout (flood only); read-off as in sweep64.
+int sweep64_pair(gabp_ctx* c, int T, const double* b, double* x, hipStream_t s,
+                 double* xadd = nullptr, bool xset = false) {
+  const int fresh = c->fresh64 ? 0 : -1;
+  c->fresh64 = false;
+  if (c->opt.mode == GABP_MODE_JOINT) {
+    SweepArgs a{&c->L, sweep_coef(c, T), b, c->lam[c->parity], c->msg[c->parity],
+                c->lam[c->parity ^ 1], c->msg[c->parity ^ 1], x, -1, fresh};
+    a.xadd = xadd;
+    a.xset = xset;
+    if (c->poison_outputs) {
+      GABP_HIP(launch_fill64(a.lam_out, c->L.epad, kPoison, s));
+      GABP_HIP(launch_fill64(a.msg_out, c->L.epad, kPoison, s));
+    }
+    GABP_HIP(launch_joint_pair(a, s));
+  } else {
+    MeanPairArgs<double> a{&c->L, c->pre[T].lamout, c->pre[T].lamout, c->pre[T].S, b,
+                           c->msg[c->parity], c->msg[c->parity ^ 1], x, fresh};
+    if (seq_mode(c)) {
+      const int k = c->seq_pos64;
+      if (T != 0 || k + 1 >= c->seq.depth)
+        return fail(GABP_EINVAL, "per-sweep precision messages missing for this sweep");
+      a.lamA = c->seq.lamout[k];
+      a.lamB = c->seq.lamout[k + 1];
+      a.SxB = c->seq.S[k + 1];
+      c->seq_pos64 += 2;
+    }
+    a.xadd = xadd;
+    a.xset = xset;
+    if (c->poison_outputs) GABP_HIP(launch_fill64(a.msg_out, c->L.epad, kPoison, s));
+    GABP_HIP(launch_mean_pair64(a, s));
+  }
+  c->parity ^= 1;
+  return GABP_OK;
+}
+
+int sweep32_pair(gabp_ctx* c, int T, const float* b, float* x, hipStream_t s,
+                 double* xadd = nullptr, bool xset = false) {
+  MeanPairArgs<float> a{&c->L, c->pre[T].lamout32, c->pre[T].lamout32, c->pre[T].invS32, b,
+                        c->msg32[c->parity32], c->msg32[c->parity32 ^ 1], x,
+                        c->fresh32 ? 0 : -1};
+  if (seq_mode(c)) {
+    const int k = c->seq_pos32;
+    if (T != 0 || k + 1 >= c->seq.depth)
+      return fail(GABP_EINVAL, "per-sweep precision messages missing for this sweep");
+    a.lamA = c->seq.lamout32[k];
+    a.lamB = c->seq.lamout32[k + 1];
+    a.SxB = c->seq.invS32[k + 1];
+    c->seq_pos32 += 2;
+  }
+  c->fresh32 = false;
+  a.xadd = xadd;
+  a.xset = xset;
+  if (c->poison_outputs)
+    GABP_HIP(launch_fill32(a.msg_out, c->L.epad, static_cast<float>(kPoison), s));
+  GABP_HIP(launch_mean_pair32(a, s));
+  c->parity32 ^= 1;
+  return GABP_OK;
+}
+
+inline bool tiled(const gabp_ctx* c) { return c->L.ntiles > 0 && !c->lines; }
+
+// launches that k sweeps take: pairs on a tiled layout, one each otherwise (the ping-pong
+// parity flips once per launch)
+inline int sweep_launches(const gabp_ctx* c, int k) { return tiled(c) ? k / 2 + k % 2 : k; }
+
+// k FP64 sweeps; the read-off of the last goes to x (or is added to / stored into xadd)
+int run_sweeps64(gabp_ctx* c, int T, const double* b, int k, double* x, hipStream_t s,
+                 double* xadd = nullptr, bool xset = false) {
+  for (int i = 0; i < k;) {
+    const int step = tiled(c) && k - i >= 2 ? 2 : 1;
+    const bool last = i + step == k;
+    const int st = step == 2 ? sweep64_pair(c, T, b, last ? x : nullptr, s, last ? xadd : nullptr, xset)
+                             : sweep64(c, T, b, last ? x : nullptr, s, last ? xadd : nullptr, xset);
+    if (st != GABP_OK) return st;
+    i += step;
+  }
+  return GABP_OK;
+}
+
+int run_sweeps32(gabp_ctx* c, int T, const float* b, int k, float* x, hipStream_t s,
+                 double* xadd = nullptr, bool xset = false) {
+  for (int i = 0; i < k;) {
+    const int step = tiled(c) && k - i >= 2 ? 2 : 1;
+    const bool last = i + step == k;
+    const int st = step == 2 ? sweep32_pair(c, T, b, last ? x : nullptr, s, last ? xadd : nullptr, xset)
+                             : sweep32(c, T, b, last ? x : nullptr, s, last ? xadd : nullptr, xset);
+    if (st != GABP_OK) return st;
+    i += step;
   }
   return GABP_OK;
 }
@@ -378,18 +494,16 @@ int solve64(gabp_ctx* c, int T, const double* b, double* x, double tol, int max_
                    [&](hipStream_t ss) -> int {
                      c->parity = start;
                      c->fresh64 = fresh;
-                     for (int i = 0; i < k; ++i) {
-                       const int e = sweep64(c, T, b, i == k - 1 ? x : nullptr, ss);
-                       if (e != GABP_OK) return e;
-                     }
-                     const int e = residual(c, T, b, x, nullptr, nullptr, nullptr, ss);
+                     int e = run_sweeps64(c, T, b, k, x, ss);
+                     if (e != GABP_OK) return e;
+                     e = residual(c, T, b, x, nullptr, nullptr, nullptr, ss);
                      if (e != GABP_OK) return e;
                      GABP_HIP(hipMemcpyAsync(c->host_red, c->red, 4 * sizeof(double),
                                              hipMemcpyDeviceToHost, ss));
                      return GABP_OK;
                    });
     if (st != GABP_OK) return st;
-    c->parity = rb ? start : start ^ (k & 1);
+    c->parity = rb ? start : start ^ (sweep_launches(c, k) & 1);
     c->fresh64 = false;
     done += k;
     GABP_HIP(hipStreamSynchronize(s));
@@ -469,18 +583,16 @@ int solve_ir(gabp_ctx* c, int T, const double* b, double* x, double tol, int max
                      [&](hipStream_t ss) -> int {
                        c->parity32 = start;
                        c->fresh32 = fresh;
-                       for (int i = 0; i < k; ++i) {
-                         const int e = sweep32(c, T, c->r32, i == k - 1 ? c->d32 : nullptr, ss);
-                         if (e != GABP_OK) return e;
-                       }
-                       const int e = residual(c, T, b, x, c->d32, scale, rt, ss);
+                       int e = run_sweeps32(c, T, c->r32, k, c->d32, ss);
+                       if (e != GABP_OK) return e;
+                       e = residual(c, T, b, x, c->d32, scale, rt, ss);
                        if (e != GABP_OK) return e;
                        GABP_HIP(hipMemcpyAsync(c->host_red, c->red, 4 * sizeof(double),
                                                hipMemcpyDeviceToHost, ss));
                        return GABP_OK;
                      });
       if (st != GABP_OK) return st;
-      c->parity32 = rb ? start : start ^ (k & 1);
+      c->parity32 = rb ? start : start ^ (sweep_launches(c, k) & 1);
       c->fresh32 = false;
       inner += k;
       total += k;
@@ -602,26 +714,20 @@ int gabp_sweeps(gabp_ctx* c, const double* b, double* x, int32_t sweeps, int32_t
     GABP_HIP(launch_cast_scaled(c->r32, b, nullptr, c->L.n, s));
     if ((st = prep_rhs32(c, c->r32, s)) != GABP_OK) return st;
     if ((reset || fresh) && (st = reset_messages32(c, s)) != GABP_OK) return st;
-    for (int i = 0; i < sweeps; ++i)
-      if ((st = sweep32(c, T, c->r32, i == sweeps - 1 ? c->d32 : nullptr, s)) != GABP_OK) return st;
-    GABP_HIP(launch_fill64(x, c->L.n, 0.0, s));
-    GABP_HIP(launch_axpy32(x, c->d32, nullptr, c->L.n, s));
-    return GABP_OK;
+    return run_sweeps32(c, T, c->r32, sweeps, nullptr, s, x, true);
   }
   if (c->opt.mode == GABP_MODE_PRECOMP && (st = ensure_pre(c, T, s)) != GABP_OK) return st;
   if (seq_mode(c) && (st = ensure_seq(c, (reset ? 0 : c->seq_pos64) + sweeps, s)) != GABP_OK)
     return st;
   if (reset && (st = reset_messages64(c, s)) != GABP_OK) return st;
   if ((st = prep_rhs64(c, b, s)) != GABP_OK) return st;
-  for (int i = 0; i < sweeps; ++i)
-    if ((st = sweep64(c, T, b, i == sweeps - 1 ? x : nullptr, s)) != GABP_OK) return st;
-  return GABP_OK;
+  return run_sweeps64(c, T, b, sweeps, x, s);
 }
 
 int gabp_smooth(gabp_ctx* c, const double* b, double* x, int32_t mu, hipStream_t s) {
   if (!c || !b || !x) return fail(GABP_EINVAL, "NULL argument");
   if (mu < 1) return fail(GABP_EINVAL, "mu must be >= 1");
-  return gabp::smooth_from(c, b, x, mu, false, s);
+  return gabp::smooth_from(c, b, x, mu, false, false, s);
 }
 
 }  // extern "C"
@@ -629,31 +735,37 @@ int gabp_smooth(gabp_ctx* c, const double* b, double* x, int32_t mu, hipStream_t
 namespace gabp {
 
 // Algorithm 3 with the residual either computed here or already in c->r (r_ready: the
-// caller has just formed b - A x for this x into c->r with the same residual kernel).
-int smooth_from(gabp_ctx* c, const double* b, double* x, int mu, bool r_ready, hipStream_t s) {
+// caller has just formed b - A x for this x into c->r with the same residual kernel), or
+// not needed (x_zero: x is zero on entry and is not read; the error equation's right-hand
+// side is b itself). The correction is added to x by the last sweep itself (stored, for
+// x_zero).
+int smooth_from(gabp_ctx* c, const double* b, double* x, int mu, bool r_ready, bool x_zero,
+                hipStream_t s) {
   int st;
-  const int64_t n = c->L.n;
-  if (!r_ready && (st = residual(c, 0, b, x, nullptr, nullptr, c->r, s, false)) != GABP_OK)
-    return st;
   if (seq_mode(c) && (st = ensure_seq(c, mu, s)) != GABP_OK) return st;
   if (c->opt.precision == GABP_F32_IR) {
     if (!seq_mode(c) && (st = ensure_pre(c, 0, s)) != GABP_OK) return st;
     if ((st = ensure_msg32(c, s)) != GABP_OK) return st;
-    GABP_HIP(launch_cast_scaled(c->r32, c->r, nullptr, n, s));
+    if (x_zero) {
+      GABP_HIP(launch_cast_scaled(c->r32, b, nullptr, c->L.n, s));
+    } else if (r_ready) {
+      GABP_HIP(launch_cast_scaled(c->r32, c->r, nullptr, c->L.n, s));
+    } else if ((st = residual(c, 0, b, x, nullptr, nullptr, nullptr, s, false, c->r32)) !=
+               GABP_OK) {
+      return st;
+    }
     if ((st = prep_rhs32(c, c->r32, s)) != GABP_OK) return st;
     if ((st = reset_messages32(c, s)) != GABP_OK) return st;
-    for (int i = 0; i < mu; ++i)
-      if ((st = sweep32(c, 0, c->r32, i == mu - 1 ? c->d32 : nullptr, s)) != GABP_OK) return st;
-    GABP_HIP(launch_axpy32(x, c->d32, nullptr, n, s));
-    return GABP_OK;
+    return run_sweeps32(c, 0, c->r32, mu, nullptr, s, x, x_zero);
   }
+  if (!x_zero && !r_ready &&
+      (st = residual(c, 0, b, x, nullptr, nullptr, c->r, s, false)) != GABP_OK)
+    return st;
+  const double* rhs = x_zero ? b : c->r;
   if (c->opt.mode == GABP_MODE_PRECOMP && (st = ensure_pre(c, 0, s)) != GABP_OK) return st;
   if ((st = reset_messages64(c, s)) != GABP_OK) return st;
-  if ((st = prep_rhs64(c, c->r, s)) != GABP_OK) return st;
-  for (int i = 0; i < mu; ++i)
-    if ((st = sweep64(c, 0, c->r, i == mu - 1 ? c->e : nullptr, s)) != GABP_OK) return st;
-  GABP_HIP(launch_axpy64(x, c->e, n, s));
-  return GABP_OK;
+  if ((st = prep_rhs64(c, rhs, s)) != GABP_OK) return st;
+  return run_sweeps64(c, 0, rhs, mu, nullptr, s, x, x_zero);
 }
 
 }  // namespace gabp

@@ -37,6 +37,7 @@ class Options(ctypes.Structure):
                 ("ir_inner_tol", ctypes.c_double), ("ir_max_inner", ctypes.c_int32),
                 ("schedule", ctypes.c_int32), ("use_graphs", ctypes.c_int32),
                 ("grid_nx", ctypes.c_int32), ("grid_ny", ctypes.c_int32),
+                ("tiles", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("progress_s", ctypes.c_double)]
 
 
@@ -79,7 +80,7 @@ _SIGS = {
     "gabp_get_messages": (ctypes.c_int, [_P, _P, _P, _P]),
     "gabp_layout_info": (ctypes.c_int, [_P, _PI32, _PI64, _PI64, _PI64, _PI32]),
     "gabp_copy_probe": (ctypes.c_int, [_P, _P, _I64, _P]),
-    "gabp_autotune": (ctypes.c_int, [_P, _PI32, _PI32, _P]),
+    "gabp_autotune": (ctypes.c_int, [_P, _PI32, _PI32, _PI32, _P]),
     "gabp_setup_batched": (ctypes.c_int, [ctypes.POINTER(_P), _I32, _P, _I32, _I64, _P, _P, _P,
                                           _I32, ctypes.POINTER(Options), _P]),
     "gabp_solve_batched": (ctypes.c_int, [_P, _P, _P, _D, _I32, _P, _P]),
@@ -181,7 +182,7 @@ class Solver:
                  precision="f64", check_every=16, tol_lambda=1e-14,
                  max_lambda_sweeps=100000, ir_inner_tol=1e-4,
                  ir_max_inner=1000000, schedule="flood", use_graphs=True, grid=None,
-                 progress_s=0.0):
+                 progress_s=0.0, block=256, tiles=False):
         lib = load()
         self._lib = lib
         o = Options()
@@ -193,6 +194,8 @@ class Solver:
         o.schedule = SCHEDULES[schedule]
         o.use_graphs = int(bool(use_graphs))
         o.progress_s = float(progress_s)
+        o.block = int(block)
+        o.tiles = int(bool(tiles))
         if grid is not None:                  # (nx, ny) of the line schedules
             o.grid_nx, o.grid_ny = int(grid[0]), int(grid[1])
         self.options = o
@@ -335,10 +338,12 @@ class Solver:
         return out
 
     def autotune(self):
-        """Pick streaming hints and the check interval by measurement (see gabp_autotune)."""
-        ce, hints = ctypes.c_int32(0), ctypes.c_int32(0)
-        _check(self._lib.gabp_autotune(self._h, ctypes.byref(ce), ctypes.byref(hints), _stream()))
-        return {"check_every": ce.value, "stream_hints": hints.value}
+        """Pick streaming hints, workgroup size and the check interval by measurement (see
+        gabp_autotune)."""
+        ce, hints, blk = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
+        _check(self._lib.gabp_autotune(self._h, ctypes.byref(ce), ctypes.byref(hints),
+                                       ctypes.byref(blk), _stream()))
+        return {"check_every": ce.value, "stream_hints": hints.value, "block": blk.value}
 
     def layout_info(self):
         n, nnz, slots, pad = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
@@ -403,9 +408,10 @@ class BatchSolver:
         self._h = h
 
     def autotune(self):
-        ce, hints = ctypes.c_int32(0), ctypes.c_int32(0)
-        _check(self._lib.gabp_autotune(self._h, ctypes.byref(ce), ctypes.byref(hints), _stream()))
-        return {"check_every": ce.value, "stream_hints": hints.value}
+        ce, hints, blk = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
+        _check(self._lib.gabp_autotune(self._h, ctypes.byref(ce), ctypes.byref(hints),
+                                       ctypes.byref(blk), _stream()))
+        return {"check_every": ce.value, "stream_hints": hints.value, "block": blk.value}
 
     def solve(self, B, tol, max_sweeps, X=None):
         """B, X: CUDA float64 tensors of shape (nrhs, n). Returns X and per-pair infos."""

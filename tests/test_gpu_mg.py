@@ -60,6 +60,29 @@ def test_vcycle_matches_oracle(B, case, problem):
         assert np.abs(xg - xo).max() <= TOL * scale * (1 + cycle), (smoother, gkw, cycle)
 
 
+@pytest.mark.parametrize("gkw,okw", [
+    (dict(mode="seq", schedule="redblack"), dict(gabp_mode="joint", schedule="redblack")),
+    (dict(mode="joint", schedule="redblack"), dict(gabp_mode="joint", schedule="redblack")),
+    (dict(mode="seq"), dict(gabp_mode="joint"))])
+def test_midsize_vcycle_matches_oracle(B, gkw, okw):
+    """511 x 511 anisotropic convection-diffusion hierarchy (8 levels down to 3 x 3, cell
+    Peclet 4 on the finest grid): two V(2,2) cycles against the oracle's. The per-sweep
+    precomputed smoother is compared with the oracle's joint smoother."""
+    levels = W.mg_hierarchy(9, coarsest=3, kx=1.0, ky=0.01, peclet=4.0)
+    assert len(levels) == 8 and levels[0].n == 511 * 511
+    b = W.rng(506, 0).uniform(-1, 1, levels[0].n)
+    mg = _gpu_mg(B, levels, "gabp", 2, 2, **gkw)
+    ho = MG.Hierarchy(levels, smoother="gabp", nu1=2, nu2=2, **okw)
+    bt = torch.as_tensor(b).cuda()
+    x = torch.zeros(levels[0].n, dtype=torch.float64, device="cuda")
+    xo = np.zeros(levels[0].n)
+    for cycle in range(2):
+        mg.vcycle(bt, x)
+        xo = ho.vcycle(b, xo)
+        scale = np.abs(xo).max()
+        assert np.abs(x.cpu().numpy() - xo).max() <= 1e-11 * scale, (gkw, cycle)
+
+
 def test_rbgs_vcycle_poisson_converges(B):
     levels = W.mg_hierarchy(7, coarsest=3, kx=1.0, ky=1.0, peclet=0.0)
     b = W.rng(501, 0).uniform(-1, 1, levels[0].n)
@@ -117,6 +140,7 @@ def test_recorded_vcycles_match_eager(B, mode):
 
 @pytest.mark.parametrize("kw,tol", [
     (dict(mode="joint", schedule="redblack"), 1e-11),
+    (dict(mode="seq", precision="f32_ir", schedule="redblack"), 1e-4),
     (dict(mode="precomp", precision="f32_ir", schedule="redblack", tol_lambda=1e-7), 1e-4)])
 def test_full_size_vcycles_are_linear_and_scale_invariant(B, kw, tol):
     """The 4095 x 4095 multigrid configuration (11 levels, kx/ky = 100, cell Peclet 4) with
@@ -147,8 +171,26 @@ def test_full_size_vcycles_are_linear_and_scale_invariant(B, kw, tol):
     assert err <= tol, err
 
 
+def test_full_size_seq_vcycles_equal_joint_vcycles(B):
+    """At the 4095 x 4095 configuration the per-sweep precomputed smoother (mean-only
+    sweeps) gives the joint smoother's V-cycles: two cycles agree to rounding."""
+    levels = W.mg_hierarchy(12, coarsest=3, kx=1.0, ky=0.01, peclet=4.0)
+    n = levels[0].n
+    bt = torch.as_tensor(W.rng(332, 0).uniform(-1, 1, n)).cuda()
+    xs = []
+    for mode in ("joint", "seq"):
+        mg = _gpu_mg(B, levels, "gabp", 2, 2, mode=mode, schedule="redblack")
+        x = torch.zeros(n, dtype=torch.float64, device="cuda")
+        for _ in range(2):
+            mg.vcycle(bt, x)
+        xs.append(x.cpu().numpy())
+        del mg
+    assert np.abs(xs[1] - xs[0]).max() <= 1e-12 * np.abs(xs[0]).max()
+
+
 @pytest.mark.parametrize("kw", [
     dict(mode="joint", schedule="redblack"),
+    dict(mode="seq", precision="f32_ir", schedule="redblack"),
     dict(mode="precomp", precision="f32_ir", schedule="redblack", tol_lambda=1e-7),
     dict(mode="joint", schedule="lines_alt", lines=True),
     dict(mode="precomp", precision="f32_ir", schedule="lines_alt", tol_lambda=1e-7, lines=True)])

@@ -508,6 +508,41 @@ def test_checkpoint_resume_is_bitwise(B):
     assert np.array_equal(x12, x1)   # 7 + 5 sweeps from zero, same bits
 
 
+def test_checkpoint_rejects_another_layout_or_mode(B):
+    """On a 32 x 32 grid the flood and the red-black layouts have the same padded slot count
+    but different message positions: a blob of one must not load into the other, nor into
+    a context of another mode or precision."""
+    a, b, _ = CASES["upwind32"]
+    bt = _cuda(b)
+    flood = B.Solver.from_csr(a)
+    rb = B.Solver.from_csr(a, colour=W.grid_colouring(32), schedule="redblack")
+    assert flood.layout_info()["padded_slots"] == rb.layout_info()["padded_slots"]
+    flood.sweeps(bt, 4)
+    blob = flood.get_state()
+    for other in (rb, B.Solver.from_csr(a, mode="seq"),
+                  B.Solver.from_csr(a, mode="precomp", precision="f32_ir")):
+        with pytest.raises(B.GaBPError) as e:
+            other.set_state(blob)
+        assert e.value.status == B.EINVAL
+    B.Solver.from_csr(a).set_state(blob)                   # same layout and mode: accepted
+
+
+def test_seq_checkpoint_resumes(B):
+    """The per-sweep mode's checkpoint carries the sweep position: 4 sweeps, checkpoint,
+    3 more equal 7 from zero messages (the stored sequence grows to 7 on demand)."""
+    a, b, _ = CASES["walk200"]
+    bt = _cuda(b)
+    s = B.Solver.from_csr(a, mode="seq")
+    s.sweeps(bt, 4)
+    blob = s.get_state()
+    r = B.Solver.from_csr(a, mode="seq")
+    r.set_state(blob)
+    x = r.sweeps(bt, 3, reset=False).cpu().numpy()
+    assert np.array_equal(x, s.sweeps(bt, 7).cpu().numpy())
+    xo, _, _ = G.run(G.Graph.from_csr(a), b, 7)
+    assert _rel_inf(x, xo) <= TOL
+
+
 @pytest.mark.parametrize("kw", [dict(mode="joint"),
                                 dict(mode="joint", schedule="redblack"),
                                 dict(mode="precomp", precision="f32_ir", tol_lambda=1e-10),
@@ -690,29 +725,36 @@ def _ball(a, centre, radius):
 def test_full_size_sampled_parity(B):
     """2048 x 2048 variable-coefficient operator (4.19M unknowns) in the launch
     configuration the benchmark times: sampled read-offs after s sweeps equal the oracle run
-    on the radius-s ball around each sample (x_j after s sweeps depends on nothing else)."""
+    on the radius-s ball around each sample (x_j after s sweeps depends on nothing else),
+    and the messages into each sample after s updates equal the oracle's on the radius
+    s + 1 ball (a message i -> j depends on the radius-s ball around i)."""
     a, b = W.precision_at_scale(2048)
     s = B.Solver.from_csr(a)
     bt = _cuda(b)
-    samples = W.rng(305, 0).choice(a.n, 12, replace=False)
-    samples[0], samples[1] = 0, a.n - 1                   # corners
-    for sweeps in (1, 2, 5):
+    samples = W.rng(305, 0).choice(a.n, 48, replace=False)
+    samples[0], samples[1], samples[2] = 0, a.n - 1, 2047    # corners
+    for sweeps in (1, 2, 5, 12, 20):
         x = s.sweeps(bt, sweeps).cpu().numpy()
+        lam, msg = ((t.cpu().numpy() for t in s.messages()) if sweeps in (1, 5, 20)
+                    else (None, None))
         for j in samples:
-            nodes = _ball(a, j, sweeps)
-            sub = np.searchsorted(nodes, j)
-            rows = []
-            for u in nodes:
-                lo, hi = a.rowptr[u], a.rowptr[u + 1]
-                keep = np.isin(a.col[lo:hi], nodes)
-                rows.append((np.searchsorted(nodes, a.col[lo:hi][keep]), a.val[lo:hi][keep]))
-            rp = np.zeros(len(nodes) + 1, dtype=np.int32)
-            rp[1:] = np.cumsum([len(c) for c, _ in rows])
-            sub_a = W.CSR(len(nodes), rp, np.concatenate([c for c, _ in rows]).astype(np.int32),
-                          np.concatenate([v for _, v in rows]))
-            xo, _, _ = G.run(G.Graph.from_csr(sub_a), b[nodes], sweeps)
-            assert abs(x[j] - xo[sub]) <= TOL * max(abs(xo[sub]), 1e-300) + 1e-300, (j, sweeps)
-    # property at full size: the residual of the 5-sweep read-off is finite and below that of x = 0
+            sub_a, sub_b, nodes, sj = _ball_problem(a, b, j, sweeps)
+            xo, _, _ = G.run(G.Graph.from_csr(sub_a), sub_b, sweeps)
+            assert abs(x[j] - xo[sj]) <= TOL * max(abs(xo[sj]), 1e-300) + 1e-300, (j, sweeps)
+            if lam is None:
+                continue
+            sub_a, sub_b, nodes, sj = _ball_problem(a, b, j, sweeps + 1)
+            g = G.Graph.from_csr(sub_a)
+            _, Lt, m = G.run(g, sub_b, sweeps)
+            into = np.nonzero(g.dst == sj)[0]                    # oracle edges i -> j
+            lo, hi = a.rowptr[j], a.rowptr[j + 1]
+            off = np.nonzero(a.col[lo:hi] != j)[0] + lo          # CSR entries (j, i)
+            assert len(into) == len(off)
+            assert np.allclose(lam[off], Lt[into], rtol=TOL, atol=0), (j, sweeps)
+            assert np.allclose(msg[off], m[into], rtol=TOL,
+                               atol=TOL * np.abs(m[into]).max()), (j, sweeps)
+    # property at full size: the residual of the 20-sweep read-off is finite and below that
+    # of x = 0
     r, (n2, _, bn) = s.residual(bt, torch.as_tensor(x).cuda())
     assert np.isfinite(n2) and n2 < bn
 
@@ -875,11 +917,30 @@ def test_autotune_keeps_results_correct(B, kw):
     s = B.Solver.from_csr(a, tol_lambda=1e-10, **kw)
     t = s.autotune()
     assert t["check_every"] in (8, 16, 32, 64, 128, 256) and t["stream_hints"] in (0, 1)
+    assert t["block"] in (64, 128, 256)
     assert s.autotune() == t                       # cached
     x, info = s.solve(_cuda(b), 1e-11, 200000)
     assert info.status == B.OK and info.sweeps % t["check_every"] == 0 or info.outer_iters > 0
     xs = np.linalg.solve(W.csr_to_dense(a), b)
     assert _rel_inf(x.cpu().numpy(), xs) <= 1e-8
+
+
+@pytest.mark.parametrize("schedule", ["flood", "redblack"])
+def test_workgroup_sizes_agree(B, schedule):
+    """The sweep kernels give the same bits at every workgroup size the autotuner picks
+    from (one, two or four 64-row slices per workgroup)."""
+    a, b, _ = CASES["upwind32"]
+    col = G.grid_colour(32) if schedule == "redblack" else None
+    outs = []
+    for blk in (64, 128, 256):
+        for kw in (dict(mode="joint"), dict(mode="seq"), dict(mode="precomp", precision="f32_ir")):
+            s = B.Solver.from_csr(a, colour=col, schedule=schedule, block=blk, **kw)
+            outs.append((blk, str(kw), s.sweeps(_cuda(b), 9).cpu().numpy()))
+    for blk, kw, x in outs:
+        ref = next(o for o in outs if o[1] == kw)[2]
+        assert np.array_equal(x, ref), (blk, kw)
+    with pytest.raises(B.GaBPError):
+        B.Solver.from_csr(a, block=96)
 
 
 def test_stream_hint_variants_agree(B):
