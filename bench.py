@@ -961,7 +961,7 @@ def suite_adjoint(log, n_full=1024, n_small=128, batch=8):
     return out
 
 
-def suite_adjoint_full(log, n=1024, batch=8, tol=1e-8):
+def suite_adjoint_full(log, n=1024, batch=8, tol=1e-8, tiles=True):
     """The differentiation configuration at its full size: 8 theta fields on the 1024 x 1024
     grid, L = 0.5 ||x(theta) - x_target||^2, FP32 messages inside FP64 refinement to rel.res
     1e-8 for the forward and the transposed (adjoint) solve, gradient reduced onto theta;
@@ -973,7 +973,8 @@ def suite_adjoint_full(log, n=1024, batch=8, tol=1e-8):
     from paper_1904_04093_amd import workloads as W
     field = AG.ThetaField(n)
     solver = gabp.Solver.from_csr(field.pattern, mode="precomp", precision="f32_ir",
-                                  tol_lambda=1e-7, progress_s=30.0)
+                                  tol_lambda=1e-7, progress_s=30.0,
+                                  **(dict(tiles=True, grid=(n, n)) if tiles else {}))
     tuned = solver.autotune()
     b = torch.as_tensor(W.rng(5, 101).uniform(-1, 1, n * n)).cuda()
     xt = torch.as_tensor(W.rng(5, 100).uniform(-1, 1, n * n)).cuda()
@@ -1002,7 +1003,7 @@ def suite_adjoint_full(log, n=1024, batch=8, tol=1e-8):
     total = time.perf_counter() - t_all
     e = field.pattern.nnz - field.pattern.n
     sweeps = sum(r["forward"]["sweeps"] + r["adjoint"]["sweeps"] for r in per)
-    return {"grid": f"{n}x{n}", "batch": batch, "tol": tol, "autotuned": tuned,
+    return {"grid": f"{n}x{n}", "batch": batch, "tol": tol, "autotuned": tuned, "tiles": tiles,
             "seconds": total, "per_theta_s": total / batch, "per_theta": per,
             "fp32_edge_updates_per_s": e * sweeps / total,
             "cpu_baseline": cpu_baseline_adjoint(log)}

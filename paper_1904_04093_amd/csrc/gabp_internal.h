@@ -40,15 +40,17 @@ constexpr int kMaxColours = 8;  // colour classes of the coloured schedule
 // Layout::row_slot packs a row's first slot (below 2^29) and its slice width (below 8)
 constexpr int kRowSlotShift = 29;
 constexpr unsigned kRowSlotMask = (1u << kRowSlotShift) - 1u;
-// Tiles of the two-sweep (temporally blocked) flood kernels: kTileSlices slices of 64 lanes
-// per tile, one thread per lane, plus kHaloThreads threads for the tile's halo rows (a
-// 5-point tile of 13 x 64 nodes has 154), in one workgroup of kTileThreads; rows of at most
-// kTileMaxWidth slots, so a tile's incoming messages fit in LDS (FP64 joint:
-// 2 x 8 B x 13 x 64 x 4 = 52 KiB)
-constexpr int kTileSlices = 13;
-constexpr int kTileLanes = kTileSlices * kSlice;
+// Tiles of the two-sweep (temporally blocked) flood kernels: Layout::tile_slices slices of
+// 64 lanes per tile (a multiple of kTileUnit), handled by kTileOwnThreads threads (one lane
+// per thread and kTileUnit slices, i.e. one or two lanes per thread) plus kHaloThreads
+// threads for the tile's halo rows (a 5-point tile of 13 x 64 nodes has 154, of 26 x 64
+// nodes 180), in one workgroup of kTileThreads; rows of at most kTileMaxWidth slots, so a
+// tile's incoming messages fit in LDS (FP64 joint, 13 slices: 2 x 8 B x 13 x 64 x 4 =
+// 52 KiB; FP64 mean-only, 13 slices: 26 KiB; FP32 mean-only, 26 slices: 26 KiB)
+constexpr int kTileUnit = 13;
+constexpr int kTileOwnThreads = kTileUnit * kSlice;
 constexpr int kHaloThreads = 192;
-constexpr int kTileThreads = kTileLanes + kHaloThreads;
+constexpr int kTileThreads = kTileOwnThreads + kHaloThreads;
 constexpr int kTileMaxWidth = 4;
 
 struct Precomp {
@@ -120,13 +122,13 @@ struct Layout {
   // null when a slot index or width does not fit
   int32_t* row_slot = nullptr;
   uint64_t hash = 0;                  // of the slot and lane layout (checkpoint check)
-  // tiled layout (opt.tiles): lanes tile-major, tile t = lanes [t, t + 1) * kTileLanes;
-  // halo of tile t = entries tile_halo[tile_hptr[t] .. tile_hptr[t + 1]) (rows outside the
-  // tile that send into it), each {first slot, slots, row, 0}
+  // tiled layout (opt.tiles): lanes tile-major, tile t = lanes [t, t + 1) * tile_slices * 64;
+  // halo of tile t = entries tile_halo[t * kHaloThreads ...] (the rows outside the tile that
+  // send into it, {first slot, slots, row, 0}; entries past the halo have no slots)
   int32_t ntiles = 0;
+  int32_t tile_slices = 0;            // 13 (FP64 sweeps) or 26 (FP32 mean-only sweeps)
   int32_t tile_slots_max = 0;         // largest slot range of one tile
-  int32_t* tile_hptr = nullptr;       // [ntiles + 1]
-  int4* tile_halo = nullptr;
+  int4* tile_halo = nullptr;          // [ntiles * kHaloThreads]
 };
 
 }  // namespace gabp

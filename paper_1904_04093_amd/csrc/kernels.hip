@@ -234,9 +234,9 @@ __global__ __launch_bounds__(kBlock) void k_mean(
 
 // ---------------------------------------------------------------------------------------
 // Two flood sweeps in one pass (temporal blocking) over a tiled layout: one workgroup per
-// tile (kTileSlices slices of 64 lanes). The first kTileLanes threads own the tile's rows,
-// the last kHaloThreads its halo (the rows outside the tile that send into it, given by
-// {first slot, slots, row}). Sweep 1 runs for both; of the messages it sends, those into
+// tile (kTileUnit slices of 64 lanes). The first kTileOwnThreads threads own the tile's
+// rows, the last kHaloThreads its halo (the rows outside the tile that send into it, one
+// per thread, given by {first slot, slots, row}). Sweep 1 runs for both; of the messages it sends, those into
 // the tile go to LDS and the rest are dropped (the tiles they belong to compute them for
 // themselves). Sweep 2 runs for the tile's rows from the LDS messages and writes its
 // messages to the output buffers like a plain sweep. Same operations in the same order as
@@ -246,7 +246,7 @@ __global__ __launch_bounds__(kBlock) void k_mean(
 template <int WX, bool NT, bool FIRST>
 __global__ __launch_bounds__(kTileThreads) void k_joint2(
     const int32_t* __restrict__ sptr, const int32_t* __restrict__ rev,
-    const int32_t* __restrict__ hptr, const int4* __restrict__ halo,
+    const int4* __restrict__ halo,
     const double* __restrict__ coef, const double* __restrict__ diag,
     const double* __restrict__ b, const double* lam_in, const double* msg_in,
     double* lam_out, double* msg_out, double* __restrict__ x,
@@ -255,16 +255,16 @@ __global__ __launch_bounds__(kTileThreads) void k_joint2(
   double* Ls = lds;
   double* Ms = lds + slots_max;
   const int tile = blockIdx.x;
-  const int ts0 = sptr[tile * kTileSlices];
-  const unsigned nts = static_cast<unsigned>(sptr[(tile + 1) * kTileSlices] - ts0);
-  const bool own = threadIdx.x < kTileLanes;
+  const int ts0 = sptr[tile * kTileUnit];
+  const unsigned nts = static_cast<unsigned>(sptr[(tile + 1) * kTileUnit] - ts0);
+  const bool own = threadIdx.x < kTileOwnThreads;
   // own rows: coefficients, reverse slots, diagonal and b stay in registers for sweep 2
   double a[kTileMaxWidth], l[kTileMaxWidth], m[kTileMaxWidth];
   int r[kTileMaxWidth];
   int w = 0, p0 = 0, j = -1;
   double dj = 0.0, bj = 0.0;
   if (own) {
-    const int tl = tile * kTileLanes + static_cast<int>(threadIdx.x);
+    const int tl = tile * kTileOwnThreads + static_cast<int>(threadIdx.x);
     j = perm[tl];
     if (j >= 0) {
       p0 = row_base(sptr, tl, &w);
@@ -307,9 +307,9 @@ __global__ __launch_bounds__(kTileThreads) void k_joint2(
       send1(w, S, M);
     }
   } else {
-    const int h0 = hptr[tile], nh = hptr[tile + 1] - h0;
-    for (int e = threadIdx.x - kTileLanes; e < nh; e += kHaloThreads) {
-      const int4 h = halo[h0 + e];   // {first slot, slots, row, -}
+    // one halo row per halo thread (entries past the tile's halo have no slots)
+    const int4 h = halo[tile * kHaloThreads + static_cast<int>(threadIdx.x) - kTileOwnThreads];
+    if (h.y > 0) {   // {first slot, slots, row, -}
 #pragma unroll
       for (int k = 0; k < kTileMaxWidth; ++k) {
         if (k < h.y) {
@@ -359,90 +359,111 @@ __global__ __launch_bounds__(kTileThreads) void k_joint2(
 }
 
 // Mean-only form (frozen or per-sweep precomputed Lt): sweep 1 sends with lamA, sweep 2
-// reads off with SxB (Sigma, or 1/Sigma for FP32) and sends with lamB.
-template <typename T, int WX, bool NT, bool FIRST>
+// reads off with SxB (Sigma, or 1/Sigma for FP32) and sends with lamB. Tiles of TS slices:
+// each own thread takes TS / kTileUnit lanes, kTileOwnThreads apart.
+template <typename T, int TS, int WX, bool NT, bool FIRST>
 __global__ __launch_bounds__(kTileThreads) void k_mean2(
     const int32_t* __restrict__ sptr, const int32_t* __restrict__ rev,
-    const int32_t* __restrict__ hptr, const int4* __restrict__ halo,
+    const int4* __restrict__ halo,
     const T* __restrict__ lamA, const T* __restrict__ lamB, const T* __restrict__ SxB,
     const T* __restrict__ b, const T* msg_in, T* msg_out, T* __restrict__ x,
     const int32_t* __restrict__ perm, double* __restrict__ xadd) {
+  constexpr int RPT = TS / kTileUnit;
   extern __shared__ double lds_raw[];
   T* Ms = reinterpret_cast<T*>(lds_raw);
   const int tile = blockIdx.x;
-  const int ts0 = sptr[tile * kTileSlices];
-  const unsigned nts = static_cast<unsigned>(sptr[(tile + 1) * kTileSlices] - ts0);
-  const bool own = threadIdx.x < kTileLanes;
-  T lo[kTileMaxWidth], lb[kTileMaxWidth], m[kTileMaxWidth];
-  int r[kTileMaxWidth];
-  int w = 0, p0 = 0, j = -1;
-  T bj = T(0);
-  if (own) {
-    const int tl = tile * kTileLanes + static_cast<int>(threadIdx.x);
-    j = perm[tl];
-    if (j >= 0) {
-      p0 = row_base(sptr, tl, &w);
-      bj = b[j];
+  const int ts0 = sptr[tile * TS];
+  const unsigned nts = static_cast<unsigned>(sptr[(tile + 1) * TS] - ts0);
+  const bool own = threadIdx.x < kTileOwnThreads;
+  T lb[RPT][kTileMaxWidth], m[RPT][kTileMaxWidth];
+  int r[RPT][kTileMaxWidth];
+  int w[RPT], p0[RPT], j[RPT];
+  T bj[RPT];
 #pragma unroll
-      for (int k = 0; k < kTileMaxWidth; ++k) {
-        if (k < w) {
-          const int p = p0 + 64 * k;
-          lo[k] = ld_s<NT>(lamA + p);
-          lb[k] = lamB == lamA ? lo[k] : ld_s<NT>(lamB + p);
-          r[k] = ld_s<NT>(rev + p);
-          m[k] = FIRST ? T(0) : ld_s<NT>(msg_in + p);
+  for (int q = 0; q < RPT; ++q) {
+    j[q] = -1;
+    w[q] = 0;
+    p0[q] = 0;
+  }
+  if (own) {
+    // every load of the thread's lanes first, then the sends
+    T lo[RPT][kTileMaxWidth];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int tl = tile * TS * kSlice + static_cast<int>(threadIdx.x) + q * kTileOwnThreads;
+      j[q] = perm[tl];
+      if (j[q] >= 0) {
+        p0[q] = row_base(sptr, tl, &w[q]);
+        bj[q] = b[j[q]];
+#pragma unroll
+        for (int k = 0; k < kTileMaxWidth; ++k) {
+          if (k < w[q]) {
+            const int p = p0[q] + 64 * k;
+            lo[q][k] = ld_s<NT>(lamA + p);
+            lb[q][k] = lamB == lamA ? lo[q][k] : ld_s<NT>(lamB + p);
+            r[q][k] = ld_s<NT>(rev + p);
+            m[q][k] = FIRST ? T(0) : ld_s<NT>(msg_in + p);
+          }
         }
       }
-      T M = bj;
+    }
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      if (j[q] < 0) continue;
+      T M = bj[q];
 #pragma unroll
       for (int k = 0; k < kTileMaxWidth; ++k)
-        if (k < w) M += m[k];
+        if (k < w[q]) M += m[q][k];
 #pragma unroll
       for (int k = 0; k < kTileMaxWidth; ++k) {
-        const unsigned q = static_cast<unsigned>(r[k] - ts0);
-        if (k < w && q < nts) Ms[q] = lo[k] * (M - m[k]);
+        const unsigned qq = static_cast<unsigned>(r[q][k] - ts0);
+        if (k < w[q] && qq < nts) Ms[qq] = lo[q][k] * (M - m[q][k]);
       }
     }
   } else {
-    const int h0 = hptr[tile], nh = hptr[tile + 1] - h0;
-    for (int e = threadIdx.x - kTileLanes; e < nh; e += kHaloThreads) {
-      const int4 h = halo[h0 + e];
+    const int4 h = halo[tile * kHaloThreads + static_cast<int>(threadIdx.x) - kTileOwnThreads];
+    if (h.y > 0) {   // {first slot, slots, row, -}
+      T loh[kTileMaxWidth], mh[kTileMaxWidth];
+      int rh[kTileMaxWidth];
 #pragma unroll
       for (int k = 0; k < kTileMaxWidth; ++k) {
         if (k < h.y) {
           const int p = h.x + 64 * k;
-          lo[k] = lamA[p];
-          r[k] = rev[p];
-          m[k] = FIRST ? T(0) : msg_in[p];
+          loh[k] = lamA[p];
+          rh[k] = rev[p];
+          mh[k] = FIRST ? T(0) : msg_in[p];
         }
       }
       T M = b[h.z];
 #pragma unroll
       for (int k = 0; k < kTileMaxWidth; ++k)
-        if (k < h.y) M += m[k];
+        if (k < h.y) M += mh[k];
 #pragma unroll
       for (int k = 0; k < kTileMaxWidth; ++k) {
-        const unsigned q = static_cast<unsigned>(r[k] - ts0);
-        if (k < h.y && q < nts) Ms[q] = lo[k] * (M - m[k]);
+        const unsigned qq = static_cast<unsigned>(rh[k] - ts0);
+        if (k < h.y && qq < nts) Ms[qq] = loh[k] * (M - mh[k]);
       }
     }
   }
   __syncthreads();
-  if (j < 0) return;
-  T M = bj;
 #pragma unroll
-  for (int k = 0; k < kTileMaxWidth; ++k) {
-    if (k < w) {
-      m[k] = Ms[p0 + 64 * k - ts0];
-      M += m[k];
+  for (int q = 0; q < RPT; ++q) {
+    if (j[q] < 0) continue;
+    T M = bj[q];
+#pragma unroll
+    for (int k = 0; k < kTileMaxWidth; ++k) {
+      if (k < w[q]) {
+        m[q][k] = Ms[p0[q] + 64 * k - ts0];
+        M += m[q][k];
+      }
     }
-  }
-  if constexpr (WX == 1) x[j] = ReadOff<T>::f(M, SxB, j);
-  if constexpr (WX == 2) xadd[j] += static_cast<double>(ReadOff<T>::f(M, SxB, j));
-  if constexpr (WX == 3) xadd[j] = static_cast<double>(ReadOff<T>::f(M, SxB, j));
+    if constexpr (WX == 1) x[j[q]] = ReadOff<T>::f(M, SxB, j[q]);
+    if constexpr (WX == 2) xadd[j[q]] += static_cast<double>(ReadOff<T>::f(M, SxB, j[q]));
+    if constexpr (WX == 3) xadd[j[q]] = static_cast<double>(ReadOff<T>::f(M, SxB, j[q]));
 #pragma unroll
-  for (int k = 0; k < kTileMaxWidth; ++k)
-    if (k < w) st_s<NT>(lb[k] * (M - m[k]), msg_out + r[k]);
+    for (int k = 0; k < kTileMaxWidth; ++k)
+      if (k < w[q]) st_s<NT>(lb[q][k] * (M - m[q][k]), msg_out + r[q][k]);
+  }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1013,10 +1034,10 @@ hipError_t mean_dispatch(const Layout& L, const A& a, const T* Sx, bool nt, hipS
 
 hipError_t launch_joint_pair(const SweepArgs& a, hipStream_t s) {
   const Layout& L = *a.L;
-  if (L.ntiles <= 0) return hipErrorInvalidValue;
+  if (L.ntiles <= 0 || L.tile_slices != kTileUnit) return hipErrorInvalidValue;
   const size_t lds = 2 * static_cast<size_t>(L.tile_slots_max) * sizeof(double);
 #define JOINT2_ARGS                                                                         \
-  L.sptr, L.rev, L.tile_hptr, L.tile_halo, a.coef, L.diag, a.b, a.lam_in, a.msg_in,          \
+  L.sptr, L.rev, L.tile_halo, a.coef, L.diag, a.b, a.lam_in, a.msg_in,          \
       a.lam_out, a.msg_out, a.x, L.perm, a.xadd, L.tile_slots_max
   GABP_DISPATCH_FIRST(a.fresh >= 0, GABP_DISPATCH_NT(L.stream_hints,
     GABP_DISPATCH_WX(a.xadd ? (a.xset ? 3 : 2) : (a.x ? 1 : 0), {
@@ -1032,11 +1053,14 @@ hipError_t mean_pair_dispatch(const MeanPairArgs<T>& a, bool nt, hipStream_t s) 
   if (L.ntiles <= 0) return hipErrorInvalidValue;
   const size_t lds = static_cast<size_t>(L.tile_slots_max) * sizeof(T);
 #define MEAN2_ARGS                                                                          \
-  L.sptr, L.rev, L.tile_hptr, L.tile_halo, a.lamA, a.lamB, a.SxB, a.b, a.msg_in, a.msg_out,  \
+  L.sptr, L.rev, L.tile_halo, a.lamA, a.lamB, a.SxB, a.b, a.msg_in, a.msg_out,  \
       a.x, L.perm, a.xadd
   GABP_DISPATCH_FIRST(a.fresh >= 0, GABP_DISPATCH_NT(nt,
     GABP_DISPATCH_WX(a.xadd ? (a.xset ? 3 : 2) : (a.x ? 1 : 0), {
-      k_mean2<T, WXB, NTB, FB><<<L.ntiles, kTileThreads, lds, s>>>(MEAN2_ARGS);
+      if (L.tile_slices == 2 * kTileUnit)
+        k_mean2<T, 2 * kTileUnit, WXB, NTB, FB><<<L.ntiles, kTileThreads, lds, s>>>(MEAN2_ARGS);
+      else
+        k_mean2<T, kTileUnit, WXB, NTB, FB><<<L.ntiles, kTileThreads, lds, s>>>(MEAN2_ARGS);
     })))
 #undef MEAN2_ARGS
   return hipGetLastError();

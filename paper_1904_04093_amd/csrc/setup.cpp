@@ -185,9 +185,13 @@ int gabp_setup(gabp_ctx** out, int32_t n, int64_t nnz, const int32_t* rowptr,
     }
   }
   // --- tiles (temporal blocking, flood schedule on a grid): lanes tile-major, each tile
-  // kTileSlices slices of 64 x-consecutive nodes of kTileSlices consecutive grid rows,
+  // tsl slices of 64 x-consecutive nodes of tsl consecutive grid rows,
   // padded with empty lanes past the grid's right and top edges
   const bool tiled = o.tiles != 0;
+  // FP64 sweeps: one lane per thread (more registers per lane would halve the workgroups
+  // per CU); FP32 mean-only sweeps: two lanes per thread, twice the tile and half the
+  // halo per row
+  const int32_t tsl = o.precision == GABP_F32_IR ? 2 * kTileUnit : kTileUnit;
   int32_t tiles_x = 0, tiles_y = 0;
   if (tiled) {
     if (colour || o.schedule != GABP_SCHED_FLOOD)
@@ -198,20 +202,20 @@ int gabp_setup(gabp_ctx** out, int32_t n, int64_t nnz, const int32_t* rowptr,
       return fail(GABP_ENOTSUPP, "tiles need rows of at most " + std::to_string(kTileMaxWidth) +
                                      " off-diagonal neighbours (5-point grids)");
     tiles_x = (o.grid_nx + kSlice - 1) / kSlice;
-    tiles_y = (o.grid_ny + kTileSlices - 1) / kTileSlices;
-    nlanes = static_cast<int64_t>(tiles_x) * tiles_y * kTileSlices * kSlice;
+    tiles_y = (o.grid_ny + tsl - 1) / tsl;
+    nlanes = static_cast<int64_t>(tiles_x) * tiles_y * tsl * kSlice;
     if (nlanes >= std::numeric_limits<int32_t>::max() - kBlock)
       return fail(GABP_ENOTSUPP, "too many rows for a tiled layout");
     lane_of_row.assign(n, -1);
     row_of_lane.assign(static_cast<size_t>(nlanes), -1);
     for (int32_t ty = 0; ty < tiles_y; ++ty)
       for (int32_t tx = 0; tx < tiles_x; ++tx)
-        for (int32_t r = 0; r < kTileSlices; ++r)
+        for (int32_t r = 0; r < tsl; ++r)
           for (int32_t cx = 0; cx < kSlice; ++cx) {
             const int64_t x = static_cast<int64_t>(tx) * kSlice + cx;
-            const int64_t y = static_cast<int64_t>(ty) * kTileSlices + r;
+            const int64_t y = static_cast<int64_t>(ty) * tsl + r;
             if (x >= o.grid_nx || y >= o.grid_ny) continue;
-            const int64_t t = ((static_cast<int64_t>(ty) * tiles_x + tx) * kTileSlices + r) * kSlice + cx;
+            const int64_t t = ((static_cast<int64_t>(ty) * tiles_x + tx) * tsl + r) * kSlice + cx;
             const int32_t j = static_cast<int32_t>(y * o.grid_nx + x);
             lane_of_row[j] = static_cast<int32_t>(t);
             row_of_lane[t] = j;
@@ -386,8 +390,8 @@ int gabp_setup(gabp_ctx** out, int32_t n, int64_t nnz, const int32_t* rowptr,
     std::vector<int32_t> mark(static_cast<size_t>(nlanes), -1);
     int32_t slots_max = 0;
     for (int32_t t = 0; t < ntiles; ++t) {
-      const int64_t l0 = static_cast<int64_t>(t) * kTileSlices * kSlice;
-      const int64_t l1 = l0 + kTileSlices * kSlice;
+      const int64_t l0 = static_cast<int64_t>(t) * tsl * kSlice;
+      const int64_t l1 = l0 + tsl * kSlice;
       std::vector<int32_t> h;
       for (int64_t ln = l0; ln < l1; ++ln) {
         const int32_t j = row_of_lane[ln];
@@ -404,19 +408,25 @@ int gabp_setup(gabp_ctx** out, int32_t n, int64_t nnz, const int32_t* rowptr,
       hlane.insert(hlane.end(), h.begin(), h.end());
       hptr[t + 1] = static_cast<int32_t>(hlane.size());
       slots_max = std::max<int32_t>(
-          slots_max, static_cast<int32_t>(sptr64[(t + 1) * kTileSlices] - sptr64[t * kTileSlices]));
+          slots_max, static_cast<int32_t>(sptr64[(t + 1) * tsl] - sptr64[t * tsl]));
     }
-    UP(L.tile_hptr, hptr);
-    halo.assign(std::max<size_t>(hlane.size(), 1), int4{0, 0, 0, 0});
-    for (size_t q = 0; q < hlane.size(); ++q) {
-      const int64_t t = hlane[q];
-      const int64_t sl = t / kSlice;
-      halo[q] = int4{static_cast<int32_t>(sptr64[sl] + t % kSlice),
-                     static_cast<int32_t>((sptr64[sl + 1] - sptr64[sl]) / kSlice),
-                     row_of_lane[t], 0};
+    // one entry per halo thread of each tile's workgroup, {first slot, slots, row, 0}
+    halo.assign(static_cast<size_t>(ntiles) * kHaloThreads, int4{0, 0, 0, 0});
+    for (int32_t t = 0; t < ntiles; ++t) {
+      if (hptr[t + 1] - hptr[t] > kHaloThreads)
+        return cleanup_fail(fail(GABP_ENOTSUPP, "a tile's halo exceeds " +
+                                                    std::to_string(kHaloThreads) + " rows"));
+      for (int32_t q = hptr[t]; q < hptr[t + 1]; ++q) {
+        const int64_t ln = hlane[q];
+        const int64_t sl = ln / kSlice;
+        halo[static_cast<size_t>(t) * kHaloThreads + (q - hptr[t])] =
+            int4{static_cast<int32_t>(sptr64[sl] + ln % kSlice),
+                 static_cast<int32_t>((sptr64[sl + 1] - sptr64[sl]) / kSlice), row_of_lane[ln], 0};
+      }
     }
     UP(L.tile_halo, halo);
     L.ntiles = ntiles;
+    L.tile_slices = tsl;
     L.tile_slots_max = slots_max;
   }
   if (colour) {
@@ -500,7 +510,7 @@ void gabp_destroy(gabp_ctx* c) {
   Layout& L = c->L;
   F(L.sptr); F(L.rev); F(L.rev16); F(L.col); F(L.val); F(L.aT); F(L.diag); F(L.val_src); F(L.aT_src);
   F(L.diag_src); F(L.csr_row); F(L.csr_col); F(L.perm); F(L.lane_of_row_d);
-  F(L.tile_hptr); F(L.tile_halo); F(L.row_slot);
+  F(L.tile_halo); F(L.row_slot);
   for (int q = 0; q < 2; ++q) {
     F(c->lam[q]); F(c->msg[q]); F(c->msg32[q]);
     F(c->pre[q].lamout); F(c->pre[q].S); F(c->pre[q].lamout32); F(c->pre[q].invS32);
