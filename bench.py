@@ -57,19 +57,19 @@ def sweep_bytes_mean64(slots, n, rb=4):
 
 
 def measured_traffic(kernel):
-    """HBM bytes per launch from the committed counter summary, or None when the kernel
-    source has changed since those counters were taken."""
+    """HBM bytes per launch of `kernel` (its name with template arguments) from the committed
+    counter summary, or None when that kernel was not counted or the kernel source has
+    changed since the counters were taken."""
     import hashlib
     try:
         rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))
         src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+        entry = rec["kernels"][kernel]
     except (OSError, ValueError, KeyError):
-        return None
-    if rec.get("kernel") != kernel:
         return None
     if hashlib.sha256(src).hexdigest()[:16] != rec.get("source_sha256_prefix"):
         return None
-    return rec["hbm_bytes_per_launch"]
+    return entry["hbm_bytes_per_launch"]
 
 
 def _events_time(fn, reps):
@@ -156,6 +156,9 @@ def main():
     sj = gabp.Solver.from_csr(a, mode="joint", check_every=CE, **tkw)
     lay = sj.layout_info()
     log(f"[bench] setup {time.time()-t0:.1f}s layout {lay}")
+    # streaming hints by measurement (the library's autotuner, as a user would call it)
+    tuned = sj.autotune()
+    log(f"[bench] autotuned {tuned}")
     bt = torch.as_tensor(b).cuda()
     x = torch.zeros(a.n, dtype=torch.float64, device="cuda")
 
@@ -200,6 +203,9 @@ def main():
     rb = 4 if tiles else lay["rev_bytes"]
     ab = sweep_bytes_joint64(lay["slots"], a.n, rb)
     achieved = ab / t_launch / 1e9
+    nt = "true" if tuned["stream_hints"] else "false"
+    kname = (f"k_joint2<0, {nt}, false>" if tiles
+             else f"k_joint<4, 0, {nt}, {'true' if rb == 2 else 'false'}, false>")
     log(f"[bench] joint sweep kernel {t_launch*1e6:.1f} us per launch ({per_launch} sweeps), "
         f"{achieved:.0f} GB/s algorithmic")
 
@@ -220,6 +226,8 @@ def main():
     lsw = s32.precompute_lambda()
     sp = gabp.Solver.from_csr(a, mode="precomp", check_every=CE, tol_lambda=1e-12, **tkw)
     lsw64 = sp.precompute_lambda()
+    s32.autotune()
+    sp.autotune()
     sp.sweeps(bt, 1, reset=True, x=x)
     t_m64 = _events_time(lambda k: sp.sweeps(bt, k, reset=False, x=x), NS) / NS
     # FP32 mean-only sweeps (the inner kernel of iterative refinement): the call also casts
@@ -247,16 +255,16 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"upwind convection-diffusion {n}x{n}, variable k=exp(g), "
                                "rotating v, FP64 joint flood GaBP, 16 sweeps + residual check per step"
-                               + (" (two sweeps per launch over 16x64 tiles)" if tiles else ""),
+                               + (" (two sweeps per launch over 13x64 tiles)" if tiles else ""),
                    "unknowns": a.n, "nnz": a.nnz, "directed_edges": edges,
-                   "sweeps_per_step": CE, "tiles": tiles},
+                   "sweeps_per_step": CE, "tiles": tiles,
+                   "stream_hints": tuned["stream_hints"]},
         "roofline": {"bound": "hbm",
-                     "kernel": ("k_joint2 (two FP64 joint flood sweeps per launch, tiled)"
-                                if tiles else "k_joint (FP64 joint flood sweep)"),
+                     "kernel": kname + (" (two FP64 joint flood sweeps per launch, tiled)"
+                                        if tiles else " (FP64 joint flood sweep)"),
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic("k_joint2<0, true, false>" if tiles
-                                                 else "k_joint<4, false, true, true, false>"),
+                     "traffic": measured_traffic(kname),
                      "frac_of_copy": achieved / copy_gbs,
                      "algorithmic_bytes_per_launch": ab, "launch_us": t_launch * 1e6,
                      "sweeps_per_launch": per_launch, "reverse_index_bytes": rb},

@@ -97,7 +97,8 @@ typedef struct {
                                 neighbours (5-point pattern); lines of at most 4096 nodes
                                                                   default 0, 0             */
   int32_t tiles;             /* 1: temporal blocking of the flood schedule -- the rows are
-                                laid out in tiles of 16 grid rows x 64 columns and one
+                                laid out in tiles of 13 grid rows (26 with GABP_F32_IR)
+                                x 64 columns and one
                                 launch does two sweeps per tile, keeping the messages of
                                 the first in LDS (the tile's neighbour rows are swept once
                                 more to supply them); needs grid_nx, grid_ny (node (x, y) is

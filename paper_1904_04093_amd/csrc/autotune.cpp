@@ -34,10 +34,12 @@ std::string key_of(const gabp_ctx* c) {
   std::string dev = "unknown";
   if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) dev = prop.gcnArchName;
   char buf[256];
-  std::snprintf(buf, sizeof(buf), "%s|n=%d|slots=%lld|w=%d|R=%d|sys=%d|mode=%d|prec=%d|sched=%d",
+  // the layout hash separates layouts of one matrix (tiled or not, colour-major, lines)
+  std::snprintf(buf, sizeof(buf),
+                "%s|n=%d|slots=%lld|w=%d|R=%d|sys=%d|mode=%d|prec=%d|sched=%d|layout=%016llx",
                 dev.c_str(), c->L.n, static_cast<long long>(c->L.epad), c->L.max_width,
                 c->batch ? c->batch->R : 1, c->batch ? c->batch->nsys : 1, c->opt.mode,
-                c->opt.precision, c->opt.schedule);
+                c->opt.precision, c->opt.schedule, static_cast<unsigned long long>(c->L.hash));
   return buf;
 }
 
@@ -179,8 +181,10 @@ int gabp_autotune(gabp_ctx* c, int32_t* check_every_out, int32_t* hints_out,
   if (!cache_lookup(key, &t)) {
     int st;
     const bool seq = c->opt.mode == GABP_MODE_PRECOMP_SEQ;
+    // a tiled layout is timed with its two-sweep kernels, the ones its solves launch
+    const bool pairs = !c->batch && c->L.ntiles > 0;
     if (seq) {
-      if ((st = ensure_seq(c, 1, s)) != GABP_OK) return st;
+      if ((st = ensure_seq(c, pairs ? 2 : 1, s)) != GABP_OK) return st;
     } else if (f32 || c->opt.mode == GABP_MODE_PRECOMP) {
       if ((st = precompute(c, 0, s)) != GABP_OK) return st;
     }
@@ -215,7 +219,23 @@ int gabp_autotune(gabp_ctx* c, int32_t* check_every_out, int32_t* hints_out,
     int par = 0;
     auto one_sweep = [&]() -> int {
       Batch* B = c->batch;
-      if (B) {
+      if (pairs) {
+        if (f32) {
+          MeanPairArgs<float> a{&c->L, lam32, seq ? c->seq.lamout32[1] : lam32,
+                                seq ? c->seq.invS32[1] : invS32, zero32, c->msg32[par],
+                                c->msg32[par ^ 1], nullptr};
+          GABP_HIP(launch_mean_pair32(a, s));
+        } else if (c->opt.mode == GABP_MODE_JOINT) {
+          SweepArgs a{&c->L, c->L.aT, zero64, c->lam[par], c->msg[par], c->lam[par ^ 1],
+                      c->msg[par ^ 1], nullptr, -1};
+          GABP_HIP(launch_joint_pair(a, s));
+        } else {
+          MeanPairArgs<double> a{&c->L, lam64, seq ? c->seq.lamout[1] : lam64,
+                                 seq ? c->seq.S[1] : S64, zero64, c->msg[par],
+                                 c->msg[par ^ 1], nullptr};
+          GABP_HIP(launch_mean_pair64(a, s));
+        }
+      } else if (B) {
         if (f32) GABP_HIP(batch_mean32(c, B, B->msg32[par], B->msg32[par ^ 1], nullptr, s));
         else if (c->opt.mode == GABP_MODE_JOINT)
           GABP_HIP(batch_joint64(c, B, c->lam[par], B->msg64[par], c->lam[par ^ 1], B->msg64[par ^ 1], nullptr, s));
@@ -242,15 +262,17 @@ int gabp_autotune(gabp_ctx* c, int32_t* check_every_out, int32_t* hints_out,
       if ((st = time_it(s, reps, one_sweep, &t_sweep)) != GABP_OK) return st;
       t.hints = 0;
     } else {
-      // every (hints, workgroup size) pair; the fastest is kept
+      // every (hints, workgroup size) pair; the fastest is kept (the two-sweep kernels have
+      // one workgroup per tile: hints only, per sweep)
       static const int kBlocks[3] = {64, 128, 256};
       t_sweep = 0.0;
       for (int h = 0; h < 2; ++h)
-        for (int bi = 0; bi < 3; ++bi) {
+        for (int bi = pairs ? 2 : 0; bi < 3; ++bi) {
           hints = h != 0;
           c->L.block = kBlocks[bi];
           double tt = 0.0;
           if ((st = time_it(s, reps, one_sweep, &tt)) != GABP_OK) return st;
+          if (pairs) tt *= 0.5;
           if (t_sweep == 0.0 || tt < t_sweep) {
             t_sweep = tt;
             t.hints = h;

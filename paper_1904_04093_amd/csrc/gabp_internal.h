@@ -40,6 +40,8 @@ constexpr int kMaxColours = 8;  // colour classes of the coloured schedule
 // Layout::row_slot packs a row's first slot (below 2^29) and its slice width (below 8)
 constexpr int kRowSlotShift = 29;
 constexpr unsigned kRowSlotMask = (1u << kRowSlotShift) - 1u;
+constexpr int kXcds = 8;   // XCDs of an MI355X (8 x 32 compute units, one L2 each)
+
 // Tiles of the two-sweep (temporally blocked) flood kernels: Layout::tile_slices slices of
 // 64 lanes per tile (a multiple of kTileUnit), handled by kTileOwnThreads threads (one lane
 // per thread and kTileUnit slices, i.e. one or two lanes per thread) plus kHaloThreads
@@ -129,6 +131,8 @@ struct Layout {
   int32_t tile_slices = 0;            // 13 (FP64 sweeps) or 26 (FP32 mean-only sweeps)
   int32_t tile_slots_max = 0;         // largest slot range of one tile
   int4* tile_halo = nullptr;          // [ntiles * kHaloThreads]
+  int32_t tiles_x = 0;                // tile columns (tile t sits at column t % tiles_x)
+  int32_t tile_strip = 1;             // tile columns per strip of the XCD-aware tile order
 };
 
 }  // namespace gabp

@@ -250,11 +250,12 @@ __global__ __launch_bounds__(kTileThreads) void k_joint2(
     const double* __restrict__ coef, const double* __restrict__ diag,
     const double* __restrict__ b, const double* lam_in, const double* msg_in,
     double* lam_out, double* msg_out, double* __restrict__ x,
-    const int32_t* __restrict__ perm, double* __restrict__ xadd, int slots_max) {
+    const int32_t* __restrict__ perm, double* __restrict__ xadd, int slots_max, int tiles_x,
+    int strip) {
   extern __shared__ double lds[];
   double* Ls = lds;
   double* Ms = lds + slots_max;
-  const int tile = blockIdx.x;
+  const int tile = tile_of_block(blockIdx.x, gridDim.x, tiles_x, strip);
   const int ts0 = sptr[tile * kTileUnit];
   const unsigned nts = static_cast<unsigned>(sptr[(tile + 1) * kTileUnit] - ts0);
   const bool own = threadIdx.x < kTileOwnThreads;
@@ -367,11 +368,11 @@ __global__ __launch_bounds__(kTileThreads) void k_mean2(
     const int4* __restrict__ halo,
     const T* __restrict__ lamA, const T* __restrict__ lamB, const T* __restrict__ SxB,
     const T* __restrict__ b, const T* msg_in, T* msg_out, T* __restrict__ x,
-    const int32_t* __restrict__ perm, double* __restrict__ xadd) {
+    const int32_t* __restrict__ perm, double* __restrict__ xadd, int tiles_x, int strip) {
   constexpr int RPT = TS / kTileUnit;
   extern __shared__ double lds_raw[];
   T* Ms = reinterpret_cast<T*>(lds_raw);
-  const int tile = blockIdx.x;
+  const int tile = tile_of_block(blockIdx.x, gridDim.x, tiles_x, strip);
   const int ts0 = sptr[tile * TS];
   const unsigned nts = static_cast<unsigned>(sptr[(tile + 1) * TS] - ts0);
   const bool own = threadIdx.x < kTileOwnThreads;
@@ -1038,7 +1039,7 @@ hipError_t launch_joint_pair(const SweepArgs& a, hipStream_t s) {
   const size_t lds = 2 * static_cast<size_t>(L.tile_slots_max) * sizeof(double);
 #define JOINT2_ARGS                                                                         \
   L.sptr, L.rev, L.tile_halo, a.coef, L.diag, a.b, a.lam_in, a.msg_in,          \
-      a.lam_out, a.msg_out, a.x, L.perm, a.xadd, L.tile_slots_max
+      a.lam_out, a.msg_out, a.x, L.perm, a.xadd, L.tile_slots_max, L.tiles_x, L.tile_strip
   GABP_DISPATCH_FIRST(a.fresh >= 0, GABP_DISPATCH_NT(L.stream_hints,
     GABP_DISPATCH_WX(a.xadd ? (a.xset ? 3 : 2) : (a.x ? 1 : 0), {
       k_joint2<WXB, NTB, FB><<<L.ntiles, kTileThreads, lds, s>>>(JOINT2_ARGS);
@@ -1054,7 +1055,7 @@ hipError_t mean_pair_dispatch(const MeanPairArgs<T>& a, bool nt, hipStream_t s) 
   const size_t lds = static_cast<size_t>(L.tile_slots_max) * sizeof(T);
 #define MEAN2_ARGS                                                                          \
   L.sptr, L.rev, L.tile_halo, a.lamA, a.lamB, a.SxB, a.b, a.msg_in, a.msg_out,  \
-      a.x, L.perm, a.xadd
+      a.x, L.perm, a.xadd, L.tiles_x, L.tile_strip
   GABP_DISPATCH_FIRST(a.fresh >= 0, GABP_DISPATCH_NT(nt,
     GABP_DISPATCH_WX(a.xadd ? (a.xset ? 3 : 2) : (a.x ? 1 : 0), {
       if (L.tile_slices == 2 * kTileUnit)

@@ -1,9 +1,11 @@
 """Temporal blocking of the flood schedule (opt.tiles): two sweeps per launch over tiles of
-16 grid rows x 64 columns, the first sweep's messages kept in LDS and the tile's halo rows
+13 grid rows x 64 columns (26 rows for FP32 messages), the first sweep's messages kept in LDS and the tile's halo rows
 swept once more to supply them. The iterates must be those of plain flood sweeps: against
 the FP64 oracle to 1e-12 (joint, frozen and per-sweep precomputed Lt, transposed), bit for
 bit against the untiled layout, with every output slot written (poisoned buffers), and at
 the benchmark's full size on sampled read-offs and messages."""
+import json
+
 import numpy as np
 import pytest
 
@@ -35,11 +37,11 @@ def _rel_inf(x, y):
 def _grids():
     out = {}
     a, b = W.small_upwind(32)
-    out["upwind32"] = (a, b, 32, 32)                        # 1 x 2 tiles, no x padding
+    out["upwind32"] = (a, b, 32, 32)                        # 1 x 3 tiles, x padding
     a, b = W.precision_at_scale(45)
     out["field45"] = (a, b, 45, 45)                         # ragged in x and y
     a = W.random_grid_5pt(130, 70, W.rng(330, 0), one_way=0.15, flip=0.2)
-    out["rand130x70"] = (a, W.rng(330, 1).uniform(-1, 1, a.n), 130, 70)   # 3 x 5 tiles
+    out["rand130x70"] = (a, W.rng(330, 1).uniform(-1, 1, a.n), 130, 70)   # 3 x 6 tiles
     a = W.random_grid_5pt(200, 3, W.rng(330, 2))
     out["strip200x3"] = (a, W.rng(330, 3).uniform(-1, 1, a.n), 200, 3)    # one tile row
     return out
@@ -114,6 +116,45 @@ def test_tiled_equals_untiled_bitwise(B, monkeypatch, kw):
             assert np.array_equal(xg.cpu().numpy(), xw.cpu().numpy())
 
 
+@pytest.mark.parametrize("kw", [dict(mode="joint"),
+                                dict(mode="precomp", precision="f32_ir", tol_lambda=1e-7)])
+def test_tiled_xcd_order_covers_every_tile(B, monkeypatch, kw):
+    """A grid wide enough for several strips in the XCD-aware tile order, the last strip
+    narrower (650 columns: 11 tile columns in strips of 2): every tile is taken exactly once
+    (poisoned output buffers) and the iterates equal the untiled layout's bit for bit."""
+    a = W.random_grid_5pt(650, 40, W.rng(333, 0))
+    bt = _cuda(W.rng(333, 1).uniform(-1, 1, a.n))
+    plain = B.Solver.from_csr(a, **kw)
+    monkeypatch.setenv("GABP_FAULT_INJECT", "poison-outputs")
+    tiled = B.Solver.from_csr(a, tiles=True, grid=(650, 40), **kw)
+    monkeypatch.delenv("GABP_FAULT_INJECT")
+    for k in (2, 3, 8):
+        got = tiled.sweeps(bt, k).cpu().numpy()
+        assert np.all(np.isfinite(got)) and np.array_equal(got, plain.sweeps(bt, k).cpu().numpy()), k
+
+
+@pytest.mark.parametrize("kw", [dict(mode="joint"), dict(mode="seq"),
+                                dict(mode="precomp", precision="f32_ir", tol_lambda=1e-7)])
+def test_tiled_autotune(B, tmp_path, monkeypatch, kw):
+    """The autotuner times a tiled layout with its two-sweep kernels under a cache entry of
+    its own (the untiled layout of the same matrix gets another one), and the tuned kernels
+    keep the iterates."""
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("GABP_AUTOTUNE_CACHE", str(cache))
+    a, b, nx, ny = GRIDS["rand130x70"]
+    bt = _cuda(b)
+    ref = B.Solver.from_csr(a, **kw).sweeps(bt, 7).cpu().numpy()
+    tiled = B.Solver.from_csr(a, tiles=True, grid=(nx, ny), **kw)
+    plain = B.Solver.from_csr(a, **kw)
+    t = tiled.autotune()
+    plain.autotune()
+    assert t["stream_hints"] in (0, 1) and t["check_every"] in (8, 16, 32, 64, 128, 256)
+    keys = [json.loads(line)["key"] for line in cache.read_text().splitlines()]
+    assert len(keys) == 2 and keys[0] != keys[1]
+    assert np.array_equal(tiled.sweeps(bt, 7).cpu().numpy(), ref)
+    assert np.array_equal(plain.sweeps(bt, 7).cpu().numpy(), ref)
+
+
 def test_tiled_options_are_checked(B):
     a, b, nx, ny = GRIDS["upwind32"]
     with pytest.raises(B.GaBPError):
@@ -163,8 +204,8 @@ def test_tiled_full_size_sampled_parity(B):
     s = B.Solver.from_csr(a, tiles=True, grid=(n, n))
     bt = _cuda(b)
     r = W.rng(332, 0)
-    pick = [0, n - 1, n * n - 1, n * (n - 1), 63, 64, 15 * n + 63, 16 * n + 64, 16 * n + 63,
-            31 * n + 1000]
+    pick = [0, n - 1, n * n - 1, n * (n - 1), 63, 64, 12 * n + 63, 13 * n + 64, 13 * n + 63,
+            12 * n + 64, 25 * n + 127, 26 * n + 128, 2047 * n - 1000, 31 * n + 1000]
     samples = np.concatenate([np.array(pick), r.choice(n * n, 30, replace=False)])
     for sweeps in (2, 3, 16):
         x = s.sweeps(bt, sweeps).cpu().numpy()
