@@ -22,12 +22,17 @@ def test_traffic_record_matches_its_source():
     rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))
     assert os.path.exists(os.path.join(ROOT, rec["source"]))
     assert os.path.exists(os.path.join(ROOT, rec["summary"]))
-    assert rec["fetch_scale"] == 2.0 and rec["write_scale"] == 0.999
+    cal = rec["calibration"]
+    assert cal["fetch_scale"] == 2.0 and cal["write_scale"] == 0.999
     sys.path.insert(0, ROOT)
     import hashlib
     import bench
     src = open(os.path.join(ROOT, rec["source"]), "rb").read()
     same = hashlib.sha256(src).hexdigest()[:16] == rec["source_sha256_prefix"]
-    got = bench.measured_traffic(rec["kernel"])
-    assert got == (rec["hbm_bytes_per_launch"] if same else None)
+    assert rec["kernels"]
+    for name, k in rec["kernels"].items():
+        # the calibrated bytes are the counters times the copy-probe factors
+        want = (k["fetch_kib"] * cal["fetch_scale"] + k["write_kib"] * cal["write_scale"]) * 1024
+        assert abs(k["hbm_bytes_per_launch"] - want) <= 1e5
+        assert bench.measured_traffic(name) == (k["hbm_bytes_per_launch"] if same else None)
     assert bench.measured_traffic("k_not_a_kernel") is None
