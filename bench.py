@@ -267,7 +267,12 @@ def main():
                      "traffic": measured_traffic(kname),
                      "frac_of_copy": achieved / copy_gbs,
                      "algorithmic_bytes_per_launch": ab, "launch_us": t_launch * 1e6,
-                     "sweeps_per_launch": per_launch, "reverse_index_bytes": rb},
+                     "sweeps_per_launch": per_launch, "reverse_index_bytes": rb,
+                     # the bytes one-sweep launches would stream for this launch's work
+                     # (2-byte reverse deltas), over this launch's time: above 1 of the
+                     # peak means the launch did more work than streaming allows
+                     "streaming_equivalent_GBs": per_launch * sweep_bytes_joint64(
+                         lay["slots"], a.n, 2) / t_launch / 1e9},
         "wall_s_timed": t_wall,
         "kernels": {
             "joint_f64_sweep_us": t_sw * 1e6,
@@ -843,6 +848,7 @@ def suite_sweeps_large(log, n=4095, sweeps=40):
             lay = s.layout_info()
             if kw["mode"] == "precomp":
                 s.precompute_lambda()
+            tuned = s.autotune()
             x = torch.zeros(a.n, dtype=torch.float64, device="cuda")
             s.sweeps(bt, 2, x=x)
             torch.cuda.synchronize()
@@ -857,7 +863,8 @@ def suite_sweeps_large(log, n=4095, sweeps=40):
                    "algorithmic_bytes_per_launch": ab,
                    "GBps_per_launch": ab / (per * dt) / 1e9,
                    "frac_of_hbm_peak": ab / (per * dt) / 1e9 / HBM_PEAK_GBS,
-                   "edge_updates_per_s": (a.nnz - a.n) / dt}
+                   "edge_updates_per_s": (a.nnz - a.n) / dt,
+                   "stream_hints": tuned["stream_hints"]}
             out[("tiled_" if tiles else "plain_") + name] = rec
             log(f"[suite] sweeps {n}x{n} tiles={tiles} {name}: {rec}")
             del s

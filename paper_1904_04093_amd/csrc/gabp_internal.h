@@ -132,6 +132,7 @@ struct Layout {
   int32_t tile_slots_max = 0;         // largest slot range of one tile
   int4* tile_halo = nullptr;          // [ntiles * kHaloThreads]
   int32_t tiles_x = 0;                // tile columns (tile t sits at column t % tiles_x)
+  int32_t grid_nx = 0, grid_ny = 0;   // the grid: node (x, y) is row y * grid_nx + x
   int32_t tile_strip = 1;             // tile columns per strip of the XCD-aware tile order
 };
 

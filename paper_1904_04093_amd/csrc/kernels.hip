@@ -34,6 +34,17 @@ __device__ __forceinline__ int row_base(const int32_t* __restrict__ sptr, int j,
   return a + (j & 63);
 }
 
+// The same for a lane t whose whole wavefront lies in one slice (launches over lanes that
+// start on a slice boundary, in workgroups of whole wavefronts): the slice index is made
+// wave-uniform, so its two sptr reads are scalar loads, issued without waiting for any
+// vector load (in particular not for the lane's row).
+__device__ __forceinline__ int row_base_wave(const int32_t* __restrict__ sptr, int t, int* w) {
+  const int s = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int a = sptr[s];
+  *w = (sptr[s + 1] - a) >> 6;
+  return a + (t & 63);
+}
+
 // ---- streaming loads/stores ----------------------------------------------------------
 // Per-slot arrays are touched once per sweep and the sweep's footprint exceeds the
 // last-level cache, so they are read and written with non-temporal hints.
@@ -97,14 +108,13 @@ __global__ __launch_bounds__(kBlock) void k_joint(
   const int t = t0 + static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x);
   if (t >= t1) return;
   const int j = row_of(perm, t);
-  if (j < 0) return;
   int w;
-  const int p0 = row_base(sptr, t, &w);
-  double S = diag[j];
-  double M = b[j];
+  const int p0 = row_base_wave(sptr, t, &w);
   if constexpr (KMAX > 0) {
     double l[KMAX], m[KMAX], a[KMAX];
     int r[KMAX];
+    // the slot loads are issued before the lane's row is known (a padding lane reads its
+    // own padding slots and stops below)
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) {
       if (k < w) {
@@ -121,6 +131,9 @@ __global__ __launch_bounds__(kBlock) void k_joint(
         }
       }
     }
+    if (j < 0) return;
+    double S = diag[j];
+    double M = b[j];
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) {
       if (k < w) {
@@ -140,6 +153,9 @@ __global__ __launch_bounds__(kBlock) void k_joint(
       }
     }
   } else {
+    if (j < 0) return;
+    double S = diag[j];
+    double M = b[j];
     auto in = [&](const double* buf, int p) -> double {
       if constexpr (FIRST) return rev_of<false, R16>(rev, rev16, p, rshift) < fresh ? buf[p] : 0.0;
       else return buf[p];
@@ -190,13 +206,12 @@ __global__ __launch_bounds__(kBlock) void k_mean(
   const int t = t0 + static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x);
   if (t >= t1) return;
   const int j = row_of(perm, t);
-  if (j < 0) return;
   int w;
-  const int p0 = row_base(sptr, t, &w);
-  T M = b[j];
+  const int p0 = row_base_wave(sptr, t, &w);
   if constexpr (KMAX > 0) {
     T m[KMAX], lo[KMAX];
     int r[KMAX];
+    // slot loads first, as in k_joint
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) {
       if (k < w) {
@@ -207,6 +222,8 @@ __global__ __launch_bounds__(kBlock) void k_mean(
         else m[k] = ld_s<NT>(msg_in + p);
       }
     }
+    if (j < 0) return;
+    T M = b[j];
 #pragma unroll
     for (int k = 0; k < KMAX; ++k)
       if (k < w) M += m[k];
@@ -217,6 +234,8 @@ __global__ __launch_bounds__(kBlock) void k_mean(
     for (int k = 0; k < KMAX; ++k)
       if (k < w) st_s<NT>(lo[k] * (M - m[k]), msg_out + r[k]);
   } else {
+    if (j < 0) return;
+    T M = b[j];
     auto in = [&](int p) -> T {
       if constexpr (FIRST) return rev_of<false, R16>(rev, rev16, p, rshift) < fresh ? msg_in[p] : T(0);
       else return msg_in[p];
@@ -250,8 +269,7 @@ __global__ __launch_bounds__(kTileThreads) void k_joint2(
     const double* __restrict__ coef, const double* __restrict__ diag,
     const double* __restrict__ b, const double* lam_in, const double* msg_in,
     double* lam_out, double* msg_out, double* __restrict__ x,
-    const int32_t* __restrict__ perm, double* __restrict__ xadd, int slots_max, int tiles_x,
-    int strip) {
+    double* __restrict__ xadd, int slots_max, int tiles_x, int strip, int nx, int ny) {
   extern __shared__ double lds[];
   double* Ls = lds;
   double* Ms = lds + slots_max;
@@ -265,21 +283,26 @@ __global__ __launch_bounds__(kTileThreads) void k_joint2(
   int w = 0, p0 = 0, j = -1;
   double dj = 0.0, bj = 0.0;
   if (own) {
+    // one slice (one grid row of 64 nodes) per own wavefront: the slot range is read with
+    // scalar loads and the row follows from the tile's position, so every load of the row
+    // is issued at once (a padding lane past the grid's edge reads its own padding slots
+    // and row 0's entries, and sends nothing)
     const int tl = tile * kTileOwnThreads + static_cast<int>(threadIdx.x);
-    j = perm[tl];
-    if (j >= 0) {
-      p0 = row_base(sptr, tl, &w);
-      dj = diag[j];
-      bj = b[j];
+    p0 = row_base_wave(sptr, tl, &w);
+    const int gx = (tile % tiles_x) * kSlice + (static_cast<int>(threadIdx.x) & 63);
+    const int gy = (tile / tiles_x) * kTileUnit + (static_cast<int>(threadIdx.x) >> 6);
+    j = gx < nx && gy < ny ? gy * nx + gx : -1;
+    const int jc = j < 0 ? 0 : j;
+    dj = diag[jc];
+    bj = b[jc];
 #pragma unroll
-      for (int k = 0; k < kTileMaxWidth; ++k) {
-        if (k < w) {
-          const int p = p0 + 64 * k;
-          a[k] = ld_s<NT>(coef + p);
-          r[k] = ld_s<NT>(rev + p);
-          l[k] = FIRST ? 0.0 : ld_s<NT>(lam_in + p);
-          m[k] = FIRST ? 0.0 : ld_s<NT>(msg_in + p);
-        }
+    for (int k = 0; k < kTileMaxWidth; ++k) {
+      if (k < w) {
+        const int p = p0 + 64 * k;
+        a[k] = ld_s<NT>(coef + p);
+        r[k] = ld_s<NT>(rev + p);
+        l[k] = FIRST ? 0.0 : ld_s<NT>(lam_in + p);
+        m[k] = FIRST ? 0.0 : ld_s<NT>(msg_in + p);
       }
     }
   }
@@ -368,7 +391,7 @@ __global__ __launch_bounds__(kTileThreads) void k_mean2(
     const int4* __restrict__ halo,
     const T* __restrict__ lamA, const T* __restrict__ lamB, const T* __restrict__ SxB,
     const T* __restrict__ b, const T* msg_in, T* msg_out, T* __restrict__ x,
-    const int32_t* __restrict__ perm, double* __restrict__ xadd, int tiles_x, int strip) {
+    double* __restrict__ xadd, int tiles_x, int strip, int nx, int ny) {
   constexpr int RPT = TS / kTileUnit;
   extern __shared__ double lds_raw[];
   T* Ms = reinterpret_cast<T*>(lds_raw);
@@ -391,20 +414,21 @@ __global__ __launch_bounds__(kTileThreads) void k_mean2(
     T lo[RPT][kTileMaxWidth];
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
+      // as in k_joint2: scalar slot range per wavefront, the row from the tile's position
       const int tl = tile * TS * kSlice + static_cast<int>(threadIdx.x) + q * kTileOwnThreads;
-      j[q] = perm[tl];
-      if (j[q] >= 0) {
-        p0[q] = row_base(sptr, tl, &w[q]);
-        bj[q] = b[j[q]];
+      p0[q] = row_base_wave(sptr, tl, &w[q]);
+      const int gx = (tile % tiles_x) * kSlice + (static_cast<int>(threadIdx.x) & 63);
+      const int gy = (tile / tiles_x) * TS + (static_cast<int>(threadIdx.x) >> 6) + q * kTileUnit;
+      j[q] = gx < nx && gy < ny ? gy * nx + gx : -1;
+      bj[q] = b[j[q] < 0 ? 0 : j[q]];
 #pragma unroll
-        for (int k = 0; k < kTileMaxWidth; ++k) {
-          if (k < w[q]) {
-            const int p = p0[q] + 64 * k;
-            lo[q][k] = ld_s<NT>(lamA + p);
-            lb[q][k] = lamB == lamA ? lo[q][k] : ld_s<NT>(lamB + p);
-            r[q][k] = ld_s<NT>(rev + p);
-            m[q][k] = FIRST ? T(0) : ld_s<NT>(msg_in + p);
-          }
+      for (int k = 0; k < kTileMaxWidth; ++k) {
+        if (k < w[q]) {
+          const int p = p0[q] + 64 * k;
+          lo[q][k] = ld_s<NT>(lamA + p);
+          lb[q][k] = lamB == lamA ? lo[q][k] : ld_s<NT>(lamB + p);
+          r[q][k] = ld_s<NT>(rev + p);
+          m[q][k] = FIRST ? T(0) : ld_s<NT>(msg_in + p);
         }
       }
     }
@@ -1039,7 +1063,8 @@ hipError_t launch_joint_pair(const SweepArgs& a, hipStream_t s) {
   const size_t lds = 2 * static_cast<size_t>(L.tile_slots_max) * sizeof(double);
 #define JOINT2_ARGS                                                                         \
   L.sptr, L.rev, L.tile_halo, a.coef, L.diag, a.b, a.lam_in, a.msg_in,          \
-      a.lam_out, a.msg_out, a.x, L.perm, a.xadd, L.tile_slots_max, L.tiles_x, L.tile_strip
+      a.lam_out, a.msg_out, a.x, a.xadd, L.tile_slots_max, L.tiles_x, L.tile_strip, L.grid_nx, \
+      L.grid_ny
   GABP_DISPATCH_FIRST(a.fresh >= 0, GABP_DISPATCH_NT(L.stream_hints,
     GABP_DISPATCH_WX(a.xadd ? (a.xset ? 3 : 2) : (a.x ? 1 : 0), {
       k_joint2<WXB, NTB, FB><<<L.ntiles, kTileThreads, lds, s>>>(JOINT2_ARGS);
@@ -1055,7 +1080,7 @@ hipError_t mean_pair_dispatch(const MeanPairArgs<T>& a, bool nt, hipStream_t s) 
   const size_t lds = static_cast<size_t>(L.tile_slots_max) * sizeof(T);
 #define MEAN2_ARGS                                                                          \
   L.sptr, L.rev, L.tile_halo, a.lamA, a.lamB, a.SxB, a.b, a.msg_in, a.msg_out,  \
-      a.x, L.perm, a.xadd, L.tiles_x, L.tile_strip
+      a.x, a.xadd, L.tiles_x, L.tile_strip, L.grid_nx, L.grid_ny
   GABP_DISPATCH_FIRST(a.fresh >= 0, GABP_DISPATCH_NT(nt,
     GABP_DISPATCH_WX(a.xadd ? (a.xset ? 3 : 2) : (a.x ? 1 : 0), {
       if (L.tile_slices == 2 * kTileUnit)

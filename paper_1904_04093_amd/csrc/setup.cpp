@@ -427,6 +427,8 @@ int gabp_setup(gabp_ctx** out, int32_t n, int64_t nnz, const int32_t* rowptr,
     UP(L.tile_halo, halo);
     L.ntiles = ntiles;
     L.tiles_x = tiles_x;
+    L.grid_nx = o.grid_nx;
+    L.grid_ny = o.grid_ny;
     // XCD-aware tile order: one strip of tile columns per XCD where the width allows
     L.tile_strip = std::max<int32_t>(1, (tiles_x + kXcds - 1) / kXcds);
     L.tile_slices = tsl;
