@@ -263,9 +263,10 @@ int gabp_layout_info(const gabp_ctx* ctx, int32_t* n, int64_t* nnz, int64_t* slo
  * systems, at workgroup sizes of 64, 128 and 256 threads (1, 2 or 4 slices of 64 rows per
  * workgroup), keeps the fastest pair, then sets opt.check_every to the smallest power of
  * two in [8, 256] for which one residual check (kernel, reduction, readback, host wait)
- * costs at most 2% of the sweeps between checks. Results are cached per (architecture,
- * sizes, mode) in memory and, when the environment variable GABP_AUTOTUNE_CACHE names a
- * file, in that JSON-lines file. Runs sweeps on a zero right-hand side, so the context's
+ * costs at most 2% of the sweeps between checks. A tiled context (opt.tiles) is timed with
+ * its two-sweep kernels (one workgroup per tile: hints only). Results are cached per
+ * (architecture, sizes, mode, schedule, layout) in memory and, when the environment
+ * variable GABP_AUTOTUNE_CACHE names a file, in that JSON-lines file. Runs sweeps on a zero right-hand side, so the context's
  * message state is reset; computes the precomputed Lt first when the mode needs it.
  * Outputs (host, may be NULL): the chosen check interval, hint setting (0/1) and workgroup
  * size. Because it changes check_every, later solves may stop at a different (rounded-up)

@@ -163,7 +163,10 @@ struct gabp_ctx {
   float* dbest32 = nullptr;   // [n] best inner correction of the current refinement step
   // reductions
   int32_t nred = 0;           // blocks of the residual kernel
-  double* partials = nullptr; // [3 * nred]
+  // per-block partials, shared by the residual kernel (3 per block of kRedBlock rows) and
+  // the Lt-phase kernel (2 per block of kBlock lanes): [npartials], enough for both
+  double* partials = nullptr;
+  int64_t npartials = 0;
   double* red = nullptr;      // [8] device scalars: 0 ||r||2^2, 1 max|r|, 2 ||b||2^2,
                               // 3 max|r| again, 4 refinement scale, 5 max|dLt|, 6 max|Lt|
   unsigned long long* lmax = nullptr;  // [2] max|dLt|, max|Lt| as ordered bit patterns

@@ -464,7 +464,9 @@ int gabp_setup(gabp_ctx** out, int32_t n, int64_t nnz, const int32_t* rowptr,
   AL(c->r32, n);
   AL(c->d32, n);
   c->nred = static_cast<int32_t>((nlanes + kRedBlock - 1) / kRedBlock);
-  AL(c->partials, 3 * (int64_t)c->nred);
+  c->npartials = std::max<int64_t>(3 * static_cast<int64_t>(c->nred),
+                                   2 * ((nlanes + kBlock - 1) / kBlock));
+  AL(c->partials, c->npartials);
   AL(c->red, 8);
   AL(c->lmax, 2);
 #undef UP

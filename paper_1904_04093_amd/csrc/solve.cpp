@@ -138,6 +138,8 @@ int ensure_pre(gabp_ctx* c, int T, hipStream_t s) {
   GABP_HIP(launch_fill64(c->lam[0], L.epad + 1, 0.0, s));
   GABP_HIP(launch_fill64(c->lam[1], L.epad + 1, 0.0, s));
   const double* coef = sweep_coef(c, T);
+  if (2 * ((L.nlanes + kBlock - 1) / kBlock) > c->npartials)   // k_lambda's partials
+    return fail(GABP_EINVAL, "internal: partials buffer smaller than the Lt phase needs");
   int par = 0, done = 0;
   const double tol = c->opt.tol_lambda;
   for (int it = 1; it <= c->opt.max_lambda_sweeps; ++it) {
