@@ -166,6 +166,8 @@ int gabp_setup(gabp_ctx** out, int32_t n, int64_t nnz, const int32_t* rowptr,
     }
     std::vector<int64_t> cnt(ncolours, 0), next(ncolours);
     for (int32_t j = 0; j < n; ++j) ++cnt[colour[j]];
+    // every class starts on a slice boundary: a class launch's wavefronts then each lie in
+    // one slice, which the sweep kernels rely on (they read a wavefront's slot range once)
     int64_t acc = 0;
     for (int c = 0; c < ncolours; ++c) {
       next[c] = acc;
