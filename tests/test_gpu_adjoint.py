@@ -31,7 +31,8 @@ def _loss_dense(n, theta, b, xt):
 
 
 @pytest.mark.parametrize("precision,schedule", [("f32_ir", "flood"), ("f64", "flood"),
-                                                 ("f64", "lines_alt")])
+                                                 ("f64", "lines_alt"), ("f32_ir", "tiles"),
+                                                 ("f64", "tiles")])
 def test_theta_gradient_matches_fd_and_dense_adjoint(mods, precision, schedule):
     gabp, AG = mods
     n = 16
@@ -48,10 +49,13 @@ def test_theta_gradient_matches_fd_and_dense_adjoint(mods, precision, schedule):
     # precomputed Lt alone cannot reach 1e-13; refinement removes that floor)
     mode = "precomp" if precision == "f32_ir" else "joint"
     # line GaBP as the solver too: its transposed solve runs the line recurrences on A^T
-    grid = (n, n) if schedule.startswith("lines") else None
+    # and the flood schedule with two sweeps per launch on grid tiles (forward and A^T)
+    grid = (n, n) if schedule != "flood" else None
+    tiles = schedule == "tiles"
     solver = gabp.Solver.from_csr(field.pattern, mode=mode, precision=precision,
-                                  check_every=16, tol_lambda=1e-12, schedule=schedule,
-                                  grid=grid)
+                                  check_every=16, tol_lambda=1e-12,
+                                  schedule="flood" if tiles else schedule, grid=grid,
+                                  tiles=tiles)
     bt = torch.as_tensor(b, device="cuda")
     x = AG.gabp_solve(vals, bt, solver, tol=1e-13)
     loss = 0.5 * ((x - torch.as_tensor(xt, device="cuda")) ** 2).sum()

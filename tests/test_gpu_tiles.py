@@ -155,6 +155,30 @@ def test_tiled_autotune(B, tmp_path, monkeypatch, kw):
     assert np.array_equal(plain.sweeps(bt, 7).cpu().numpy(), ref)
 
 
+@pytest.mark.parametrize("kw", [dict(mode="joint"), dict(mode="seq"),
+                                dict(mode="precomp", tol_lambda=1e-12),
+                                dict(mode="seq", precision="f32_ir")])
+def test_tiled_smoother_equals_untiled(B, kw):
+    """Algorithm 3 on a tiled layout (two-sweep launches, a plain one for an odd count, the
+    correction added by the last launch): the same bits as the untiled smoother, against
+    the oracle's joint smoother to 1e-12 in FP64."""
+    a, b, nx, ny = GRIDS["rand130x70"]
+    g = G.Graph.from_csr(a)
+    bt = _cuda(b)
+    plain = B.Solver.from_csr(a, **kw)
+    tiled = B.Solver.from_csr(a, tiles=True, grid=(nx, ny), **kw)
+    x0 = W.rng(334, 0).uniform(-1, 1, a.n)
+    xp, xt = _cuda(x0), _cuda(x0)
+    xo = x0.copy()
+    for mu in (1, 2, 3, 4):
+        plain.smooth(bt, xp, mu)
+        tiled.smooth(bt, xt, mu)
+        assert np.array_equal(xt.cpu().numpy(), xp.cpu().numpy()), (kw, mu)
+        if kw["mode"] in ("joint", "seq") and "precision" not in kw:
+            xo = G.smooth(g, b, xo, mu)
+            assert _rel_inf(xt.cpu().numpy(), xo) <= TOL, (kw, mu)
+
+
 def test_tiled_options_are_checked(B):
     a, b, nx, ny = GRIDS["upwind32"]
     with pytest.raises(B.GaBPError):
