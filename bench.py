@@ -11,8 +11,11 @@ residual check r = b - A x with its norms. ``value`` = directed edge-message upd
 second over the timed steps (inputs resident in HBM).
 
 Also reported on the same JSON line:
-  * roofline of the dominant kernel (the joint sweep): algorithmic bytes per launch over its
-    average launch time from HIP events on the launch stream;
+  * roofline of the dominant kernel (the joint sweep kernel; by default the tiled layout,
+    two sweeps per launch, `--no-tiles` for one): algorithmic bytes per launch (one pass
+    over the message state) over its average launch time from HIP events on the launch
+    stream, the counted HBM bytes from the committed counter record, and the streaming
+    equivalent (the bytes one-sweep launches would move for the same sweeps);
   * FP32 mean-only sweep rate (the inner kernel of FP32-message iterative refinement) and
     FP64 mean-only sweep rate with precomputed Lt;
   * time to relative residual 1e-8 on the same 2048 x 2048 operator through gabp_solve:
