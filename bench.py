@@ -207,7 +207,7 @@ def main():
     ab = sweep_bytes_joint64(lay["slots"], a.n, rb)
     achieved = ab / t_launch / 1e9
     nt = "true" if tuned["stream_hints"] else "false"
-    kname = (f"k_joint2<0, {nt}, false>" if tiles
+    kname = (f"k_joint2<0, {tuned['stream_hints']}, false>" if tiles
              else f"k_joint<4, 0, {nt}, {'true' if rb == 2 else 'false'}, false>")
     log(f"[bench] joint sweep kernel {t_launch*1e6:.1f} us per launch ({per_launch} sweeps), "
         f"{achieved:.0f} GB/s algorithmic")

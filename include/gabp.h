@@ -110,6 +110,13 @@ typedef struct {
   double progress_s;         /* > 0: gabp_solve / gabp_solve_transposed print one line to
                                 stderr (sweeps done, relative residual, seconds) at the
                                 first check after every progress_s seconds     default 0 */
+  int32_t stream_hints;      /* cache hints of the single-system sweep kernels' per-slot
+                                streams: -1 by the footprint (non-temporal once a sweep's
+                                bytes exceed the last-level cache; gabp_autotune measures
+                                instead), 0 plain, 1 non-temporal loads and stores, 2
+                                non-temporal stores with plain loads (tiled layouts only:
+                                a tile's halo reads its neighbours' lines, which plain loads
+                                keep in L2)                                  default -1 */
 } gabp_options;
 
 typedef struct {
@@ -268,8 +275,8 @@ int gabp_layout_info(const gabp_ctx* ctx, int32_t* n, int64_t* nnz, int64_t* slo
  * (architecture, sizes, mode, schedule, layout) in memory and, when the environment
  * variable GABP_AUTOTUNE_CACHE names a file, in that JSON-lines file. Runs sweeps on a zero right-hand side, so the context's
  * message state is reset; computes the precomputed Lt first when the mode needs it.
- * Outputs (host, may be NULL): the chosen check interval, hint setting (0/1) and workgroup
- * size. Because it changes check_every, later solves may stop at a different (rounded-up)
+ * Outputs (host, may be NULL): the chosen check interval, hint setting (0/1, and 2 for a
+ * tiled context: the values of opt.stream_hints) and workgroup size. Because it changes check_every, later solves may stop at a different (rounded-up)
  * sweep count than untuned ones. Line schedules have no hint or workgroup variants: only
  * the check interval is tuned (from one line sweep), hints_out is 0 and block_out 256;
  * batches keep 256-thread workgroups. */

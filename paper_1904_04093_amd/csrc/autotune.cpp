@@ -1,5 +1,6 @@
 // Autotuner: per context, measure and pick (1) whether the sweep kernels stream their
-// per-slot arrays with non-temporal hints, (2) the workgroup size of the single-system
+// per-slot arrays with non-temporal hints (for tiled layouts also: non-temporal stores with
+// plain loads), (2) the workgroup size of the single-system
 // sweep kernels (64, 128 or 256 threads: 1, 2 or 4 slices of 64 rows) and (3) the number of
 // sweeps between residual checks. Results are cached per (device, sizes, mode) in a JSON-lines file named by the
 // environment variable GABP_AUTOTUNE_CACHE (in memory only when it is unset).
@@ -178,6 +179,7 @@ int gabp_autotune(gabp_ctx* c, int32_t* check_every_out, int32_t* hints_out,
   Tuned t{};
   const bool f32 = c->opt.precision == GABP_F32_IR;
   bool& hints = f32 ? c->L.stream_hints32 : c->L.stream_hints;
+  bool& store_only = f32 ? c->L.store_hints32 : c->L.store_hints;
   if (!cache_lookup(key, &t)) {
     int st;
     const bool seq = c->opt.mode == GABP_MODE_PRECOMP_SEQ;
@@ -263,12 +265,14 @@ int gabp_autotune(gabp_ctx* c, int32_t* check_every_out, int32_t* hints_out,
       t.hints = 0;
     } else {
       // every (hints, workgroup size) pair; the fastest is kept (the two-sweep kernels have
-      // one workgroup per tile: hints only, per sweep)
+      // one workgroup per tile: hints only, per sweep, with the third setting of
+      // non-temporal stores and plain loads)
       static const int kBlocks[3] = {64, 128, 256};
       t_sweep = 0.0;
-      for (int h = 0; h < 2; ++h)
+      for (int h = 0; h < (pairs ? 3 : 2); ++h)
         for (int bi = pairs ? 2 : 0; bi < 3; ++bi) {
-          hints = h != 0;
+          hints = h == 1;
+          store_only = h == 2;
           c->L.block = kBlocks[bi];
           double tt = 0.0;
           if ((st = time_it(s, reps, one_sweep, &tt)) != GABP_OK) return st;
@@ -279,7 +283,8 @@ int gabp_autotune(gabp_ctx* c, int32_t* check_every_out, int32_t* hints_out,
             t.block = kBlocks[bi];
           }
         }
-      hints = t.hints != 0;
+      hints = t.hints == 1;
+      store_only = t.hints == 2;
       c->L.block = t.block;
     }
     // one residual check: residual kernel, reduction, readback and host wait
@@ -308,7 +313,8 @@ int gabp_autotune(gabp_ctx* c, int32_t* check_every_out, int32_t* hints_out,
     c->fresh64 = true;
     c->fresh32 = true;
   }
-  hints = t.hints != 0;
+  hints = t.hints == 1;
+  store_only = t.hints == 2 && c->L.ntiles > 0;
   if (!c->batch) c->L.block = t.block;
   c->opt.check_every = t.check_every;
   c->graphs->clear();

@@ -87,6 +87,10 @@ struct Layout {
   // once a sweep's footprint exceeds the last-level cache and cost time below it
   bool stream_hints = false;
   bool stream_hints32 = false;
+  // tiled kernels only: non-temporal stores while the loads stay plain (a tile's halo reads
+  // lines its neighbours load, and plain loads keep them in L2)
+  bool store_hints = false;
+  bool store_hints32 = false;
   // threads per workgroup of the single-system sweep kernels: 64, 128 or 256 (1, 2 or 4
   // slices), picked by the autotuner
   int32_t block = kBlock;

@@ -262,7 +262,10 @@ __global__ __launch_bounds__(kBlock) void k_mean(
 // two plain sweeps, so the results are the same bits; HBM traffic is about one sweep's plus
 // the halo's.
 // ---------------------------------------------------------------------------------------
-template <int WX, bool NT, bool FIRST>
+// HS: cache hints of the own rows' slot streams: 0 plain, 1 non-temporal loads and stores,
+// 2 non-temporal stores only (the outputs are read by the next launch, not this one; plain
+// loads keep the lines a neighbouring tile's halo reads in L2)
+template <int WX, int HS, bool FIRST>
 __global__ __launch_bounds__(kTileThreads) void k_joint2(
     const int32_t* __restrict__ sptr, const int32_t* __restrict__ rev,
     const int4* __restrict__ halo,
@@ -299,10 +302,10 @@ __global__ __launch_bounds__(kTileThreads) void k_joint2(
     for (int k = 0; k < kTileMaxWidth; ++k) {
       if (k < w) {
         const int p = p0 + 64 * k;
-        a[k] = ld_s<NT>(coef + p);
-        r[k] = ld_s<NT>(rev + p);
-        l[k] = FIRST ? 0.0 : ld_s<NT>(lam_in + p);
-        m[k] = FIRST ? 0.0 : ld_s<NT>(msg_in + p);
+        a[k] = ld_s<HS == 1>(coef + p);
+        r[k] = ld_s<HS == 1>(rev + p);
+        l[k] = FIRST ? 0.0 : ld_s<HS == 1>(lam_in + p);
+        m[k] = FIRST ? 0.0 : ld_s<HS == 1>(msg_in + p);
       }
     }
   }
@@ -376,8 +379,8 @@ __global__ __launch_bounds__(kTileThreads) void k_joint2(
   for (int k = 0; k < kTileMaxWidth; ++k) {
     if (k < w) {
       const double L = -a[k] / (S - l[k] * a[k]);
-      st_s<NT>(L, lam_out + r[k]);
-      st_s<NT>(L * (M - m[k]), msg_out + r[k]);
+      st_s<HS != 0>(L, lam_out + r[k]);
+      st_s<HS != 0>(L * (M - m[k]), msg_out + r[k]);
     }
   }
 }
@@ -385,7 +388,7 @@ __global__ __launch_bounds__(kTileThreads) void k_joint2(
 // Mean-only form (frozen or per-sweep precomputed Lt): sweep 1 sends with lamA, sweep 2
 // reads off with SxB (Sigma, or 1/Sigma for FP32) and sends with lamB. Tiles of TS slices:
 // each own thread takes TS / kTileUnit lanes, kTileOwnThreads apart.
-template <typename T, int TS, int WX, bool NT, bool FIRST>
+template <typename T, int TS, int WX, int HS, bool FIRST>
 __global__ __launch_bounds__(kTileThreads) void k_mean2(
     const int32_t* __restrict__ sptr, const int32_t* __restrict__ rev,
     const int4* __restrict__ halo,
@@ -425,10 +428,10 @@ __global__ __launch_bounds__(kTileThreads) void k_mean2(
       for (int k = 0; k < kTileMaxWidth; ++k) {
         if (k < w[q]) {
           const int p = p0[q] + 64 * k;
-          lo[q][k] = ld_s<NT>(lamA + p);
-          lb[q][k] = lamB == lamA ? lo[q][k] : ld_s<NT>(lamB + p);
-          r[q][k] = ld_s<NT>(rev + p);
-          m[q][k] = FIRST ? T(0) : ld_s<NT>(msg_in + p);
+          lo[q][k] = ld_s<HS == 1>(lamA + p);
+          lb[q][k] = lamB == lamA ? lo[q][k] : ld_s<HS == 1>(lamB + p);
+          r[q][k] = ld_s<HS == 1>(rev + p);
+          m[q][k] = FIRST ? T(0) : ld_s<HS == 1>(msg_in + p);
         }
       }
     }
@@ -487,7 +490,7 @@ __global__ __launch_bounds__(kTileThreads) void k_mean2(
     if constexpr (WX == 3) xadd[j[q]] = static_cast<double>(ReadOff<T>::f(M, SxB, j[q]));
 #pragma unroll
     for (int k = 0; k < kTileMaxWidth; ++k)
-      if (k < w[q]) st_s<NT>(lb[q][k] * (M - m[q][k]), msg_out + r[q][k]);
+      if (k < w[q]) st_s<HS != 0>(lb[q][k] * (M - m[q][k]), msg_out + r[q][k]);
   }
 }
 
@@ -980,6 +983,10 @@ int grid_for(int64_t n) {
 #define GABP_DISPATCH_NT(NTV, ...)                   \
   if (NTV) { constexpr bool NTB = true; __VA_ARGS__; } \
   else { constexpr bool NTB = false; __VA_ARGS__; }
+#define GABP_DISPATCH_HS(HV, ...)                                    \
+  if ((HV) == 2) { constexpr int HSB = 2; __VA_ARGS__; }             \
+  else if ((HV) == 1) { constexpr int HSB = 1; __VA_ARGS__; }        \
+  else { constexpr int HSB = 0; __VA_ARGS__; }
 #define GABP_DISPATCH_R16(RV, ...)                     \
   if (RV) { constexpr bool R16B = true; __VA_ARGS__; } \
   else { constexpr bool R16B = false; __VA_ARGS__; }
@@ -1065,39 +1072,42 @@ hipError_t launch_joint_pair(const SweepArgs& a, hipStream_t s) {
   L.sptr, L.rev, L.tile_halo, a.coef, L.diag, a.b, a.lam_in, a.msg_in,          \
       a.lam_out, a.msg_out, a.x, a.xadd, L.tile_slots_max, L.tiles_x, L.tile_strip, L.grid_nx, \
       L.grid_ny
-  GABP_DISPATCH_FIRST(a.fresh >= 0, GABP_DISPATCH_NT(L.stream_hints,
+  const int hs = L.stream_hints ? 1 : (L.store_hints ? 2 : 0);
+  GABP_DISPATCH_FIRST(a.fresh >= 0, GABP_DISPATCH_HS(hs,
     GABP_DISPATCH_WX(a.xadd ? (a.xset ? 3 : 2) : (a.x ? 1 : 0), {
-      k_joint2<WXB, NTB, FB><<<L.ntiles, kTileThreads, lds, s>>>(JOINT2_ARGS);
+      k_joint2<WXB, HSB, FB><<<L.ntiles, kTileThreads, lds, s>>>(JOINT2_ARGS);
     })))
 #undef JOINT2_ARGS
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t mean_pair_dispatch(const MeanPairArgs<T>& a, bool nt, hipStream_t s) {
+hipError_t mean_pair_dispatch(const MeanPairArgs<T>& a, int hs, hipStream_t s) {
   const Layout& L = *a.L;
   if (L.ntiles <= 0) return hipErrorInvalidValue;
   const size_t lds = static_cast<size_t>(L.tile_slots_max) * sizeof(T);
 #define MEAN2_ARGS                                                                          \
   L.sptr, L.rev, L.tile_halo, a.lamA, a.lamB, a.SxB, a.b, a.msg_in, a.msg_out,  \
       a.x, a.xadd, L.tiles_x, L.tile_strip, L.grid_nx, L.grid_ny
-  GABP_DISPATCH_FIRST(a.fresh >= 0, GABP_DISPATCH_NT(nt,
+  GABP_DISPATCH_FIRST(a.fresh >= 0, GABP_DISPATCH_HS(hs,
     GABP_DISPATCH_WX(a.xadd ? (a.xset ? 3 : 2) : (a.x ? 1 : 0), {
       if (L.tile_slices == 2 * kTileUnit)
-        k_mean2<T, 2 * kTileUnit, WXB, NTB, FB><<<L.ntiles, kTileThreads, lds, s>>>(MEAN2_ARGS);
+        k_mean2<T, 2 * kTileUnit, WXB, HSB, FB><<<L.ntiles, kTileThreads, lds, s>>>(MEAN2_ARGS);
       else
-        k_mean2<T, kTileUnit, WXB, NTB, FB><<<L.ntiles, kTileThreads, lds, s>>>(MEAN2_ARGS);
+        k_mean2<T, kTileUnit, WXB, HSB, FB><<<L.ntiles, kTileThreads, lds, s>>>(MEAN2_ARGS);
     })))
 #undef MEAN2_ARGS
   return hipGetLastError();
 }
 
 hipError_t launch_mean_pair64(const MeanPairArgs<double>& a, hipStream_t s) {
-  return mean_pair_dispatch<double>(a, a.L->stream_hints, s);
+  const Layout& L = *a.L;
+  return mean_pair_dispatch<double>(a, L.stream_hints ? 1 : (L.store_hints ? 2 : 0), s);
 }
 
 hipError_t launch_mean_pair32(const MeanPairArgs<float>& a, hipStream_t s) {
-  return mean_pair_dispatch<float>(a, a.L->stream_hints32, s);
+  const Layout& L = *a.L;
+  return mean_pair_dispatch<float>(a, L.stream_hints32 ? 1 : (L.store_hints32 ? 2 : 0), s);
 }
 
 hipError_t launch_mean_sweep64(const MeanArgs64& a, hipStream_t s) {

@@ -67,6 +67,7 @@ void gabp_default_options(gabp_options* o) {
   o->block = kBlock;
   o->tiles = 0;
   o->progress_s = 0.0;
+  o->stream_hints = -1;
 }
 
 
@@ -86,8 +87,10 @@ int gabp_setup(gabp_ctx** out, int32_t n, int64_t nnz, const int32_t* rowptr,
       (o.schedule < GABP_SCHED_FLOOD || o.schedule > GABP_SCHED_LINES_ALT) ||
       o.ir_max_inner < 1 || !(o.progress_s >= 0.0) ||
       (o.block != 64 && o.block != 128 && o.block != 256) || (o.tiles != 0 && o.tiles != 1) ||
-      !(o.ir_inner_tol > 0.0))
+      !(o.ir_inner_tol > 0.0) || o.stream_hints < -1 || o.stream_hints > 2)
     return fail(GABP_EINVAL, "invalid options");
+  if (o.stream_hints == 2 && !o.tiles)
+    return fail(GABP_EINVAL, "stream_hints 2 (non-temporal stores only) needs a tiled layout");
   if (o.schedule == GABP_SCHED_REDBLACK && !colour)
     return fail(GABP_EINVAL, "red-black schedule needs node colours");
   if (o.mode == GABP_MODE_PRECOMP_SEQ &&
@@ -343,6 +346,10 @@ int gabp_setup(gabp_ctx** out, int32_t n, int64_t nnz, const int32_t* rowptr,
   constexpr double kLLC = 256.0 * 1024 * 1024;
   L.stream_hints = 44.0 * epad + 16.0 * n > kLLC;
   L.stream_hints32 = 16.0 * epad + 4.0 * n > 2.0 * kLLC;
+  if (o.stream_hints >= 0) {
+    L.stream_hints = L.stream_hints32 = o.stream_hints == 1;
+    L.store_hints = L.store_hints32 = o.stream_hints == 2;
+  }
   auto cleanup_fail = [&](int code) {
     gabp_destroy(c);
     return code;

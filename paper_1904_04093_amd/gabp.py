@@ -38,7 +38,7 @@ class Options(ctypes.Structure):
                 ("schedule", ctypes.c_int32), ("use_graphs", ctypes.c_int32),
                 ("grid_nx", ctypes.c_int32), ("grid_ny", ctypes.c_int32),
                 ("tiles", ctypes.c_int32), ("block", ctypes.c_int32),
-                ("progress_s", ctypes.c_double)]
+                ("progress_s", ctypes.c_double), ("stream_hints", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -182,7 +182,7 @@ class Solver:
                  precision="f64", check_every=16, tol_lambda=1e-14,
                  max_lambda_sweeps=100000, ir_inner_tol=1e-4,
                  ir_max_inner=1000000, schedule="flood", use_graphs=True, grid=None,
-                 progress_s=0.0, block=256, tiles=False):
+                 progress_s=0.0, block=256, tiles=False, stream_hints=-1):
         lib = load()
         self._lib = lib
         o = Options()
@@ -196,6 +196,7 @@ class Solver:
         o.progress_s = float(progress_s)
         o.block = int(block)
         o.tiles = int(bool(tiles))
+        o.stream_hints = int(stream_hints)
         if grid is not None:                  # (nx, ny) of the line schedules
             o.grid_nx, o.grid_ny = int(grid[0]), int(grid[1])
         self.options = o

@@ -39,6 +39,8 @@ def test_strerror_and_defaults():
     o = B.Options()
     lib.gabp_default_options(o)
     assert o.check_every == 16 and o.mode == 0 and o.tol_lambda == 1e-14
+    # the last fields: the binding's struct has the header's layout
+    assert o.tiles == 0 and o.block == 256 and o.progress_s == 0.0 and o.stream_hints == -1
 
 
 def _rev(a):

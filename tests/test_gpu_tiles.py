@@ -148,7 +148,7 @@ def test_tiled_autotune(B, tmp_path, monkeypatch, kw):
     plain = B.Solver.from_csr(a, **kw)
     t = tiled.autotune()
     plain.autotune()
-    assert t["stream_hints"] in (0, 1) and t["check_every"] in (8, 16, 32, 64, 128, 256)
+    assert t["stream_hints"] in (0, 1, 2) and t["check_every"] in (8, 16, 32, 64, 128, 256)
     keys = [json.loads(line)["key"] for line in cache.read_text().splitlines()]
     assert len(keys) == 2 and keys[0] != keys[1]
     assert np.array_equal(tiled.sweeps(bt, 7).cpu().numpy(), ref)
@@ -177,6 +177,23 @@ def test_tiled_smoother_equals_untiled(B, kw):
         if kw["mode"] in ("joint", "seq") and "precision" not in kw:
             xo = G.smooth(g, b, xo, mu)
             assert _rel_inf(xt.cpu().numpy(), xo) <= TOL, (kw, mu)
+
+
+@pytest.mark.parametrize("kw", [dict(mode="joint"), dict(mode="precomp", tol_lambda=1e-12),
+                                dict(mode="precomp", precision="f32_ir", tol_lambda=1e-7)])
+def test_tiled_cache_hints_keep_the_bits(B, kw):
+    """The three cache-hint settings of the tiled kernels (plain; non-temporal loads and
+    stores; non-temporal stores only) compute the same bits; the third needs a tiled
+    layout."""
+    a, b, nx, ny = GRIDS["rand130x70"]
+    bt = _cuda(b)
+    outs = [B.Solver.from_csr(a, tiles=True, grid=(nx, ny), stream_hints=h, **kw)
+            .sweeps(bt, 7).cpu().numpy() for h in (0, 1, 2)]
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+    with pytest.raises(B.GaBPError):
+        B.Solver.from_csr(a, stream_hints=2, **kw)
+    with pytest.raises(B.GaBPError):
+        B.Solver.from_csr(a, tiles=True, grid=(nx, ny), stream_hints=3, **kw)
 
 
 def test_tiled_options_are_checked(B):
