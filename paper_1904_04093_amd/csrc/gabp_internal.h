@@ -91,6 +91,9 @@ struct Layout {
   // lines its neighbours load, and plain loads keep them in L2)
   bool store_hints = false;
   bool store_hints32 = false;
+  // the residual kernel's streamed inputs (row slots, b, diag, columns, coefficients) with
+  // non-temporal loads (x, which it gathers, stays plain): its bytes exceed the LLC
+  bool res_hints = false;
   // threads per workgroup of the single-system sweep kernels: 64, 128 or 256 (1, 2 or 4
   // slices), picked by the autotuner
   int32_t block = kBlock;

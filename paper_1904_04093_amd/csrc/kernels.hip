@@ -664,9 +664,11 @@ __global__ __launch_bounds__(kBlock) void k_lambda_step(
 // Residual r = b - A x (coef_row = val) or b - A^T x (coef_row = aT), optionally at
 // x + scale * dx, with per-block partial norms. Threads take rows in row order, also for a
 // colour-major layout (a row's slots found through its lane), so that b, x, diag and r are
-// read and written in whole runs and a row's neighbours are gathered near its own x.
+// read and written in whole runs and a row's neighbours are gathered near its own x. NT:
+// the streamed inputs (row slots, b, diag, columns, coefficients) with non-temporal loads,
+// x (gathered by the neighbouring rows) with plain ones.
 // ---------------------------------------------------------------------------------------
-template <int KMAX, bool XADD>
+template <int KMAX, bool XADD, bool NT>
 __global__ __launch_bounds__(kRedBlock) void k_residual(
     int n, const int32_t* __restrict__ sptr, const int32_t* __restrict__ col,
     const double* __restrict__ coef_row, const double* __restrict__ diag,
@@ -682,7 +684,7 @@ __global__ __launch_bounds__(kRedBlock) void k_residual(
   if (j >= 0) {
     int w, p0;
     if (row_slot) {   // first slot and slice width of row j, packed: one load, no sptr
-      const unsigned v = static_cast<unsigned>(row_slot[j]);
+      const unsigned v = static_cast<unsigned>(ld_s<NT>(row_slot + j));
       p0 = static_cast<int>(v & kRowSlotMask);
       w = static_cast<int>(v >> kRowSlotShift);
     } else {
@@ -691,8 +693,8 @@ __global__ __launch_bounds__(kRedBlock) void k_residual(
     const double sc = XADD ? scale[0] : 0.0;
     double xj = x[j];
     if (XADD) xj = fma(sc, static_cast<double>(dx[j]), xj);
-    const double bj = b[j];
-    double acc = fma(-diag[j], xj, bj);
+    const double bj = ld_s<NT>(b + j);
+    double acc = fma(-ld_s<NT>(diag + j), xj, bj);
     if constexpr (KMAX > 0) {
       // all index and coefficient loads first, then the gathers: more bytes in flight
       int cc[KMAX];
@@ -700,8 +702,8 @@ __global__ __launch_bounds__(kRedBlock) void k_residual(
 #pragma unroll
       for (int k = 0; k < KMAX; ++k) {
         if (k < w) {
-          cc[k] = col[p0 + 64 * k];
-          cf[k] = coef_row[p0 + 64 * k];
+          cc[k] = ld_s<NT>(col + p0 + 64 * k);
+          cf[k] = ld_s<NT>(coef_row + p0 + 64 * k);
         }
       }
 #pragma unroll
@@ -1167,19 +1169,21 @@ hipError_t launch_residual(const Layout* Lp, const double* coef_row, const doubl
   const Layout& L = *Lp;
 #define RES_ARGS(DX, SC) \
   L.n, L.sptr, L.col, coef_row, L.diag, b, x, DX, SC, r, partials, L.lane_of_row_d, r32, L.row_slot
-  if (dx) {
-    GABP_DISPATCH_WIDTH(L.max_width,
-                        (k_residual<4, true><<<nred, kRedBlock, 0, s>>>(RES_ARGS(dx, scale))),
-                        (k_residual<8, true><<<nred, kRedBlock, 0, s>>>(RES_ARGS(dx, scale))),
-                        (k_residual<16, true><<<nred, kRedBlock, 0, s>>>(RES_ARGS(dx, scale))),
-                        (k_residual<0, true><<<nred, kRedBlock, 0, s>>>(RES_ARGS(dx, scale))));
-  } else {
-    GABP_DISPATCH_WIDTH(L.max_width,
-                        (k_residual<4, false><<<nred, kRedBlock, 0, s>>>(RES_ARGS(nullptr, nullptr))),
-                        (k_residual<8, false><<<nred, kRedBlock, 0, s>>>(RES_ARGS(nullptr, nullptr))),
-                        (k_residual<16, false><<<nred, kRedBlock, 0, s>>>(RES_ARGS(nullptr, nullptr))),
-                        (k_residual<0, false><<<nred, kRedBlock, 0, s>>>(RES_ARGS(nullptr, nullptr))));
-  }
+  GABP_DISPATCH_NT(L.res_hints, {
+    if (dx) {
+      GABP_DISPATCH_WIDTH(L.max_width,
+                          (k_residual<4, true, NTB><<<nred, kRedBlock, 0, s>>>(RES_ARGS(dx, scale))),
+                          (k_residual<8, true, NTB><<<nred, kRedBlock, 0, s>>>(RES_ARGS(dx, scale))),
+                          (k_residual<16, true, NTB><<<nred, kRedBlock, 0, s>>>(RES_ARGS(dx, scale))),
+                          (k_residual<0, true, NTB><<<nred, kRedBlock, 0, s>>>(RES_ARGS(dx, scale))));
+    } else {
+      GABP_DISPATCH_WIDTH(L.max_width,
+                          (k_residual<4, false, NTB><<<nred, kRedBlock, 0, s>>>(RES_ARGS(nullptr, nullptr))),
+                          (k_residual<8, false, NTB><<<nred, kRedBlock, 0, s>>>(RES_ARGS(nullptr, nullptr))),
+                          (k_residual<16, false, NTB><<<nred, kRedBlock, 0, s>>>(RES_ARGS(nullptr, nullptr))),
+                          (k_residual<0, false, NTB><<<nred, kRedBlock, 0, s>>>(RES_ARGS(nullptr, nullptr))));
+    }
+  })
 #undef RES_ARGS
   if (norms) k_finalize_norms<<<1, kFinBlock, 0, s>>>(nred, partials, red);
   return hipGetLastError();

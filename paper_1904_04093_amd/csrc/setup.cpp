@@ -346,6 +346,8 @@ int gabp_setup(gabp_ctx** out, int32_t n, int64_t nnz, const int32_t* rowptr,
   constexpr double kLLC = 256.0 * 1024 * 1024;
   L.stream_hints = 44.0 * epad + 16.0 * n > kLLC;
   L.stream_hints32 = 16.0 * epad + 4.0 * n > 2.0 * kLLC;
+  // residual: 12 B per slot (column, coefficient) + 32 B per row (row slot, b, diag, x, r)
+  L.res_hints = 12.0 * epad + 32.0 * n > kLLC;
   if (o.stream_hints >= 0) {
     L.stream_hints = L.stream_hints32 = o.stream_hints == 1;
     L.store_hints = L.store_hints32 = o.stream_hints == 2;
