@@ -76,6 +76,9 @@ struct LineLayout {
   double* xcol = nullptr;                  // [n] read-off in the column layout
   float* xcol32 = nullptr;
   double* partials = nullptr;              // [2 * (nx + ny)] per-line max|dLambda|, max|Lambda|
+  // mean-only line sweeps with non-temporal loads: FP64 / FP32 sweep bytes (40 / 20 B per
+  // node and orientation) above the last-level cache
+  bool nt64 = false, nt32 = false;
 };
 
 // Arguments of one orientation's line update.
@@ -106,6 +109,7 @@ struct LineMeanArgs {
   const T* b;
   const T* m_in;
   T* m_out;
+  bool nt = false;   // non-temporal loads of the streamed arrays (the sweep exceeds the LLC)
 };
 
 template <typename T>

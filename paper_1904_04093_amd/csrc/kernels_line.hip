@@ -34,11 +34,12 @@ __device__ inline int bidx(int k) { return static_cast<int>(threadIdx.x) * (NPL 
 __device__ inline bool in_stripe(int j, int len) {
   return (j + 1) * kLT <= len || (j * kLT < len && static_cast<int>(threadIdx.x) < len - j * kLT);
 }
-template <typename T>
+template <typename T, bool NT = false>
 __device__ inline T ld_stripe(const T* __restrict__ p, int j, int len) {
   const unsigned t = threadIdx.x + j * kLT;
-  if ((j + 1) * kLT <= len) return p[t];
-  return p[min(t, static_cast<unsigned>(len) - 1u)];
+  const unsigned i = (j + 1) * kLT <= len ? t : min(t, static_cast<unsigned>(len) - 1u);
+  if constexpr (NT) return __builtin_nontemporal_load(p + i);
+  else return p[i];
 }
 
 // ---- 3x3 projective maps with the sparsity [[a b 0] [c d 0] [e f g]] -------------------
@@ -443,7 +444,7 @@ __global__ __launch_bounds__(kLT, 2) void k_line_joint(LineArgs a0, LineArgs a1,
 // g_t = c_t - alpha_t g_{t-1}, q_t = c_t - beta_t q_{t+1}, m_out = -alpha_t g_{t-1} -
 // beta_t q_{t+1}, c_t = b_t + m_in(t).
 // ---------------------------------------------------------------------------------------
-template <typename T, int NPL>
+template <typename T, int NPL, bool NT>
 __global__ __launch_bounds__(kLT, 3) void k_line_mean(LineMeanArgs<T> a0, LineMeanArgs<T> a1,
                                                    int nblk0) {
   __shared__ T sh[kLT * (NPL + 1)];
@@ -460,9 +461,10 @@ __global__ __launch_bounds__(kLT, 3) void k_line_mean(LineMeanArgs<T> a0, LineMe
     T ga[NPL], gb[NPL], gc[NPL];
 #pragma unroll
     for (int j = 0; j < NPL; ++j) {
-      ga[j] = ld_stripe(A.alpha + base, j, len);
-      gb[j] = ld_stripe(A.beta + base, j, len);
-      gc[j] = ld_stripe(A.b + base, j, len) + (A.m_in ? ld_stripe(A.m_in + base, j, len) : T(0));
+      ga[j] = ld_stripe<T, NT>(A.alpha + base, j, len);
+      gb[j] = ld_stripe<T, NT>(A.beta + base, j, len);
+      gc[j] = ld_stripe<T, NT>(A.b + base, j, len) +
+              (A.m_in ? ld_stripe<T, NT>(A.m_in + base, j, len) : T(0));
     }
     stage_regs<NPL>(sh, ga, len);
     stage_take<NPL>(sh, t0, len, T(0), al);
@@ -596,13 +598,25 @@ hipError_t joint_dispatch(const LineArgs& a0, const LineArgs& a1, int nblk0, int
 template <typename T>
 hipError_t mean_dispatch(const LineMeanArgs<T>& a0, const LineMeanArgs<T>& a1, int nblk0,
                          int nblk, int npl, hipStream_t s) {
-  switch (npl) {
-    case 1: k_line_mean<T, 1><<<nblk, kLT, 0, s>>>(a0, a1, nblk0); break;
-    case 2: k_line_mean<T, 2><<<nblk, kLT, 0, s>>>(a0, a1, nblk0); break;
-    case 4: k_line_mean<T, 4><<<nblk, kLT, 0, s>>>(a0, a1, nblk0); break;
-    case 8: k_line_mean<T, 8><<<nblk, kLT, 0, s>>>(a0, a1, nblk0); break;
-    case 16: k_line_mean<T, 16><<<nblk, kLT, 0, s>>>(a0, a1, nblk0); break;
-    default: return hipErrorInvalidValue;
+  // the hint is a property of the context (both orientations of one sweep)
+  if (a0.nt) {
+    switch (npl) {
+      case 1: k_line_mean<T, 1, true><<<nblk, kLT, 0, s>>>(a0, a1, nblk0); break;
+      case 2: k_line_mean<T, 2, true><<<nblk, kLT, 0, s>>>(a0, a1, nblk0); break;
+      case 4: k_line_mean<T, 4, true><<<nblk, kLT, 0, s>>>(a0, a1, nblk0); break;
+      case 8: k_line_mean<T, 8, true><<<nblk, kLT, 0, s>>>(a0, a1, nblk0); break;
+      case 16: k_line_mean<T, 16, true><<<nblk, kLT, 0, s>>>(a0, a1, nblk0); break;
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    switch (npl) {
+      case 1: k_line_mean<T, 1, false><<<nblk, kLT, 0, s>>>(a0, a1, nblk0); break;
+      case 2: k_line_mean<T, 2, false><<<nblk, kLT, 0, s>>>(a0, a1, nblk0); break;
+      case 4: k_line_mean<T, 4, false><<<nblk, kLT, 0, s>>>(a0, a1, nblk0); break;
+      case 8: k_line_mean<T, 8, false><<<nblk, kLT, 0, s>>>(a0, a1, nblk0); break;
+      case 16: k_line_mean<T, 16, false><<<nblk, kLT, 0, s>>>(a0, a1, nblk0); break;
+      default: return hipErrorInvalidValue;
+    }
   }
   return hipGetLastError();
 }

@@ -154,6 +154,11 @@ int line_setup(gabp_ctx* c, int nx, int ny, const int32_t* rowptr, const int32_t
   G->ny = ny;
   G->n = n;
   G->alt = c->opt.schedule == GABP_SCHED_LINES_ALT;
+  {
+    constexpr double kLLC = 256.0 * 1024 * 1024;   // last-level cache
+    G->nt64 = 40.0 * 2 * static_cast<double>(n) > kLLC;
+    G->nt32 = 20.0 * 2 * static_cast<double>(n) > kLLC;
+  }
   // side 0: rows, index y*nx + x, predecessor W, successor E
   // side 1: columns, index x*ny + y, predecessor S, successor N
   // A^T along a line: (A^T)_{t,t-1} = A_{t-1,t} (successor coupling of t-1) and
@@ -330,8 +335,9 @@ int line_sweep64(gabp_ctx* c, int T, const double* b, double* x, hipStream_t s) 
     return joint_update(G, a, x, s, first);
   }
   LineMeanArgs<double> m[2] = {
-      {R.nlines, R.len, R.alpha[T], R.beta[T], b, first ? nullptr : C.m_x, R.m_own},
-      {C.nlines, C.len, C.alpha[T], C.beta[T], G.bcol, rows_zero ? nullptr : R.m_x, C.m_own}};
+      {R.nlines, R.len, R.alpha[T], R.beta[T], b, first ? nullptr : C.m_x, R.m_own, G.nt64},
+      {C.nlines, C.len, C.alpha[T], C.beta[T], G.bcol, rows_zero ? nullptr : R.m_x, C.m_own,
+       G.nt64}};
   if (!G.alt) {
     GABP_HIP(launch_line_mean64(m, 2, s));
     if (x && (st = readoff_col64(G, G.invS[T], x, s, rows_zero)) != GABP_OK) return st;
@@ -363,9 +369,10 @@ int line_sweep32(gabp_ctx* c, int T, const float* b, float* x, hipStream_t s) {
     return GABP_OK;
   };
   LineMeanArgs<float> m[2] = {
-      {R.nlines, R.len, R.alpha32[T], R.beta32[T], b, first ? nullptr : C.m32_x, R.m32_own},
+      {R.nlines, R.len, R.alpha32[T], R.beta32[T], b, first ? nullptr : C.m32_x, R.m32_own,
+       G.nt32},
       {C.nlines, C.len, C.alpha32[T], C.beta32[T], G.bcol32, rows_zero ? nullptr : R.m32_x,
-       C.m32_own}};
+       C.m32_own, G.nt32}};
   if (!G.alt) {
     GABP_HIP(launch_line_mean32(m, 2, s));
     if (x && (st = readoff()) != GABP_OK) return st;
