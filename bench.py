@@ -291,6 +291,9 @@ def main():
                         "(a launch does sweeps_per_launch sweeps)",
             "residual_us": t_res * 1e6,
             "residual_GBs": (12 * lay["slots"] + 32 * a.n) / t_res / 1e9,
+            "residual_note": "one residual check: k_residual and the single-block norm "
+                             "reduction k_finalize_norms, replayed from a graph; GB/s are "
+                             "k_residual's bytes over both",
             "copy_probe_GBs": copy_gbs,
             "lambda_phase_sweeps_f32": lsw, "lambda_phase_sweeps_f64": lsw64,
         },
