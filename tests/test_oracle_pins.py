@@ -532,3 +532,81 @@ def test_pins_detect_planted_mistakes(kind, monkeypatch):
         x2, _, _ = G.run(_graph(lap), bb, 2)
     failures += not (abs(x2[8 * n + 8] - 1 / 3) < 1e-15 and abs(x2[8 * n + 9] - 1 / 12) < 1e-15)
     assert failures >= 1, f"planted mistake {kind} passed every pin"
+
+
+# The coloured and the mean-only sweeps get the same treatment: each plausible mistake,
+# planted in a copy on the CPU, breaks one of the pins above that do not go through the
+# flood sweep (red-black first-sweep closed form, coloured and mean-only fixed points,
+# the interior read-offs 3b/8 and (3b + sum)/8 of Sec. 4.2's precomputed form).
+
+def _mutated_coloured(kind):
+    def sweep_coloured(g, b, Lt, m, colour, lambda_fixed=None):
+        colour = np.asarray(colour)
+        x = np.zeros(g.n)
+        Lt, m = Lt.copy(), m.copy()
+        S0, M0 = G.node_totals(g, b, Lt, m)
+        for c in range(int(colour.max()) + 1):
+            if kind == "stale_totals":          # Jacobi: totals from the start of the sweep
+                S, M = S0, M0
+            else:
+                S, M = G.node_totals(g, b, Lt, m)
+            if lambda_fixed is not None:
+                S = lambda_fixed[1]
+            sel = colour == c
+            x[sel] = M[sel] / S[sel]
+            upd = (colour[g.dst] if kind == "receiver_class" else colour[g.src]) == c
+            back_m = G._gather(m, g.rev)
+            if kind == "no_cavity":
+                back_m = 0 * back_m
+            if lambda_fixed is None:
+                with np.errstate(all="ignore"):
+                    L_new = -g.a_ij / (S[g.src] - G._gather(Lt, g.rev) * g.a_ij)
+                Lt = np.where(upd, L_new, Lt)
+            else:
+                L_new = lambda_fixed[0]
+            m = np.where(upd, L_new * (M[g.src] - back_m), m)
+        return x, Lt, m
+    return sweep_coloured
+
+
+@pytest.mark.parametrize("kind", ["stale_totals", "receiver_class", "no_cavity"])
+def test_coloured_pins_detect_planted_mistakes(kind, monkeypatch):
+    monkeypatch.setattr(G, "sweep_coloured", _mutated_coloured(kind))
+    checks = [test_redblack_first_sweep_closed_form,
+              lambda: test_redblack_fixed_point_is_dense_solution(False),
+              lambda: test_redblack_fixed_point_is_dense_solution(True)]
+    failures = 0
+    for check in checks:
+        try:
+            with np.errstate(all="ignore"):
+                check()
+        except AssertionError:
+            failures += 1
+    assert failures >= 1, f"planted mistake {kind} passed every coloured-sweep pin"
+
+
+def _mutated_msweep(kind):
+    def msweep(g, b, Lt_star, S_star, m):
+        M = b + np.bincount(g.dst, weights=m, minlength=g.n)
+        if kind == "receiver_total":            # receiver's total instead of the sender's
+            back = G._gather(m, g.rev)
+            return M / S_star, Lt_star * (M[g.dst] - back)
+        if kind == "no_cavity":
+            return M / S_star, Lt_star * M[g.src]
+        if kind == "stale_readoff":             # read-off before the incoming sum
+            return b / S_star, Lt_star * (M[g.src] - G._gather(m, g.rev))
+        raise AssertionError(kind)
+    return msweep
+
+
+@pytest.mark.parametrize("kind", ["receiver_total", "no_cavity", "stale_readoff"])
+def test_mean_only_pins_detect_planted_mistakes(kind, monkeypatch):
+    monkeypatch.setattr(G, "msweep", _mutated_msweep(kind))
+    failures = 0
+    for check in (test_interior_lambda_closed_form, test_precomp_reaches_dense_solution):
+        try:
+            with np.errstate(all="ignore"):
+                check()
+        except AssertionError:
+            failures += 1
+    assert failures >= 1, f"planted mistake {kind} passed every mean-only pin"
