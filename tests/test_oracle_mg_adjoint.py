@@ -136,3 +136,75 @@ def test_transposed_graph_swaps_coefficients():
     b = r.uniform(-1, 1, 20)
     x, info, _, _ = G.solve(gt, b, 1e-14, 5000)
     assert np.allclose(x, np.linalg.solve(g.dense().T, b), rtol=1e-11)
+
+
+# The multigrid pins catch plausible mistakes: each one below, planted in a copy on the CPU
+# (the oracle itself untouched), breaks at least one of the transfer-operator identities or
+# the textbook V-cycle checks above.
+
+def _restrict_no_corners(r, n_f):
+    n_c = (n_f - 1) // 2
+    R = np.asarray(r, dtype=np.float64).reshape(n_f, n_f)
+    c = 4.0 * R[1::2, 1::2]
+    c += 2.0 * (R[0:-1:2, 1::2] + R[2::2, 1::2] + R[1::2, 0:-1:2] + R[1::2, 2::2])
+    return (c / 16.0).reshape(-1)
+
+
+def _prolong_constant_in_y(e_c, n_c):
+    n_f = 2 * n_c + 1
+    E = np.zeros((n_c + 2, n_c + 2))
+    E[1:-1, 1:-1] = np.asarray(e_c, dtype=np.float64).reshape(n_c, n_c)
+    F = np.zeros((n_f + 2, n_f + 2))
+    F[::2, ::2] = E
+    F[::2, 1::2] = 0.5 * (E[:, :-1] + E[:, 1:])
+    F[1::2, :] = F[0:-1:2, :]                   # no average between coarse rows
+    return F[1:-1, 1:-1].reshape(-1)
+
+
+def _rbgs_jacobi(g, b, x, n, sweeps):
+    x = np.array(x, dtype=np.float64)
+    off = g.rows != g.cols
+    for _ in range(sweeps):
+        s = np.bincount(g.rows[off], weights=g.vals[off] * x[g.cols[off]], minlength=g.n)
+        x = (b - s) / g.diag                    # both colours from the old iterate
+    return x
+
+
+def _vcycle_mutant(kind):
+    def vcycle(self, b, x, l=0):
+        g = self.graphs[l]
+        if l == len(self.graphs) - 1:
+            return self.coarse @ b
+        x = self._smooth(l, b, x, self.nu1)
+        r = b if kind == "restrict_b" else g.residual(b, x)
+        ec = self.vcycle(MG.restrict_fw(r, self.sides[l]),
+                         np.zeros(self.graphs[l + 1].n), l + 1)
+        e = MG.prolong_bilinear(ec, self.sides[l + 1])
+        x = x - e if kind == "sign" else x + e
+        return self._smooth(l, b, x, self.nu2)
+    return vcycle
+
+
+@pytest.mark.parametrize("kind", ["restrict_no_corners", "prolong_constant_in_y",
+                                  "rbgs_jacobi", "sign", "restrict_b"])
+def test_mg_pins_detect_planted_mistakes(kind, monkeypatch):
+    if kind == "restrict_no_corners":
+        monkeypatch.setattr(MG, "restrict_fw", _restrict_no_corners)
+    elif kind == "prolong_constant_in_y":
+        monkeypatch.setattr(MG, "prolong_bilinear", _prolong_constant_in_y)
+    elif kind == "rbgs_jacobi":
+        monkeypatch.setattr(MG, "rbgs", _rbgs_jacobi)
+    else:
+        monkeypatch.setattr(MG.Hierarchy, "vcycle", _vcycle_mutant(kind))
+    failures = 0
+    for check in (test_full_weighting_is_quarter_transpose_of_bilinear,
+                  test_bilinear_reproduces_bilinear_functions,
+                  test_full_weighting_of_linear_function,
+                  test_vcycle_rbgs_poisson_textbook_contraction,
+                  test_vcycle_exact_coarse_solve_two_levels):
+        try:
+            with np.errstate(all="ignore"):
+                check()
+        except AssertionError:
+            failures += 1
+    assert failures >= 1, f"planted mistake {kind} passed every multigrid pin"
