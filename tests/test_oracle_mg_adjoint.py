@@ -208,3 +208,62 @@ def test_mg_pins_detect_planted_mistakes(kind, monkeypatch):
         except AssertionError:
             failures += 1
     assert failures >= 1, f"planted mistake {kind} passed every multigrid pin"
+
+
+def test_entry_gradient_matches_central_differences():
+    """dL/dA_e = -lambda_i x_j for the stored entry e = (i, j), checked entry by entry
+    against central differences of L(A^-1 b) on a nonsymmetric upwind matrix (A_ij != A_ji,
+    so a transposed gradient cannot pass, unlike the theta chain, whose weights are equal
+    for A_ij and A_ji)."""
+    a, _ = W.small_upwind(6)
+    A = W.csr_to_dense(a)
+    r = W.rng(124, 0)
+    b = r.uniform(-1, 1, a.n)                    # O(1) x and gradient: FD floor far below
+    xt = 0.5 * np.linalg.solve(A, b) + r.uniform(-0.1, 0.1, a.n)
+    rows, cols = a.row_of_nnz(), a.col
+    ref = AD.dense_reference(A, b, xt, rows, cols)
+    loss = lambda M: 0.5 * float(((x := np.linalg.solve(M, b)) - xt) @ (x - xt))
+    eps = 1e-6
+    es = W.rng(124, 1).choice(a.nnz, 24, replace=False)
+    fd = []
+    for e in es:
+        Ap, Am = A.copy(), A.copy()
+        Ap[rows[e], cols[e]] += eps
+        Am[rows[e], cols[e]] -= eps
+        fd.append((loss(Ap) - loss(Am)) / (2 * eps))
+    fd = np.array(fd)
+    assert np.linalg.norm(fd - ref["G"][es]) <= 1e-6 * np.linalg.norm(fd)
+
+
+# The adjoint pins catch plausible mistakes as well (planted in copies, on the CPU): a
+# transposed or sign-flipped entry gradient, dropped Jacobian weights, and an adjoint solve
+# with A in place of A^T each break a finite-difference or dense-LU check above.
+
+def _adjoint_mutant(kind, monkeypatch):
+    if kind == "gradient_transposed":
+        monkeypatch.setattr(AD, "nnz_gradient",
+                            lambda rows, cols, lam, x: -np.asarray(lam)[cols] * np.asarray(x)[rows])
+    elif kind == "gradient_sign":
+        monkeypatch.setattr(AD, "nnz_gradient",
+                            lambda rows, cols, lam, x: np.asarray(lam)[rows] * np.asarray(x)[cols])
+    elif kind == "unweighted_chain":
+        real = AD.reduce_to_params
+        monkeypatch.setattr(AD, "reduce_to_params",
+                            lambda G_, jptr, jnnz, jw: real(G_, jptr, jnnz, np.ones(len(jw))))
+    elif kind == "forward_operator":
+        monkeypatch.setattr(G.Graph, "transposed", lambda self: self)
+
+
+@pytest.mark.parametrize("kind", ["gradient_transposed", "gradient_sign", "unweighted_chain",
+                                  "forward_operator"])
+def test_adjoint_pins_detect_planted_mistakes(kind, monkeypatch):
+    _adjoint_mutant(kind, monkeypatch)
+    failures = 0
+    for check in (test_adjoint_gradient_matches_central_differences,
+                  test_entry_gradient_matches_central_differences,
+                  test_adjoint_dot_product_identity_and_gabp_adjoint):
+        try:
+            check()
+        except AssertionError:
+            failures += 1
+    assert failures >= 1, f"planted mistake {kind} passed every adjoint pin"
