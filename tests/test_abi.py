@@ -99,3 +99,66 @@ def test_binding_refuses_host_tensors():
     torch = pytest.importorskip("torch")
     with pytest.raises(TypeError):
         B._dev(torch.zeros(4, dtype=torch.float64), 4)
+
+
+def _setup_status(a, opts, colour=None):
+    """gabp_setup on host CSR arrays with the given options; the rejections below all
+    happen in host code, before the library makes any HIP call."""
+    import ctypes
+    lib = B.load()
+    h = ctypes.c_void_p()
+    rp = np.ascontiguousarray(a.rowptr, dtype=np.int32)
+    cl = np.ascontiguousarray(a.col, dtype=np.int32)
+    vl = np.ascontiguousarray(a.val, dtype=np.float64)
+    ck = None if colour is None else np.ascontiguousarray(colour, dtype=np.uint8)
+    st = lib.gabp_setup(ctypes.byref(h), a.n, a.nnz, rp.ctypes.data, cl.ctypes.data,
+                        vl.ctypes.data, None, None if ck is None else ck.ctypes.data,
+                        ctypes.byref(opts), None)
+    assert not h.value, "a rejected set-up leaves no context"
+    return st, lib.gabp_last_error().decode()
+
+
+def _opts(**kw):
+    o = B.Options()
+    B.load().gabp_default_options(o)
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+@pytest.mark.parametrize("field,value", [
+    ("check_every", 0), ("mode", 3), ("precision", 2), ("schedule", 9), ("block", 96),
+    ("tiles", 2), ("stream_hints", 3), ("stream_hints", -2), ("ir_inner_tol", 0.0),
+    ("ir_max_inner", 0), ("tol_lambda", -1.0), ("progress_s", float("nan"))])
+def test_setup_rejects_invalid_options(field, value):
+    a, _ = W.small_upwind(8)
+    st, msg = _setup_status(a, _opts(**{field: value}))
+    assert st == B.EINVAL and "invalid options" in msg
+
+
+def test_setup_rejects_inconsistent_layout_requests():
+    a, _ = W.small_upwind(8)
+    # non-temporal stores only: a setting of the tiled kernels
+    st, msg = _setup_status(a, _opts(stream_hints=2))
+    assert st == B.EINVAL and "tiled" in msg
+    # tiles: flood schedule, grid sides that multiply to n
+    st, msg = _setup_status(a, _opts(tiles=1, grid_nx=8, grid_ny=8, schedule=B.SCHEDULES["redblack"]),
+                            colour=(np.arange(64) + np.arange(64) // 8) % 2)
+    assert st == B.EINVAL and "flood" in msg
+    st, msg = _setup_status(a, _opts(tiles=1, grid_nx=8, grid_ny=7))
+    assert st == B.EINVAL and "grid_nx" in msg
+    st, msg = _setup_status(a, _opts(tiles=1))
+    assert st == B.EINVAL and "grid_nx" in msg
+    # rows wider than a tile's register budget (9-point stencil: 8 neighbours)
+    g9 = W.random_grid_9pt(9, 9, W.rng(201, 0))
+    st, msg = _setup_status(g9, _opts(tiles=1, grid_nx=9, grid_ny=9))
+    assert st == B.ENOTSUPP and "neighbours" in msg
+    # red-black without colours; per-sweep precision messages with a line schedule
+    st, msg = _setup_status(a, _opts(schedule=B.SCHEDULES["redblack"]))
+    assert st == B.EINVAL and "colours" in msg
+    st, msg = _setup_status(a, _opts(mode=B.MODES["seq"], schedule=B.SCHEDULES["lines"],
+                                     grid_nx=8, grid_ny=8))
+    assert st == B.ENOTSUPP and "point schedules" in msg
+    # colours at or above the supported number of classes
+    st, msg = _setup_status(a, _opts(schedule=B.SCHEDULES["redblack"]), colour=np.full(64, 200))
+    assert st == B.EINVAL and "colour" in msg
