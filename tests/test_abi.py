@@ -162,3 +162,61 @@ def test_setup_rejects_inconsistent_layout_requests():
     # colours at or above the supported number of classes
     st, msg = _setup_status(a, _opts(schedule=B.SCHEDULES["redblack"]), colour=np.full(64, 200))
     assert st == B.EINVAL and "colour" in msg
+
+
+def _batched_status(a, sys_off, nrhs=1, opts=None):
+    import ctypes
+    lib = B.load()
+    h = ctypes.c_void_p()
+    so = np.ascontiguousarray(sys_off, dtype=np.int32)
+    rp = np.ascontiguousarray(a.rowptr, dtype=np.int32)
+    cl = np.ascontiguousarray(a.col, dtype=np.int32)
+    vl = np.ascontiguousarray(a.val, dtype=np.float64)
+    st = lib.gabp_setup_batched(ctypes.byref(h), len(so) - 1, so.ctypes.data, a.n, a.nnz,
+                                rp.ctypes.data, cl.ctypes.data, vl.ctypes.data, nrhs,
+                                ctypes.byref(opts or _opts()), None)
+    assert not h.value
+    return st, lib.gabp_last_error().decode()
+
+
+def test_batched_setup_rejects_bad_batches():
+    """Host-side rejections of gabp_setup_batched (before any HIP call)."""
+    a, _ = W.small_upwind(8)
+    n = a.n
+    assert _batched_status(a, [0, n], nrhs=3)[0] == B.EINVAL
+    st, msg = _batched_status(a, [0, n], opts=_opts(schedule=B.SCHEDULES["lines"]))
+    assert st == B.ENOTSUPP and "point schedules" in msg
+    st, msg = _batched_status(a, [0, n], opts=_opts(mode=B.MODES["seq"]))
+    assert st == B.ENOTSUPP
+    st, msg = _batched_status(a, [0, n - 1])
+    assert st == B.EINVAL and "0 to n" in msg
+    st, msg = _batched_status(a, [0, 32, 32, n])
+    assert st == B.EINVAL and "empty" in msg
+    # the 8 x 8 grid split after row 30: row 30 couples to row 31 in the other system
+    st, msg = _batched_status(a, [0, 31, n])
+    assert st == B.EINVAL and "couples two systems" in msg
+    # a bad CSR is caught before the system scan reads it
+    col = a.col.copy()
+    col[4] = n + 7
+    bad = W.CSR(a.n, a.rowptr, col, a.val)
+    assert _batched_status(bad, [0, n])[0] == B.EINVAL
+
+
+def test_multigrid_setup_rejects_bad_hierarchies():
+    """Host-side rejections of mg_setup that need no level context."""
+    import ctypes
+    lib = B.load()
+    h = ctypes.c_void_p()
+    ctxs = (ctypes.c_void_p * 3)()
+    sides = np.array([15, 7, 3], dtype=np.int32)
+    def status(levels, smoother=0, nu1=2, nu2=2):
+        st = lib.mg_setup(ctypes.byref(h), levels, ctxs, sides.ctypes.data, smoother, nu1,
+                          nu2, None)
+        assert not h.value
+        return st, lib.gabp_last_error().decode()
+    st, msg = status(1)
+    assert st == B.EINVAL and "two levels" in msg
+    assert status(3, smoother=2)[0] == B.EINVAL
+    assert status(3, nu1=-1)[0] == B.EINVAL
+    st, msg = status(3)
+    assert st == B.EINVAL and "NULL level context" in msg
