@@ -273,11 +273,15 @@ int gabp_layout_info(const gabp_ctx* ctx, int32_t* n, int64_t* nnz, int64_t* slo
  * costs at most 2% of the sweeps between checks. A tiled context (opt.tiles) is timed with
  * its two-sweep kernels (one workgroup per tile: hints only). Results are cached per
  * (architecture, sizes, mode, schedule, layout) in memory and, when the environment
- * variable GABP_AUTOTUNE_CACHE names a file, in that JSON-lines file. Runs sweeps on a zero right-hand side, so the context's
- * message state is reset; computes the precomputed Lt first when the mode needs it.
- * Outputs (host, may be NULL): the chosen check interval, hint setting (0/1, and 2 for a
- * tiled context: the values of opt.stream_hints) and workgroup size. Because it changes check_every, later solves may stop at a different (rounded-up)
- * sweep count than untuned ones. Line schedules have no hint or workgroup variants: only
+ * variable GABP_AUTOTUNE_CACHE names a file, in that JSON-lines file. Runs sweeps on a
+ * zero right-hand side, so the context's message state is reset; computes the
+ * precomputed Lt first when the mode needs it. The measured hint setting and workgroup
+ * size replace those given at set-up (opt.stream_hints, opt.block). Outputs (host, may be
+ * NULL): the chosen check interval, hint setting (0/1, and 2 for a tiled context: the
+ * values of opt.stream_hints) and workgroup size. Because it changes check_every, later
+ * solves may stop at a different (rounded-up) sweep count than untuned ones. Sweeps give
+ * the same bits under every hint setting and workgroup size (hints change only how the
+ * caches treat the streams). Line schedules have no hint or workgroup variants: only
  * the check interval is tuned (from one line sweep), hints_out is 0 and block_out 256;
  * batches keep 256-thread workgroups. */
 int gabp_autotune(gabp_ctx* ctx, int32_t* check_every_out, int32_t* hints_out,
