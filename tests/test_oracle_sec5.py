@@ -80,6 +80,32 @@ def test_sec5_unreproduced_counts_converge(key):
     assert ours is not None and printed / 2 <= ours <= 2 * printed, (key, printed, ours)
 
 
+# printed counts missed by one cycle: at the printed count the residual is just above the
+# threshold (2.27e-4, 2.34e-4 and 3.25e-4 for 2e-4)
+NEAR_MISS = {("boundary_layers", "eps=0.02", "line_gabp"),
+             ("stretched", "p=20,eta=0.5,eps=8e-8", "redblack_gabp"),
+             ("stretched", "p=20,eta=0.5,eps=8e-8", "line_gabp")}
+
+
+@pytest.mark.parametrize("key", sorted(NEAR_MISS))
+def test_sec5_near_miss_residual_at_printed_count(key):
+    """Tighter than the factor-two bound above: after the printed number of V-cycles the
+    oracle's residual is within a factor two of the printed stopping threshold, and one
+    cycle later below it (the printed count is missed only at the threshold)."""
+    prob, _, smoother = key
+    kw, nu, printed = PRINTED[key]
+    levels, b = W.sec5_hierarchy(prob, 6, 1, **kw)
+    h = MG.Hierarchy(levels, nu1=int(nu[0]), nu2=int(nu[1]), **SMOOTHER[smoother])
+    g = h.graphs[0]
+    x = np.zeros(g.n)
+    res = []
+    for _ in range(printed + 1):
+        x = h.vcycle(b, x)
+        res.append(float(np.abs(g.residual(b, x)).max()))
+    assert 2e-4 < res[printed - 1] <= 4e-4, (key, res[printed - 1])
+    assert res[printed] <= 2e-4, (key, res[printed])
+
+
 @pytest.mark.xfail(strict=True, reason="the paper prints 3 cycles; red-black GaBP (5,0) "
                    "diverges on this discretisation of the eps = 0.01 boundary layer")
 @pytest.mark.parametrize("key", sorted(DIVERGES_HERE))
