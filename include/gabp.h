@@ -222,7 +222,10 @@ int gabp_residual_noalloc(gabp_ctx* ctx, const double* b, const double* x, doubl
  * DEVICE n doubles; G: DEVICE nnz doubles (may be NULL). If jptr != NULL the entry
  * gradient is also reduced onto nparam parameters through a parameter-major sparse
  * Jacobian: dtheta_p = sum_{k in jptr[p]..jptr[p+1]} jw[k] * G[jnnz[k]] (jptr, jnnz, jw,
- * dtheta: DEVICE). Each parameter is reduced by one thread in index order (deterministic). */
+ * dtheta: DEVICE). Each parameter is reduced by one thread in index order (deterministic).
+ * The caller guarantees jptr[0] = 0, jptr non-decreasing, and 0 <= jnnz[k] < nnz: the
+ * arrays are read on the device without a check (indices outside that range read outside
+ * the context's entry arrays). */
 int gabp_adjoint_scatter(gabp_ctx* ctx, const double* lambda, const double* x, double* G,
                          int32_t nparam, const int32_t* jptr, const int32_t* jnnz,
                          const double* jw, double* dtheta, hipStream_t stream);

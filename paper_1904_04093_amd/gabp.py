@@ -157,6 +157,21 @@ def _dev(t, n, dtype_name="float64"):
     return _P(t.data_ptr())
 
 
+def _check_jacobian(jptr, jnnz, jw, nnz):
+    """The parameter Jacobian's index arrays must stay inside the matrix, since the library
+    reads them on the device unchecked: jptr runs from 0 to len(jnnz) without decreasing,
+    jw has one weight per jnnz entry and every jnnz lies in [0, nnz). Works on host or
+    device tensors (a device check reads four scalars back)."""
+    m = int(jnnz.numel())
+    if int(jw.numel()) != m or int(jptr.numel()) < 1:
+        raise ValueError("the parameter Jacobian needs len(jw) == len(jnnz) and a jptr")
+    if int(jptr[0]) != 0 or int(jptr[-1]) != m or \
+            (jptr.numel() > 1 and bool((jptr[1:] < jptr[:-1]).any())):
+        raise ValueError("jptr must run from 0 to len(jnnz) without decreasing")
+    if m and (int(jnnz.min()) < 0 or int(jnnz.max()) >= nnz):
+        raise ValueError("jnnz must index stored entries: 0 <= jnnz < nnz")
+
+
 def copy_probe(src, dst):
     """dst <- src with the library's plain streaming copy kernel (CUDA tensors, same size)."""
     nb = src.numel() * src.element_size()
@@ -287,6 +302,7 @@ class Solver:
         args = [None, 0, None, None, None, None]
         if jac is not None:
             jptr, jnnz, jw = jac
+            _check_jacobian(jptr, jnnz, jw, self.nnz)
             npar = int(jptr.numel()) - 1
             dtheta = torch.empty(npar, dtype=torch.float64, device="cuda")
             args = [_dev(jptr, npar + 1, "int32"), _dev(jnnz, jnnz.numel(), "int32"),

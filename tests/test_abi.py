@@ -220,3 +220,28 @@ def test_multigrid_setup_rejects_bad_hierarchies():
     assert status(3, nu1=-1)[0] == B.EINVAL
     st, msg = status(3)
     assert st == B.EINVAL and "NULL level context" in msg
+
+
+def test_parameter_jacobian_is_checked_before_the_device_reads_it():
+    """The binding rejects Jacobian index arrays that would make the parameter reduction
+    read outside the stored entries (the library reads them on the device unchecked)."""
+    torch = pytest.importorskip("torch")
+    n = 8
+    a, jptr, jnnz, jw = W.theta_jacobian(n, W.theta_problem(n, 0))
+    jp, jn, w = torch.as_tensor(jptr), torch.as_tensor(jnnz), torch.as_tensor(jw)
+    B._check_jacobian(jp, jn, w, a.nnz)              # the generator's Jacobian passes
+    bad = jn.clone()
+    bad[3] = a.nnz
+    with pytest.raises(ValueError, match="jnnz"):
+        B._check_jacobian(jp, bad, w, a.nnz)
+    bad[3] = -1
+    with pytest.raises(ValueError, match="jnnz"):
+        B._check_jacobian(jp, bad, w, a.nnz)
+    dec = jp.clone()
+    dec[2], dec[3] = jp[3], jp[2] - 1
+    with pytest.raises(ValueError, match="jptr"):
+        B._check_jacobian(dec, jn, w, a.nnz)
+    with pytest.raises(ValueError, match="jptr"):
+        B._check_jacobian(jp[:-1], jn, w, a.nnz)
+    with pytest.raises(ValueError, match="len"):
+        B._check_jacobian(jp, jn, w[:-1], a.nnz)
