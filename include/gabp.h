@@ -160,7 +160,12 @@ int gabp_setup(gabp_ctx** out, int32_t n, int64_t nnz, const int32_t* rowptr,
                const uint8_t* colour, const gabp_options* opt, hipStream_t stream);
 
 /* Replace the values of A, same pattern as at setup. val: DEVICE pointer, nnz doubles in
- * the setup CSR order. Precomputed Lt (if any) is invalidated and rebuilt on next use. */
+ * the setup CSR order. Precomputed Lt (if any) is invalidated and rebuilt on next use.
+ * The new diagonal is checked on the device (one flag read back, so the call waits for
+ * the stream): EZERODIAG if any A_ii is zero or not finite. The values are installed
+ * either way, so after EZERODIAG the context must get valid values before it solves.
+ * Off-diagonal values are not checked (a non-finite one ends a later solve with
+ * ENUMERIC). */
 int gabp_update_values(gabp_ctx* ctx, const double* val, hipStream_t stream);
 
 void gabp_destroy(gabp_ctx* ctx);
