@@ -36,3 +36,23 @@ def test_traffic_record_matches_its_source():
         assert abs(k["hbm_bytes_per_launch"] - want) <= 1e5
         assert bench.measured_traffic(name) == (k["hbm_bytes_per_launch"] if same else None)
     assert bench.measured_traffic("k_not_a_kernel") is None
+
+
+def test_algorithmic_bytes_per_sweep():
+    """The roofline's algorithmic bytes: joint FP64 sweep 40 B per slot (incoming Lt and m,
+    coefficient, outgoing Lt and m) plus the reverse index, 16 B per row (diagonal, b);
+    mean-only FP64 24 B + reverse per slot, 8 B per row; FP32 12 B + reverse, 4 B per row.
+    At the 2048^2 benchmark operator (16,769,024 directed slots, 4,194,304 rows) a joint
+    pass is 804,945,920 B with 4-byte reverse indices (the tiled launch) and 771,407,872 B
+    with 2-byte deltas (the one-sweep kernel)."""
+    sys.path.insert(0, ROOT)
+    import bench
+    slots, n = 16769024, 4194304
+    assert bench.sweep_bytes_joint64(slots, n, 4) == 804945920
+    assert bench.sweep_bytes_joint64(slots, n, 2) == 771407872
+    assert bench.sweep_bytes_mean64(1, 0, 2) == 26 and bench.sweep_bytes_mean64(0, 1) == 8
+    assert bench.sweep_bytes_mean32(1, 0, 2) == 14 and bench.sweep_bytes_mean32(0, 1) == 4
+    # the fraction the benchmark line reports: one pass per launch over the launch's time
+    t_launch = 162.83e-6
+    frac = bench.sweep_bytes_joint64(slots, n, 4) / t_launch / 1e9 / bench.HBM_PEAK_GBS
+    assert abs(frac - 0.618) < 1e-3 and bench.HBM_PEAK_GBS == 8000.0
