@@ -610,3 +610,71 @@ def test_mean_only_pins_detect_planted_mistakes(kind, monkeypatch):
         except AssertionError:
             failures += 1
     assert failures >= 1, f"planted mistake {kind} passed every mean-only pin"
+
+
+# The precision-message precomputes: planted mistakes in copies of lambda_phase (converged
+# Lt*) and lambda_sequence (the per-sweep Lt of the smoother) each break a pin above.
+
+def _mutated_lambda_phase(kind):
+    def lambda_phase(g, tol_lambda=1e-14, max_sweeps=10000):
+        Lt = np.zeros(g.E)
+        zeros = np.zeros(g.n)
+        a_num = g.a_ji if kind == "transposed" else g.a_ij
+        for _ in range(max_sweeps):
+            S, _ = G.node_totals(g, zeros, Lt, np.zeros(g.E))
+            back = 0 * Lt if kind == "no_cavity" else G._gather(Lt, g.rev)
+            with np.errstate(all="ignore"):
+                Lt_new = -a_num / (S[g.src] - back * g.a_ij)
+            done = float(np.abs(Lt_new - Lt).max()) <= tol_lambda * float(np.abs(Lt_new).max())
+            Lt = Lt_new
+            if tol_lambda > 0 and done:
+                break
+        S_star, _ = G.node_totals(g, zeros, Lt, np.zeros(g.E))
+        if kind == "diag_only":                 # Sigma* without the incoming precisions
+            S_star = g.diag.copy()
+        return Lt, S_star, max_sweeps
+    return lambda_phase
+
+
+@pytest.mark.parametrize("kind", ["transposed", "no_cavity", "diag_only"])
+def test_lambda_phase_pins_detect_planted_mistakes(kind, monkeypatch):
+    monkeypatch.setattr(G, "lambda_phase", _mutated_lambda_phase(kind))
+    failures = 0
+    for check in (test_interior_lambda_closed_form, test_precomp_reaches_dense_solution):
+        try:
+            with np.errstate(all="ignore"):
+                check()
+        except AssertionError:
+            failures += 1
+    assert failures >= 1, f"planted mistake {kind} passed every precompute pin"
+
+
+def _mutated_lambda_sequence(kind):
+    real = G.lambda_sequence
+
+    def lambda_sequence(g, depth, colour=None):
+        if kind == "shifted":                   # read-off precisions one sweep late
+            seq = real(g, depth + 1, colour)
+            return [(seq[s][0], seq[s + 1][1]) for s in range(depth)]
+        if kind == "all_classes":               # a coloured sweep updating every class at once
+            return real(g, depth, None)
+        if kind == "transposed":
+            gt = g.transposed()
+            return [(Lt, S) for Lt, S in real(gt, depth, colour)]
+        raise AssertionError(kind)
+    return lambda_sequence
+
+
+@pytest.mark.parametrize("kind", ["shifted", "all_classes", "transposed"])
+def test_lambda_sequence_pins_detect_planted_mistakes(kind, monkeypatch):
+    monkeypatch.setattr(G, "lambda_sequence", _mutated_lambda_sequence(kind))
+    failures = 0
+    for check in (test_sequence_interior_closed_form,
+                  lambda: test_sequence_smoother_equals_joint_smoother("flood"),
+                  lambda: test_sequence_smoother_equals_joint_smoother("redblack")):
+        try:
+            with np.errstate(all="ignore"):
+                check()
+        except AssertionError:
+            failures += 1
+    assert failures >= 1, f"planted mistake {kind} passed every sequence pin"
