@@ -267,3 +267,10 @@ def test_adjoint_pins_detect_planted_mistakes(kind, monkeypatch):
         except AssertionError:
             failures += 1
     assert failures >= 1, f"planted mistake {kind} passed every adjoint pin"
+
+
+def test_unplanted_vcycle_copy_passes_every_pin(monkeypatch):
+    """The V-cycle copy the planted mistakes go into passes the V-cycle pins unchanged."""
+    monkeypatch.setattr(MG.Hierarchy, "vcycle", _vcycle_mutant("none"))
+    test_vcycle_rbgs_poisson_textbook_contraction()
+    test_vcycle_exact_coarse_solve_two_levels()

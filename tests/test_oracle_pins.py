@@ -595,7 +595,7 @@ def _mutated_msweep(kind):
             return M / S_star, Lt_star * M[g.src]
         if kind == "stale_readoff":             # read-off before the incoming sum
             return b / S_star, Lt_star * (M[g.src] - G._gather(m, g.rev))
-        raise AssertionError(kind)
+        return M / S_star, Lt_star * (M[g.src] - G._gather(m, g.rev))
     return msweep
 
 
@@ -678,3 +678,22 @@ def test_lambda_sequence_pins_detect_planted_mistakes(kind, monkeypatch):
         except AssertionError:
             failures += 1
     assert failures >= 1, f"planted mistake {kind} passed every sequence pin"
+
+
+def test_unplanted_copies_pass_every_pin(monkeypatch):
+    """The copies the planted mistakes go into are faithful: with nothing planted they pass
+    every pin they are run against, so each failure above comes from its mistake."""
+    monkeypatch.setattr(G, "sweep", _mutated_sweep("none"))
+    a = W.random_tridiagonal(12, W.rng(101, 0))
+    b = W.rng(102, 0).uniform(-1, 1, 12)
+    x, _, _ = G.run(_graph(a), b, 12)
+    assert _relerr(x, np.linalg.solve(_dense(a), b)) < 1e-13
+    test_lfa_stencils()
+    monkeypatch.setattr(G, "sweep_coloured", _mutated_coloured("none"))
+    test_redblack_first_sweep_closed_form()
+    test_redblack_fixed_point_is_dense_solution(False)
+    test_redblack_fixed_point_is_dense_solution(True)
+    monkeypatch.setattr(G, "msweep", _mutated_msweep("none"))
+    monkeypatch.setattr(G, "lambda_phase", _mutated_lambda_phase("none"))
+    test_interior_lambda_closed_form()
+    test_precomp_reaches_dense_solution()

@@ -338,3 +338,16 @@ def test_rows_then_columns_smoother_in_a_v_cycle(mode):
                      schedule="lines_alt")
     _, hist = h.solve(b, 1e-8, 30)
     assert hist[-1] <= 1e-8 and len(hist) <= 20
+
+
+def test_unplanted_copy_passes_the_pins(monkeypatch):
+    """The copy of the region sweep the mistakes go into passes both pins with nothing
+    planted, so each failure above comes from its mistake."""
+    monkeypatch.setattr(RG, "sweep", _mutated_sweep("none"))
+    assert _bethe_vs_gabp(W.random_grid_5pt(4, 3, W.rng(412, 0), one_way=0.3),
+                          np.ones(12), 4) < 1e-13
+    nx = 13
+    a = W.random_grid_5pt(nx, 1, W.rng(412, 1), one_way=0.2)
+    b = W.rng(412, 2).uniform(-1, 1, nx)
+    x2, _, _ = RG.run(_lines(a, nx, 1), b, 2)
+    assert _relerr(x2, np.linalg.solve(W.csr_to_dense(a), b)) < 1e-13
