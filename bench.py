@@ -112,7 +112,7 @@ def main():
                     help="also measure the multigrid, batching and adjoint configurations")
     ap.add_argument("--suite-only", action="store_true")
     ap.add_argument("--suite-part", default="all",
-                    choices=["all", "small", "batch", "batch_full", "mg", "mg_profile",
+                    choices=["all", "small", "batch", "batch_full", "mg", "mg_c4", "mg_profile",
                              "sweeps_large",
                              "adjoint", "adjoint_full", "lines", "sec5", "colours"],
                     help="with --suite-only: run one part of the suite")
@@ -403,7 +403,12 @@ def suite(log, part="all", line_sweeps=50):
     if part != "all":
         fn = {"small": lambda: suite_small(log), "batch": lambda: suite_batch(log),
               "batch_full": lambda: suite_batch(log, full_only=True),
-              "mg": lambda: suite_mg(log), "adjoint": lambda: suite_adjoint(log),
+              "mg": lambda: suite_mg(log),
+              "mg_c4": lambda: suite_mg(log, problems=("anisotropic_peclet4",),
+                                        smoothers=("redblack_gabp_f32_seq_lambda_2_2",
+                                                   "redblack_gabp_f64_seq_lambda_2_2"),
+                                        cap=100),
+              "adjoint": lambda: suite_adjoint(log),
               "adjoint_full": lambda: suite_adjoint_full(log),
               "mg_profile": lambda: suite_mg_profile(log),
               "sweeps_large": lambda: suite_sweeps_large(log),
@@ -770,7 +775,9 @@ def cpu_baseline_batch(systems, rhs_l, t_batch, log):
     return rec
 
 
-def suite_mg(log, J=12):
+def suite_mg(log, J=12, problems=None, smoothers=None, cap=60):
+    """V(2,2) multigrid to rel.res 1e-8 (at most ``cap`` cycles) per problem and smoother;
+    ``problems`` / ``smoothers``: names to run (None: all)."""
     import torch
     from paper_1904_04093_amd import gabp
     from paper_1904_04093_amd import workloads as W
@@ -778,13 +785,16 @@ def suite_mg(log, J=12):
     for name, JJ, kw in (("anisotropic_peclet4", J, dict(kx=1.0, ky=0.01, peclet=4.0)),
                          ("poisson", J, dict(kx=1.0, ky=1.0, peclet=0.0)),
                          ("anisotropic_peclet4_63x63", 6, dict(kx=1.0, ky=0.01, peclet=4.0))):
+        if problems is not None and name not in problems:
+            continue
         t0 = time.perf_counter()
         levels = W.mg_hierarchy(JJ, coarsest=3, **kw)
         sides = [int(round(np.sqrt(x.n))) for x in levels]
         gen = time.perf_counter() - t0
         b = W.rng(4, 1).uniform(-1, 1, levels[0].n)
         bt = torch.as_tensor(b).cuda()
-        entry = {"grid": f"{sides[0]}x{sides[0]}", "levels": len(levels), "generate_s": gen}
+        entry = {"grid": f"{sides[0]}x{sides[0]}", "levels": len(levels), "generate_s": gen,
+                 "cycle_cap": cap}
         for sm_name, smoother, kwg in (
                 ("rbgs_2_2", "rbgs", {}),
                 ("redblack_gabp_f32_seq_lambda_2_2", "gabp",
@@ -799,6 +809,8 @@ def suite_mg(log, J=12):
                 ("lines_alt_gabp_f32_frozen_lambda_2_2", "gabp",
                  dict(mode="precomp", precision="f32_ir", schedule="lines_alt", tol_lambda=1e-7)),
                 ("lines_alt_gabp_f64_joint_2_2", "gabp", dict(mode="joint", schedule="lines_alt"))):
+            if smoothers is not None and sm_name not in smoothers:
+                continue
             t0 = time.perf_counter()
             lines = kwg.get("schedule", "").startswith("lines")
             solvers = [gabp.Solver.from_csr(x, colour=None if lines else W.grid_colouring(sd),
@@ -810,7 +822,7 @@ def suite_mg(log, J=12):
             torch.cuda.synchronize()
             setup = time.perf_counter() - t0
             t0 = time.perf_counter()
-            x, info = mg.solve(bt, 1e-8, 60)
+            x, info = mg.solve(bt, 1e-8, cap)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             entry[sm_name] = {"status": info["status"], "cycles": info["cycles"],
